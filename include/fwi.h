@@ -1,0 +1,222 @@
+/*
+ * fwi.h - C ABI of the MI355X (gfx950) hot path of TV-regularized
+ * frequency-domain full-waveform inversion for single-sided linear arrays.
+ *
+ * The method (Guo, Auerbach, Eldar): the total field of transmit i at
+ * frequency l solves the volume integral equation (Eq. 5)
+ *     p = p0 + k0^2 int_V G(x, x') m(x') p(x') dx',
+ * the scattered data are P^s_{i,j,l} = k0^2 int G m p at receiver j (Eq. 4),
+ * the Green's-function product is an FFT convolution and the system is
+ * solved by a Krylov method (Sec. IV-A), the gradient and Jacobian products
+ * come from forward and adjoint fields (Eq. 15-17), and the model is updated
+ * by ADMM with an isotropic TV prior (Eq. 7-14, Algorithm 1).
+ *
+ * Discretisation (the paper says only "after discretization"): square/cubic
+ * cells of size dx, pulse basis, collocation at cell centres, cell integral of
+ * G over the equal-area disk / equal-volume ball (Richmond), point elements on
+ * the top face z = 0, point receivers with the midpoint rule. Time convention
+ * e^{-i omega t}: complex values are the conjugates of the paper's.
+ *
+ * Conventions for every entry point
+ *  - Grids are depth-major: index ((iz * ny) + iy) * nx + ix, x fastest; ny = 1
+ *    in 2D. Cell centres at ((ix+1/2)dx, (iy+1/2)dx, (iz+1/2)dx).
+ *  - Complex arrays are interleaved (re, im): complex128 = 2 doubles,
+ *    complex64 = 2 floats.
+ *  - Data arrays are [nf][ne][ne] with layout [l][i][j] (transmit i, receiver j).
+ *  - Fields / RHS arrays are [nf][ne][n] (frequency-major, then transmit).
+ *  - fwi_problem and its freq_hz / elem_xyz arrays, option/param structs and
+ *    scalar outputs (misfit, stats, report) are HOST memory. Every grid, data,
+ *    field and state array argument is DEVICE memory on the context's device.
+ *  - Calls are enqueued on the context's HIP stream; they return after the
+ *    host-visible scalars (misfit, stats, report) are known, which requires
+ *    synchronising that stream. Array outputs are complete when the call
+ *    returns FWI_OK.
+ *  - The library never frees or retains caller memory; it reads inputs as
+ *    const and writes only the named outputs and its workspace.
+ *  - Return codes are 0 (FWI_OK) or a negative FWI_E_* code; no exception
+ *    crosses the ABI. fwi_last_error() gives a message for the last failure
+ *    on that context. One context per stream; contexts are not thread-safe.
+ */
+#ifndef FWI_H
+#define FWI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWI_OK 0
+#define FWI_E_INVAL (-1)       /* invalid argument (shape, pointer, value) */
+#define FWI_E_NOMEM (-2)       /* caller workspace too small / allocation failed */
+#define FWI_E_NOCONV (-3)      /* a solve hit max_iter; outputs are still written */
+#define FWI_E_NONFINITE (-4)   /* NaN/Inf in an input or a residual */
+#define FWI_E_DEVICE (-5)      /* HIP runtime error */
+#define FWI_E_UNSUPPORTED (-6) /* size or mode outside what the library implements */
+
+#define FWI_FP64 0          /* complex128 everywhere */
+#define FWI_FP32_REFINE 1   /* complex64 Krylov solves inside FP64-residual refinement */
+
+typedef struct fwi_ctx fwi_ctx;
+
+/* Problem statement (Sec. II): grid of cells, constant-density background
+ * c0 (lossless), frequencies and element positions on the top face z = 0.
+ * Each axis must satisfy 1 <= n <= 512 (padded FFT length 2^a 3^b <= 1024). */
+typedef struct fwi_problem {
+  int dim;                 /* 2 or 3 */
+  int nx, ny, nz;          /* cells: lateral x, elevation y (1 in 2D), depth z */
+  double dx;               /* cell size [m] */
+  double c0;               /* background speed of sound [m/s] */
+  int nf;                  /* number of frequencies */
+  const double* freq_hz;   /* host [nf], > 0 */
+  int ne;                  /* number of elements (transmit set = receive set) */
+  const double* elem_xyz;  /* host [ne][3] positions [m]; z must be 0 */
+} fwi_problem;
+
+/* Solver options (Sec. IV-A: Krylov solve of the discretised Eq. 5). */
+typedef struct fwi_solve_opts {
+  int precision;        /* FWI_FP64 or FWI_FP32_REFINE */
+  double rtol;          /* target ||b - A x|| / ||b|| in FP64, per RHS */
+  int max_iter;         /* cap on Krylov iterations per RHS (all cycles) */
+  int restart;          /* GMRES basis length: 8, 16 or 32 */
+  int max_refine;       /* FP32_REFINE: cap on refinement steps */
+  double inner_rtol;    /* FP32_REFINE: relative target of each inner solve */
+  int max_rhs;          /* cap on RHS per batched solve (0: all frequencies at once) */
+  int check_every;      /* iterations between host convergence checks (>= 1) */
+  int reciprocity_adjoint; /* 1: adjoint fields as sum_j conj(r_ij) p_j (no adjoint solves) */
+} fwi_solve_opts;
+
+/* Per-call statistics (host struct, written when non-NULL). */
+typedef struct fwi_stats {
+  int iterations;          /* max Krylov iterations over the RHS of the call */
+  int cycles;              /* max restart cycles / refinement steps of a batch */
+  int unconverged;         /* RHS that did not reach rtol */
+  double max_rel_residual; /* max final FP64 relative residual */
+  long long solves;        /* right-hand sides solved (forward + adjoint) */
+  long long matvecs;       /* operator applications summed over RHS */
+  double t_setup_ms;       /* contrast, Green spectra, incident fields */
+  double t_solve_ms;       /* Krylov solves */
+  double t_total_ms;       /* whole call */
+} fwi_stats;
+
+/* ADMM parameters (Eq. 8-14, Algorithm 1). */
+typedef struct fwi_admm_params {
+  double lambda;      /* TV weight */
+  double rho;         /* augmented-Lagrangian penalty */
+  double gamma;       /* reference-model weight (ignored when m_ref is NULL) */
+  int n_cg;           /* CG iterations on the normal equations (Eq. 11-12) */
+  double data_scale;  /* s multiplying the data term; <= 0 selects 1/||d_obs||^2 */
+  double dual_step;   /* u += dual_step (g - grad m); the paper prints rho */
+} fwi_admm_params;
+
+typedef struct fwi_admm_report {
+  double misfit;   /* 1/2 ||F(m_k) - d_obs||^2 at the input model */
+  double tv;       /* ||grad m_{k+1}||_{1,2} */
+  double dm_norm;  /* ||m_{k+1} - m_k|| */
+} fwi_admm_report;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device` enqueuing on `hip_stream` (a
+ * hipStream_t; NULL = default stream). The context owns only caches (twiddle
+ * tables, Green spectra and incident fields of the last problem) and, when no
+ * caller workspace is set, an internal workspace. */
+int fwi_create(fwi_ctx** out, int device, void* hip_stream);
+void fwi_destroy(fwi_ctx* ctx);
+const char* fwi_last_error(const fwi_ctx* ctx);
+int fwi_set_stream(fwi_ctx* ctx, void* hip_stream);
+void fwi_default_opts(fwi_solve_opts* opts);
+
+/* Host-only argument check; returns FWI_OK or FWI_E_INVAL / FWI_E_UNSUPPORTED.
+ * Elements must lie on z = 0 within the lateral extent; frequencies > 0. */
+int fwi_validate_problem(const fwi_problem* prob);
+/* Padded FFT length used for an axis of n cells (smallest 2^a 3^b >= 2n), 0 if n > 512. */
+int fwi_padded_length(int n);
+
+/* Workspace bytes an entry point needs (host-only). entry: 0 forward,
+ * 1 adjoint gradient / vjp, 2 ADMM step. Returns FWI_OK and writes *bytes. */
+#define FWI_ENTRY_FORWARD 0
+#define FWI_ENTRY_GRADIENT 1
+#define FWI_ENTRY_ADMM 2
+int fwi_workspace_size(const fwi_problem* prob, const fwi_solve_opts* opts, int entry, size_t* bytes);
+/* Use caller device memory as workspace (NULL/0 returns to internal allocation).
+ * Calls needing more than `bytes` fail with FWI_E_NOMEM. */
+int fwi_set_workspace(fwi_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------- hot path */
+/* F(m): forward solves for every transmit and frequency and the scattered
+ * data (Eq. 3-6). c [n] speed of sound [m/s] > 0, alpha [n] attenuation
+ * [Np/m/Hz] >= 0 or NULL (zero), both double. data_out [nf][ne][ne]
+ * complex128. fields_out NULL or [nf][ne][n] complex128 total fields. */
+int fwi_forward(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha,
+                const fwi_solve_opts* opts, void* data_out, void* fields_out, fwi_stats* stats);
+
+/* Same as fwi_forward for a contrast m [n] complex128 (Eq. 3). */
+int fwi_forward_m(fwi_ctx* ctx, const fwi_problem* prob, const void* m, const fwi_solve_opts* opts,
+                  void* data_out, void* fields_out, fwi_stats* stats);
+
+/* Misfit phi = 1/2 ||F(m) - d_obs||^2 and its gradient by adjoint solves
+ * with the same operator (Eq. 15-17): g_n = dV sum_l conj(k_l^2) sum_i
+ * conj(p_li(x_n) lam_li(x_n)), lam_li = A_l^{-1} sum_j conj(r_lij) p0_lj.
+ * d_obs [nf][ne][ne] complex128. misfit_out: host double or NULL.
+ * grad_m_out [n] complex128 (d phi/d Re m + i d phi/d Im m) or NULL;
+ * grad_c_out, grad_alpha_out [n] double (chain rule) or NULL. */
+int fwi_adjoint_gradient(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha,
+                         const void* d_obs, const fwi_solve_opts* opts, double* misfit_out, void* grad_m_out,
+                         double* grad_c_out, double* grad_alpha_out, fwi_stats* stats);
+
+/* Vector-Jacobian product J^H b at contrast m (Eq. 17) via forward and
+ * adjoint solves: the backward of fwi_forward_m for automatic differentiation.
+ * m [n] complex128, grad_data [nf][ne][ne] complex128, grad_m_out [n] complex128. */
+int fwi_vjp(fwi_ctx* ctx, const fwi_problem* prob, const void* m, const void* grad_data,
+            const fwi_solve_opts* opts, void* grad_m_out, fwi_stats* stats);
+
+/* One iteration of Algorithm 1: forward solves at m_k, Gauss-Newton model
+ * update by params->n_cg CG iterations on (s J^H J + rho grad^T grad + gamma I)
+ * dm = s J^H(d_obs - F(m_k)) + rho grad^T(g + u - grad m_k) + gamma(m_ref - m_k)
+ * (Eq. 11-12, the gamma terms dropped when m_ref is NULL), then
+ * g = shrink_{lambda/rho}(grad m_{k+1} - u) (Eq. 13-14) and
+ * u += dual_step (g - grad m_{k+1}). grad: forward differences, unit spacing,
+ * zero at the last index; components ordered x, (y,) z.
+ * m_inout [n], g_inout [dim][n], u_inout [dim][n], m_ref [n] or NULL,
+ * d_obs [nf][ne][ne]: all complex128, updated in place. */
+int fwi_tv_admm_step(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_params* params, void* m_inout,
+                     void* g_inout, void* u_inout, const void* m_ref, const void* d_obs,
+                     const fwi_solve_opts* opts, fwi_admm_report* report, fwi_stats* stats);
+
+/* ------------------------------------------------- building blocks (parity) */
+/* y = A_l x for B vectors (Eq. 5 discretised): y_b = x_b - k_l^2 sum W m x_b.
+ * precision FWI_FP64: x, y complex128; FWI_FP32_REFINE: complex64 (one FP32
+ * operator application). m [n] complex128; freq_index host [B] in [0, nf). */
+int fwi_apply_operator(fwi_ctx* ctx, const fwi_problem* prob, int precision, const void* m, int B,
+                       const int* freq_index, const void* x, void* y);
+
+/* Solve A_l x_b = rhs_b for B right-hand sides with the batched solver.
+ * m [n], rhs [B][n], x_out [B][n]: complex128; freq_index host [B]. */
+int fwi_solve(fwi_ctx* ctx, const fwi_problem* prob, const void* m, int B, const int* freq_index, const void* rhs,
+              const fwi_solve_opts* opts, void* x_out, fwi_stats* stats);
+
+/* Incident fields p0 [ne][n] complex128 of frequency freq_index (Sec. II). */
+int fwi_incident(fwi_ctx* ctx, const fwi_problem* prob, int freq_index, void* out);
+
+/* Green spectrum FFT(k^2 W)/npad on the padded grid [Lz][Ly][Lx] complex128. */
+int fwi_green_spectrum(fwi_ctx* ctx, const fwi_problem* prob, int freq_index, void* out);
+
+/* Zero-padded forward FFT of in [nz][ny][nx] into out [Lz][Ly][Lx] (precision
+ * as in fwi_apply_operator). Diagnostic of the FFT passes. */
+int fwi_fft_padded(fwi_ctx* ctx, const fwi_problem* prob, int precision, const void* in, void* out);
+
+/* Jacobian products from stored fields [nf][ne][n] complex128 (Eq. 16-17):
+ * out_data [nf][ne][ne] = J a for a [n];  out_m [n] = J^H b for b [nf][ne][ne]. */
+int fwi_jacobian_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields, const void* a, void* out_data);
+int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields, const void* b,
+                               void* out_m);
+
+/* Host evaluation of the FP64 Bessel routine used by the kernels:
+ * out4 = {J0(x), J1(x), Y0(x), Y1(x)} for x > 0. */
+void fwi_host_bessel01(double x, double* out4);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWI_H */

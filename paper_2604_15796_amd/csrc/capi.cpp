@@ -1,0 +1,1125 @@
+// C ABI of the FWI hot path (include/fwi.h): argument validation, the
+// per-problem caches (Green spectra, incident fields), the workspace arena,
+// the batched Krylov driver and the entry points of Sec. II-IV.
+#include "../../include/fwi.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <set>
+#include <sstream>
+#include <string>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "data.hpp"
+#include "internal.hpp"
+#include "krylov.hpp"
+
+using namespace fwi;
+
+namespace fwi {
+
+int length_index(int L) {
+  for (int i = 0; i < kNumLengths; ++i)
+    if (kLengths[i] == L) return i;
+  return -1;
+}
+int padded_length(int n) {
+  if (n < 1) return 0;
+  for (int i = 0; i < kNumLengths; ++i)
+    if (kLengths[i] >= 2 * n) return kLengths[i];
+  return 0;
+}
+template <>
+const c128* Twiddles::get<double>(int L) const {
+  const int i = length_index(L);
+  if (i < 0) throw Error(FWI_E_UNSUPPORTED, "no twiddles for length " + std::to_string(L));
+  return d64[i];
+}
+template <>
+const c64* Twiddles::get<float>(int L) const {
+  const int i = length_index(L);
+  if (i < 0) throw Error(FWI_E_UNSUPPORTED, "no twiddles for length " + std::to_string(L));
+  return d32[i];
+}
+
+}  // namespace fwi
+
+namespace {
+
+// --------------------------------------------------------------- arena ---
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool dry = true;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    const size_t off = used;
+    used += bytes;
+    if (dry) return nullptr;
+    if (used > cap) throw Error(FWI_E_NOMEM, "workspace exhausted");
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// ------------------------------------------------------- problem cache ---
+struct ProblemCache {
+  std::string key;
+  Geo g;
+  int nf = 0, ne = 0;
+  std::vector<double> k;
+  c128* ghat64 = nullptr;   // [nf][npad]
+  c64* ghat32 = nullptr;    // [nf][npad]
+  c128* P0 = nullptr;       // [nf][ne][n]
+  c128* k2 = nullptr;       // [nf]  k_l^2
+  c128* coef = nullptr;     // [nf]  k_l^2 dV
+  int* rhs_freq = nullptr;  // [nf*ne]
+  double* elems = nullptr;  // [ne][3]
+  void release() {
+    void* ps[] = {ghat64, ghat32, P0, k2, coef, rhs_freq, elems};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+    ghat64 = nullptr;
+    ghat32 = nullptr;
+    P0 = nullptr;
+    k2 = coef = nullptr;
+    rhs_freq = nullptr;
+    elems = nullptr;
+    key.clear();
+  }
+};
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct fwi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  Twiddles tw;
+  std::vector<void*> tw_allocs;
+  char* ws_ext = nullptr;
+  size_t ws_ext_bytes = 0;
+  char* ws_int = nullptr;
+  size_t ws_int_bytes = 0;
+  ProblemCache pc;
+  int* h_int = nullptr;        // pinned host scratch
+  double* h_dbl = nullptr;
+  int* d_int = nullptr;        // device scratch for checks
+};
+
+namespace {
+
+int fail(fwi_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+// ---------------------------------------------------------- validation ---
+int validate_problem(const fwi_problem* p, std::string& msg) {
+  if (!p) return msg = "problem is NULL", FWI_E_INVAL;
+  if (p->dim != 2 && p->dim != 3) return msg = "dim must be 2 or 3", FWI_E_UNSUPPORTED;
+  if (p->nx < 1 || p->nz < 1 || p->ny < 1) return msg = "grid extents must be >= 1", FWI_E_INVAL;
+  if (p->dim == 2 && p->ny != 1) return msg = "ny must be 1 in 2D", FWI_E_INVAL;
+  if (!padded_length(p->nx) || !padded_length(p->nz) || (p->dim == 3 && !padded_length(p->ny)))
+    return msg = "grid extent above 512 cells per axis", FWI_E_UNSUPPORTED;
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return msg = "dx must be finite and > 0", FWI_E_INVAL;
+  if (!(p->c0 > 0.0) || !std::isfinite(p->c0)) return msg = "c0 must be finite and > 0", FWI_E_INVAL;
+  if (p->nf < 1 || !p->freq_hz) return msg = "need nf >= 1 frequencies", FWI_E_INVAL;
+  for (int l = 0; l < p->nf; ++l)
+    if (!(p->freq_hz[l] > 0.0) || !std::isfinite(p->freq_hz[l])) return msg = "frequencies must be > 0", FWI_E_INVAL;
+  if (p->ne < 1 || !p->elem_xyz) return msg = "need ne >= 1 elements", FWI_E_INVAL;
+  if (p->ne > 256) return msg = "more than 256 elements", FWI_E_UNSUPPORTED;
+  const double wx = p->nx * p->dx, wy = p->ny * p->dx;
+  std::set<std::pair<double, double>> seen;
+  for (int e = 0; e < p->ne; ++e) {
+    const double x = p->elem_xyz[3 * e], y = p->elem_xyz[3 * e + 1], z = p->elem_xyz[3 * e + 2];
+    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return msg = "non-finite element position", FWI_E_INVAL;
+    if (z != 0.0) return msg = "elements must lie on the top face z = 0", FWI_E_UNSUPPORTED;
+    if (x < 0.0 || x > wx) return msg = "element outside the lateral extent", FWI_E_INVAL;
+    if (p->dim == 3 && (y < 0.0 || y > wy)) return msg = "element outside the elevation extent", FWI_E_INVAL;
+    if (p->dim == 2 && y != 0.0) return msg = "2D elements must have y = 0", FWI_E_INVAL;
+    if (!seen.insert({x, y}).second) return msg = "duplicate element position", FWI_E_INVAL;
+  }
+  return FWI_OK;
+}
+
+int validate_opts(const fwi_solve_opts* o, std::string& msg) {
+  if (!o) return msg = "opts is NULL", FWI_E_INVAL;
+  if (o->precision != FWI_FP64 && o->precision != FWI_FP32_REFINE) return msg = "bad precision", FWI_E_INVAL;
+  if (!(o->rtol > 0.0 && o->rtol < 1.0)) return msg = "rtol must be in (0, 1)", FWI_E_INVAL;
+  if (o->restart != 8 && o->restart != 16 && o->restart != 32) return msg = "restart must be 8, 16 or 32", FWI_E_UNSUPPORTED;
+  if (o->max_iter < 1) return msg = "max_iter must be >= 1", FWI_E_INVAL;
+  if (o->precision == FWI_FP32_REFINE) {
+    if (o->max_refine < 1) return msg = "max_refine must be >= 1", FWI_E_INVAL;
+    if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0)) return msg = "inner_rtol must be in (0, 1)", FWI_E_INVAL;
+  }
+  if (o->max_rhs < 0) return msg = "max_rhs must be >= 0", FWI_E_INVAL;
+  if (o->check_every < 1) return msg = "check_every must be >= 1", FWI_E_INVAL;
+  return FWI_OK;
+}
+
+Geo make_geo(const fwi_problem* p) {
+  Geo g;
+  g.dim = p->dim;
+  g.nx = p->nx;
+  g.ny = p->dim == 3 ? p->ny : 1;
+  g.nz = p->nz;
+  g.Lx = padded_length(g.nx);
+  g.Ly = p->dim == 3 ? padded_length(g.ny) : 1;
+  g.Lz = padded_length(g.nz);
+  g.dx = p->dx;
+  g.c0 = p->c0;
+  return g;
+}
+
+std::string problem_key(const fwi_problem* p) {
+  std::ostringstream os;
+  os.precision(17);
+  os << p->dim << ' ' << p->nx << ' ' << p->ny << ' ' << p->nz << ' ' << p->dx << ' ' << p->c0 << ' ' << p->nf;
+  for (int l = 0; l < p->nf; ++l) os << ' ' << p->freq_hz[l];
+  os << ' ' << p->ne;
+  for (int e = 0; e < 3 * p->ne; ++e) os << ' ' << p->elem_xyz[e];
+  return os.str();
+}
+
+// ------------------------------------------------------------ twiddles ---
+void make_twiddles(fwi_ctx* c) {
+  for (int li = 0; li < kNumLengths; ++li) {
+    const int L = kLengths[li];
+    std::vector<c128> h64(L);
+    std::vector<c64> h32(L);
+    for (int m = 0; m < L; ++m) {
+      const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)L;
+      h64[m] = mk((double)cosl(ang), (double)sinl(ang));
+      h32[m] = mk((float)cosl(ang), (float)sinl(ang));
+    }
+    void *p64 = nullptr, *p32 = nullptr;
+    FWI_HIP(hipMalloc(&p64, sizeof(c128) * L));
+    c->tw_allocs.push_back(p64);
+    FWI_HIP(hipMalloc(&p32, sizeof(c64) * L));
+    c->tw_allocs.push_back(p32);
+    FWI_HIP(hipMemcpy(p64, h64.data(), sizeof(c128) * L, hipMemcpyHostToDevice));
+    FWI_HIP(hipMemcpy(p32, h32.data(), sizeof(c64) * L, hipMemcpyHostToDevice));
+    c->tw.d64[li] = (const c128*)p64;
+    c->tw.d32[li] = (const c64*)p32;
+  }
+}
+
+// --------------------------------------------------------- cache build ---
+// Green spectra (FP64 FFT of the circulant table, cast to FP32 as well) and
+// incident fields of every frequency; reused while the problem is unchanged.
+double ensure_cache(fwi_ctx* c, const fwi_problem* p) {
+  const std::string key = problem_key(p);
+  if (key == c->pc.key) return 0.0;
+  const double t0 = now_ms();
+  c->pc.release();
+  ProblemCache& pc = c->pc;
+  pc.g = make_geo(p);
+  pc.nf = p->nf;
+  pc.ne = p->ne;
+  const Geo& g = pc.g;
+  const long n = g.n(), np = g.npad();
+  hipStream_t st = c->stream;
+  FWI_HIP(hipMalloc((void**)&pc.ghat64, sizeof(c128) * np * pc.nf));
+  FWI_HIP(hipMalloc((void**)&pc.ghat32, sizeof(c64) * np * pc.nf));
+  FWI_HIP(hipMalloc((void**)&pc.P0, sizeof(c128) * n * pc.ne * pc.nf));
+  FWI_HIP(hipMalloc((void**)&pc.k2, sizeof(c128) * pc.nf));
+  FWI_HIP(hipMalloc((void**)&pc.coef, sizeof(c128) * pc.nf));
+  FWI_HIP(hipMalloc((void**)&pc.rhs_freq, sizeof(int) * pc.nf * pc.ne));
+  FWI_HIP(hipMalloc((void**)&pc.elems, sizeof(double) * 3 * pc.ne));
+  FWI_HIP(hipMemcpyAsync(pc.elems, p->elem_xyz, sizeof(double) * 3 * pc.ne, hipMemcpyHostToDevice, st));
+  std::vector<c128> hk2(pc.nf), hcoef(pc.nf);
+  std::vector<int> hrf((size_t)pc.nf * pc.ne);
+  const double dV = std::pow(g.dx, g.dim);
+  pc.k.resize(pc.nf);
+  c128 *table = nullptr, *work = nullptr;
+  FWI_HIP(hipMalloc((void**)&table, sizeof(c128) * np));
+  FWI_HIP(hipMalloc((void**)&work, sizeof(c128) * np));
+  for (int l = 0; l < pc.nf; ++l) {
+    const double k = 2.0 * 3.14159265358979323846 * p->freq_hz[l] / p->c0;
+    pc.k[l] = k;
+    hk2[l] = mk(k * k, 0.0);
+    hcoef[l] = mk(k * k * dV, 0.0);
+    for (int e = 0; e < pc.ne; ++e) hrf[(size_t)l * pc.ne + e] = l;
+    launch_green_table(g, k, table, st);
+    launch_fft_full(g, c->tw, table, work, pc.ghat64 + (long)l * np, st);
+    launch_cast_64_32(np, pc.ghat64 + (long)l * np, pc.ghat32 + (long)l * np, st);
+    launch_incident(g, k, pc.ne, pc.elems, pc.P0 + (long)l * pc.ne * n, st);
+  }
+  FWI_HIP(hipMemcpyAsync(pc.k2, hk2.data(), sizeof(c128) * pc.nf, hipMemcpyHostToDevice, st));
+  FWI_HIP(hipMemcpyAsync(pc.coef, hcoef.data(), sizeof(c128) * pc.nf, hipMemcpyHostToDevice, st));
+  FWI_HIP(hipMemcpyAsync(pc.rhs_freq, hrf.data(), sizeof(int) * hrf.size(), hipMemcpyHostToDevice, st));
+  FWI_HIP(hipStreamSynchronize(st));
+  FWI_HIP(hipFree(table));
+  FWI_HIP(hipFree(work));
+  pc.key = key;
+  return now_ms() - t0;
+}
+
+// ----------------------------------------------------------- workspace ---
+void bind_workspace(fwi_ctx* c, Arena& a, size_t need) {
+  a.dry = false;
+  a.used = 0;
+  if (c->ws_ext) {
+    if (need > c->ws_ext_bytes)
+      throw Error(FWI_E_NOMEM, "caller workspace too small: need " + std::to_string(need) + " bytes");
+    a.base = c->ws_ext;
+    a.cap = c->ws_ext_bytes;
+    return;
+  }
+  if (need > c->ws_int_bytes) {
+    if (c->ws_int) FWI_HIP(hipFree(c->ws_int));
+    c->ws_int = nullptr;
+    c->ws_int_bytes = 0;
+    if (hipMalloc((void**)&c->ws_int, need) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(FWI_E_NOMEM, "cannot allocate " + std::to_string(need) + " bytes of workspace");
+    }
+    c->ws_int_bytes = need;
+  }
+  a.base = c->ws_int;
+  a.cap = c->ws_int_bytes;
+}
+
+// ------------------------------------------------------- solve buffers ---
+template <typename T>
+struct SolveBufs {
+  KrylovState<T> ks;
+  c128* r64 = nullptr;
+  cplx<T>* U1 = nullptr;
+  cplx<T>* U2 = nullptr;
+  c128* U1_64 = nullptr;
+  c128* U2_64 = nullptr;
+};
+
+template <typename T>
+void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
+  KrylovState<T>& k = s.ks;
+  const long n = g.n();
+  k.B = B;
+  k.JM = JM;
+  k.n = n;
+  k.nblk = krylov_nblk(n);
+  k.chunk = (int)((n + k.nblk - 1) / k.nblk);
+  k.V = a.take<cplx<T>>((size_t)(JM + 1) * B * n);
+  k.H = a.take<c128>((size_t)B * (JM + 1) * JM);
+  k.cs = a.take<double>((size_t)B * JM);
+  k.sn = a.take<c128>((size_t)B * JM);
+  k.gv = a.take<c128>((size_t)B * (JM + 1));
+  k.y = a.take<c128>((size_t)B * JM);
+  k.dotp = a.take<c128>((size_t)B * k.nblk * (JM + 1));
+  k.nrmp = a.take<double>((size_t)B * k.nblk);
+  k.rnorm = a.take<double>(B);
+  k.bnorm = a.take<double>(B);
+  k.target = a.take<double>(B);
+  k.rscale = a.take<double>(B);
+  k.scal = a.take<cplx<T>>(B);
+  k.active = a.take<int>(B);
+  k.ncol = a.take<int>(B);
+  k.iters = a.take<int>(B);
+  k.counters = a.take<int>(2);
+  k.maxrel = a.take<double>(1);
+  s.r64 = a.take<c128>((size_t)B * n);
+  s.U1 = a.take<cplx<T>>((size_t)B * g.u1());
+  s.U2 = g.dim == 3 ? a.take<cplx<T>>((size_t)B * g.u2()) : nullptr;
+  if (std::is_same<T, float>::value) {
+    s.U1_64 = a.take<c128>((size_t)B * g.u1());
+    s.U2_64 = g.dim == 3 ? a.take<c128>((size_t)B * g.u2()) : nullptr;
+  } else {
+    s.U1_64 = reinterpret_cast<c128*>(s.U1);
+    s.U2_64 = reinterpret_cast<c128*>(s.U2);
+  }
+}
+
+struct SolveTotals {
+  int iters_max = 0, cycles = 0, unconverged = 0;
+  double maxrel = 0.0;
+  long long solves = 0, matvecs = 0;
+  double t_solve = 0.0;
+  void merge(const SolveTotals& o) {
+    iters_max = std::max(iters_max, o.iters_max);
+    cycles = std::max(cycles, o.cycles);
+    unconverged += o.unconverged;
+    maxrel = std::max(maxrel, o.maxrel);
+    solves += o.solves;
+    matvecs += o.matvecs;
+    t_solve += o.t_solve;
+  }
+};
+
+// Batched solve A_{f_b} x_b = b_b for B right-hand sides (restarted GMRES in
+// FP64, or FP32 GMRES cycles inside FP64-residual iterative refinement).
+// Each cycle starts from the true FP64 residual r = b - A x, normalises it,
+// runs at most `restart` Arnoldi steps per RHS (stopping each RHS at its
+// target) and adds the correction to the FP64 solution x.
+template <typename T>
+SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* mT, const c128* ghat64,
+                      const cplx<T>* ghatT, int B, const c128* b64, const int* rhs_freq, c128* x64,
+                      const fwi_solve_opts& o, SolveBufs<T>& s) {
+  hipStream_t st = c->stream;
+  KrylovState<T>& ks = s.ks;
+  const bool fp32 = std::is_same<T, float>::value;
+  const double inner = fp32 ? o.inner_rtol : 0.0;
+  const int max_cycles = fp32 ? o.max_refine : (o.max_iter + o.restart - 1) / o.restart + 1;
+  const long vs = ks.vstride();
+  const double t0 = now_ms();
+  SolveTotals res;
+  res.solves = B;
+  launch_fill_zero_c128((long)B * ks.n, x64, st);
+  krylov_reset_iters(ks, st);
+  int total = 0, cyc = 0;
+  for (;; ++cyc) {
+    const c128* r = b64;
+    if (cyc > 0) {
+      launch_vie<double>(g, c->tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64, s.r64, b64,
+                         EPI_RESID, st);
+      r = s.r64;
+      res.matvecs += B;
+    }
+    krylov_norms(ks, r, st);
+    krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
+    FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipMemcpyAsync(c->h_dbl, ks.maxrel, sizeof(double), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipStreamSynchronize(st));
+    res.maxrel = c->h_dbl[0];
+    if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
+    const int nact = c->h_int[0];
+    if (nact == 0) break;
+    if (cyc >= max_cycles || total >= o.max_iter) {
+      res.unconverged = nact;
+      break;
+    }
+    krylov_start_basis(ks, r, st);
+    for (int j = 0; j < ks.JM; ++j) {
+      launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, nullptr, ks.active, mT, ghatT, rhs_freq, s.U1, s.U2,
+                    ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
+      krylov_arnoldi(ks, j, st);
+      ++total;
+      if ((j + 1) % o.check_every == 0 || j + 1 == ks.JM || total >= o.max_iter) {
+        FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+        FWI_HIP(hipStreamSynchronize(st));
+        if (c->h_int[0] == 0) break;
+      }
+      if (total >= o.max_iter) break;
+    }
+    krylov_finish_cycle(ks, x64, st);
+  }
+  res.cycles = cyc;
+  std::vector<int> it(B);
+  FWI_HIP(hipMemcpyAsync(it.data(), ks.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
+  FWI_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < B; ++b) {
+    res.iters_max = std::max(res.iters_max, it[b]);
+    res.matvecs += it[b];
+  }
+  res.t_solve = now_ms() - t0;
+  return res;
+}
+
+// Groups of whole frequencies solved together: at most max_rhs RHS per batch.
+int freqs_per_group(const fwi_problem* p, const fwi_solve_opts& o) {
+  if (o.max_rhs <= 0) return p->nf;
+  const int f = o.max_rhs / p->ne;
+  return f < 1 ? 1 : (f > p->nf ? p->nf : f);
+}
+
+// Per-call device buffers of the model and of one frequency group.
+struct CallBufs {
+  c128* m64 = nullptr;
+  c64* m32 = nullptr;
+  c128* fields = nullptr;   // [B][n]  (group fields, or all fields for ADMM)
+  c128* S = nullptr;        // [B][n]  adjoint sources
+  c128* lam = nullptr;      // [B][n]  adjoint fields
+  c128* data = nullptr;     // [nf][ne][ne]
+  c128* r = nullptr;        // [nf][ne][ne]
+  c128* gpart = nullptr;    // [nks][nfg][ne][ne] or [nseg][n]
+  c128* gacc = nullptr;     // [n]
+  double* misfits = nullptr;  // [ngroups]
+  int* rfreq = nullptr;     // [B]
+  // ADMM
+  c128 *cg_x = nullptr, *cg_r = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *vec = nullptr;
+  c128 *gm = nullptr, *tmpd = nullptr, *Jp = nullptr;
+  double *dpart = nullptr, *sc = nullptr;
+};
+
+constexpr int kGradSeg = 16;
+
+int gemm_splits(long n) {
+  long s = (n + 2047) / 2048;
+  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+}
+
+// Plans every buffer of an entry point; `entry` as in fwi_workspace_size.
+template <typename T>
+void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entry, CallBufs& cb, SolveBufs<T>& sb,
+               int B_override = 0) {
+  const Geo g = make_geo(p);
+  const long n = g.n();
+  const int nfg = freqs_per_group(p, o);
+  const int B = B_override > 0 ? B_override : nfg * p->ne;
+  const int ngroups = (p->nf + nfg - 1) / nfg;
+  const long ndata = (long)p->nf * p->ne * p->ne;
+  cb.m64 = a.take<c128>(n);
+  cb.m32 = a.take<c64>(n);
+  cb.rfreq = a.take<int>(B);
+  cb.data = a.take<c128>(ndata);
+  cb.r = a.take<c128>(ndata);
+  cb.misfits = a.take<double>(ngroups + 2);
+  const long gp = std::max((long)gemm_splits(n) * nfg * p->ne * p->ne, (long)kGradSeg * n);
+  cb.gpart = a.take<c128>(std::max(gp, (long)gemm_splits(n) * p->nf * p->ne * p->ne));
+  cb.gacc = a.take<c128>(n);
+  if (entry == FWI_ENTRY_ADMM)
+    cb.fields = a.take<c128>((size_t)p->nf * p->ne * n);
+  else
+    cb.fields = a.take<c128>((size_t)B * n);
+  if (entry != FWI_ENTRY_FORWARD) {
+    cb.S = a.take<c128>((size_t)B * n);
+    cb.lam = a.take<c128>((size_t)B * n);
+  }
+  if (entry == FWI_ENTRY_ADMM) {
+    cb.cg_x = a.take<c128>(n);
+    cb.cg_r = a.take<c128>(n);
+    cb.cg_p = a.take<c128>(n);
+    cb.cg_Ap = a.take<c128>(n);
+    cb.vec = a.take<c128>(n);
+    cb.gm = a.take<c128>((size_t)g.dim * n);
+    cb.tmpd = a.take<c128>((size_t)g.dim * n);
+    cb.Jp = a.take<c128>(ndata);
+    cb.dpart = a.take<double>(std::max(dot_blocks(n), (int)((n + 255) / 256)) + 8);
+    cb.sc = a.take<double>(8);
+  }
+  plan_solve<T>(a, g, B, o.restart, sb);
+}
+
+// ---------------------------------------------------------- pipelines ---
+struct Runner {
+  fwi_ctx* c;
+  const fwi_problem* p;
+  fwi_solve_opts o;
+  Geo g;
+  long n;
+  int nfg, ngroups;
+  CallBufs cb;
+  SolveTotals tot;
+  double t_setup = 0.0;
+
+  Runner(fwi_ctx* c_, const fwi_problem* p_, const fwi_solve_opts& o_) : c(c_), p(p_), o(o_) {
+    g = make_geo(p);
+    n = g.n();
+    nfg = freqs_per_group(p, o);
+    ngroups = (p->nf + nfg - 1) / nfg;
+  }
+
+  // Solve the forward problem for frequencies [l0, l0+nf) into `fields`.
+  template <typename T>
+  void solve_rhs(SolveBufs<T>& sb, int l0, int nf, const c128* rhs, c128* out) {
+    const ProblemCache& pc = c->pc;
+    const int B = nf * p->ne;
+    const cplx<T>* mT = std::is_same<T, float>::value ? (const cplx<T>*)cb.m32 : (const cplx<T>*)cb.m64;
+    const cplx<T>* gT = std::is_same<T, float>::value ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
+    // a short batch reuses the planned buffers with a smaller B
+    SolveBufs<T> s = sb;
+    s.ks.B = B;
+    SolveTotals r = run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, pc.rhs_freq + (long)l0 * p->ne, out, o, s);
+    tot.merge(r);
+  }
+
+  template <typename T>
+  void forward(SolveBufs<T>& sb, c128* data_out, c128* fields_out) {
+    const ProblemCache& pc = c->pc;
+    hipStream_t st = c->stream;
+    const long ne2 = (long)p->ne * p->ne;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
+      c128* F = fields_out ? fields_out + (long)l0 * p->ne * n : cb.fields;
+      solve_rhs<T>(sb, l0, nf, pc.P0 + (long)l0 * p->ne * n, F);
+      launch_gemm_nt(nf, F, (long)p->ne * n, p->ne, cb.m64, pc.P0 + (long)l0 * p->ne * n, (long)p->ne * n, p->ne, n,
+                     pc.coef + l0, cb.gpart, gemm_splits(n), data_out + l0 * ne2, st);
+    }
+  }
+
+  // misfit and J^H r (or J^H b with upstream b) by adjoint solves
+  template <typename T>
+  double gradient(SolveBufs<T>& sb, const c128* dobs, const c128* upstream, c128* data_out, const double* cc,
+                  const double* alpha, c128* gm_out, double* gc, double* ga) {
+    const ProblemCache& pc = c->pc;
+    hipStream_t st = c->stream;
+    const long ne2 = (long)p->ne * p->ne;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
+      const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
+      solve_rhs<T>(sb, l0, nf, P0g, cb.fields);
+      launch_gemm_nt(nf, cb.fields, (long)p->ne * n, p->ne, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0,
+                     cb.gpart, gemm_splits(n), data_out + l0 * ne2, st);
+      const c128* rg;
+      if (upstream) {
+        rg = upstream + l0 * ne2;
+      } else {
+        launch_residual(nf * ne2, data_out + l0 * ne2, dobs + l0 * ne2, cb.r + l0 * ne2, cb.misfits + gi, st);
+        rg = cb.r + l0 * ne2;
+      }
+      if (o.reciprocity_adjoint) {
+        launch_gemm_cn(nf, rg, p->ne, p->ne, cb.fields, (long)p->ne * n, n, cb.lam, (long)p->ne * n, st);
+      } else {
+        launch_gemm_cn(nf, rg, p->ne, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)p->ne * n, st);
+        solve_rhs<T>(sb, l0, nf, cb.S, cb.lam);
+      }
+      launch_gradient_accum(n, nf, p->ne, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
+    }
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, cc, alpha, gm_out, gc, ga, st);
+    double phi = 0.0;
+    if (!upstream) {
+      std::vector<double> mf(ngroups);
+      FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * ngroups, hipMemcpyDeviceToHost, st));
+      FWI_HIP(hipStreamSynchronize(st));
+      for (double v : mf) phi += v;
+    }
+    return phi;
+  }
+};
+
+void fill_stats(fwi_stats* s, const SolveTotals& t, double t_setup, double t_total) {
+  if (!s) return;
+  s->iterations = t.iters_max;
+  s->cycles = t.cycles;
+  s->unconverged = t.unconverged;
+  s->max_rel_residual = t.maxrel;
+  s->solves = t.solves;
+  s->matvecs = t.matvecs;
+  s->t_setup_ms = t_setup;
+  s->t_solve_ms = t.t_solve;
+  s->t_total_ms = t_total;
+}
+
+void check_sos(fwi_ctx* c, long n, const double* cc, const double* alpha) {
+  launch_check_sos(n, cc, alpha, c->d_int, c->stream);
+  FWI_HIP(hipMemcpyAsync(c->h_int, c->d_int, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  if (c->h_int[0] || c->h_int[1])
+    throw Error(FWI_E_NONFINITE, "speed of sound must be finite and > 0, attenuation finite and >= 0");
+}
+void check_complex(fwi_ctx* c, long n, const c128* x, const char* what) {
+  launch_check_complex(n, x, c->d_int, c->stream);
+  FWI_HIP(hipMemcpyAsync(c->h_int, c->d_int, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  if (c->h_int[0]) throw Error(FWI_E_NONFINITE, std::string("non-finite values in ") + what);
+}
+
+template <typename F>
+int guarded(fwi_ctx* c, F&& body) {
+  if (!c) return FWI_E_INVAL;
+  try {
+    FWI_HIP(hipSetDevice(c->device));
+    return body();
+  } catch (const Error& e) {
+    c->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return FWI_E_DEVICE;
+  }
+}
+
+template <typename T>
+size_t plan_bytes(const fwi_problem* p, const fwi_solve_opts& o, int entry) {
+  Arena a;
+  CallBufs cb;
+  SolveBufs<T> sb;
+  plan_call<T>(a, p, o, entry, cb, sb);
+  return a.used;
+}
+
+// Prepare: validate, cache, bind workspace and plan buffers.
+template <typename T>
+void prepare(fwi_ctx* c, Runner& R, SolveBufs<T>& sb, int entry, int B_override = 0) {
+  std::string msg;
+  int rc = validate_problem(R.p, msg);
+  if (rc) throw Error(rc, msg);
+  rc = validate_opts(&R.o, msg);
+  if (rc) throw Error(rc, msg);
+  R.t_setup += ensure_cache(c, R.p);
+  Arena dry;
+  CallBufs cbd;
+  SolveBufs<T> sbd;
+  plan_call<T>(dry, R.p, R.o, entry, cbd, sbd, B_override);
+  Arena a;
+  bind_workspace(c, a, dry.used);
+  plan_call<T>(a, R.p, R.o, entry, R.cb, sb, B_override);
+}
+
+int finish_rc(const SolveTotals& t) { return t.unconverged ? FWI_E_NOCONV : FWI_OK; }
+
+// ----------------------------------------------------------- entries ---
+template <typename T>
+int forward_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* m_in,
+                 const fwi_solve_opts* opts, void* data_out, void* fields_out, fwi_stats* stats) {
+  const double t0 = now_ms();
+  if (!data_out || (!m_in && !cc)) throw Error(FWI_E_INVAL, "NULL array argument");
+  Runner R(c, p, *opts);
+  SolveBufs<T> sb;
+  prepare<T>(c, R, sb, FWI_ENTRY_FORWARD);
+  const double ts = now_ms();
+  if (m_in) {
+    check_complex(c, R.n, (const c128*)m_in, "m");
+    launch_copy_c128(R.n, (const c128*)m_in, R.cb.m64, c->stream);
+    launch_cast_64_32(R.n, R.cb.m64, R.cb.m32, c->stream);
+  } else {
+    check_sos(c, R.n, cc, alpha);
+    launch_contrast(R.n, p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+  }
+  R.t_setup += now_ms() - ts;
+  R.forward<T>(sb, (c128*)data_out, (c128*)fields_out);
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+  return finish_rc(R.tot);
+}
+
+template <typename T>
+int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* m_in,
+                  const void* dobs, const void* upstream, const fwi_solve_opts* opts, double* misfit_out,
+                  void* grad_m_out, double* gc, double* ga, fwi_stats* stats) {
+  const double t0 = now_ms();
+  if ((!m_in && !cc) || (!dobs && !upstream)) throw Error(FWI_E_INVAL, "NULL array argument");
+  Runner R(c, p, *opts);
+  SolveBufs<T> sb;
+  prepare<T>(c, R, sb, FWI_ENTRY_GRADIENT);
+  const double ts = now_ms();
+  if (m_in) {
+    check_complex(c, R.n, (const c128*)m_in, "m");
+    launch_copy_c128(R.n, (const c128*)m_in, R.cb.m64, c->stream);
+    launch_cast_64_32(R.n, R.cb.m64, R.cb.m32, c->stream);
+  } else {
+    check_sos(c, R.n, cc, alpha);
+    launch_contrast(R.n, p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+  }
+  R.t_setup += now_ms() - ts;
+  const double phi = R.gradient<T>(sb, (const c128*)dobs, (const c128*)upstream, R.cb.data, cc, alpha,
+                                   (c128*)grad_m_out, gc, ga);
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  if (misfit_out) *misfit_out = phi;
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+  return finish_rc(R.tot);
+}
+
+// J^H b over all frequency groups from stored fields [nf][ne][n] -> out [n] (times dV)
+void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int nfg, const c128* fields, const c128* b,
+              c128* out) {
+  const ProblemCache& pc = c->pc;
+  const long n = g.n(), ne2 = (long)p->ne * p->ne;
+  const int ngroups = (p->nf + nfg - 1) / nfg;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
+    const c128* Fg = fields + (long)l0 * p->ne * n;
+    launch_gemm_cn(nf, b + l0 * ne2, p->ne, p->ne, Fg, (long)p->ne * n, n, cb.lam, (long)p->ne * n, c->stream);
+    launch_gradient_accum(n, nf, p->ne, Fg, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, c->stream);
+  }
+  launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, nullptr, nullptr, out, nullptr, nullptr, c->stream);
+}
+
+// J a from stored fields -> out [nf][ne][ne]
+void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, const c128* fields, const c128* a,
+             c128* out) {
+  const long n = g.n();
+  launch_gemm_nt(p->nf, fields, (long)p->ne * n, p->ne, a, fields, (long)p->ne * n, p->ne, n, c->pc.coef, cb.gpart,
+                 gemm_splits(n), out, c->stream);
+}
+
+template <typename T>
+int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void* m_io, void* g_io, void* u_io,
+              const void* m_ref, const void* dobs_v, const fwi_solve_opts* opts, fwi_admm_report* rep,
+              fwi_stats* stats) {
+  const double t0 = now_ms();
+  if (!prm || !m_io || !g_io || !u_io || !dobs_v) throw Error(FWI_E_INVAL, "NULL argument");
+  if (!(prm->rho > 0.0) || prm->lambda < 0.0 || prm->gamma < 0.0 || prm->n_cg < 0)
+    throw Error(FWI_E_INVAL, "ADMM parameters: need rho > 0, lambda >= 0, gamma >= 0, n_cg >= 0");
+  Runner R(c, p, *opts);
+  SolveBufs<T> sb;
+  prepare<T>(c, R, sb, FWI_ENTRY_ADMM);
+  hipStream_t st = c->stream;
+  const long n = R.n, ne2 = (long)p->ne * p->ne, ndata = (long)p->nf * ne2;
+  const Geo& g = R.g;
+  CallBufs& cb = R.cb;
+  c128* m = (c128*)m_io;
+  c128* gg = (c128*)g_io;
+  c128* uu = (c128*)u_io;
+  const c128* dobs = (const c128*)dobs_v;
+  const c128* mref = (const c128*)m_ref;
+  const bool use_ref = mref && prm->gamma != 0.0;
+  check_complex(c, n, m, "m");
+  launch_copy_c128(n, m, cb.m64, st);
+  launch_cast_64_32(n, cb.m64, cb.m32, st);
+  // 1. forward solves at m_k, all fields kept for the Jacobian products
+  R.forward<T>(sb, cb.data, cb.fields);
+  // 2. residual d_obs - F and data scale
+  launch_residual(ndata, cb.data, dobs, cb.r, cb.sc + 4, st);   // r = F - d_obs, sc[4] = misfit
+  launch_residual(ndata, dobs, nullptr, cb.Jp, cb.sc + 5, st);  // sc[5] = |d_obs|^2 / 2
+  FWI_HIP(hipMemcpyAsync(c->h_dbl, cb.sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  FWI_HIP(hipStreamSynchronize(st));
+  const double misfit = c->h_dbl[0];
+  double s = prm->data_scale;
+  if (!(s > 0.0)) s = c->h_dbl[1] > 0.0 ? 1.0 / (2.0 * c->h_dbl[1]) : 1.0;
+  const double rho = prm->rho, gam = use_ref ? prm->gamma : 0.0;
+  const double dual = prm->dual_step;
+  // 3. b = -s J^H(F - d) + rho grad^T(g + u - grad m) + gamma (m_ref - m)
+  jh_apply(c, p, g, cb, R.nfg, cb.fields, cb.r, cb.vec);
+  launch_tv_grad(g, m, cb.gm, st);
+  launch_lincomb((long)g.dim * n, 1.0, gg, 1.0, uu, -1.0, cb.gm, cb.tmpd, st);
+  launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_r, st);
+  launch_lincomb(n, 1.0, cb.cg_r, -s, cb.vec, 0.0, nullptr, cb.cg_r, st);
+  if (use_ref) launch_lincomb(n, 1.0, cb.cg_r, gam, mref, -gam, m, cb.cg_r, st);
+  // 4. CG on (s J^H J + rho grad^T grad + gamma I) dm = b from dm = 0
+  launch_fill_zero_c128(n, cb.cg_x, st);
+  launch_copy_c128(n, cb.cg_r, cb.cg_p, st);
+  launch_dot_re(n, cb.cg_r, cb.cg_r, cb.dpart, cb.sc + 0, st);
+  for (int it = 0; it < prm->n_cg; ++it) {
+    j_apply(c, p, g, cb, cb.fields, cb.cg_p, cb.Jp);
+    jh_apply(c, p, g, cb, R.nfg, cb.fields, cb.Jp, cb.vec);
+    launch_tv_grad(g, cb.cg_p, cb.tmpd, st);
+    launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_Ap, st);
+    launch_lincomb(n, 1.0, cb.cg_Ap, s, cb.vec, gam, use_ref ? cb.cg_p : nullptr, cb.cg_Ap, st);
+    launch_dot_re(n, cb.cg_p, cb.cg_Ap, cb.dpart, cb.sc + 1, st);
+    launch_cg_step1(n, cb.sc, cb.cg_x, cb.cg_r, cb.cg_p, cb.cg_Ap, st);
+    launch_dot_re(n, cb.cg_r, cb.cg_r, cb.dpart, cb.sc + 2, st);
+    launch_cg_step2(n, cb.sc, cb.cg_r, cb.cg_p, st);
+    launch_copy_scalar(cb.sc + 2, cb.sc + 0, st);
+  }
+  // 5. m += dm; g = shrink(grad m - u); u += dual (g - grad m)
+  launch_lincomb(n, 1.0, m, 1.0, cb.cg_x, 0.0, nullptr, m, st);
+  launch_tv_grad(g, m, cb.gm, st);
+  const int nb = launch_tv_shrink_dual(g, cb.gm, prm->lambda / rho, dual, gg, uu, cb.dpart, st);
+  launch_sum(nb, cb.dpart, cb.sc + 6, st);
+  launch_dot_re(n, cb.cg_x, cb.cg_x, cb.dpart, cb.sc + 7, st);
+  FWI_HIP(hipMemcpyAsync(c->h_dbl, cb.sc + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  FWI_HIP(hipStreamSynchronize(st));
+  if (rep) {
+    rep->misfit = misfit;
+    rep->tv = c->h_dbl[0];
+    rep->dm_norm = std::sqrt(c->h_dbl[1]);
+  }
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+  return finish_rc(R.tot);
+}
+
+}  // namespace
+
+// ===================================================================== ABI ===
+extern "C" {
+
+void fwi_default_opts(fwi_solve_opts* o) {
+  if (!o) return;
+  o->precision = FWI_FP64;
+  o->rtol = 1e-10;
+  o->max_iter = 2000;
+  o->restart = 32;
+  o->max_refine = 12;
+  o->inner_rtol = 1e-3;
+  o->max_rhs = 0;
+  o->check_every = 1;
+  o->reciprocity_adjoint = 0;
+}
+
+int fwi_padded_length(int n) { return padded_length(n); }
+
+int fwi_validate_problem(const fwi_problem* p) {
+  std::string msg;
+  return validate_problem(p, msg);
+}
+
+int fwi_workspace_size(const fwi_problem* p, const fwi_solve_opts* o, int entry, size_t* bytes) {
+  std::string msg;
+  int rc = validate_problem(p, msg);
+  if (rc) return rc;
+  rc = validate_opts(o, msg);
+  if (rc) return rc;
+  if (!bytes || entry < 0 || entry > 2) return FWI_E_INVAL;
+  *bytes = o->precision == FWI_FP32_REFINE ? plan_bytes<float>(p, *o, entry) : plan_bytes<double>(p, *o, entry);
+  return FWI_OK;
+}
+
+int fwi_create(fwi_ctx** out, int device, void* stream) {
+  if (!out) return FWI_E_INVAL;
+  *out = nullptr;
+  fwi_ctx* c = new (std::nothrow) fwi_ctx();
+  if (!c) return FWI_E_NOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  try {
+    int count = 0;
+    FWI_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw Error(FWI_E_INVAL, "no such HIP device");
+    FWI_HIP(hipSetDevice(device));
+    make_twiddles(c);
+    FWI_HIP(hipHostMalloc((void**)&c->h_int, 64 * sizeof(int), hipHostMallocDefault));
+    FWI_HIP(hipHostMalloc((void**)&c->h_dbl, 64 * sizeof(double), hipHostMallocDefault));
+    FWI_HIP(hipMalloc((void**)&c->d_int, 64 * sizeof(int)));
+  } catch (const Error& e) {
+    fwi_destroy(c);
+    return e.code;
+  }
+  *out = c;
+  return FWI_OK;
+}
+
+void fwi_destroy(fwi_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  c->pc.release();
+  for (void* p : c->tw_allocs) (void)hipFree(p);
+  if (c->ws_int) (void)hipFree(c->ws_int);
+  if (c->h_int) (void)hipHostFree(c->h_int);
+  if (c->h_dbl) (void)hipHostFree(c->h_dbl);
+  if (c->d_int) (void)hipFree(c->d_int);
+  delete c;
+}
+
+const char* fwi_last_error(const fwi_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int fwi_set_stream(fwi_ctx* c, void* stream) {
+  if (!c) return FWI_E_INVAL;
+  c->stream = (hipStream_t)stream;
+  return FWI_OK;
+}
+
+int fwi_set_workspace(fwi_ctx* c, void* ptr, size_t bytes) {
+  if (!c) return FWI_E_INVAL;
+  c->ws_ext = (char*)ptr;
+  c->ws_ext_bytes = ptr ? bytes : 0;
+  return FWI_OK;
+}
+
+int fwi_forward(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const fwi_solve_opts* o,
+                void* data_out, void* fields_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!cc) throw Error(FWI_E_INVAL, "c is NULL");
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? forward_impl<float>(c, p, cc, alpha, nullptr, o, data_out, fields_out, stats)
+               : forward_impl<double>(c, p, cc, alpha, nullptr, o, data_out, fields_out, stats);
+  });
+}
+
+int fwi_forward_m(fwi_ctx* c, const fwi_problem* p, const void* m, const fwi_solve_opts* o, void* data_out,
+                  void* fields_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!m) throw Error(FWI_E_INVAL, "m is NULL");
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE ? forward_impl<float>(c, p, nullptr, nullptr, m, o, data_out, fields_out, stats)
+                                           : forward_impl<double>(c, p, nullptr, nullptr, m, o, data_out, fields_out, stats);
+  });
+}
+
+int fwi_adjoint_gradient(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* dobs,
+                         const fwi_solve_opts* o, double* misfit_out, void* grad_m_out, double* gc, double* ga,
+                         fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!cc || !dobs) throw Error(FWI_E_INVAL, "NULL array argument");
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? gradient_impl<float>(c, p, cc, alpha, nullptr, dobs, nullptr, o, misfit_out, grad_m_out, gc, ga, stats)
+               : gradient_impl<double>(c, p, cc, alpha, nullptr, dobs, nullptr, o, misfit_out, grad_m_out, gc, ga, stats);
+  });
+}
+
+int fwi_vjp(fwi_ctx* c, const fwi_problem* p, const void* m, const void* grad_data, const fwi_solve_opts* o,
+            void* grad_m_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!m || !grad_data || !grad_m_out) throw Error(FWI_E_INVAL, "NULL array argument");
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? gradient_impl<float>(c, p, nullptr, nullptr, m, nullptr, grad_data, o, nullptr, grad_m_out, nullptr,
+                                      nullptr, stats)
+               : gradient_impl<double>(c, p, nullptr, nullptr, m, nullptr, grad_data, o, nullptr, grad_m_out, nullptr,
+                                       nullptr, stats);
+  });
+}
+
+int fwi_tv_admm_step(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void* m_io, void* g_io, void* u_io,
+                     const void* m_ref, const void* dobs, const fwi_solve_opts* o, fwi_admm_report* rep,
+                     fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE ? admm_impl<float>(c, p, prm, m_io, g_io, u_io, m_ref, dobs, o, rep, stats)
+                                           : admm_impl<double>(c, p, prm, m_io, g_io, u_io, m_ref, dobs, o, rep, stats);
+  });
+}
+
+int fwi_apply_operator(fwi_ctx* c, const fwi_problem* p, int precision, const void* m, int B, const int* freq_index,
+                       const void* x, void* y) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!m || !x || !y || !freq_index || B < 1) throw Error(FWI_E_INVAL, "bad operator arguments");
+    for (int b = 0; b < B; ++b)
+      if (freq_index[b] < 0 || freq_index[b] >= p->nf) throw Error(FWI_E_INVAL, "frequency index out of range");
+    ensure_cache(c, p);
+    const Geo g = make_geo(p);
+    const long n = g.n();
+    Arena dry;
+    auto plan = [&](Arena& a, int*& rf, void*& mT, void*& U1, void*& U2) {
+      rf = a.take<int>(B);
+      const size_t es = precision == FWI_FP32_REFINE ? sizeof(c64) : sizeof(c128);
+      mT = a.take<char>(es * n);
+      U1 = a.take<char>(es * B * g.u1());
+      U2 = a.take<char>(es * B * std::max(1L, g.u2()));
+    };
+    int* rf;
+    void *mT, *U1, *U2;
+    plan(dry, rf, mT, U1, U2);
+    Arena a;
+    bind_workspace(c, a, dry.used);
+    plan(a, rf, mT, U1, U2);
+    hipStream_t st = c->stream;
+    FWI_HIP(hipMemcpyAsync(rf, freq_index, sizeof(int) * B, hipMemcpyHostToDevice, st));
+    if (precision == FWI_FP32_REFINE) {
+      launch_cast_64_32(n, (const c128*)m, (c64*)mT, st);
+      launch_vie<float>(g, c->tw, B, (const c64*)x, nullptr, nullptr, (const c64*)mT, c->pc.ghat32, rf, (c64*)U1,
+                        (c64*)U2, (c64*)y, nullptr, EPI_VIE, st);
+    } else {
+      launch_vie<double>(g, c->tw, B, (const c128*)x, nullptr, nullptr, (const c128*)m, c->pc.ghat64, rf, (c128*)U1,
+                         (c128*)U2, (c128*)y, nullptr, EPI_VIE, st);
+    }
+    FWI_HIP(hipStreamSynchronize(st));
+    return FWI_OK;
+  });
+}
+
+int fwi_solve(fwi_ctx* c, const fwi_problem* p, const void* m, int B, const int* freq_index, const void* rhs,
+              const fwi_solve_opts* o, void* x_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    const double t0 = now_ms();
+    if (!m || !rhs || !x_out || !freq_index || B < 1 || !o) throw Error(FWI_E_INVAL, "bad solve arguments");
+    for (int b = 0; b < B; ++b)
+      if (freq_index[b] < 0 || freq_index[b] >= p->nf) throw Error(FWI_E_INVAL, "frequency index out of range");
+    Runner R(c, p, *o);
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      SolveBufs<T> sb;
+      prepare<T>(c, R, sb, FWI_ENTRY_FORWARD, B);
+      hipStream_t st = c->stream;
+      check_complex(c, R.n, (const c128*)m, "m");
+      launch_copy_c128(R.n, (const c128*)m, R.cb.m64, st);
+      launch_cast_64_32(R.n, R.cb.m64, R.cb.m32, st);
+      FWI_HIP(hipMemcpyAsync(R.cb.rfreq, freq_index, sizeof(int) * B, hipMemcpyHostToDevice, st));
+      const cplx<T>* mT = std::is_same<T, float>::value ? (const cplx<T>*)R.cb.m32 : (const cplx<T>*)R.cb.m64;
+      const cplx<T>* gT =
+          std::is_same<T, float>::value ? (const cplx<T>*)c->pc.ghat32 : (const cplx<T>*)c->pc.ghat64;
+      SolveTotals r = run_solve<T>(c, R.g, R.cb.m64, mT, c->pc.ghat64, gT, B, (const c128*)rhs, R.cb.rfreq,
+                                   (c128*)x_out, R.o, sb);
+      R.tot.merge(r);
+    };
+    if (o->precision == FWI_FP32_REFINE) run(float{});
+    else run(double{});
+    fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+    return finish_rc(R.tot);
+  });
+}
+
+int fwi_incident(fwi_ctx* c, const fwi_problem* p, int l, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!out || l < 0 || l >= p->nf) throw Error(FWI_E_INVAL, "bad arguments");
+    ensure_cache(c, p);
+    const long cnt = c->pc.g.n() * p->ne;
+    launch_copy_c128(cnt, c->pc.P0 + (long)l * cnt, (c128*)out, c->stream);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+int fwi_green_spectrum(fwi_ctx* c, const fwi_problem* p, int l, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!out || l < 0 || l >= p->nf) throw Error(FWI_E_INVAL, "bad arguments");
+    ensure_cache(c, p);
+    const long np = c->pc.g.npad();
+    launch_copy_c128(np, c->pc.ghat64 + (long)l * np, (c128*)out, c->stream);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+int fwi_fft_padded(fwi_ctx* c, const fwi_problem* p, int precision, const void* in, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!in || !out) throw Error(FWI_E_INVAL, "bad arguments");
+    const Geo g = make_geo(p);
+    const size_t es = precision == FWI_FP32_REFINE ? sizeof(c64) : sizeof(c128);
+    Arena dry;
+    dry.take<char>(es * g.u1());
+    Arena a;
+    bind_workspace(c, a, dry.used);
+    void* U1 = a.take<char>(es * g.u1());
+    if (precision == FWI_FP32_REFINE)
+      launch_fft_padded<float>(g, c->tw, (const c64*)in, (c64*)U1, (c64*)out, c->stream);
+    else
+      launch_fft_padded<double>(g, c->tw, (const c128*)in, (c128*)U1, (c128*)out, c->stream);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+int fwi_jacobian_apply(fwi_ctx* c, const fwi_problem* p, const void* fields, const void* a, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!fields || !a || !out) throw Error(FWI_E_INVAL, "bad arguments");
+    ensure_cache(c, p);
+    const Geo g = make_geo(p);
+    const long n = g.n();
+    Arena dry;
+    dry.take<c128>((size_t)gemm_splits(n) * p->nf * p->ne * p->ne);
+    Arena ar;
+    bind_workspace(c, ar, dry.used);
+    CallBufs cb;
+    cb.gpart = ar.take<c128>((size_t)gemm_splits(n) * p->nf * p->ne * p->ne);
+    j_apply(c, p, g, cb, (const c128*)fields, (const c128*)a, (c128*)out);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+int fwi_jacobian_adjoint_apply(fwi_ctx* c, const fwi_problem* p, const void* fields, const void* b, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (!fields || !b || !out) throw Error(FWI_E_INVAL, "bad arguments");
+    ensure_cache(c, p);
+    const Geo g = make_geo(p);
+    const long n = g.n();
+    auto plan = [&](Arena& a, CallBufs& cb) {
+      cb.lam = a.take<c128>((size_t)p->nf * p->ne * n);
+      cb.gpart = a.take<c128>((size_t)kGradSeg * n);
+      cb.gacc = a.take<c128>(n);
+    };
+    Arena dry;
+    CallBufs d;
+    plan(dry, d);
+    Arena ar;
+    bind_workspace(c, ar, dry.used);
+    CallBufs cb;
+    plan(ar, cb);
+    jh_apply(c, p, g, cb, p->nf, (const c128*)fields, (const c128*)b, (c128*)out);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+}  // extern "C"

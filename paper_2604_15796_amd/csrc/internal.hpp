@@ -1,0 +1,97 @@
+// Internal host-side interfaces between the C-ABI, the solver driver and the
+// kernel launchers. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "common.hpp"
+
+namespace fwi {
+
+// Error carrying a public FWI_E_* code.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define FWI_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::fwi::Error(-5, std::string("HIP error: ") + hipGetErrorString(e_) + " at " + \
+                                 __FILE__ + ":" + std::to_string(__LINE__));             \
+  } while (0)
+
+#define FWI_LAUNCH_CHECK() FWI_HIP(hipGetLastError())
+
+// Supported FFT lengths (padded axis sizes): 2^a 3^b from 32 to 1024.
+constexpr int kNumLengths = 11;
+constexpr int kLengths[kNumLengths] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+int length_index(int L);          // -1 if unsupported
+int padded_length(int n);         // smallest supported L >= 2n, 0 if none
+
+// Twiddle tables tw[m] = exp(-2 pi i m / L) for every supported L.
+struct Twiddles {
+  const c128* d64[kNumLengths] = {};
+  const c64* d32[kNumLengths] = {};
+  template <typename T>
+  const cplx<T>* get(int L) const;
+};
+
+template <>
+const c128* Twiddles::get<double>(int L) const;
+template <>
+const c64* Twiddles::get<float>(int L) const;
+
+// Grid geometry of one problem: cells and padded FFT extents.
+struct Geo {
+  int dim = 2, nx = 0, ny = 1, nz = 0;
+  int Lx = 0, Ly = 1, Lz = 0;
+  double dx = 0, c0 = 0;
+  long n() const { return (long)nx * ny * nz; }
+  long npad() const { return (long)Lx * Ly * Lz; }
+  // per-RHS intermediate sizes (elements): after the x pass / after the y pass
+  long u1() const { return (long)nz * ny * Lx; }
+  long u2() const { return dim == 3 ? (long)nz * Ly * Lx : 0; }
+};
+
+enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2 };
+
+// y = A x for B right-hand sides (Eq. 5 discretised):
+//   EPI_VIE  : y_b = s_b x_b - conv(m * s_b x_b)
+//   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored)
+// x, y, rhs: [B][n]; scale: [B] or null; active: [B] or null (inactive RHS are
+// skipped and their y left untouched); ghat: [nf][npad] spectra with k^2 and
+// 1/npad folded in; rhs_freq: [B] frequency index per RHS; U1 [B][u1],
+// U2 [B][u2] (3D) scratch.
+template <typename T>
+void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
+                const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
+                const cplx<T>* rhs, int epi, hipStream_t st);
+
+// Forward FFT of a full padded grid [Lz][Ly][Lx] (no padding, no crop), in place
+// through `work` of the same size: out = FFT(in). Used for the Green spectrum.
+void launch_fft_full(const Geo& g, const Twiddles& tw, const c128* in, c128* work, c128* out, hipStream_t st);
+
+// Zero-padded forward FFT of [nz][ny][nx] data into [Lz][Ly][Lx] (diagnostics).
+template <typename T>
+void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx<T>* U1, cplx<T>* out,
+                       hipStream_t st);
+
+// ---------------------------------------------------------- setup kernels ---
+void launch_contrast(long n, double c0, const double* c, const double* alpha, c128* m64, c64* m32, hipStream_t st);
+void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st);
+void launch_incident(const Geo& g, double k, int ne, const double* elem_xyz_dev, c128* P0, hipStream_t st);
+void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st);
+void launch_scale_c128(long count, double s, c128* x, hipStream_t st);
+
+}  // namespace fwi
+
+namespace fwi {
+void launch_check_sos(long n, const double* c, const double* alpha, int* out, hipStream_t st);
+void launch_check_complex(long n, const c128* x, int* out, hipStream_t st);
+}  // namespace fwi

@@ -1,0 +1,423 @@
+// Data-space and model-space kernels of the gradient and ADMM path:
+//  * receiver sampling / forward Jacobian product (Eq. 4, Eq. 16):
+//      C[l][i][j] = coef_l sum_n A[l][i][n] w[n] Bm[l][j][n]
+//  * residual and misfit (data term of Eq. 7)
+//  * adjoint sources / adjoint-field contraction (Eq. 17):
+//      S[l][i][n] = sum_j conj(M[l][i][j]) P[l][j][n]
+//  * gradient reduction g_n = dV sum_l conj(k_l^2) sum_i conj(p_li[n] lam_li[n])
+//    and the chain rule to c and alpha
+//  * TV operators, shrinkage and dual update (Eq. 13-14), CG vector updates.
+// All accumulations are FP64 with fixed-order two-stage reductions.
+#include "data.hpp"
+
+namespace fwi {
+
+constexpr double PI = 3.14159265358979323846;
+
+// ------------------------------------------------------------- gemm (NT) ---
+constexpr int GT = 32;  // output tile
+constexpr int GK = 32;  // k step
+
+// part[ks][l][i][j] = sum over the split's k range of A[l][i][k] w[k] Bm[l][j][k]
+__global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, long a_ls, int ni,
+                                                 const c128* __restrict__ w, const c128* __restrict__ Bm, long b_ls,
+                                                 int nj, long n, long kchunk, c128* __restrict__ part, int nf) {
+  __shared__ c128 sa[GT][GK + 1];
+  __shared__ c128 sb[GT][GK + 1];
+  const int ks = blockIdx.x;
+  const int tj_n = (nj + GT - 1) / GT;
+  const int ti = blockIdx.y / tj_n, tj = blockIdx.y % tj_n;
+  const int l = blockIdx.z;
+  const int t = threadIdx.x;
+  const int ty = t / 16, tx = t % 16;
+  const c128* Al = A + l * a_ls;
+  const c128* Bl = Bm + l * b_ls;
+  c128 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = mk(0.0, 0.0);
+  const long k0 = ks * kchunk;
+  const long k1 = min(n, k0 + kchunk);
+  for (long kb = k0; kb < k1; kb += GK) {
+    // load 32x32 tiles of A (rows ti*32..) and Bm (rows tj*32..), k in [kb, kb+32)
+    for (int e = t; e < GT * GK; e += 256) {
+      const int r = e / GK, c = e % GK;
+      const long k = kb + c;
+      const int ia = ti * GT + r, jb = tj * GT + r;
+      c128 va = mk(0.0, 0.0), vb = mk(0.0, 0.0);
+      if (k < k1) {
+        if (ia < ni) {
+          va = Al[(long)ia * n + k];
+          if (w) va = va * w[k];
+        }
+        if (jb < nj) vb = Bl[(long)jb * n + k];
+      }
+      sa[r][c] = va;
+      sb[r][c] = vb;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < GK; ++c) {
+      const c128 a0 = sa[ty][c], a1 = sa[ty + 16][c];
+      const c128 b0 = sb[tx][c], b1 = sb[tx + 16][c];
+      acc[0][0] = acc[0][0] + a0 * b0;
+      acc[0][1] = acc[0][1] + a0 * b1;
+      acc[1][0] = acc[1][0] + a1 * b0;
+      acc[1][1] = acc[1][1] + a1 * b1;
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int i = ti * GT + ty + 16 * a, j = tj * GT + tx + 16 * b;
+      if (i < ni && j < nj) part[(((long)ks * nf + l) * ni + i) * nj + j] = acc[a][b];
+    }
+}
+
+__global__ void k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, int ni, int nj,
+                                const c128* __restrict__ coef, c128* __restrict__ C) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long tot = (long)nf * ni * nj;
+  if (idx >= tot) return;
+  const int l = (int)(idx / ((long)ni * nj));
+  c128 s = mk(0.0, 0.0);
+  for (int k = 0; k < nks; ++k) s = s + part[(long)k * tot + idx];
+  C[idx] = coef[l] * s;
+}
+
+// ------------------------------------------------------------- gemm (NN) ---
+constexpr int NI = 16;  // rows of M per block
+
+// S[l][i][n] = sum_j conj(M[l][i][j]) P[l][j][n]   (i in a 16-row tile, one n per thread)
+__global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int ni, int nj,
+                                                 const c128* __restrict__ P, long p_ls, long n,
+                                                 c128* __restrict__ S, long s_ls) {
+  extern __shared__ c128 sm[];  // [NI][nj]
+  const int l = blockIdx.z;
+  const int i0 = blockIdx.y * NI;
+  for (int e = threadIdx.x; e < NI * nj; e += 256) {
+    const int r = e / nj, c = e % nj;
+    sm[e] = (i0 + r < ni) ? conj(M[((long)l * ni + i0 + r) * nj + c]) : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  c128 acc[NI];
+#pragma unroll
+  for (int r = 0; r < NI; ++r) acc[r] = mk(0.0, 0.0);
+  const c128* Pl = P + l * p_ls;
+  for (int j = 0; j < nj; ++j) {
+    const c128 p = Pl[(long)j * n + e];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) acc[r] = acc[r] + sm[r * nj + j] * p;
+  }
+#pragma unroll
+  for (int r = 0; r < NI; ++r)
+    if (i0 + r < ni) S[l * s_ls + (long)(i0 + r) * n + e] = acc[r];
+}
+
+// ------------------------------------------------------------- residual ---
+__global__ void __launch_bounds__(1024) k_residual(long count, const c128* __restrict__ data,
+                                                   const c128* __restrict__ dobs, c128* __restrict__ r,
+                                                   double* __restrict__ misfit) {
+  __shared__ double red[16];
+  double acc = 0.0;
+  for (long i = threadIdx.x; i < count; i += 1024) {
+    const c128 v = dobs ? data[i] - dobs[i] : data[i];
+    r[i] = v;
+    acc += norm2(v);
+  }
+  const double s = block_sum<1024>(acc, red);
+  if (threadIdx.x == 0) misfit[0] = 0.5 * s;
+}
+
+// ------------------------------------------------------------- gradient ---
+// part[seg][n] = sum over the segment's (l, i) of conj(k_l^2) conj(p_li[n] lam_li[n])
+__global__ void __launch_bounds__(256) k_grad_partial(const c128* __restrict__ p, const c128* __restrict__ lam,
+                                                      long n, int nf, int ni, const c128* __restrict__ k2,
+                                                      int nseg, c128* __restrict__ part) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int seg = blockIdx.y;
+  const long tot = (long)nf * ni;
+  const long s0 = tot * seg / nseg, s1 = tot * (seg + 1) / nseg;
+  c128 acc = mk(0.0, 0.0);
+  for (long li = s0; li < s1; ++li) {
+    const int l = (int)(li / ni);
+    const c128 a = p[li * n + e], b = lam[li * n + e];
+    const c128 prod = a * b;
+    acc = acc + conj(k2[l]) * conj(prod);
+  }
+  part[(long)seg * n + e] = acc;
+}
+
+// acc (+)= sum_seg part  (fixed order)
+__global__ void k_grad_accum(const c128* __restrict__ part, int nseg, long n, int first, c128* __restrict__ acc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  c128 s = first ? mk(0.0, 0.0) : acc[e];
+  for (int k = 0; k < nseg; ++k) s = s + part[(long)k * n + e];
+  acc[e] = s;
+}
+
+// g = dV acc; optional chain rule d phi/dc = Re(conj(g) dm/dc), d phi/dalpha = Re(conj(g) dm/dalpha)
+__global__ void k_grad_chain(const c128* __restrict__ acc, long n, double dV, double c0,
+                             const double* __restrict__ c, const double* __restrict__ alpha,
+                             c128* __restrict__ g, double* __restrict__ gc, double* __restrict__ ga) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const c128 s = dV * acc[e];
+  if (g) g[e] = s;
+  if (gc || ga) {
+    const double cc = c[e], a = alpha ? alpha[e] : 0.0;
+    // dm/dc = c0^2 (-2/c^3 - i alpha/(pi c^2)), dm/dalpha = c0^2 (-2 alpha/(2 pi)^2 + i/(pi c))
+    const c128 dmc = mk(c0 * c0 * (-2.0 / (cc * cc * cc)), -c0 * c0 * a / (PI * cc * cc));
+    const c128 dma = mk(-c0 * c0 * 2.0 * a / (4.0 * PI * PI), c0 * c0 / (PI * cc));
+    if (gc) gc[e] = s.x * dmc.x + s.y * dmc.y;
+    if (ga) ga[e] = s.x * dma.x + s.y * dma.y;
+  }
+}
+
+// ------------------------------------------------------------------- TV ---
+struct TvGeo {
+  int dim, nx, ny, nz;
+};
+__device__ __forceinline__ void tv_coords(const TvGeo& g, long i, int& ix, int& iy, int& iz) {
+  ix = (int)(i % g.nx);
+  iy = (int)((i / g.nx) % g.ny);
+  iz = (int)(i / ((long)g.nx * g.ny));
+}
+// component q: 0 = x, 1 = y (3D) or z (2D), 2 = z (3D)
+__device__ __forceinline__ void tv_axis(const TvGeo& g, int q, long& step, int& N, int ix, int iy, int iz, int& pos) {
+  if (q == 0) {
+    step = 1;
+    N = g.nx;
+    pos = ix;
+  } else if (g.dim == 3 && q == 1) {
+    step = g.nx;
+    N = g.ny;
+    pos = iy;
+  } else {
+    step = (long)g.nx * g.ny;
+    N = g.nz;
+    pos = iz;
+  }
+}
+
+// out[q][i] = m[i + e_q] - m[i] (0 at the last index)
+__global__ void k_tv_grad(TvGeo g, const c128* __restrict__ m, c128* __restrict__ out) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int ix, iy, iz;
+  tv_coords(g, i, ix, iy, iz);
+  for (int q = 0; q < g.dim; ++q) {
+    long st;
+    int N, pos;
+    tv_axis(g, q, st, N, ix, iy, iz, pos);
+    out[(long)q * n + i] = pos < N - 1 ? m[i + st] - m[i] : mk(0.0, 0.0);
+  }
+}
+
+// out[i] = sum_q (a_q[i - e_q] [pos >= 1] - a_q[i] [pos <= N-2]);  out = beta*out + alpha*that
+__global__ void k_tv_gradT(TvGeo g, const c128* __restrict__ a, double alpha, double beta, c128* __restrict__ out) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int ix, iy, iz;
+  tv_coords(g, i, ix, iy, iz);
+  c128 s = mk(0.0, 0.0);
+  for (int q = 0; q < g.dim; ++q) {
+    long st;
+    int N, pos;
+    tv_axis(g, q, st, N, ix, iy, iz, pos);
+    if (pos >= 1) s = s + a[(long)q * n + i - st];
+    if (pos <= N - 2) s = s - a[(long)q * n + i];
+  }
+  const c128 o = beta == 0.0 ? mk(0.0, 0.0) : beta * out[i];
+  out[i] = o + alpha * s;
+}
+
+// g = shrink_tau(grad m - u); u += dual (g - grad m); tvp[block] = sum_n |grad m|_2
+__global__ void __launch_bounds__(256) k_tv_shrink_dual(TvGeo gg, const c128* __restrict__ gm, double tau,
+                                                        double dual, c128* __restrict__ g, c128* __restrict__ u,
+                                                        double* __restrict__ tvp) {
+  __shared__ double red[4];
+  const long n = (long)gg.nx * gg.ny * gg.nz;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  double tvl = 0.0;
+  if (i < n) {
+    c128 a[3];
+    double nr = 0.0, ng = 0.0;
+    for (int q = 0; q < gg.dim; ++q) {
+      const c128 d = gm[(long)q * n + i];
+      a[q] = d - u[(long)q * n + i];
+      nr += norm2(a[q]);
+      ng += norm2(d);
+    }
+    nr = sqrt(nr);
+    tvl = sqrt(ng);
+    const double fac = nr > 0.0 ? fmax(1.0 - tau / nr, 0.0) : 0.0;
+    for (int q = 0; q < gg.dim; ++q) {
+      const c128 gn = fac * a[q];
+      g[(long)q * n + i] = gn;
+      u[(long)q * n + i] = u[(long)q * n + i] + dual * (gn - gm[(long)q * n + i]);
+    }
+  }
+  const double s = block_sum<256>(tvl, red);
+  if (threadIdx.x == 0) tvp[blockIdx.x] = s;
+}
+
+// ------------------------------------------------------------- vectors ---
+// out = a*x + b*y (+ c*z), real coefficients; x, y, z may alias out
+__global__ void k_lincomb(long n, double a, const c128* x, double b, const c128* y, double c, const c128* z,
+                          c128* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  c128 v = a * x[i];
+  if (y) v = v + b * y[i];
+  if (z) v = v + c * z[i];
+  out[i] = v;
+}
+
+// partial sums of Re <x, y> (x == y gives |x|^2)
+__global__ void __launch_bounds__(256) k_dot_re_partial(long n, const c128* __restrict__ x, const c128* __restrict__ y,
+                                                        double* __restrict__ part) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const c128 a = x[i], b = y[i];
+    acc += a.x * b.x + a.y * b.y;
+  }
+  const double s = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ void k_sum_partial(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[k];
+    out[0] = s;
+  }
+}
+
+// CG scalars on device: sc[0] = rs, sc[1] = pAp, sc[2] = rs_new
+// x += (rs/pAp) p ; r -= (rs/pAp) Ap
+__global__ void k_cg_step1(long n, const double* __restrict__ sc, c128* __restrict__ x, c128* __restrict__ r,
+                           const c128* __restrict__ p, const c128* __restrict__ Ap) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double rs = sc[0], pap = sc[1];
+  const double al = (rs > 0.0 && pap != 0.0) ? rs / pap : 0.0;
+  x[i] = x[i] + al * p[i];
+  r[i] = r[i] - al * Ap[i];
+}
+// p = r + (rs_new/rs) p
+__global__ void k_cg_step2(long n, const double* __restrict__ sc, const c128* __restrict__ r, c128* __restrict__ p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double rs = sc[0], rsn = sc[2];
+  const double be = rs > 0.0 ? rsn / rs : 0.0;
+  p[i] = r[i] + be * p[i];
+}
+__global__ void k_copy_scalar(const double* __restrict__ in, double* __restrict__ out) {
+  if (threadIdx.x == 0) out[0] = in[0];
+}
+
+// ------------------------------------------------------------- launchers ---
+void launch_gemm_nt(int nf, const c128* A, long a_ls, int ni, const c128* w, const c128* Bm, long b_ls, int nj, long n,
+                    const c128* coef, c128* part, int nks, c128* C, hipStream_t st) {
+  long kchunk = (n + nks - 1) / nks;
+  kchunk = (kchunk + GK - 1) / GK * GK;
+  const int tiles = ((ni + GT - 1) / GT) * ((nj + GT - 1) / GT);
+  hipLaunchKernelGGL(k_gemm_nt, dim3(nks, tiles, nf), dim3(256), 0, st, A, a_ls, ni, w, Bm, b_ls, nj, n, kchunk, part,
+                     nf);
+  FWI_LAUNCH_CHECK();
+  const long tot = (long)nf * ni * nj;
+  hipLaunchKernelGGL(k_gemm_nt_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nks, nf, ni, nj,
+                     coef, C);
+  FWI_LAUNCH_CHECK();
+}
+
+void launch_gemm_cn(int nf, const c128* M, int ni, int nj, const c128* P, long p_ls, long n, c128* S, long s_ls,
+                    hipStream_t st) {
+  const size_t lds = sizeof(c128) * NI * nj;
+  if (lds > 64 * 1024) throw Error(-6, "too many elements for the adjoint-source kernel");
+  hipLaunchKernelGGL(k_gemm_cn, dim3((unsigned)((n + 255) / 256), (ni + NI - 1) / NI, nf), dim3(256), lds, st, M, ni,
+                     nj, P, p_ls, n, S, s_ls);
+  FWI_LAUNCH_CHECK();
+}
+
+void launch_residual(long count, const c128* data, const c128* dobs, c128* r, double* misfit, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, st, count, data, dobs, r, misfit);
+  FWI_LAUNCH_CHECK();
+}
+
+void launch_gradient_accum(long n, int nf, int ni, const c128* p, const c128* lam, const c128* k2, c128* part,
+                           int nseg, int first, c128* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_partial, dim3((unsigned)((n + 255) / 256), nseg), dim3(256), 0, st, p, lam, n, nf, ni, k2,
+                     nseg, part);
+  FWI_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_grad_accum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, nseg, n, first, acc);
+  FWI_LAUNCH_CHECK();
+}
+
+void launch_grad_chain(long n, const c128* acc, double dV, double c0, const double* c, const double* alpha, c128* g,
+                       double* gc, double* ga, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_chain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, n, dV, c0, c, alpha, g,
+                     gc, ga);
+  FWI_LAUNCH_CHECK();
+}
+
+static TvGeo tvgeo(const Geo& g) { return TvGeo{g.dim, g.nx, g.ny, g.nz}; }
+
+void launch_tv_grad(const Geo& g, const c128* m, c128* out, hipStream_t st) {
+  const long n = g.n();
+  hipLaunchKernelGGL(k_tv_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tvgeo(g), m, out);
+  FWI_LAUNCH_CHECK();
+}
+void launch_tv_gradT(const Geo& g, const c128* a, double alpha, double beta, c128* out, hipStream_t st) {
+  const long n = g.n();
+  hipLaunchKernelGGL(k_tv_gradT, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tvgeo(g), a, alpha, beta, out);
+  FWI_LAUNCH_CHECK();
+}
+int launch_tv_shrink_dual(const Geo& g, const c128* gm, double tau, double dual, c128* gout, c128* u, double* tvp,
+                          hipStream_t st) {
+  const long n = g.n();
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_tv_shrink_dual, dim3(nb), dim3(256), 0, st, tvgeo(g), gm, tau, dual, gout, u, tvp);
+  FWI_LAUNCH_CHECK();
+  return (int)nb;
+}
+void launch_lincomb(long n, double a, const c128* x, double b, const c128* y, double c, const c128* z, c128* out,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, a, x, b, y, c, z, out);
+  FWI_LAUNCH_CHECK();
+}
+int dot_blocks(long n) {
+  long b = (n + 255) / 256;
+  return (int)(b > 512 ? 512 : (b < 1 ? 1 : b));
+}
+void launch_dot_re(long n, const c128* x, const c128* y, double* part, double* out, hipStream_t st) {
+  const int nb = dot_blocks(n);
+  hipLaunchKernelGGL(k_dot_re_partial, dim3(nb), dim3(256), 0, st, n, x, y, part);
+  FWI_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(64), 0, st, nb, part, out);
+  FWI_LAUNCH_CHECK();
+}
+void launch_sum(int nb, const double* part, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partial, dim3(1), dim3(64), 0, st, nb, part, out);
+  FWI_LAUNCH_CHECK();
+}
+void launch_cg_step1(long n, const double* sc, c128* x, c128* r, const c128* p, const c128* Ap, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_step1, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, x, r, p, Ap);
+  FWI_LAUNCH_CHECK();
+}
+void launch_cg_step2(long n, const double* sc, const c128* r, c128* p, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_step2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, sc, r, p);
+  FWI_LAUNCH_CHECK();
+}
+void launch_copy_scalar(const double* in, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(64), 0, st, in, out);
+  FWI_LAUNCH_CHECK();
+}
+
+}  // namespace fwi

@@ -1,0 +1,416 @@
+// Batched GMRES kernels: classical Gram-Schmidt Arnoldi with FP64 inner
+// products (two-stage, fixed-order reductions, no floating-point atomics),
+// device-side complex Givens rotations and per-RHS convergence masks.
+#include "krylov.hpp"
+
+namespace fwi {
+
+constexpr int KT = 256;  // threads per block of the vector kernels
+
+int krylov_nblk(long n) {
+  long nb = (n + 4095) / 4096;
+  return (int)(nb < 1 ? 1 : nb);
+}
+
+// ------------------------------------------------------------------ dots ---
+// dotp[b][blk][i] = sum over the block's chunk of conj(V_i) . V_{j+1}, i <= j
+template <typename T, int JM>
+__global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
+                                             const int* __restrict__ active, c128* __restrict__ dotp, int nblk) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const long off = (long)b * n;
+  const cplx<T>* W = V + (long)(j + 1) * vs + off;
+  double ar[JM + 1], ai[JM + 1];
+#pragma unroll
+  for (int i = 0; i <= JM; ++i) ar[i] = ai[i] = 0.0;
+  const long e0 = (long)blockIdx.x * chunk;
+  const long e1 = min(n, e0 + chunk);
+  for (long e = e0 + threadIdx.x; e < e1; e += KT) {
+    const cplx<T> w = W[e];
+    const double wx = w.x, wy = w.y;
+#pragma unroll
+    for (int i = 0; i <= JM; ++i) {
+      if (i <= j) {
+        const cplx<T> v = V[(long)i * vs + off + e];
+        const double vx = v.x, vy = v.y;
+        ar[i] += vx * wx + vy * wy;
+        ai[i] += vx * wy - vy * wx;
+      }
+    }
+  }
+  __shared__ double red[2][JM + 1][KT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i <= JM; ++i) {
+    if (i <= j) {
+      const double r = wave_sum(ar[i]), m = wave_sum(ai[i]);
+      if (lane == 0) {
+        red[0][i][wv] = r;
+        red[1][i][wv] = m;
+      }
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t <= j) {
+    double r = 0.0, m = 0.0;
+#pragma unroll
+    for (int w = 0; w < KT / 64; ++w) {
+      r += red[0][t][w];
+      m += red[1][t][w];
+    }
+    dotp[((long)b * nblk + blockIdx.x) * (JM + 1) + t] = mk(r, m);
+  }
+}
+
+// V_{j+1} -= sum_i h_i V_i with h_i reduced from dotp (same order in every block);
+// nrmp[b][blk] = |V_{j+1}|^2 over the chunk; block 0 stores the H column.
+template <typename T, int JM>
+__global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
+                                             const int* __restrict__ active, const c128* __restrict__ dotp, int nblk,
+                                             c128* __restrict__ H, double* __restrict__ nrmp) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  __shared__ double hr[JM + 1], hi[JM + 1];
+  __shared__ double red[KT / 64];
+  const int t = threadIdx.x;
+  if (t <= j) {
+    double r = 0.0, m = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+      const c128 d = dotp[((long)b * nblk + k) * (JM + 1) + t];
+      r += d.x;
+      m += d.y;
+    }
+    hr[t] = r;
+    hi[t] = m;
+    if (blockIdx.x == 0) H[((long)b * (JM + 1) + t) * JM + j] = mk(r, m);
+  }
+  __syncthreads();
+  const long off = (long)b * n;
+  cplx<T>* W = V + (long)(j + 1) * vs + off;
+  const long e0 = (long)blockIdx.x * chunk;
+  const long e1 = min(n, e0 + chunk);
+  double acc = 0.0;
+  for (long e = e0 + t; e < e1; e += KT) {
+    const cplx<T> w = W[e];
+    double wx = w.x, wy = w.y;
+#pragma unroll
+    for (int i = 0; i <= JM; ++i) {
+      if (i <= j) {
+        const cplx<T> v = V[(long)i * vs + off + e];
+        const double vx = v.x, vy = v.y;
+        wx -= hr[i] * vx - hi[i] * vy;
+        wy -= hr[i] * vy + hi[i] * vx;
+      }
+    }
+    const cplx<T> o = mk((T)wx, (T)wy);
+    W[e] = o;
+    acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+  }
+  const double s = block_sum<KT>(acc, red);
+  if (t == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
+}
+
+// One thread per RHS: finish column j (norm, previous rotations, new rotation),
+// update the residual estimate and the convergence mask; count active RHS.
+template <typename T, int JM>
+__global__ void __launch_bounds__(1024) k_givens(int j, int B, int nblk, int* __restrict__ active,
+                                                 const double* __restrict__ nrmp, c128* __restrict__ H,
+                                                 double* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ gv,
+                                                 const double* __restrict__ target, int* __restrict__ ncol,
+                                                 int* __restrict__ iters, cplx<T>* __restrict__ scal,
+                                                 int* __restrict__ counters) {
+  __shared__ double red[1024 / 64];
+  double cnt = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    if (!active[b]) continue;
+    double s2 = 0.0;
+    for (int k = 0; k < nblk; ++k) s2 += nrmp[(long)b * nblk + k];
+    const double hn = sqrt(s2);
+    c128* col = H + (long)b * (JM + 1) * JM + j;  // col[i*JM] = H[i][j]
+    for (int i = 0; i < j; ++i) {
+      const c128 a = col[i * JM], c2 = col[(i + 1) * JM];
+      const double c = cs[b * JM + i];
+      const c128 s = sn[b * JM + i];
+      col[i * JM] = c * a + s * c2;
+      col[(i + 1) * JM] = c * c2 - conj(s) * a;
+    }
+    const c128 a = col[j * JM];
+    const double aa = sqrt(norm2(a));
+    const double nu = sqrt(aa * aa + hn * hn);
+    double c;
+    c128 s;
+    if (aa == 0.0) {
+      c = 0.0;
+      s = mk(1.0, 0.0);
+    } else {
+      c = aa / nu;
+      s = (hn / (nu * aa)) * a;
+    }
+    cs[b * JM + j] = c;
+    sn[b * JM + j] = s;
+    col[j * JM] = c * a + hn * s;
+    col[(j + 1) * JM] = mk(0.0, 0.0);
+    const c128 g = gv[b * (JM + 1) + j];
+    gv[b * (JM + 1) + j] = c * g;
+    const c128 g1 = (-1.0) * (conj(s) * g);
+    gv[b * (JM + 1) + j + 1] = g1;
+    ncol[b] = j + 1;
+    iters[b] += 1;
+    const double res = sqrt(norm2(g1));
+    if (res <= target[b] || !(hn > 1e-300) || nu == 0.0) {
+      active[b] = 0;
+    } else {
+      scal[b] = mk((T)(1.0 / hn), (T)0);
+      cnt += 1.0;
+    }
+  }
+  const double tot = block_sum<1024>(cnt, red);
+  if (threadIdx.x == 0) counters[0] = (int)tot;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(KT) k_scale_basis(cplx<T>* __restrict__ W, long n, const int* __restrict__ active,
+                                                    const cplx<T>* __restrict__ scal) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const T s = scal[b].x;
+  cplx<T>* w = W + (long)b * n;
+  for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
+    const cplx<T> v = w[e];
+    w[e] = mk(v.x * s, v.y * s);
+  }
+}
+
+// |x_b|^2 partial sums of an FP64 array [B][n]
+__global__ void __launch_bounds__(KT) k_norm_partial(const c128* __restrict__ x, long n, int chunk,
+                                                     double* __restrict__ nrmp, int nblk) {
+  __shared__ double red[KT / 64];
+  const int b = blockIdx.y;
+  const long e0 = (long)blockIdx.x * chunk;
+  const long e1 = min(n, e0 + chunk);
+  const c128* xb = x + (long)b * n;
+  double acc = 0.0;
+  for (long e = e0 + threadIdx.x; e < e1; e += KT) acc += norm2(xb[e]);
+  const double s = block_sum<KT>(acc, red);
+  if (threadIdx.x == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
+}
+
+// Start of a cycle: residual norms, activity, stopping targets.
+template <typename T, int JM>
+__global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first, double rtol, double inner_rtol,
+                                                     const double* __restrict__ nrmp, double* __restrict__ rnorm,
+                                                     double* __restrict__ bnorm, double* __restrict__ target,
+                                                     double* __restrict__ rscale, int* __restrict__ active,
+                                                     int* __restrict__ ncol, c128* __restrict__ gv,
+                                                     int* __restrict__ counters, double* __restrict__ maxrel) {
+  __shared__ double red[1024 / 64];
+  __shared__ double redm[1024 / 64];
+  double cnt = 0.0, mx = 0.0;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    double s2 = 0.0;
+    for (int k = 0; k < nblk; ++k) s2 += nrmp[(long)b * nblk + k];
+    const double rn = sqrt(s2);
+    if (first) bnorm[b] = rn;
+    const double bn = bnorm[b];
+    rnorm[b] = rn;
+    ncol[b] = 0;
+    gv[(long)b * (JM + 1)] = mk(1.0, 0.0);
+    const int act = rn > rtol * bn;
+    active[b] = act;
+    const double rel = bn > 0.0 ? rn / bn : 0.0;
+    mx = fmax(mx, rel);
+    if (act) {
+      cnt += 1.0;
+      double tg = rtol * bn / rn;
+      if (inner_rtol > tg) tg = inner_rtol;
+      target[b] = tg;
+      rscale[b] = 1.0 / rn;
+    }
+  }
+  const double tot = block_sum<1024>(cnt, red);
+  // max-reduce
+  double m = mx;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) mm = fmax(mm, redm[w]);
+    maxrel[0] = mm;
+    counters[0] = (int)tot;
+    counters[1] = (int)tot;
+  }
+}
+
+// V0_b = (T)(r_b / |r_b|)
+template <typename T>
+__global__ void __launch_bounds__(KT) k_start_basis(const c128* __restrict__ r, cplx<T>* __restrict__ V0, long n,
+                                                    const int* __restrict__ active, const double* __restrict__ rscale) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const double s = rscale[b];
+  const c128* rb = r + (long)b * n;
+  cplx<T>* vb = V0 + (long)b * n;
+  for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
+    const c128 v = rb[e];
+    vb[e] = mk((T)(v.x * s), (T)(v.y * s));
+  }
+}
+
+// Back-substitution R y = g for each RHS (k = ncol columns).
+template <int JM>
+__global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __restrict__ H,
+                            const c128* __restrict__ gv, c128* __restrict__ y) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const int k = ncol[b];
+  const c128* Hb = H + (long)b * (JM + 1) * JM;
+  for (int i = k - 1; i >= 0; --i) {
+    c128 acc = gv[(long)b * (JM + 1) + i];
+    for (int l = i + 1; l < k; ++l) acc = acc - Hb[i * JM + l] * y[(long)b * JM + l];
+    const c128 d = Hb[i * JM + i];
+    const double dn = norm2(d);
+    // acc / d
+    y[(long)b * JM + i] = mk((acc.x * d.x + acc.y * d.y) / dn, (acc.y * d.x - acc.x * d.y) / dn);
+  }
+}
+
+// x_b += |r_b| sum_{i < ncol_b} y_i V_i  (FP64 accumulation)
+template <typename T, int JM>
+__global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, long vs, long n,
+                                                const int* __restrict__ ncol, const c128* __restrict__ y,
+                                                const double* __restrict__ rnorm, c128* __restrict__ x) {
+  const int b = blockIdx.y;
+  const int k = ncol[b];
+  if (k == 0) return;
+  __shared__ double yr[JM], yi[JM];
+  if (threadIdx.x < k) {
+    const c128 v = y[(long)b * JM + threadIdx.x];
+    yr[threadIdx.x] = rnorm[b] * v.x;
+    yi[threadIdx.x] = rnorm[b] * v.y;
+  }
+  __syncthreads();
+  const long off = (long)b * n;
+  for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
+    c128 acc = x[off + e];
+#pragma unroll
+    for (int i = 0; i < JM; ++i) {
+      if (i < k) {
+        const cplx<T> v = V[(long)i * vs + off + e];
+        const double vx = v.x, vy = v.y;
+        acc.x += yr[i] * vx - yi[i] * vy;
+        acc.y += yr[i] * vy + yi[i] * vx;
+      }
+    }
+    x[off + e] = acc;
+  }
+}
+
+__global__ void k_zero_int(int* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+__global__ void k_fill_zero_c128(long count, c128* p) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = mk(0.0, 0.0);
+}
+__global__ void k_copy_c128(long count, const c128* __restrict__ in, c128* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = in[i];
+}
+
+void launch_fill_zero_c128(long count, c128* p, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill_zero_c128, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, p);
+  FWI_LAUNCH_CHECK();
+}
+void launch_copy_c128(long count, const c128* in, c128* out, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_copy_c128, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, in, out);
+  FWI_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------- launchers ---
+static unsigned vec_blocks(long n) {
+  long b = (n + KT * 4 - 1) / (KT * 4);
+  if (b > 1024) b = 1024;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+#define FWI_JM_SWITCH(JM_RT, ...)                                            \
+  switch (JM_RT) {                                                           \
+    case 8: { constexpr int JMC = 8; __VA_ARGS__; } break;                   \
+    case 16: { constexpr int JMC = 16; __VA_ARGS__; } break;                 \
+    case 32: { constexpr int JMC = 32; __VA_ARGS__; } break;                 \
+    default: throw Error(-6, "unsupported GMRES basis capacity");            \
+  }
+
+template <typename T>
+void krylov_norms(const KrylovState<T>& s, const c128* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_partial, dim3(s.nblk, s.B), dim3(KT), 0, st, x, s.n, s.chunk, s.nrmp, s.nblk);
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st) {
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_cycle_init<T, JMC>), dim3(1), dim3(1024), 0, st, s.B, s.nblk, first, rtol,
+                                          inner_rtol, s.nrmp, s.rnorm, s.bnorm, s.target, s.rscale, s.active, s.ncol,
+                                          s.gv, s.counters, s.maxrel));
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st) {
+  hipLaunchKernelGGL((k_start_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, r, s.V, s.n, s.active, s.rscale);
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st) {
+  const long vs = s.vstride();
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
+                                          s.chunk, s.active, s.dotp, s.nblk));
+  FWI_LAUNCH_CHECK();
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
+                                          s.chunk, s.active, s.dotp, s.nblk, s.H, s.nrmp));
+  FWI_LAUNCH_CHECK();
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
+                                          s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters, s.scal,
+                                          s.counters));
+  FWI_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_scale_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V + (long)(j + 1) * vs, s.n,
+                     s.active, s.scal);
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_finish_cycle(const KrylovState<T>& s, c128* x, hipStream_t st) {
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_backsolve<JMC>), dim3((s.B + 63) / 64), dim3(64), 0, st, s.B, s.ncol,
+                                          s.H, s.gv, s.y));
+  FWI_LAUNCH_CHECK();
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_xupdate<T, JMC>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V,
+                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, x));
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_int, dim3((s.B + 255) / 256), dim3(256), 0, st, s.iters, s.B);
+  FWI_LAUNCH_CHECK();
+}
+
+#define FWI_INST(T)                                                                            \
+  template void krylov_norms<T>(const KrylovState<T>&, const c128*, hipStream_t);              \
+  template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
+  template void krylov_start_basis<T>(const KrylovState<T>&, const c128*, hipStream_t);        \
+  template void krylov_arnoldi<T>(const KrylovState<T>&, int, hipStream_t);                    \
+  template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, hipStream_t);             \
+  template void krylov_reset_iters<T>(const KrylovState<T>&, hipStream_t);
+FWI_INST(float)
+FWI_INST(double)
+
+}  // namespace fwi

@@ -1,0 +1,216 @@
+// Set-up kernels: contrast (Eq. 1-3), the circulant Green table of the
+// discrete volume integral operator (Eq. 5, Sec. IV-A) and the incident fields
+// of point elements (Sec. II). All evaluated in FP64.
+#include "bessel.hpp"
+#include "internal.hpp"
+
+namespace fwi {
+
+constexpr double PI = 3.14159265358979323846;
+
+// m = kappa/kappa0 - 1 with kappa rho0 = 1/c^2 - alpha^2/(2 pi)^2 + i alpha/(pi c)
+// (e^{-i omega t}) and a lossless background kappa0 rho0 = 1/c0^2.
+__global__ void k_contrast(long n, double c0, const double* __restrict__ c, const double* __restrict__ alpha,
+                           c128* __restrict__ m64, c64* __restrict__ m32) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double cc = c[i], a = alpha ? alpha[i] : 0.0;
+  const double re = c0 * c0 * (1.0 / (cc * cc) - a * a / (4.0 * PI * PI)) - 1.0;
+  const double im = c0 * c0 * a / (PI * cc);
+  m64[i] = mk(re, im);
+  if (m32) m32[i] = mk((float)re, (float)im);
+}
+
+void launch_contrast(long n, double c0, const double* c, const double* alpha, c128* m64, c64* m32, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c0, c, alpha, m64, m32);
+  FWI_LAUNCH_CHECK();
+}
+
+// Cell weight constants (Richmond: equal-area disk / equal-volume ball of radius a).
+//  2D: W(r>0) = (i/4)(2 pi a/k) J1(ka) H0(kr),  W(0) = (i pi a/(2k)) H1(ka) - 1/k^2
+//  3D: W(r>0) = (4 pi/k^3)(sin ka - ka cos ka) e^{ikr}/(4 pi r),
+//      W(0)  = ((1 - i ka) e^{ika} - 1)/k^2
+struct WeightConsts {
+  double fac;        // real factor multiplying G(r) for r > 0 (2D: (2 pi a/k) J1(ka); 3D: (4 pi/k^3)(...))
+  c128 self;         // W(0)
+};
+
+static WeightConsts weight_consts(int dim, double k, double dx) {
+  WeightConsts w{};
+  if (dim == 2) {
+    const double a = dx / std::sqrt(PI), ka = k * a;
+    double j0, j1, y0, y1;
+    bessel01(ka, &j0, &j1, &y0, &y1);
+    w.fac = (2.0 * PI * a / k) * j1;
+    // (i pi a/(2k)) (J1 + i Y1) - 1/k^2
+    const double s = PI * a / (2.0 * k);
+    w.self = mk(-s * y1 - 1.0 / (k * k), s * j1);
+  } else {
+    const double a = dx * std::cbrt(3.0 / (4.0 * PI)), ka = k * a;
+    w.fac = 4.0 * PI / (k * k * k) * (std::sin(ka) - ka * std::cos(ka));
+    // ((1 - i ka)(cos ka + i sin ka) - 1)/k^2
+    const double cs = std::cos(ka), sn = std::sin(ka);
+    w.self = mk((cs + ka * sn - 1.0) / (k * k), (sn - ka * cs) / (k * k));
+  }
+  return w;
+}
+
+// T[iz][iy][ix] = k^2 W(dx |Delta|) / (Lz Ly Lx) on the circulant grid: offset
+// i for i < n, i - L for i > L - n, and zero elsewhere (never reached by the
+// linear convolution of an n-point axis).
+__global__ void k_green_table(int dim, int nx, int ny, int nz, int Lx, int Ly, int Lz, double dx, double k,
+                              double fac, c128 self, double scale, c128* __restrict__ T) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)Lx * Ly * Lz;
+  if (i >= total) return;
+  const int ix = (int)(i % Lx);
+  const int iy = (int)((i / Lx) % Ly);
+  const int iz = (int)(i / ((long)Lx * Ly));
+  auto off = [](int idx, int n, int L, bool& ok) -> int {
+    if (idx < n) return idx;
+    if (idx > L - n) return idx - L;
+    ok = false;
+    return 0;
+  };
+  bool ok = true;
+  const int dxi = off(ix, nx, Lx, ok);
+  const int dyi = dim == 3 ? off(iy, ny, Ly, ok) : 0;
+  const int dzi = off(iz, nz, Lz, ok);
+  c128 v = mk(0.0, 0.0);
+  if (ok) {
+    const double r = dx * sqrt((double)dxi * dxi + (double)dyi * dyi + (double)dzi * dzi);
+    if (r == 0.0) {
+      v = self;
+    } else if (dim == 2) {
+      double j0, j1, y0, y1;
+      bessel01(k * r, &j0, &j1, &y0, &y1);
+      // (i/4) H0 = (i/4)(J0 + i Y0) = (-Y0/4, J0/4)
+      v = mk(-0.25 * fac * y0, 0.25 * fac * j0);
+    } else {
+      double s, c;
+      sincos(k * r, &s, &c);
+      const double g = fac / (4.0 * PI * r);
+      v = mk(g * c, g * s);
+    }
+    v = (k * k * scale) * v;
+  }
+  T[i] = v;
+}
+
+void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st) {
+  const WeightConsts w = weight_consts(g.dim, k, g.dx);
+  const long total = g.npad();
+  hipLaunchKernelGGL(k_green_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz,
+                     g.Lx, g.Ly, g.Lz, g.dx, k, w.fac, w.self, 1.0 / (double)total, table);
+  FWI_LAUNCH_CHECK();
+}
+
+// P0[e][n] = G(k |x_n - x_e|): 2D (i/4) H0^(1), 3D e^{ikr}/(4 pi r).
+__global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k, int ne,
+                           const double* __restrict__ exyz, c128* __restrict__ P0) {
+  const long n = (long)nx * ny * nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (i >= n) return;
+  const int ix = (int)(i % nx);
+  const int iy = (int)((i / nx) % ny);
+  const int iz = (int)(i / ((long)nx * ny));
+  const double px = (ix + 0.5) * dx - exyz[3 * e + 0];
+  const double py = (dim == 3 ? (iy + 0.5) * dx : 0.0) - exyz[3 * e + 1];
+  const double pz = (iz + 0.5) * dx - exyz[3 * e + 2];
+  const double r = sqrt(px * px + py * py + pz * pz);
+  c128 v;
+  if (dim == 2) {
+    double j0, j1, y0, y1;
+    bessel01(k * r, &j0, &j1, &y0, &y1);
+    v = mk(-0.25 * y0, 0.25 * j0);
+  } else {
+    double s, c;
+    sincos(k * r, &s, &c);
+    const double g = 1.0 / (4.0 * PI * r);
+    v = mk(g * c, g * s);
+  }
+  P0[(long)e * n + i] = v;
+}
+
+void launch_incident(const Geo& g, double k, int ne, const double* exyz, c128* P0, hipStream_t st) {
+  const long n = g.n();
+  if (n == 0 || ne == 0) return;
+  hipLaunchKernelGGL(k_incident, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz, g.dx,
+                     k, ne, exyz, P0);
+  FWI_LAUNCH_CHECK();
+}
+
+__global__ void k_cast_64_32(long count, const c128* __restrict__ in, c64* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = cvt<float>(in[i]);
+}
+void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_cast_64_32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, in, out);
+  FWI_LAUNCH_CHECK();
+}
+
+__global__ void k_scale_c128(long count, double s, c128* x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = s * x[i];
+}
+void launch_scale_c128(long count, double s, c128* x, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_scale_c128, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, s, x);
+  FWI_LAUNCH_CHECK();
+}
+
+}  // namespace fwi
+
+// Host evaluation of the same Bessel routine the kernels use (for CPU checks).
+extern "C" void fwi_host_bessel01(double x, double* out4) {
+  fwi::bessel01(x, &out4[0], &out4[1], &out4[2], &out4[3]);
+}
+
+namespace fwi {
+
+// Input checks (single block): out[0] = #(c <= 0 or non-finite), out[1] = #(alpha < 0 or non-finite)
+__global__ void __launch_bounds__(1024) k_check_sos(long n, const double* __restrict__ c,
+                                                    const double* __restrict__ alpha, int* __restrict__ out) {
+  __shared__ double red[16];
+  double bc = 0.0, ba = 0.0;
+  for (long i = threadIdx.x; i < n; i += 1024) {
+    const double v = c[i];
+    if (!(v > 0.0) || !isfinite(v)) bc += 1.0;
+    if (alpha) {
+      const double a = alpha[i];
+      if (!(a >= 0.0) || !isfinite(a)) ba += 1.0;
+    }
+  }
+  const double sc = block_sum<1024>(bc, red);
+  const double sa = block_sum<1024>(ba, red);
+  if (threadIdx.x == 0) {
+    out[0] = (int)sc;
+    out[1] = (int)sa;
+  }
+}
+
+// out[0] = #non-finite complex entries
+__global__ void __launch_bounds__(1024) k_check_complex(long n, const c128* __restrict__ x, int* __restrict__ out) {
+  __shared__ double red[16];
+  double b = 0.0;
+  for (long i = threadIdx.x; i < n; i += 1024) {
+    const c128 v = x[i];
+    if (!isfinite(v.x) || !isfinite(v.y)) b += 1.0;
+  }
+  const double s = block_sum<1024>(b, red);
+  if (threadIdx.x == 0) out[0] = (int)s;
+}
+
+void launch_check_sos(long n, const double* c, const double* alpha, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_sos, dim3(1), dim3(1024), 0, st, n, c, alpha, out);
+  FWI_LAUNCH_CHECK();
+}
+void launch_check_complex(long n, const c128* x, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_complex, dim3(1), dim3(1024), 0, st, n, x, out);
+  FWI_LAUNCH_CHECK();
+}
+
+}  // namespace fwi

@@ -1,0 +1,56 @@
+// Batched restarted GMRES kernels (the Krylov solver of Sec. IV-A), one
+// independent Arnoldi process per right-hand side, all advanced in lockstep.
+// Inner products, norms, the Hessenberg matrix, Givens rotations and the
+// solution accumulator are FP64; the basis may be complex64 or complex128.
+#pragma once
+
+#include "internal.hpp"
+
+namespace fwi {
+
+// Device state of one batched GMRES cycle.
+template <typename T>
+struct KrylovState {
+  int B = 0, JM = 0;   // right-hand sides, basis capacity (restart length)
+  long n = 0;          // unknowns per RHS
+  int nblk = 0, chunk = 0;
+  cplx<T>* V = nullptr;        // [JM+1][B][n]
+  c128* H = nullptr;           // [B][JM+1][JM]
+  double* cs = nullptr;        // [B][JM]
+  c128* sn = nullptr;          // [B][JM]
+  c128* gv = nullptr;          // [B][JM+1]
+  c128* y = nullptr;           // [B][JM]
+  c128* dotp = nullptr;        // [B][nblk][JM+1]
+  double* nrmp = nullptr;      // [B][nblk]
+  double* rnorm = nullptr;     // [B] residual norm at cycle start
+  double* bnorm = nullptr;     // [B]
+  double* target = nullptr;    // [B] relative stopping target of the cycle
+  double* rscale = nullptr;    // [B] 1/rnorm
+  cplx<T>* scal = nullptr;     // [B] normalisation of the newest basis vector
+  int* active = nullptr;       // [B]
+  int* ncol = nullptr;         // [B]
+  int* iters = nullptr;        // [B] accumulated iterations
+  int* counters = nullptr;     // [0] active count, [1] unconverged
+  double* maxrel = nullptr;    // [1] max relative residual at cycle start
+  long vstride() const { return (long)B * n; }
+};
+
+int krylov_nblk(long n);
+
+template <typename T>
+void krylov_norms(const KrylovState<T>& s, const c128* x, hipStream_t st);  // -> nrmp
+template <typename T>
+void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st);
+template <typename T>
+void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st);
+template <typename T>
+void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st);  // dots, orth, givens, normalise
+template <typename T>
+void krylov_finish_cycle(const KrylovState<T>& s, c128* x, hipStream_t st);  // backsolve + x update
+template <typename T>
+void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st);
+
+void launch_fill_zero_c128(long count, c128* p, hipStream_t st);
+void launch_copy_c128(long count, const c128* in, c128* out, hipStream_t st);
+
+}  // namespace fwi

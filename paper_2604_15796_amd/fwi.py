@@ -1,0 +1,436 @@
+"""Python binding of libfwi.so (include/fwi.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library.
+PyTorch provides device memory (tensors, the workspace) and the HIP stream.
+The library is loaded from this package directory; if it is missing, every
+call raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwi.so")
+
+FWI_OK = 0
+FWI_E_INVAL = -1
+FWI_E_NOMEM = -2
+FWI_E_NOCONV = -3
+FWI_E_NONFINITE = -4
+FWI_E_DEVICE = -5
+FWI_E_UNSUPPORTED = -6
+FWI_FP64 = 0
+FWI_FP32_REFINE = 1
+ENTRY_FORWARD, ENTRY_GRADIENT, ENTRY_ADMM = 0, 1, 2
+
+ERROR_NAMES = {FWI_E_INVAL: "FWI_E_INVAL", FWI_E_NOMEM: "FWI_E_NOMEM", FWI_E_NOCONV: "FWI_E_NOCONV",
+               FWI_E_NONFINITE: "FWI_E_NONFINITE", FWI_E_DEVICE: "FWI_E_DEVICE",
+               FWI_E_UNSUPPORTED: "FWI_E_UNSUPPORTED"}
+
+
+class FWIError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CProblem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("c0", C.c_double), ("nf", C.c_int), ("freq_hz", C.POINTER(C.c_double)), ("ne", C.c_int),
+                ("elem_xyz", C.POINTER(C.c_double))]
+
+
+class CSolveOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int),
+                ("max_refine", C.c_int), ("inner_rtol", C.c_double), ("max_rhs", C.c_int),
+                ("check_every", C.c_int), ("reciprocity_adjoint", C.c_int)]
+
+
+class CStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("cycles", C.c_int), ("unconverged", C.c_int),
+                ("max_rel_residual", C.c_double), ("solves", C.c_longlong), ("matvecs", C.c_longlong),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CAdmmParams(C.Structure):
+    _fields_ = [("lam", C.c_double), ("rho", C.c_double), ("gamma", C.c_double), ("n_cg", C.c_int),
+                ("data_scale", C.c_double), ("dual_step", C.c_double)]
+
+
+class CAdmmReport(C.Structure):
+    _fields_ = [("misfit", C.c_double), ("tv", C.c_double), ("dm_norm", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfwi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp = C.c_void_p, C.c_int, C.POINTER(C.c_double)
+    pp = C.POINTER(CProblem)
+    op = C.POINTER(CSolveOpts)
+    sp = C.POINTER(CStats)
+    sig = {
+        "fwi_create": (ip, [C.POINTER(vp), ip, vp]),
+        "fwi_destroy": (None, [vp]),
+        "fwi_last_error": (C.c_char_p, [vp]),
+        "fwi_set_stream": (ip, [vp, vp]),
+        "fwi_default_opts": (None, [op]),
+        "fwi_validate_problem": (ip, [pp]),
+        "fwi_padded_length": (ip, [ip]),
+        "fwi_workspace_size": (ip, [pp, op, ip, C.POINTER(C.c_size_t)]),
+        "fwi_set_workspace": (ip, [vp, vp, C.c_size_t]),
+        "fwi_forward": (ip, [vp, pp, vp, vp, op, vp, vp, sp]),
+        "fwi_forward_m": (ip, [vp, pp, vp, op, vp, vp, sp]),
+        "fwi_adjoint_gradient": (ip, [vp, pp, vp, vp, vp, op, dp, vp, vp, vp, sp]),
+        "fwi_vjp": (ip, [vp, pp, vp, vp, op, vp, sp]),
+        "fwi_tv_admm_step": (ip, [vp, pp, C.POINTER(CAdmmParams), vp, vp, vp, vp, vp, op,
+                                  C.POINTER(CAdmmReport), sp]),
+        "fwi_apply_operator": (ip, [vp, pp, ip, vp, ip, C.POINTER(C.c_int), vp, vp]),
+        "fwi_solve": (ip, [vp, pp, vp, ip, C.POINTER(C.c_int), vp, op, vp, sp]),
+        "fwi_incident": (ip, [vp, pp, ip, vp]),
+        "fwi_green_spectrum": (ip, [vp, pp, ip, vp]),
+        "fwi_fft_padded": (ip, [vp, pp, ip, vp, vp]),
+        "fwi_jacobian_apply": (ip, [vp, pp, vp, vp, vp]),
+        "fwi_jacobian_adjoint_apply": (ip, [vp, pp, vp, vp, vp]),
+        "fwi_host_bessel01": (None, [C.c_double, dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fwi_default_opts",
+            "fwi_validate_problem", "fwi_padded_length", "fwi_workspace_size", "fwi_set_workspace",
+            "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_tv_admm_step",
+            "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
+            "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01"]
+
+
+# ---------------------------------------------------------------- structs ---
+class ProblemArgs:
+    """Host-side fwi_problem built from any object with dim, nx, ny, nz, dx, c0,
+    freqs, elems (e.g. workloads.Problem); keeps its arrays alive."""
+
+    def __init__(self, p):
+        self.dim, self.nx, self.ny, self.nz = int(p.dim), int(p.nx), int(p.ny), int(p.nz)
+        self.dx, self.c0 = float(p.dx), float(p.c0)
+        self.freqs = np.ascontiguousarray(np.asarray(p.freqs, dtype=np.float64))
+        self.elems = np.ascontiguousarray(np.asarray(p.elems, dtype=np.float64).reshape(-1, 3))
+        self.nf, self.ne = len(self.freqs), self.elems.shape[0]
+        self.n = self.nx * self.ny * self.nz
+        self.c = CProblem(self.dim, self.nx, self.ny, self.nz, self.dx, self.c0, self.nf,
+                          self.freqs.ctypes.data_as(C.POINTER(C.c_double)), self.ne,
+                          self.elems.ctypes.data_as(C.POINTER(C.c_double)))
+
+    @property
+    def shape(self):
+        return (self.nz, self.nx) if self.dim == 2 else (self.nz, self.ny, self.nx)
+
+    def ref(self):
+        return C.byref(self.c)
+
+
+@dataclass
+class SolveOptions:
+    precision: int = FWI_FP64
+    rtol: float = 1e-10
+    max_iter: int = 2000
+    restart: int = 32
+    max_refine: int = 12
+    inner_rtol: float = 1e-3
+    max_rhs: int = 0
+    check_every: int = 1
+    reciprocity_adjoint: int = 0
+
+    def c(self):
+        return CSolveOpts(self.precision, self.rtol, self.max_iter, self.restart, self.max_refine,
+                          self.inner_rtol, self.max_rhs, self.check_every, self.reciprocity_adjoint)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check_dtype(t, dtype, shape, what):
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+        raise ValueError(f"{what}: expected shape {shape}, got {tuple(t.shape)}")
+
+
+class Context:
+    """One fwi_ctx bound to a HIP device; calls run on torch's current stream."""
+
+    def __init__(self, device=0, use_torch_workspace=True):
+        self.L = lib()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        rc = self.L.fwi_create(C.byref(h), device, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+        if rc != FWI_OK:
+            raise FWIError(rc, "fwi_create failed")
+        self.h = h
+        self.use_torch_workspace = use_torch_workspace
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.fwi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_noconv=False):
+        if rc == FWI_OK or (allow_noconv and rc == FWI_E_NOCONV):
+            return rc
+        raise FWIError(rc, self.L.fwi_last_error(self.h).decode())
+
+    def _stream(self):
+        self.L.fwi_set_stream(self.h, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _workspace(self, prob, opts, entry):
+        if not self.use_torch_workspace:
+            self.L.fwi_set_workspace(self.h, None, 0)
+            return
+        nbytes = C.c_size_t()
+        self._check(self.L.fwi_workspace_size(prob.ref(), C.byref(opts), entry, C.byref(nbytes)))
+        if self._ws is None or self._ws.numel() < nbytes.value:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=self.device)
+        self.L.fwi_set_workspace(self.h, C.c_void_p(self._ws.data_ptr()), self._ws.numel())
+
+    def _internal_workspace(self):
+        self.L.fwi_set_workspace(self.h, None, 0)
+
+    def release_workspace(self):
+        self._internal_workspace()
+        self._ws = None
+
+    # ------------------------------------------------------------ entries ---
+    def forward(self, prob, c, alpha=None, opts=None, fields=False, allow_noconv=False):
+        """Scattered data [nf, ne, ne] (and fields [nf, ne, n]) for c, alpha grids."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(c, torch.float64, prob.shape, "c")
+        if alpha is not None:
+            _check_dtype(alpha, torch.float64, prob.shape, "alpha")
+        data = torch.empty((prob.nf, prob.ne, prob.ne), dtype=torch.complex128, device=self.device)
+        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_FORWARD)
+        rc = self.L.fwi_forward(self.h, prob.ref(), _ptr(c), _ptr(alpha), C.byref(o), _ptr(data), _ptr(F),
+                                C.byref(st))
+        self._check(rc, allow_noconv)
+        return (data, F, st.as_dict()) if fields else (data, st.as_dict())
+
+    def forward_m(self, prob, m, opts=None, fields=False, allow_noconv=False):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        data = torch.empty((prob.nf, prob.ne, prob.ne), dtype=torch.complex128, device=self.device)
+        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_FORWARD)
+        rc = self.L.fwi_forward_m(self.h, prob.ref(), _ptr(m), C.byref(o), _ptr(data), _ptr(F), C.byref(st))
+        self._check(rc, allow_noconv)
+        return (data, F, st.as_dict()) if fields else (data, st.as_dict())
+
+    def adjoint_gradient(self, prob, c, alpha, d_obs, opts=None, chain=True, allow_noconv=False):
+        """(misfit, grad_m [n] complex, grad_c [n], grad_alpha [n], stats)."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(c, torch.float64, prob.shape, "c")
+        _check_dtype(d_obs, torch.complex128, (prob.nf, prob.ne, prob.ne), "d_obs")
+        gm = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        gc = torch.empty(prob.n, dtype=torch.float64, device=self.device) if chain else None
+        ga = torch.empty(prob.n, dtype=torch.float64, device=self.device) if chain else None
+        phi = C.c_double()
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_GRADIENT)
+        rc = self.L.fwi_adjoint_gradient(self.h, prob.ref(), _ptr(c), _ptr(alpha), _ptr(d_obs), C.byref(o),
+                                         C.byref(phi), _ptr(gm), _ptr(gc), _ptr(ga), C.byref(st))
+        self._check(rc, allow_noconv)
+        return phi.value, gm, gc, ga, st.as_dict()
+
+    def vjp(self, prob, m, grad_data, opts=None, allow_noconv=False):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        _check_dtype(grad_data, torch.complex128, (prob.nf, prob.ne, prob.ne), "grad_data")
+        gm = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_GRADIENT)
+        rc = self.L.fwi_vjp(self.h, prob.ref(), _ptr(m), _ptr(grad_data), C.byref(o), _ptr(gm), C.byref(st))
+        self._check(rc, allow_noconv)
+        return gm, st.as_dict()
+
+    def tv_admm_step(self, prob, m, g, u, d_obs, lam, rho, gamma=0.0, n_cg=10, m_ref=None, data_scale=0.0,
+                     dual_step=None, opts=None, allow_noconv=False):
+        """One ADMM iteration; m, g, u (complex128 device tensors) are updated in place."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        _check_dtype(g, torch.complex128, (prob.dim,) + prob.shape, "g")
+        _check_dtype(u, torch.complex128, (prob.dim,) + prob.shape, "u")
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        rep = CAdmmReport()
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_ADMM)
+        rc = self.L.fwi_tv_admm_step(self.h, prob.ref(), C.byref(prm), _ptr(m), _ptr(g), _ptr(u), _ptr(m_ref),
+                                     _ptr(d_obs), C.byref(o), C.byref(rep), C.byref(st))
+        self._check(rc, allow_noconv)
+        return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
+
+    # ---------------------------------------------------- building blocks ---
+    def apply_operator(self, prob, m, freq_index, x, precision=FWI_FP64):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        fi = np.ascontiguousarray(np.asarray(freq_index, dtype=np.int32))
+        dt = torch.complex64 if precision == FWI_FP32_REFINE else torch.complex128
+        _check_dtype(x, dt, (len(fi), prob.n), "x")
+        y = torch.empty_like(x)
+        self._stream()
+        self._internal_workspace()
+        rc = self.L.fwi_apply_operator(self.h, prob.ref(), precision, _ptr(m), len(fi),
+                                       fi.ctypes.data_as(C.POINTER(C.c_int)), _ptr(x), _ptr(y))
+        self._check(rc)
+        return y
+
+    def solve(self, prob, m, freq_index, rhs, opts=None, allow_noconv=False):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        fi = np.ascontiguousarray(np.asarray(freq_index, dtype=np.int32))
+        x = torch.empty_like(rhs)
+        st = CStats()
+        self._stream()
+        self._internal_workspace()
+        rc = self.L.fwi_solve(self.h, prob.ref(), _ptr(m), len(fi), fi.ctypes.data_as(C.POINTER(C.c_int)),
+                              _ptr(rhs), C.byref(o), _ptr(x), C.byref(st))
+        self._check(rc, allow_noconv)
+        return x, st.as_dict()
+
+    def incident(self, prob, l):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        out = torch.empty((prob.ne, prob.n), dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._check(self.L.fwi_incident(self.h, prob.ref(), l, _ptr(out)))
+        return out
+
+    def padded_shape(self, prob):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        Lx, Lz = self.L.fwi_padded_length(prob.nx), self.L.fwi_padded_length(prob.nz)
+        if prob.dim == 2:
+            return (Lz, Lx)
+        return (Lz, self.L.fwi_padded_length(prob.ny), Lx)
+
+    def green_spectrum(self, prob, l):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        out = torch.empty(self.padded_shape(prob), dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._check(self.L.fwi_green_spectrum(self.h, prob.ref(), l, _ptr(out)))
+        return out
+
+    def fft_padded(self, prob, x, precision=FWI_FP64):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        dt = torch.complex64 if precision == FWI_FP32_REFINE else torch.complex128
+        out = torch.empty(self.padded_shape(prob), dtype=dt, device=self.device)
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_fft_padded(self.h, prob.ref(), precision, _ptr(x), _ptr(out)))
+        return out
+
+    def jacobian_apply(self, prob, fields, a):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        out = torch.empty((prob.nf, prob.ne, prob.ne), dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_jacobian_apply(self.h, prob.ref(), _ptr(fields), _ptr(a), _ptr(out)))
+        return out
+
+    def jacobian_adjoint_apply(self, prob, fields, b):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        out = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_jacobian_adjoint_apply(self.h, prob.ref(), _ptr(fields), _ptr(b), _ptr(out)))
+        return out
+
+
+def host_bessel01(x):
+    """{J0, J1, Y0, Y1}(x) from the library's own FP64 routine (host evaluation)."""
+    out = (C.c_double * 4)()
+    lib().fwi_host_bessel01(float(x), out)
+    return np.array(out[:])
+
+
+def validate_problem(p):
+    pa = p if isinstance(p, ProblemArgs) else ProblemArgs(p)
+    return lib().fwi_validate_problem(pa.ref())
+
+
+def workspace_size(p, opts=None, entry=ENTRY_FORWARD):
+    pa = p if isinstance(p, ProblemArgs) else ProblemArgs(p)
+    o = (opts or SolveOptions()).c()
+    nb = C.c_size_t()
+    rc = lib().fwi_workspace_size(pa.ref(), C.byref(o), entry, C.byref(nb))
+    if rc != FWI_OK:
+        raise FWIError(rc, "fwi_workspace_size failed")
+    return nb.value
+
+
+# ------------------------------------------------------------- autograd ---
+class FWIData(torch.autograd.Function):
+    """d = F(m) with the adjoint-state backward J^H grad_d (Eq. 17), computed by
+    adjoint solves in the library; wavefields are recomputed in the backward
+    rather than stored."""
+
+    @staticmethod
+    def forward(ctx, m, context, prob, opts):
+        data, _ = context.forward_m(prob, m.contiguous(), opts)
+        ctx.save_for_backward(m)
+        ctx.fwi = (context, prob, opts)
+        return data
+
+    @staticmethod
+    def backward(ctx, grad_data):
+        (m,) = ctx.saved_tensors
+        context, prob, opts = ctx.fwi
+        gm, _ = context.vjp(prob, m.contiguous(), grad_data.contiguous().to(torch.complex128), opts)
+        return gm.reshape(m.shape), None, None, None
+
+
+def fwi_data(m, context, prob, opts=None):
+    """Differentiable forward model d = F(m) (complex128)."""
+    prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+    return FWIData.apply(m, context, prob, opts or SolveOptions())

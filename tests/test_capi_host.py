@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU): exports, validation, workspace
+arithmetic and the FP64 Bessel routine the kernels evaluate."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+from paper_2604_15796_amd import fwi, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fwi.lib()
+    hdr = open(os.path.join(ROOT, "include", "fwi.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char\*|size_t)\s+(fwi_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(fwi.EXPORTED)
+
+
+def test_host_bessel_matches_scipy():
+    xs = np.concatenate([np.geomspace(1e-3, 24.99, 300), np.geomspace(25.0, 3000.0, 300)])
+    for x in xs:
+        j0, j1, y0, y1 = fwi.host_bessel01(x)
+        h0, h1 = j0 + 1j * y0, j1 + 1j * y1
+        assert abs(h0 - sp.hankel1(0, x)) <= 5e-15 * abs(sp.hankel1(0, x))
+        assert abs(h1 - sp.hankel1(1, x)) <= 5e-15 * abs(sp.hankel1(1, x))
+
+
+def test_padded_lengths():
+    L = fwi.lib()
+    assert [L.fwi_padded_length(n) for n in (1, 16, 20, 64, 96, 100, 256, 384, 512, 513)] == \
+        [32, 32, 48, 128, 192, 256, 512, 768, 1024, 0]
+
+
+def _prob(**kw):
+    p = W.small2d(nx=24, nz=20, ne=4, nf=2)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_validation_codes():
+    assert fwi.validate_problem(_prob()) == fwi.FWI_OK
+    assert fwi.validate_problem(_prob(dim=4)) == fwi.FWI_E_UNSUPPORTED
+    assert fwi.validate_problem(_prob(nx=600)) == fwi.FWI_E_UNSUPPORTED
+    assert fwi.validate_problem(_prob(dx=-1.0)) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(c0=float("nan"))) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(freqs=np.array([1e6, -1.0]))) == fwi.FWI_E_INVAL
+    e = W.small2d(nx=24, nz=20, ne=4).elems.copy()
+    e[1, 2] = 1e-4
+    assert fwi.validate_problem(_prob(elems=e)) == fwi.FWI_E_UNSUPPORTED    # off the top face
+    e = W.small2d(nx=24, nz=20, ne=4).elems.copy()
+    e[1] = e[0]
+    assert fwi.validate_problem(_prob(elems=e)) == fwi.FWI_E_INVAL          # duplicate
+    e = W.small2d(nx=24, nz=20, ne=4).elems.copy()
+    e[0, 0] = -1e-3
+    assert fwi.validate_problem(_prob(elems=e)) == fwi.FWI_E_INVAL          # outside
+    p3 = W.small3d()
+    assert fwi.validate_problem(p3) == fwi.FWI_OK
+    p2 = _prob(ny=3)
+    assert fwi.validate_problem(p2) == fwi.FWI_E_INVAL
+
+
+def test_workspace_size_arithmetic():
+    p = W.small2d(nx=24, nz=20, ne=4, nf=2)
+    o64 = fwi.SolveOptions(precision=fwi.FWI_FP64, restart=16)
+    o32 = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, restart=16)
+    f64 = fwi.workspace_size(p, o64, fwi.ENTRY_FORWARD)
+    g64 = fwi.workspace_size(p, o64, fwi.ENTRY_GRADIENT)
+    a64 = fwi.workspace_size(p, o64, fwi.ENTRY_ADMM)
+    assert 0 < f64 < g64 and f64 < a64
+    n, B, JM = p.n, p.nf * p.ne, 16
+    # the Krylov basis dominates: (JM+1) B n complex entries
+    assert f64 >= (JM + 1) * B * n * 16
+    assert fwi.workspace_size(p, o32, fwi.ENTRY_FORWARD) >= (JM + 1) * B * n * 8
+    # frequency grouping caps the batch
+    og = fwi.SolveOptions(precision=fwi.FWI_FP64, restart=16, max_rhs=p.ne)
+    assert fwi.workspace_size(p, og, fwi.ENTRY_FORWARD) < f64
+    with pytest.raises(fwi.FWIError):
+        fwi.workspace_size(p, fwi.SolveOptions(restart=12))
+    with pytest.raises(fwi.FWIError):
+        fwi.workspace_size(p, fwi.SolveOptions(rtol=2.0))

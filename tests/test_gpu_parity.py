@@ -1,0 +1,248 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Element-by-element comparisons on seeded inputs at sizes the oracle finishes
+in seconds, spanning several tiles and ragged extents. Tolerances:
+plain FP64 path 1e-10 relative (solves to rtol 1e-12); FP32 operator 2e-6;
+FP32-refined solves 1e-5 on fields and 1e-4 on gradients (the bars of the
+mixed-precision form).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fwi_oracle as O
+from paper_2604_15796_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2604_15796_amd import fwi
+    return fwi
+
+
+@pytest.fixture(scope="module")
+def ctx(F):
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(x, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dtype).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_args(p):
+    return (p.dim, p.nx, p.ny, p.nz, p.dx)
+
+
+# ------------------------------------------------------------- FFT passes ---
+
+@pytest.mark.parametrize("shape", [(16, 16), (20, 13), (48, 40), (96, 64), (256, 256), (7, 9, 5), (24, 16, 20)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fft_padded_vs_numpy(ctx, F, shape, prec):
+    rng = np.random.default_rng(len(shape) * 100 + shape[0])
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    if len(shape) == 2:
+        p = W.Problem("t", 2, shape[1], 1, shape[0], 1e-4, 1540.0, np.array([1e6]),
+                      np.array([[shape[1] * 0.5e-4, 0, 0]]), None, None)
+    else:
+        p = W.Problem("t", 3, shape[2], shape[1], shape[0], 1e-4, 1540.0, np.array([1e6]),
+                      np.array([[shape[2] * 0.5e-4, shape[1] * 0.5e-4, 0]]), None, None)
+    dt = torch.complex64 if prec else torch.complex128
+    out = host(ctx.fft_padded(p, dev(x, dt), precision=prec))
+    ref = np.fft.fftn(x, s=out.shape, axes=tuple(range(x.ndim)))
+    tol = 2e-6 if prec else 1e-13
+    assert relerr(out, ref) < tol
+
+
+# ------------------------------------------------------- set-up kernels ---
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_green_spectrum_vs_oracle(ctx, dim):
+    p = W.small2d(nx=24, nz=20) if dim == 2 else W.small3d(nx=12, ny=10, nz=8)
+    for l, f in enumerate(p.freqs):
+        k = O.wavenumber(f, p.c0)
+        g = host(ctx.green_spectrum(p, l))
+        # the library pads each axis to the smallest 2^a 3^b >= 2n and folds 1/npad in
+        T = O.green_table(k, p.dim, p.nx, p.ny, p.nz, p.dx)
+        if g.shape == T.shape:
+            ref = np.fft.fftn(T) / T.size
+            assert relerr(g, ref) < 1e-13
+        # a property that holds for any padding: convolving a unit impulse at cell 0
+        imp = np.zeros(p.shape, complex)
+        imp.flat[0] = 1.0
+        ref_col = O.convolve(np.fft.fftn(T), imp)
+        pad = np.zeros(g.shape, complex)
+        pad[tuple(slice(0, s) for s in p.shape)] = imp
+        got_col = np.fft.ifftn(g * np.fft.fftn(pad))[tuple(slice(0, s) for s in p.shape)] * g.size
+        assert relerr(got_col, ref_col) < 1e-12
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_incident_vs_oracle(ctx, dim):
+    p = W.small2d(nx=33, nz=17, ne=5) if dim == 2 else W.small3d(nx=12, ny=10, nz=9, ne=4)
+    cen = O.cell_centres(p.dim, p.nx, p.ny, p.nz, p.dx)
+    for l, f in enumerate(p.freqs):
+        got = host(ctx.incident(p, l))
+        ref = O.incident_fields(O.wavenumber(f, p.c0), cen, p.elems, p.dim)
+        assert relerr(got, ref) < 1e-13
+
+
+# ------------------------------------------------------------- operator ---
+
+CASES_2D = [(24, 20, 0.154e-3), (33, 17, 0.154e-3), (64, 64, 0.154e-3), (128, 96, 0.154e-3)]
+
+
+@pytest.mark.parametrize("nx,nz,dx", CASES_2D)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_operator_2d_vs_oracle(ctx, nx, nz, dx, prec):
+    p = W.small2d(seed=nx + nz, nx=nx, nz=nz, dx=dx, nf=2)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    B = 3
+    x = W.random_complex(5, (B,) + p.shape)
+    fi = [0, 1, 1]
+    dt = torch.complex64 if prec else torch.complex128
+    y = host(ctx.apply_operator(p, dev(m), fi, dev(x.reshape(B, -1), dt), precision=prec))
+    for b in range(B):
+        Gh = O.green_spectrum(O.wavenumber(p.freqs[fi[b]], p.c0), 2, p.nx, 1, p.nz, p.dx)
+        ref = O.vie_apply(Gh, m, x[b]).ravel()
+        assert relerr(y[b], ref) < (2e-6 if prec else 1e-13)
+
+
+@pytest.mark.parametrize("shape", [(9, 10, 12), (16, 16, 16), (20, 24, 32)])
+def test_operator_3d_vs_oracle(ctx, shape):
+    nz, ny, nx = shape
+    p = W.small3d(seed=sum(shape), nx=nx, ny=ny, nz=nz)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    x = W.random_complex(6, (2,) + p.shape)
+    for prec in (0, 1):
+        dt = torch.complex64 if prec else torch.complex128
+        y = host(ctx.apply_operator(p, dev(m), [0, 0], dev(x.reshape(2, -1), dt), precision=prec))
+        Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), 3, p.nx, p.ny, p.nz, p.dx)
+        for b in range(2):
+            ref = O.vie_apply(Gh, m, x[b]).ravel()
+            assert relerr(y[b], ref) < (2e-6 if prec else 1e-13)
+
+
+# --------------------------------------------------------------- solves ---
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_vs_oracle(ctx, F, prec):
+    p = W.small2d(seed=21, nx=40, nz=36, ne=6, nf=2)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    cen = O.cell_centres(2, p.nx, 1, p.nz, p.dx)
+    rhs, fi = [], []
+    for l, f in enumerate(p.freqs):
+        P0 = O.incident_fields(O.wavenumber(f, p.c0), cen, p.elems, 2)
+        rhs.append(P0[:3])
+        fi += [l] * 3
+    rhs = np.concatenate(rhs)
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16)
+    x, st = ctx.solve(p, dev(m), fi, dev(rhs), opts)
+    x = host(x)
+    for b in range(len(fi)):
+        ref = O.solve(O.wavenumber(p.freqs[fi[b]], p.c0), m, rhs[b:b + 1], 2, p.nx, 1, p.nz, p.dx)[0]
+        assert relerr(x[b], ref) < 1e-10
+    assert st["unconverged"] == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forward_vs_oracle(ctx, F, prec):
+    p = W.small2d(seed=22, nx=30, nz=26, ne=5, nf=3)
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16, max_rhs=10)
+    data, fields, st = ctx.forward(p, dev(p.c, torch.float64), dev(p.alpha, torch.float64), opts, fields=True)
+    rd, rf, _ = O.forward(p.c, p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert relerr(host(fields), rf) < 1e-10
+    assert relerr(host(data), rd) < 1e-10
+    assert st["solves"] == p.nf * p.ne
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("recip", [0, 1])
+def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
+    p = W.small2d(seed=23, nx=28, nz=24, ne=5, nf=2)
+    d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16, reciprocity_adjoint=recip)
+    phi, gm, gc, ga, st = ctx.adjoint_gradient(p, dev(p.c, torch.float64), dev(p.alpha, torch.float64),
+                                               dev(d_obs), opts)
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs,
+                                               p.elems)
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert relerr(host(gm), rg) < 1e-9
+    assert relerr(host(gc), rgc) < 1e-9
+    assert relerr(host(ga), rga) < 1e-9
+    assert st["solves"] == (1 if recip else 2) * p.nf * p.ne
+
+
+def test_jacobian_products_vs_oracle(ctx):
+    p = W.small2d(seed=24, nx=20, nz=18, ne=4, nf=2)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    _, fields, _ = O.forward_m(m, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    a = W.random_complex(8, p.n)
+    b = W.random_complex(9, (p.nf, p.ne, p.ne))
+    Ja = host(ctx.jacobian_apply(p, dev(fields), dev(a)))
+    JHb = host(ctx.jacobian_adjoint_apply(p, dev(fields), dev(b)))
+    assert relerr(Ja, O.jacobian_apply(fields, a, p.freqs, p.c0, p.dx, 2)) < 1e-12
+    assert relerr(JHb, O.jacobian_adjoint_apply(fields, b, p.freqs, p.c0, p.dx, 2)) < 1e-12
+
+
+@pytest.mark.parametrize("with_ref", [True, False])
+def test_admm_step_vs_oracle(ctx, F, with_ref):
+    p = W.small2d(seed=25, nx=22, nz=20, ne=4, nf=2)
+    m0 = O.contrast(p.c, p.alpha, p.c0) * 0.5
+    d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    g = O.tv_grad(m0)
+    u = W.random_complex(3, g.shape, 1e-3)
+    m_ref = np.zeros_like(m0) if with_ref else None
+    lam, rho, gam, ncg = 1e-3, 1e-2, 1e-5, 6
+    s = 1.0 / float(np.sum(np.abs(d_obs) ** 2))
+    rm, rgv, ru, rep = O.admm_step(m0, g, u, m_ref, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems,
+                                   lam, rho, gam, ncg, data_scale=s)
+    mt, gt, ut = dev(m0), dev(g), dev(u)
+    opts = F.SolveOptions(rtol=1e-13, restart=16)
+    grep, _ = ctx.tv_admm_step(p, mt, gt, ut, dev(d_obs), lam, rho, gam, ncg,
+                               m_ref=dev(m_ref) if with_ref else None, data_scale=s, opts=opts)
+    assert relerr(host(mt), rm) < 1e-8
+    assert relerr(host(gt), rgv) < 1e-8
+    assert relerr(host(ut), ru) < 1e-8
+    assert abs(grep["misfit"] - rep["misfit"]) < 1e-9 * rep["misfit"]
+    assert abs(grep["tv"] - rep["tv"]) < 1e-8 * rep["tv"]
+    assert abs(grep["dm_norm"] - rep["dm_norm"]) < 1e-8 * rep["dm_norm"]
+
+
+# ----------------------------------------------------- differentiation ---
+
+def test_autograd_vjp_matches_oracle_gradient(ctx, F):
+    p = W.small2d(seed=26, nx=16, nz=14, ne=4, nf=2)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    mt = dev(m).requires_grad_(True)
+    data = F.fwi_data(mt, ctx, p, F.SolveOptions(rtol=1e-13, restart=16))
+    loss = 0.5 * torch.sum(torch.abs(data - dev(d_obs)) ** 2)
+    loss.backward()
+    _, rg, _, _ = O.adjoint_gradient_m(m, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert relerr(host(mt.grad).ravel(), rg) < 1e-9
+
+
+def test_autograd_gradcheck_tiny(ctx, F):
+    p = W.small2d(seed=27, nx=6, nz=5, ne=2, nf=1)
+    m = dev(O.contrast(p.c, p.alpha, p.c0)).requires_grad_(True)
+    opts = F.SolveOptions(rtol=1e-14, restart=32)
+    assert torch.autograd.gradcheck(lambda z: F.fwi_data(z, ctx, p, opts), (m,), eps=1e-7, atol=1e-9,
+                                    rtol=1e-6, fast_mode=True)
