@@ -1,0 +1,226 @@
+"""Benchmark: forward + adjoint solves per second of the FWI gradient on one MI355X.
+
+Workload (default): 2D 256 x 256 grid, dx = 0.154 mm, 8 frequencies 0.3-1.0 MHz,
+64-element top-edge array at 0.3 mm, seeded ellipse phantom. One step is one
+fwi_adjoint_gradient call: 512 forward solves (all transmits of all
+frequencies), the data residual, 512 adjoint solves with the same operator and
+the gradient reduction. The timed path is the mixed-precision form (complex64
+Krylov solves inside FP64-residual refinement); the plain FP64 GPU solve is
+timed beside it for the speedup, and the field / gradient errors of the timed
+form against the plain FP64 solve are reported (bar: 1e-5 fields, 1e-4
+gradient).
+
+Prints one JSON line (rank 0, N = 1). `--gpus N` with N > 1 is refused: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "forward+adjoint solves/s at 1e-5 rel err vs FP64 plain; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--inner-rtol", type=float, default=1e-3)
+    ap.add_argument("--restart", type=int, default=16)
+    ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile variants")
+    ap.add_argument("--cpu-solves", type=int, default=6, help="oracle forward solves in the CPU sample")
+    ap.add_argument("--counter-sample", action="store_true",
+                    help="short run for hardware-counter passes: warmup, one step, then a plain copy of "
+                         "known size (the incident-field cache) for calibrating FETCH_SIZE / WRITE_SIZE")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU frequency-sharded layout is design-only.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2604_15796_amd import fwi, workloads as W
+
+    dev = torch.device("cuda", 0)
+    p = W.config1()
+    prob = fwi.ProblemArgs(p)
+    ctx = fwi.Context(0)
+    c = torch.as_tensor(p.c).to(dev)
+    a = torch.as_tensor(p.alpha).to(dev)
+    c_obs = torch.as_tensor(p.extra["c_obs"]).to(dev)
+    ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32)
+    log("setup: observed data from the perturbed model (FP64, untimed)")
+    d_obs, st0 = ctx.forward(prob, c_obs, a, ref_opts)
+    log(f"setup done: cache {st0['t_setup_ms']:.1f} ms, {st0['iterations']} its")
+
+    # autotune the FFT-pass tiles for this grid (untimed set-up), then time one
+    # step with the built-in tiles for the "fixed vs autotuned" comparison
+    tune = {}
+    if not args.no_tune:
+        tune["c64"] = ctx.autotune(prob, fwi.FWI_FP32_REFINE, B=p.nf * p.ne, reps=3)
+        tune["c128"] = ctx.autotune(prob, fwi.FWI_FP64, B=p.nf * p.ne, reps=2)
+        log(f"autotune: {tune}")
+    tuned_table = ctx.get_tuning()
+
+    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
+                             inner_rtol=args.inner_rtol, check_every=args.check_every)
+    plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=args.restart,
+                             check_every=args.check_every)
+    solves_per_step = 2 * p.nf * p.ne
+
+    def step(opts):
+        return ctx.adjoint_gradient(prob, c, a, d_obs, opts)
+
+    if args.counter_sample:
+        step(mixed)
+        torch.cuda.synchronize()
+        out = ctx.incident(prob, 0)   # device copy of ne*n complex128 values
+        torch.cuda.synchronize()
+        print(json.dumps({"counter_sample": True, "copy_bytes_each_way": out.numel() * 16}), flush=True)
+        return
+
+    # warmup, then one profiled step to find the dominant kernel class
+    for w in range(args.warmup):
+        step(mixed)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    fixed_ms = None
+    if tune:
+        ctx.set_tuning(None)
+        step(mixed)
+        torch.cuda.synchronize()
+        tf0 = time.perf_counter()
+        step(mixed)
+        torch.cuda.synchronize()
+        fixed_ms = (time.perf_counter() - tf0) * 1e3
+        ctx.set_tuning(tuned_table)
+        step(mixed)
+    ctx.profile(fwi.KERNEL_CLASSES)
+    step(mixed)
+    prof_all = ctx.profile_read()
+    ctx.profile([])
+    dominant = max(prof_all, key=lambda k: prof_all[k]["ms"])
+    log("per-class event time in one step: " +
+        ", ".join(f"{k} {v['ms']:.1f} ms/{v['launches']}" for k, v in prof_all.items()))
+
+    # timed region: only the dominant class carries events
+    ctx.profile([dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for k in range(args.steps):
+        stats = step(mixed)[4]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()[dominant]
+    ctx.profile([])
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = solves_per_step / (ms_step * 1e-3)
+    log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
+    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dominant, "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
+                "bytes_per_launch": prof["bytes"] / prof["launches"], "launches": prof["launches"]}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": "2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
+                                  "forward+adjoint gradient (512+512 solves)",
+                      "grid": [p.nz, p.nx], "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
+                      "precision": "complex64 GMRES in FP64-residual refinement",
+                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
+           "roofline": roofline,
+           "autotune": {"fixed_tiles_ms_per_step": None if fixed_ms is None else round(fixed_ms, 3),
+                        "autotuned_ms_per_step": round(ms_step, 3), "passes": tune},
+           "solver": {"iterations_max": stats["iterations"], "refinements": stats["cycles"],
+                      "matvecs_per_step": stats["matvecs"], "max_rel_residual": stats["max_rel_residual"]}}
+
+    # accuracy of the timed form against the plain FP64 solve (full size)
+    if not args.no_fp64:
+        _, F32, _ = ctx.forward(prob, c, a, mixed, fields=True)
+        _, F64, _ = ctx.forward(prob, c, a, ref_opts, fields=True)
+        ferr = torch.linalg.vector_norm(F32 - F64, dim=2) / torch.linalg.vector_norm(F64, dim=2)
+        field_err = float(ferr.max())
+        del F32, F64
+        _, g32, _, _, _ = step(mixed)
+        _, g64, _, _, _ = ctx.adjoint_gradient(prob, c, a, d_obs, ref_opts)
+        grad_err = float(torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64))
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        step(plain)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - tp0) * 1e3
+        out["accuracy"] = {"field_rel_err_max": field_err, "grad_rel_err": grad_err,
+                           "reference": "plain FP64 GPU solve, rtol 1e-12"}
+        out["fp64_plain"] = {"ms_per_step": round(ms_plain, 3),
+                             "solves_per_s": round(solves_per_step / (ms_plain * 1e-3), 2),
+                             "rtol": args.rtol}
+        out["speedup_vs_fp64_plain"] = round(ms_plain / ms_step, 3)
+        log(f"accuracy: field {field_err:.2e}, grad {grad_err:.2e}; fp64 plain {ms_plain:.1f} ms")
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(p, ctx, prob, c, a, nsolve):
+    """The FP64 oracle timed on the host on a bounded sample of the same workload:
+    `nsolve` forward solves (first transmits of the lowest frequency) and as many
+    adjoint solves (sources from seeded residuals), plus a check of the GPU fields
+    of those transmits against the oracle's."""
+    import torch
+
+    from oracle import fwi_oracle as O
+    k = O.wavenumber(p.freqs[0], p.c0)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    cen = O.cell_centres(2, p.nx, 1, p.nz, p.dx)
+    P0 = O.incident_fields(k, cen, p.elems, 2)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal((nsolve, p.ne)) + 1j * rng.standard_normal((nsolve, p.ne))
+    S = np.conj(r) @ P0
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    fields = O.solve(k, m, P0[:nsolve], 2, p.nx, 1, p.nz, p.dx)
+    O.solve(k, m, S, 2, p.nx, 1, p.nz, p.dx)
+    dt = time.perf_counter() - t0
+    rate = 2 * nsolve / dt
+    # the same transmits from the GPU (mixed form) for a sampled parity check
+    from paper_2604_15796_amd import fwi
+    opts = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=1e-8, restart=16, inner_rtol=1e-3)
+    x, _ = ctx.solve(prob, torch.as_tensor(m).to(c.device), [0] * nsolve,
+                     torch.as_tensor(np.ascontiguousarray(P0[:nsolve])).to(c.device), opts)
+    x = x.cpu().numpy()
+    err = float(max(np.linalg.norm(x[i] - fields[i]) / np.linalg.norm(fields[i]) for i in range(nsolve)))
+    log(f"cpu oracle: {2 * nsolve} solves in {dt:.1f} s on {cores} cores ({rate:.3f} solves/s); "
+        f"GPU field err vs oracle {err:.2e}")
+    return {"value": round(rate, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{nsolve} forward + {nsolve} adjoint solves (256x256, f=0.3 MHz) of the same workload, "
+                      f"scipy GMRES rtol 1e-12, {dt:.1f} s",
+            "gpu_field_rel_err_vs_oracle": err}
+
+
+if __name__ == "__main__":
+    main()

@@ -211,6 +211,45 @@ int fwi_jacobian_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields
 int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields, const void* b,
                                void* out_m);
 
+/* ----------------------------------------------------------- measurement */
+/* Kernel classes: 0 row forward FFT pass, 1 Green convolution pass (forward
+ * FFT, spectrum product, inverse FFT along the depth axis), 2 row inverse
+ * pass with epilogue, 3 / 4 forward / inverse elevation passes (3D),
+ * 5 Arnoldi inner products, 6 Arnoldi orthogonalisation. */
+#define FWI_KC_ROW_FWD 0
+#define FWI_KC_CONV 1
+#define FWI_KC_ROW_INV 2
+#define FWI_KC_Y_FWD 3
+#define FWI_KC_Y_INV 4
+#define FWI_KC_DOTS 5
+#define FWI_KC_ORTH 6
+/* Class k + 7 is the complex128 launch of class k (k + 0: complex64).
+ * Time every launch of the classes in `mask` (bit k = class k) with HIP events
+ * recorded on the context's stream; resets the accumulated figures. 0 turns it off. */
+int fwi_profile(fwi_ctx* ctx, unsigned mask);
+/* Accumulated event time [ms], launch count and algorithmic HBM bytes (the
+ * bytes each launch must read and write for the RHS it processes) of a class. */
+int fwi_profile_read(const fwi_ctx* ctx, int cls, double* total_ms, long long* launches, double* bytes);
+
+/* ------------------------------------------------------------- autotuner */
+/* Each FFT pass of the operator exists in three tile variants (row passes:
+ * 2048 / 4096 / 8192 points per workgroup; strided passes: 4 / 8 / 16 columns
+ * per workgroup). fwi_autotune times every variant of every pass on the device
+ * for this problem's grid with B right-hand sides (reps launches each, HIP
+ * events) and stores the fastest per (pass, precision, padded length) in the
+ * context; later calls use it. Report rows: 0 row forward, 1 convolution,
+ * 2 row inverse, 3 / 4 elevation forward / inverse (3D). */
+typedef struct fwi_tune_report {
+  double variant_ms[5][3];  /* mean time per launch of each variant [ms] */
+  int variant[5];           /* chosen variant */
+  int default_variant[5];   /* built-in variant before tuning */
+} fwi_tune_report;
+int fwi_autotune(fwi_ctx* ctx, const fwi_problem* prob, int precision, int B, int reps, fwi_tune_report* report);
+/* Copy the tuning table out / in (count = 4*2*11 bytes, -1 = built-in default);
+ * in = NULL restores the defaults. For caching tuning results across runs. */
+int fwi_get_tuning(const fwi_ctx* ctx, signed char* out, int count);
+int fwi_set_tuning(fwi_ctx* ctx, const signed char* in, int count);
+
 /* Host evaluation of the FP64 Bessel routine used by the kernels:
  * out4 = {J0(x), J1(x), Y0(x), Y1(x)} for x > 0. */
 void fwi_host_bessel01(double x, double* out4);

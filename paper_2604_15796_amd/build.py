@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfwi.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["kern_fft.hip", "kern_setup.hip", "kern_krylov.hip", "kern_data.hip", "capi.cpp"]
+SOURCES = ["kern_fft_f32.hip", "kern_fft_f64.hip", "kern_setup.hip", "kern_krylov.hip", "kern_data.hip", "capi.cpp"]
 
 
 def hipcc():

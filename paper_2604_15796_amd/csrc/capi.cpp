@@ -22,6 +22,28 @@ using namespace fwi;
 
 namespace fwi {
 
+thread_local LaunchProfiler* tl_prof = nullptr;
+thread_local long tl_active = 0;
+thread_local int tl_nfreq = 0;
+thread_local const FftTuning* tl_tune = nullptr;
+thread_local int tl_force_variant = -1;
+
+int default_variant(int pass, bool dbl, int L) {
+  (void)L;
+  if (pass == PK_ROW_FWD || pass == PK_ROW_INV) return dbl ? 0 : 1;  // 2048 / 4096 points
+  return dbl ? 1 : 2;                                                  // 8 / 16 columns
+}
+
+int tune_variant(int pass, bool dbl, int L) {
+  if (tl_force_variant >= 0) return tl_force_variant;
+  const int li = length_index(L);
+  if (tl_tune && li >= 0) {
+    const int v = tl_tune->v[pass][dbl ? 1 : 0][li];
+    if (v >= 0 && v < kNumVariants) return v;
+  }
+  return default_variant(pass, dbl, L);
+}
+
 int length_index(int L) {
   for (int i = 0; i < kNumLengths; ++i)
     if (kLengths[i] == L) return i;
@@ -93,6 +115,66 @@ struct ProblemCache {
   }
 };
 
+// HIP-event timing of selected kernel classes, on the stream they run on.
+struct EventProfiler : LaunchProfiler {
+  unsigned mask = 0;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t cur[2 * KC_COUNT] = {};
+  double tot_ms[2 * KC_COUNT] = {};
+  long long cnt[2 * KC_COUNT] = {};
+  double byt[2 * KC_COUNT] = {};
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      FWI_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls, hipStream_t st) override {
+    if (!((mask >> cls) & 1u)) return;
+    cur[cls] = get();
+    FWI_HIP(hipEventRecord(cur[cls], st));
+  }
+  void end(int cls, hipStream_t st, double bytes) override {
+    if (!((mask >> cls) & 1u)) return;
+    hipEvent_t b = get();
+    FWI_HIP(hipEventRecord(b, st));
+    recs.push_back({cls, cur[cls], b, bytes});
+  }
+  void flush() {
+    for (const Rec& r : recs) {
+      FWI_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      FWI_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      tot_ms[r.cls] += ms;
+      cnt[r.cls] += 1;
+      byt[r.cls] += r.bytes;
+    }
+    recs.clear();
+    used = 0;
+  }
+  void reset() {
+    recs.clear();
+    used = 0;
+    for (int k = 0; k < 2 * KC_COUNT; ++k) {
+      tot_ms[k] = 0.0;
+      cnt[k] = 0;
+      byt[k] = 0.0;
+    }
+  }
+  ~EventProfiler() override {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -114,6 +196,8 @@ struct fwi_ctx {
   int* h_int = nullptr;        // pinned host scratch
   double* h_dbl = nullptr;
   int* d_int = nullptr;        // device scratch for checks
+  EventProfiler prof;
+  FftTuning tune;
 };
 
 namespace {
@@ -364,7 +448,8 @@ struct SolveTotals {
 template <typename T>
 SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* mT, const c128* ghat64,
                       const cplx<T>* ghatT, int B, const c128* b64, const int* rhs_freq, c128* x64,
-                      const fwi_solve_opts& o, SolveBufs<T>& s) {
+                      const fwi_solve_opts& o, SolveBufs<T>& s, int nfreq) {
+  tl_nfreq = nfreq;
   hipStream_t st = c->stream;
   KrylovState<T>& ks = s.ks;
   const bool fp32 = std::is_same<T, float>::value;
@@ -380,6 +465,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   for (;; ++cyc) {
     const c128* r = b64;
     if (cyc > 0) {
+      tl_active = B;
       launch_vie<double>(g, c->tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64, s.r64, b64,
                          EPI_RESID, st);
       r = s.r64;
@@ -393,6 +479,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     res.maxrel = c->h_dbl[0];
     if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
     const int nact = c->h_int[0];
+    tl_active = nact;
     if (nact == 0) break;
     if (cyc >= max_cycles || total >= o.max_iter) {
       res.unconverged = nact;
@@ -407,6 +494,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       if ((j + 1) % o.check_every == 0 || j + 1 == ks.JM || total >= o.max_iter) {
         FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
         FWI_HIP(hipStreamSynchronize(st));
+        tl_active = c->h_int[0];
         if (c->h_int[0] == 0) break;
       }
       if (total >= o.max_iter) break;
@@ -529,7 +617,8 @@ struct Runner {
     // a short batch reuses the planned buffers with a smaller B
     SolveBufs<T> s = sb;
     s.ks.B = B;
-    SolveTotals r = run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, pc.rhs_freq + (long)l0 * p->ne, out, o, s);
+    SolveTotals r =
+        run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, pc.rhs_freq + (long)l0 * p->ne, out, o, s, nf);
     tot.merge(r);
   }
 
@@ -617,14 +706,34 @@ void check_complex(fwi_ctx* c, long n, const c128* x, const char* what) {
 template <typename F>
 int guarded(fwi_ctx* c, F&& body) {
   if (!c) return FWI_E_INVAL;
+  struct Scope {
+    Scope(fwi_ctx* c) {
+      tl_prof = c->prof.mask ? &c->prof : nullptr;
+      tl_tune = &c->tune;
+      tl_force_variant = -1;
+      tl_active = 0;
+      tl_nfreq = 0;
+    }
+    ~Scope() {
+      tl_prof = nullptr;
+      tl_tune = nullptr;
+      tl_force_variant = -1;
+    }
+  } scope(c);
   try {
     FWI_HIP(hipSetDevice(c->device));
-    return body();
+    const int rc = body();
+    if (c->prof.mask) c->prof.flush();
+    return rc;
   } catch (const Error& e) {
     c->err = e.what();
+    c->prof.recs.clear();
+    c->prof.used = 0;
     return e.code;
   } catch (const std::exception& e) {
     c->err = e.what();
+    c->prof.recs.clear();
+    c->prof.used = 0;
     return FWI_E_DEVICE;
   }
 }
@@ -829,6 +938,21 @@ void fwi_default_opts(fwi_solve_opts* o) {
 
 int fwi_padded_length(int n) { return padded_length(n); }
 
+int fwi_profile(fwi_ctx* c, unsigned mask) {
+  if (!c) return FWI_E_INVAL;
+  c->prof.mask = mask & ((1u << (2 * KC_COUNT)) - 1u);
+  c->prof.reset();
+  return FWI_OK;
+}
+
+int fwi_profile_read(const fwi_ctx* c, int cls, double* total_ms, long long* launches, double* bytes) {
+  if (!c || cls < 0 || cls >= 2 * KC_COUNT) return FWI_E_INVAL;
+  if (total_ms) *total_ms = c->prof.tot_ms[cls];
+  if (launches) *launches = c->prof.cnt[cls];
+  if (bytes) *bytes = c->prof.byt[cls];
+  return FWI_OK;
+}
+
 int fwi_validate_problem(const fwi_problem* p) {
   std::string msg;
   return validate_problem(p, msg);
@@ -1013,8 +1137,9 @@ int fwi_solve(fwi_ctx* c, const fwi_problem* p, const void* m, int B, const int*
       const cplx<T>* mT = std::is_same<T, float>::value ? (const cplx<T>*)R.cb.m32 : (const cplx<T>*)R.cb.m64;
       const cplx<T>* gT =
           std::is_same<T, float>::value ? (const cplx<T>*)c->pc.ghat32 : (const cplx<T>*)c->pc.ghat64;
+      const int nfreq = (int)std::set<int>(freq_index, freq_index + B).size();
       SolveTotals r = run_solve<T>(c, R.g, R.cb.m64, mT, c->pc.ghat64, gT, B, (const c128*)rhs, R.cb.rfreq,
-                                   (c128*)x_out, R.o, sb);
+                                   (c128*)x_out, R.o, sb, nfreq);
       R.tot.merge(r);
     };
     if (o->precision == FWI_FP32_REFINE) run(float{});
@@ -1120,6 +1245,125 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* c, const fwi_problem* p, const void* fie
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
   });
+}
+
+int fwi_autotune(fwi_ctx* c, const fwi_problem* p, int precision, int B, int reps, fwi_tune_report* rep) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    if (B < 1 || reps < 1 || (precision != FWI_FP64 && precision != FWI_FP32_REFINE))
+      throw Error(FWI_E_INVAL, "bad autotune arguments");
+    ensure_cache(c, p);
+    const ProblemCache& pc = c->pc;
+    const Geo g = make_geo(p);
+    const long n = g.n();
+    const bool dbl = precision == FWI_FP64;
+    const size_t es = dbl ? sizeof(c128) : sizeof(c64);
+    auto plan = [&](Arena& a, int*& rf, char*& x, char*& y, char*& mT, char*& U1, char*& U2) {
+      rf = a.take<int>(B);
+      x = a.take<char>(es * B * n);
+      y = a.take<char>(es * B * n);
+      mT = a.take<char>(es * n);
+      U1 = a.take<char>(es * B * g.u1());
+      U2 = a.take<char>(es * B * std::max(1L, g.u2()));
+    };
+    int* rf;
+    char *x, *y, *mT, *U1, *U2;
+    Arena dry;
+    plan(dry, rf, x, y, mT, U1, U2);
+    Arena ar;
+    bind_workspace(c, ar, dry.used);
+    plan(ar, rf, x, y, mT, U1, U2);
+    hipStream_t st = c->stream;
+    const long nsrc = (long)pc.nf * pc.ne;
+    std::vector<int> hrf(B);
+    for (int b = 0; b < B; ++b) hrf[b] = (int)((b % nsrc) / pc.ne);
+    FWI_HIP(hipMemcpyAsync(rf, hrf.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+    for (int b = 0; b < B; ++b) {
+      const c128* src = pc.P0 + (b % nsrc) * n;
+      if (dbl) launch_copy_c128(n, src, (c128*)x + (long)b * n, st);
+      else launch_cast_64_32(n, src, (c64*)x + (long)b * n, st);
+    }
+    // a contrast-like operand: a copy of the first incident field
+    if (dbl) {
+      launch_copy_c128(n, pc.P0, (c128*)mT, st);
+    } else {
+      launch_cast_64_32(n, pc.P0, (c64*)mT, st);
+    }
+    tl_nfreq = std::min<long>(pc.nf, (B + pc.ne - 1) / pc.ne);
+    tl_active = B;
+    EventProfiler local;
+    local.mask = (1u << (2 * KC_COUNT)) - 1u;
+    LaunchProfiler* saved = tl_prof;
+    double t[KC_COUNT][kNumVariants] = {};
+    for (int v = 0; v < kNumVariants; ++v) {
+      tl_force_variant = v;
+      tl_prof = nullptr;
+      auto run = [&]() {
+        if (dbl)
+          launch_vie<double>(g, c->tw, B, (const c128*)x, nullptr, nullptr, (const c128*)mT, pc.ghat64, rf,
+                             (c128*)U1, (c128*)U2, (c128*)y, nullptr, EPI_VIE, st);
+        else
+          launch_vie<float>(g, c->tw, B, (const c64*)x, nullptr, nullptr, (const c64*)mT, pc.ghat32, rf, (c64*)U1,
+                            (c64*)U2, (c64*)y, nullptr, EPI_VIE, st);
+      };
+      run();  // warm
+      local.reset();
+      tl_prof = &local;
+      for (int r = 0; r < reps; ++r) run();
+      FWI_HIP(hipStreamSynchronize(st));
+      local.flush();
+      const int off = dbl ? KC_COUNT : 0;
+      for (int k = 0; k < KC_COUNT; ++k)
+        t[k][v] = local.cnt[k + off] ? local.tot_ms[k + off] / local.cnt[k + off] : 0.0;
+    }
+    tl_prof = saved;
+    tl_force_variant = -1;
+    // class -> pass kind and length
+    const int kinds[KC_COUNT] = {PK_ROW_FWD, PK_CONV, PK_ROW_INV, PK_STRIDED, PK_STRIDED, -1, -1};
+    const int lens[KC_COUNT] = {g.Lx, g.Lz, g.Lx, g.Ly, g.Ly, 0, 0};
+    double strided_sum[kNumVariants] = {};
+    for (int v = 0; v < kNumVariants; ++v) strided_sum[v] = t[KC_Y_FWD][v] + t[KC_Y_INV][v];
+    for (int k = 0; k < KC_COUNT; ++k) {
+      if (kinds[k] < 0 || k == KC_Y_INV) continue;
+      const double* tv = k == KC_Y_FWD ? strided_sum : t[k];
+      if (tv[0] == 0.0) continue;
+      int best = 0;
+      for (int v = 1; v < kNumVariants; ++v)
+        if (tv[v] < tv[best]) best = v;
+      c->tune.v[kinds[k]][dbl ? 1 : 0][length_index(lens[k])] = (signed char)best;
+    }
+    if (rep) {
+      for (int k = 0; k < 5; ++k) {
+        int best = 0;
+        for (int v = 0; v < kNumVariants; ++v) {
+          rep->variant_ms[k][v] = t[k][v];
+          if (t[k][v] < t[k][best]) best = v;
+        }
+        rep->variant[k] = best;
+        rep->default_variant[k] = kinds[k] >= 0 ? default_variant(kinds[k], dbl, lens[k]) : -1;
+      }
+    }
+    return FWI_OK;
+  });
+}
+
+int fwi_get_tuning(const fwi_ctx* c, signed char* out, int count) {
+  if (!c || !out || count != (int)sizeof(FftTuning::v)) return FWI_E_INVAL;
+  std::memcpy(out, c->tune.v, sizeof(FftTuning::v));
+  return FWI_OK;
+}
+
+int fwi_set_tuning(fwi_ctx* c, const signed char* in, int count) {
+  if (!c) return FWI_E_INVAL;
+  if (!in) {
+    c->tune = FftTuning();
+    return FWI_OK;
+  }
+  if (count != (int)sizeof(FftTuning::v)) return FWI_E_INVAL;
+  std::memcpy(c->tune.v, in, sizeof(FftTuning::v));
+  return FWI_OK;
 }
 
 }  // extern "C"

@@ -115,19 +115,49 @@ __device__ __forceinline__ void dft(cplx<T>* v, int sgn) {
   }
 }
 
+// v[r] *= w1^r for r = 1 .. R-1, with the powers built by a product tree of
+// depth <= 3 from one table value (one load per butterfly instead of R-1).
+template <int R, typename T>
+__device__ __forceinline__ void apply_twiddles(cplx<T>* v, cplx<T> w1) {
+  if constexpr (R >= 2) v[1] = v[1] * w1;
+  if constexpr (R >= 3) {
+    const cplx<T> w2 = w1 * w1;
+    v[2] = v[2] * w2;
+    if constexpr (R >= 4) {
+      const cplx<T> w3 = w2 * w1;
+      v[3] = v[3] * w3;
+      if constexpr (R >= 5) {
+        const cplx<T> w4 = w2 * w2;
+        v[4] = v[4] * w4;
+        if constexpr (R >= 6) v[5] = v[5] * (w4 * w1);
+        if constexpr (R >= 7) v[6] = v[6] * (w4 * w2);
+        if constexpr (R >= 8) v[7] = v[7] * (w4 * w3);
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------- line config ---
 // NL lines of length L per workgroup of NT threads. LF (line-fastest): the
 // butterfly index b maps to (line = b % NL, j = b / NL) and LDS holds point p of
 // a line at p*NL + line (strided passes: neighbouring threads touch
 // neighbouring columns in HBM). Otherwise j is fastest and LDS holds a line
 // contiguously (row passes).
+//
+// LDS padding: one extra element (row passes) or one extra row of NL elements
+// (strided passes) after every 8 points. The first stage of every plan has
+// radix 8 and writes points 8j + r, so without padding the 64 lanes of a wave
+// would land on a few banks; with it they spread over all of them.
 template <typename T_, int L_, int NL_, int NT_, bool LF_>
 struct LineCfg {
   using T = T_;
   static constexpr int L = L_, NL = NL_, NT = NT_;
   static constexpr bool LF = LF_;
-  static constexpr int LDS_ELEMS = NL * L;
-  __device__ static __forceinline__ int lds(int line, int p) { return LF ? p * NL + line : line * L + p; }
+  static constexpr int LP = L + L / 8;  // padded line length (points)
+  static constexpr int LDS_ELEMS = NL * LP;
+  __device__ static __forceinline__ int lds(int line, int p) {
+    return LF ? (p + (p >> 3)) * NL + line : line * LP + p + (p >> 3);
+  }
   template <int R>
   __device__ static __forceinline__ void split(int b, int& line, int& j) {
     if constexpr (LF) {
@@ -167,12 +197,9 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
       C::template split<R>(b, line, j);
       const int k = j % Ns;
       if constexpr (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cplx<T> w = tw[k * r * (L / (Ns * R))];
-          if (sgn > 0) w.y = -w.y;
-          v[t][r] = v[t][r] * w;
-        }
+        cplx<T> w1 = tw[k * (L / (Ns * R))];
+        if (sgn > 0) w1.y = -w1.y;
+        apply_twiddles<R>(v[t], w1);
       }
       dft<R>(v[t], sgn);
       const int base = (j / Ns) * Ns * R + k;
@@ -208,12 +235,10 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
     if (NB % C::NT == 0 || b < NB) {
       int line, j;
       C::template split<R>(b, line, j);
-      const int k = j;  // j < Ns
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[t][r] = v[t][r] * tw[k * r];
+      apply_twiddles<R>(v[t], tw[j]);  // k = j < Ns, twiddle step 1
       dft<R>(v[t], -1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[t][r] = v[t][r] * gh(line, j + r * Ns);
+      for (int r = 0; r < R; ++r) v[t][r] = v[t][r] * gh(t, r, line, j + r * Ns);
       dft<R>(v[t], +1);
 #pragma unroll
       for (int r = 0; r < R; ++r) snk(line, j * R + r, v[t][r]);
@@ -259,6 +284,24 @@ __device__ __forceinline__ void fft_line_transform(const cplx<typename C::T>* __
   constexpr int NsL = ns_before<C::L, dir, S - 1>();
   fft_stage<C, RL, NsL, false>(sgn, tw, [&](int line, int p) { return sh[C::lds(line, p)]; }, snk);
 }
+
+// Points of the convolution middle stage held by this thread: butterfly t,
+// leg r -> (line, p). Used to prefetch the kernel spectrum into registers.
+template <class C>
+struct ConvMidMap {
+  static constexpr int S = plan_stages(C::L);
+  static constexpr int R = stage_radix(C::L, 0, S - 1);
+  static constexpr int NB = C::NL * (C::L / R);
+  static constexpr int TT = (NB + C::NT - 1) / C::NT;
+  __device__ static __forceinline__ bool at(int t, int r, int& line, int& p) {
+    const int b = threadIdx.x + t * C::NT;
+    if (!(NB % C::NT == 0 || b < NB)) return false;
+    int j;
+    C::template split<R>(b, line, j);
+    p = j + r * (C::L / R);
+    return true;
+  }
+};
 
 // Convolution along a line: forward (from src), multiply by gh, inverse (to snk).
 template <class C, class Src, class Gh, class Snk>

@@ -1,33 +1,33 @@
-// FFT passes of the Green's-function convolution (Sec. IV-A): the discrete
-// operator y = x - crop(IFFT(Ghat . FFT(pad(m x)))) of Eq. 5, batched over
-// right-hand sides.
-//
-// 2D (grid [nz][nx], padded [Lz][Lx]):
-//   pass 1  rows   : U1[b][z][:]  = FFT_Lx(pad(m . s_b x_b[z][:]))
-//   pass 2  columns: U1[b][:][kx] = crop(IFFT_Lz(Ghat[f_b][:][kx] . FFT_Lz(pad(U1[b][:][kx]))))   (in place)
-//   pass 3  rows   : y_b[z][:]    = s_b x_b[z][:] - crop(IFFT_Lx(U1[b][z][:]))
-// 3D adds a forward and an inverse pass along y around the z convolution.
-// Every pass reads and writes its data once in HBM; the 1/(Lz Ly Lx) of the
-// inverse transform and k^2 are folded into Ghat.
+// FFT pass kernels of the Green's-function convolution (Sec. IV-A), shared by
+// the complex64 and complex128 translation units. Each pass exists in three
+// tile variants (points per workgroup for row passes, columns per workgroup for
+// strided passes); the variant is picked per (pass, length, precision) from
+// the tuning table that the on-device autotuner fills.
+#pragma once
+
 #include "fft.hpp"
 #include "internal.hpp"
 
 namespace fwi {
 
 constexpr int NT = 256;
+constexpr int kLdsMax = 160 * 1024;
 
-template <typename T>
-__host__ __device__ constexpr int pts_per_wg() {
-  return sizeof(T) == 4 ? 8192 : 4096;
-}
-template <typename T, int L>
+// rows per workgroup of variant v: 2048 / 4096 / 8192 points
+template <typename T, int L, int V>
 __host__ __device__ constexpr int row_nl() {
-  return pts_per_wg<T>() / L > 1 ? pts_per_wg<T>() / L : 1;
+  constexpr int pts = V == 0 ? 2048 : V == 1 ? 4096 : 8192;
+  constexpr int nl0 = pts / L > 1 ? pts / L : 1;
+  // keep the workgroup inside the LDS budget
+  return nl0 * (L + L / 8) * (int)sizeof(cplx<T>) <= kLdsMax - 4096 ? nl0 : (nl0 / 2 > 0 ? nl0 / 2 : 1);
 }
-template <typename T, int L>
+// columns per workgroup of variant v: 4 / 8 / 16 (halved while over budget)
+template <typename T, int L, int V>
 __host__ __device__ constexpr int col_nl() {
-  // power of two, 4..16 lines (coalesced 32..128-byte column segments)
-  return pts_per_wg<T>() / L >= 16 ? 16 : pts_per_wg<T>() / L >= 8 ? 8 : 4;
+  constexpr int nl0 = V == 0 ? 4 : V == 1 ? 8 : 16;
+  constexpr int lp = L + L / 8;
+  return nl0 * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0
+       : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0 / 2 : nl0 / 4;
 }
 
 // ------------------------------------------------------------- row pass 1 ---
@@ -44,9 +44,9 @@ struct RowFwdArgs {
   long in_stride;
 };
 
-template <typename T, int L>
+template <typename T, int L, int NLV>
 __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
-  using C = LineCfg<T, L, row_nl<T, L>(), NT, false>;
+  using C = LineCfg<T, L, NLV, NT, false>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ long s_x[C::NL];
   __shared__ int s_m[C::NL];
@@ -91,9 +91,9 @@ struct RowInvArgs {
   int rows_per_rhs, nout;
 };
 
-template <typename T, int L, int EPI>
+template <typename T, int L, int NLV, int EPI>
 __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
-  using C = LineCfg<T, L, row_nl<T, L>(), NT, false>;
+  using C = LineCfg<T, L, NLV, NT, false>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
@@ -144,9 +144,9 @@ struct StridedArgs {
   int lin, lout;          // nonzero input points, output points kept
 };
 
-template <typename T, int L, int MODE>  // MODE 0 forward, 1 inverse, 2 convolution
+template <typename T, int L, int NLV, int MODE>  // MODE 0 forward, 1 inverse, 2 convolution
 __global__ void __launch_bounds__(NT) k_strided(StridedArgs<T> a) {
-  using C = LineCfg<T, L, col_nl<T, L>(), NT, true>;
+  using C = LineCfg<T, L, NLV, NT, true>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   const long plane = blockIdx.y;
   const int b = (int)(plane / a.planes_per_rhs);
@@ -163,98 +163,94 @@ __global__ void __launch_bounds__(NT) k_strided(StridedArgs<T> a) {
     if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
   };
   if constexpr (MODE == 2) {
+    // prefetch this thread's kernel-spectrum values; the loads complete while
+    // the forward stages run
+    using Map = ConvMidMap<C>;
     const cplx<T>* gp = a.ghat + (long)a.rhs_freq[b] * a.gstride + line0;
-    auto gh = [&](int line, int p) -> cplx<T> { return line < nl ? gp[p * a.pstride + line] : mk((T)0, (T)0); };
+    cplx<T> gpre[Map::TT][Map::R];
+#pragma unroll
+    for (int t = 0; t < Map::TT; ++t)
+#pragma unroll
+      for (int r = 0; r < Map::R; ++r) {
+        int line, p;
+        gpre[t][r] = (Map::at(t, r, line, p) && line < nl) ? gp[p * a.pstride + line] : mk((T)0, (T)0);
+      }
+    auto gh = [&](int t, int r, int, int) -> cplx<T> { return gpre[t][r]; };
     fft_line_convolve<C>(a.tw, sh, src, gh, snk);
   } else {
     fft_line_transform<C, MODE>(a.tw, sh, src, snk);
   }
 }
 
+
 // ---------------------------------------------------------------- dispatch ---
-template <typename T>
-struct Launch {
-  template <int L>
-  static void row_fwd(const RowFwdArgs<T>& a, hipStream_t st) {
-    constexpr int NL = row_nl<T, L>();
-    const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
-    if (grid == 0) return;
-    hipLaunchKernelGGL((k_row_fwd<T, L>), dim3(grid), dim3(NT), 0, st, a);
-    FWI_LAUNCH_CHECK();
+template <typename T, int L, int V>
+void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
+  constexpr int NL = row_nl<T, L, V>();
+  const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
+  if (grid == 0) return;
+  hipLaunchKernelGGL((k_row_fwd<T, L, NL>), dim3(grid), dim3(NT), 0, st, a);
+  FWI_LAUNCH_CHECK();
+}
+template <typename T, int L, int V>
+void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
+  constexpr int NL = row_nl<T, L, V>();
+  const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
+  if (grid == 0) return;
+  if (epi == EPI_VIE) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
+  else if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
+  else hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
+  FWI_LAUNCH_CHECK();
+}
+template <typename T, int L, int V>
+void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
+  constexpr int NL = col_nl<T, L, V>();
+  if (planes == 0) return;
+  if (planes > 65535) throw Error(-6, "too many planes for one strided pass");
+  dim3 grid((a.nlines + NL - 1) / NL, (unsigned)planes);
+  if (mode == 0) hipLaunchKernelGGL((k_strided<T, L, NL, 0>), grid, dim3(NT), 0, st, a);
+  else if (mode == 1) hipLaunchKernelGGL((k_strided<T, L, NL, 1>), grid, dim3(NT), 0, st, a);
+  else hipLaunchKernelGGL((k_strided<T, L, NL, 2>), grid, dim3(NT), 0, st, a);
+  FWI_LAUNCH_CHECK();
+}
+
+#define FWI_VARIANTS(FN, L, v, ...)           \
+  do {                                        \
+    if (v == 0) FN<T, L, 0>(__VA_ARGS__);     \
+    else if (v == 1) FN<T, L, 1>(__VA_ARGS__); \
+    else FN<T, L, 2>(__VA_ARGS__);            \
+  } while (0)
+
+#define FWI_LENGTHS(FN, L, v, ...)                                           \
+  switch (L) {                                                               \
+    case 32: FWI_VARIANTS(FN, 32, v, __VA_ARGS__); break;                    \
+    case 48: FWI_VARIANTS(FN, 48, v, __VA_ARGS__); break;                    \
+    case 64: FWI_VARIANTS(FN, 64, v, __VA_ARGS__); break;                    \
+    case 96: FWI_VARIANTS(FN, 96, v, __VA_ARGS__); break;                    \
+    case 128: FWI_VARIANTS(FN, 128, v, __VA_ARGS__); break;                  \
+    case 192: FWI_VARIANTS(FN, 192, v, __VA_ARGS__); break;                  \
+    case 256: FWI_VARIANTS(FN, 256, v, __VA_ARGS__); break;                  \
+    case 384: FWI_VARIANTS(FN, 384, v, __VA_ARGS__); break;                  \
+    case 512: FWI_VARIANTS(FN, 512, v, __VA_ARGS__); break;                  \
+    case 768: FWI_VARIANTS(FN, 768, v, __VA_ARGS__); break;                  \
+    case 1024: FWI_VARIANTS(FN, 1024, v, __VA_ARGS__); break;                \
+    default: throw Error(-6, "unsupported FFT length " + std::to_string(L)); \
   }
-  template <int L>
-  static void row_inv(const RowInvArgs<T>& a, int epi, hipStream_t st) {
-    constexpr int NL = row_nl<T, L>();
-    const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
-    if (grid == 0) return;
-    if (epi == EPI_VIE) hipLaunchKernelGGL((k_row_inv<T, L, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
-    else if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_row_inv<T, L, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
-    FWI_LAUNCH_CHECK();
-  }
-  template <int L>
-  static void strided(const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
-    constexpr int NL = col_nl<T, L>();
-    if (planes == 0) return;
-    if (planes > 65535) throw Error(-6, "too many planes for one strided pass");
-    dim3 grid((a.nlines + NL - 1) / NL, (unsigned)planes);
-    if (mode == 0) hipLaunchKernelGGL((k_strided<T, L, 0>), grid, dim3(NT), 0, st, a);
-    else if (mode == 1) hipLaunchKernelGGL((k_strided<T, L, 1>), grid, dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_strided<T, L, 2>), grid, dim3(NT), 0, st, a);
-    FWI_LAUNCH_CHECK();
-  }
-};
 
 template <typename T>
-static void strided_call(int L, const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
-  switch (L) {
-    case 32: Launch<T>::template strided<32>(a, planes, mode, st); break;
-    case 48: Launch<T>::template strided<48>(a, planes, mode, st); break;
-    case 64: Launch<T>::template strided<64>(a, planes, mode, st); break;
-    case 96: Launch<T>::template strided<96>(a, planes, mode, st); break;
-    case 128: Launch<T>::template strided<128>(a, planes, mode, st); break;
-    case 192: Launch<T>::template strided<192>(a, planes, mode, st); break;
-    case 256: Launch<T>::template strided<256>(a, planes, mode, st); break;
-    case 384: Launch<T>::template strided<384>(a, planes, mode, st); break;
-    case 512: Launch<T>::template strided<512>(a, planes, mode, st); break;
-    case 768: Launch<T>::template strided<768>(a, planes, mode, st); break;
-    case 1024: Launch<T>::template strided<1024>(a, planes, mode, st); break;
-    default: throw Error(-6, "unsupported FFT length " + std::to_string(L));
-  }
+void strided_call(int L, const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
+  const int v = tune_variant(mode == 2 ? PK_CONV : PK_STRIDED, sizeof(T) == 8, L);
+  FWI_LENGTHS(launch_strided_v, L, v, a, planes, mode, st);
 }
 template <typename T>
-static void row_fwd_call(int L, const RowFwdArgs<T>& a, hipStream_t st) {
-  switch (L) {
-    case 32: Launch<T>::template row_fwd<32>(a, st); break;
-    case 48: Launch<T>::template row_fwd<48>(a, st); break;
-    case 64: Launch<T>::template row_fwd<64>(a, st); break;
-    case 96: Launch<T>::template row_fwd<96>(a, st); break;
-    case 128: Launch<T>::template row_fwd<128>(a, st); break;
-    case 192: Launch<T>::template row_fwd<192>(a, st); break;
-    case 256: Launch<T>::template row_fwd<256>(a, st); break;
-    case 384: Launch<T>::template row_fwd<384>(a, st); break;
-    case 512: Launch<T>::template row_fwd<512>(a, st); break;
-    case 768: Launch<T>::template row_fwd<768>(a, st); break;
-    case 1024: Launch<T>::template row_fwd<1024>(a, st); break;
-    default: throw Error(-6, "unsupported FFT length " + std::to_string(L));
-  }
+void row_fwd_call(int L, const RowFwdArgs<T>& a, hipStream_t st) {
+  const int v = tune_variant(PK_ROW_FWD, sizeof(T) == 8, L);
+  FWI_LENGTHS(launch_row_fwd_v, L, v, a, st);
 }
 template <typename T>
-static void row_inv_call(int L, const RowInvArgs<T>& a, int epi, hipStream_t st) {
-  switch (L) {
-    case 32: Launch<T>::template row_inv<32>(a, epi, st); break;
-    case 48: Launch<T>::template row_inv<48>(a, epi, st); break;
-    case 64: Launch<T>::template row_inv<64>(a, epi, st); break;
-    case 96: Launch<T>::template row_inv<96>(a, epi, st); break;
-    case 128: Launch<T>::template row_inv<128>(a, epi, st); break;
-    case 192: Launch<T>::template row_inv<192>(a, epi, st); break;
-    case 256: Launch<T>::template row_inv<256>(a, epi, st); break;
-    case 384: Launch<T>::template row_inv<384>(a, epi, st); break;
-    case 512: Launch<T>::template row_inv<512>(a, epi, st); break;
-    case 768: Launch<T>::template row_inv<768>(a, epi, st); break;
-    case 1024: Launch<T>::template row_inv<1024>(a, epi, st); break;
-    default: throw Error(-6, "unsupported FFT length " + std::to_string(L));
-  }
+void row_inv_call(int L, const RowInvArgs<T>& a, int epi, hipStream_t st) {
+  const int v = tune_variant(PK_ROW_INV, sizeof(T) == 8, L);
+  FWI_LENGTHS(launch_row_inv_v, L, v, a, epi, st);
 }
 
 template <typename T>
@@ -262,6 +258,11 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
                 const cplx<T>* rhs, int epi, hipStream_t st) {
   const long rows_per_rhs = (long)g.nz * g.ny;
+  const double es = sizeof(cplx<T>);
+  const double act = (double)(active && tl_active > 0 && tl_active < B ? tl_active : B);
+  const double gbytes = (double)(tl_nfreq > 0 ? tl_nfreq : 1) * g.npad() * es;
+  const double n = (double)g.n();
+  const int po = sizeof(T) == 8 ? KC_COUNT : 0;  // FP64 launches are separate classes
   // pass 1: rows along x
   RowFwdArgs<T> f{};
   f.x = x;
@@ -274,7 +275,9 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.rows_per_rhs = (int)rows_per_rhs;
   f.nin = g.nx;
   f.in_stride = g.nx;
+  prof_begin(KC_ROW_FWD + po, st);
   row_fwd_call<T>(g.Lx, f, st);
+  prof_end(KC_ROW_FWD + po, st, act * (n + g.u1()) * es + n * es);
   if (g.dim == 2) {
     // pass 2: columns along z, convolution, in place
     StridedArgs<T> s{};
@@ -290,7 +293,9 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.nlines = g.Lx;
     s.planes_per_rhs = 1;
     s.lin = s.lout = g.nz;
+    prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, s, B, 2, st);
+    prof_end(KC_CONV + po, st, act * 2.0 * g.u1() * es + gbytes);
   } else {
     // forward along y: U1 [b][z][ny][Lx] -> U2 [b][z][Ly][Lx]
     StridedArgs<T> s{};
@@ -305,7 +310,9 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.planes_per_rhs = g.nz;
     s.lin = g.ny;
     s.lout = g.Ly;
+    prof_begin(KC_Y_FWD + po, st);
     strided_call<T>(g.Ly, s, (long)B * g.nz, 0, st);
+    prof_end(KC_Y_FWD + po, st, act * (double)(g.u1() + g.u2()) * es);
     // convolution along z, in place on U2
     StridedArgs<T> c{};
     c.in = U2;
@@ -320,7 +327,9 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     c.nlines = g.Ly * g.Lx;
     c.planes_per_rhs = 1;
     c.lin = c.lout = g.nz;
+    prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, c, B, 2, st);
+    prof_end(KC_CONV + po, st, act * 2.0 * g.u2() * es + gbytes);
     // inverse along y with crop: U2 -> U1
     StridedArgs<T> v{};
     v.in = U2;
@@ -334,7 +343,9 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     v.planes_per_rhs = g.nz;
     v.lin = g.Ly;
     v.lout = g.ny;
+    prof_begin(KC_Y_INV + po, st);
     strided_call<T>(g.Ly, v, (long)B * g.nz, 1, st);
+    prof_end(KC_Y_INV + po, st, act * (double)(g.u1() + g.u2()) * es);
   }
   // last pass: rows along x, inverse, crop, epilogue
   RowInvArgs<T> r{};
@@ -348,9 +359,12 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   r.nrows = rows_per_rhs * B;
   r.rows_per_rhs = (int)rows_per_rhs;
   r.nout = g.nx;
+  prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
+  prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() + (epi == EPI_RESID ? 3.0 : 2.0) * n) * es);
 }
 
+#ifdef FWI_FFT_WITH_FULL
 void launch_fft_full(const Geo& g, const Twiddles& tw, const c128* in, c128* work, c128* out, hipStream_t st) {
   // rows: in -> work (full length, no padding)
   RowFwdArgs<double> f{};
@@ -385,6 +399,8 @@ void launch_fft_full(const Geo& g, const Twiddles& tw, const c128* in, c128* wor
   z.lin = z.lout = g.Lz;
   strided_call<double>(g.Lz, z, 1, 0, st);
 }
+
+#endif
 
 template <typename T>
 void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx<T>* U1, cplx<T>* out,
@@ -429,12 +445,5 @@ void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx
   z.lout = g.Lz;
   strided_call<T>(g.Lz, z, 1, 0, st);
 }
-
-template void launch_vie<double>(const Geo&, const Twiddles&, int, const c128*, const c128*, const int*, const c128*,
-                                 const c128*, const int*, c128*, c128*, c128*, const c128*, int, hipStream_t);
-template void launch_vie<float>(const Geo&, const Twiddles&, int, const c64*, const c64*, const int*, const c64*,
-                                const c64*, const int*, c64*, c64*, c64*, const c64*, int, hipStream_t);
-template void launch_fft_padded<double>(const Geo&, const Twiddles&, const c128*, c128*, c128*, hipStream_t);
-template void launch_fft_padded<float>(const Geo&, const Twiddles&, const c64*, c64*, c64*, hipStream_t);
 
 }  // namespace fwi

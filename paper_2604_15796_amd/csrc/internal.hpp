@@ -28,10 +28,46 @@ struct Error : std::runtime_error {
 
 #define FWI_LAUNCH_CHECK() FWI_HIP(hipGetLastError())
 
+// Kernel classes that can be timed with HIP events (fwi_profile).
+enum KernelClass { KC_ROW_FWD = 0, KC_CONV, KC_ROW_INV, KC_Y_FWD, KC_Y_INV, KC_DOTS, KC_ORTH, KC_COUNT };
+// Per-thread hooks set by the entry points: launch sites report each launch of
+// a class with its algorithmic HBM bytes; active-RHS and frequency-count hints
+// let them compute those bytes for masked batches.
+struct LaunchProfiler {
+  virtual void begin(int cls, hipStream_t st) = 0;
+  virtual void end(int cls, hipStream_t st, double bytes) = 0;
+  virtual ~LaunchProfiler() = default;
+};
+extern thread_local LaunchProfiler* tl_prof;
+extern thread_local long tl_active;  // RHS that the next launches actually process
+extern thread_local int tl_nfreq;    // distinct frequencies in the batch (Ghat reads)
+inline void prof_begin(int cls, hipStream_t st) {
+  if (tl_prof) tl_prof->begin(cls, st);
+}
+inline void prof_end(int cls, hipStream_t st, double bytes) {
+  if (tl_prof) tl_prof->end(cls, st, bytes);
+}
+
 // Supported FFT lengths (padded axis sizes): 2^a 3^b from 32 to 1024.
 constexpr int kNumLengths = 11;
 constexpr int kLengths[kNumLengths] = {32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
 int length_index(int L);          // -1 if unsupported
+
+// Tile variants of the FFT passes, chosen per (pass, precision, length).
+enum PassKind { PK_ROW_FWD = 0, PK_ROW_INV, PK_CONV, PK_STRIDED, PK_COUNT };
+constexpr int kNumVariants = 3;
+struct FftTuning {
+  signed char v[PK_COUNT][2][kNumLengths];  // -1: built-in default
+  FftTuning() {
+    for (auto& a : v)
+      for (auto& b : a)
+        for (auto& c : b) c = -1;
+  }
+};
+extern thread_local const FftTuning* tl_tune;
+extern thread_local int tl_force_variant;  // >= 0: every pass uses this variant
+int default_variant(int pass, bool dbl, int L);
+int tune_variant(int pass, bool dbl, int L);
 int padded_length(int n);         // smallest supported L >= 2n, 0 if none
 
 // Twiddle tables tw[m] = exp(-2 pi i m / L) for every supported L.

@@ -372,12 +372,19 @@ void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st) 
 template <typename T>
 void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st) {
   const long vs = s.vstride();
+  const double act = (double)(tl_active > 0 && tl_active < s.B ? tl_active : s.B);
+  const double vb = (double)s.n * sizeof(cplx<T>);
+  const int po = sizeof(T) == 8 ? KC_COUNT : 0;
+  prof_begin(KC_DOTS + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
                                           s.chunk, s.active, s.dotp, s.nblk));
   FWI_LAUNCH_CHECK();
+  prof_end(KC_DOTS + po, st, act * (j + 2) * vb);
+  prof_begin(KC_ORTH + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
                                           s.chunk, s.active, s.dotp, s.nblk, s.H, s.nrmp));
   FWI_LAUNCH_CHECK();
+  prof_end(KC_ORTH + po, st, act * (j + 3) * vb);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
                                           s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters, s.scal,
                                           s.counters));

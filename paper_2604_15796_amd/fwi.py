@@ -108,6 +108,11 @@ def lib():
         "fwi_jacobian_apply": (ip, [vp, pp, vp, vp, vp]),
         "fwi_jacobian_adjoint_apply": (ip, [vp, pp, vp, vp, vp]),
         "fwi_host_bessel01": (None, [C.c_double, dp]),
+        "fwi_profile": (ip, [vp, C.c_uint]),
+        "fwi_profile_read": (ip, [vp, ip, dp, C.POINTER(C.c_longlong), dp]),
+        "fwi_autotune": (ip, [vp, pp, ip, ip, ip, C.POINTER(CTuneReport)]),
+        "fwi_get_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
+        "fwi_set_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -121,7 +126,18 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_validate_problem", "fwi_padded_length", "fwi_workspace_size", "fwi_set_workspace",
             "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_tv_admm_step",
             "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
-            "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01"]
+            "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
+            "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning"]
+TUNING_BYTES = 4 * 2 * 11
+PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
+
+_BASE_CLASSES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv", "dots", "orth"]
+# class k: complex64 launches; class k + 7: complex128 launches
+KERNEL_CLASSES = [f"{c}_c64" for c in _BASE_CLASSES] + [f"{c}_c128" for c in _BASE_CLASSES]
+
+
+class CTuneReport(C.Structure):
+    _fields_ = [("variant_ms", (C.c_double * 3) * 5), ("variant", C.c_int * 5), ("default_variant", C.c_int * 5)]
 
 
 # ---------------------------------------------------------------- structs ---
@@ -312,6 +328,49 @@ class Context:
                                      _ptr(d_obs), C.byref(o), C.byref(rep), C.byref(st))
         self._check(rc, allow_noconv)
         return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
+
+    def profile(self, classes):
+        """Start HIP-event timing of the named kernel classes (empty: stop)."""
+        mask = 0
+        for name in classes:
+            mask |= 1 << KERNEL_CLASSES.index(name)
+        self._check(self.L.fwi_profile(self.h, mask))
+
+    def profile_read(self):
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            t, n, b = C.c_double(), C.c_longlong(), C.c_double()
+            self._check(self.L.fwi_profile_read(self.h, k, C.byref(t), C.byref(n), C.byref(b)))
+            if n.value:
+                out[name] = {"ms": t.value, "launches": n.value, "bytes": b.value}
+        return out
+
+    def autotune(self, prob, precision=FWI_FP32_REFINE, B=64, reps=3):
+        """Time every tile variant of every FFT pass for this grid on the device and
+        keep the fastest in the context. Returns {pass: {"ms": [..3], "chosen", "default"}}."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        rep = CTuneReport()
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_autotune(self.h, prob.ref(), precision, B, reps, C.byref(rep)))
+        out = {}
+        for k, name in enumerate(PASS_NAMES):
+            ms = [rep.variant_ms[k][v] for v in range(3)]
+            if any(ms):
+                out[name] = {"ms": ms, "chosen": rep.variant[k], "default": rep.default_variant[k]}
+        return out
+
+    def get_tuning(self):
+        buf = (C.c_byte * TUNING_BYTES)()
+        self._check(self.L.fwi_get_tuning(self.h, buf, TUNING_BYTES))
+        return bytes(bytearray(buf))
+
+    def set_tuning(self, table=None):
+        if table is None:
+            self._check(self.L.fwi_set_tuning(self.h, None, 0))
+            return
+        buf = (C.c_byte * TUNING_BYTES).from_buffer_copy(bytes(table))
+        self._check(self.L.fwi_set_tuning(self.h, buf, TUNING_BYTES))
 
     # ---------------------------------------------------- building blocks ---
     def apply_operator(self, prob, m, freq_index, x, precision=FWI_FP64):

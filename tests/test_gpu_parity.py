@@ -140,6 +140,31 @@ def test_operator_3d_vs_oracle(ctx, shape):
             assert relerr(y[b], ref) < (2e-6 if prec else 1e-13)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_operator_every_tile_variant_and_autotune(ctx, F, dim):
+    """Each tile variant of each pass gives the same operator; the autotuner's
+    choice is then used and still matches the oracle."""
+    p = W.small2d(seed=31, nx=40, nz=36, nf=1) if dim == 2 else W.small3d(seed=32, nx=16, ny=12, nz=10)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    x = W.random_complex(10, (3,) + p.shape)
+    Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), p.dim, p.nx, p.ny, p.nz, p.dx)
+    ref = np.stack([O.vie_apply(Gh, m, x[b]).ravel() for b in range(3)])
+    for v in range(3):
+        ctx.set_tuning(bytes([v] * F.TUNING_BYTES))
+        for prec in (0, 1):
+            dt = torch.complex64 if prec else torch.complex128
+            y = host(ctx.apply_operator(p, dev(m), [0, 0, 0], dev(x.reshape(3, -1), dt), precision=prec))
+            assert relerr(y, ref) < (2e-6 if prec else 1e-13), (v, prec)
+    ctx.set_tuning(None)
+    for prec in (0, 1):
+        rep = ctx.autotune(p, prec, B=3, reps=2)
+        assert "conv" in rep and all(0 <= r["chosen"] < 3 for r in rep.values())
+        dt = torch.complex64 if prec else torch.complex128
+        y = host(ctx.apply_operator(p, dev(m), [0, 0, 0], dev(x.reshape(3, -1), dt), precision=prec))
+        assert relerr(y, ref) < (2e-6 if prec else 1e-13)
+    ctx.set_tuning(None)
+
+
 # --------------------------------------------------------------- solves ---
 
 @pytest.mark.parametrize("prec", [0, 1])
