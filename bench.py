@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--restart", type=int, default=16)
     ap.add_argument("--check-every", type=int, default=1)
@@ -121,7 +121,8 @@ def main():
     ctx.profile([])
     dominant = max(prof_all, key=lambda k: prof_all[k]["ms"])
     log("per-class event time in one step: " +
-        ", ".join(f"{k} {v['ms']:.1f} ms/{v['launches']}" for k, v in prof_all.items()))
+        ", ".join(f"{k} {v['ms']:.2f} ms/{v['launches']} ({v['bytes'] / v['ms'] / 1e6:.0f} GB/s)"
+                  for k, v in prof_all.items()))
 
     # timed region: only the dominant class carries events
     ctx.profile([dominant])

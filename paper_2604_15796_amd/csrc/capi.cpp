@@ -406,7 +406,7 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.bnorm = a.take<double>(B);
   k.target = a.take<double>(B);
   k.rscale = a.take<double>(B);
-  k.scal = a.take<cplx<T>>(B);
+  k.vscale = a.take<cplx<T>>((size_t)(JM + 1) * B);
   k.active = a.take<int>(B);
   k.ncol = a.take<int>(B);
   k.iters = a.take<int>(B);
@@ -487,8 +487,8 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     }
     krylov_start_basis(ks, r, st);
     for (int j = 0; j < ks.JM; ++j) {
-      launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, nullptr, ks.active, mT, ghatT, rhs_freq, s.U1, s.U2,
-                    ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
+      launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, ghatT, rhs_freq,
+                    s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
       krylov_arnoldi(ks, j, st);
       ++total;
       if ((j + 1) % o.check_every == 0 || j + 1 == ks.JM || total >= o.max_iter) {

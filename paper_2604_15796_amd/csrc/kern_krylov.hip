@@ -16,7 +16,8 @@ int krylov_nblk(long n) {
 // dotp[b][blk][i] = sum over the block's chunk of conj(V_i) . V_{j+1}, i <= j
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
-                                             const int* __restrict__ active, c128* __restrict__ dotp, int nblk) {
+                                             const int* __restrict__ active, const cplx<T>* __restrict__ vscale,
+                                             int B, c128* __restrict__ dotp, int nblk) {
   const int b = blockIdx.y;
   if (!active[b]) return;
   const long off = (long)b * n;
@@ -26,16 +27,29 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
   for (int i = 0; i <= JM; ++i) ar[i] = ai[i] = 0.0;
   const long e0 = (long)blockIdx.x * chunk;
   const long e1 = min(n, e0 + chunk);
-  for (long e = e0 + threadIdx.x; e < e1; e += KT) {
-    const cplx<T> w = W[e];
-    const double wx = w.x, wy = w.y;
+  // UNR elements per thread per trip: UNR independent loads of every vector in flight
+  constexpr int UNR = 4;
+  for (long eb = e0 + threadIdx.x; eb < e1; eb += UNR * KT) {
+    double wx[UNR], wy[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long e = eb + u * KT;
+      const cplx<T> w = e < e1 ? W[e] : mk((T)0, (T)0);
+      wx[u] = w.x;
+      wy[u] = w.y;
+    }
 #pragma unroll
     for (int i = 0; i <= JM; ++i) {
       if (i <= j) {
-        const cplx<T> v = V[(long)i * vs + off + e];
-        const double vx = v.x, vy = v.y;
-        ar[i] += vx * wx + vy * wy;
-        ai[i] += vx * wy - vy * wx;
+        const cplx<T>* Vi = V + (long)i * vs + off;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const long e = eb + u * KT;
+          const cplx<T> v = e < e1 ? Vi[e] : mk((T)0, (T)0);
+          const double vx = v.x, vy = v.y;
+          ar[i] += vx * wx[u] + vy * wy[u];
+          ai[i] += vx * wy[u] - vy * wx[u];
+        }
       }
     }
   }
@@ -44,7 +58,8 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
 #pragma unroll
   for (int i = 0; i <= JM; ++i) {
     if (i <= j) {
-      const double r = wave_sum(ar[i]), m = wave_sum(ai[i]);
+      const double sc = (double)vscale[(long)i * B + b].x;  // stored V_i = basis vector / sc
+      const double r = sc * wave_sum(ar[i]), m = sc * wave_sum(ai[i]);
       if (lane == 0) {
         red[0][i][wv] = r;
         red[1][i][wv] = m;
@@ -68,8 +83,9 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
 // nrmp[b][blk] = |V_{j+1}|^2 over the chunk; block 0 stores the H column.
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
-                                             const int* __restrict__ active, const c128* __restrict__ dotp, int nblk,
-                                             c128* __restrict__ H, double* __restrict__ nrmp) {
+                                             const int* __restrict__ active, const cplx<T>* __restrict__ vscale,
+                                             int B, const c128* __restrict__ dotp, int nblk, c128* __restrict__ H,
+                                             double* __restrict__ nrmp) {
   const int b = blockIdx.y;
   if (!active[b]) return;
   __shared__ double hr[JM + 1], hi[JM + 1];
@@ -82,9 +98,11 @@ __global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, i
       r += d.x;
       m += d.y;
     }
-    hr[t] = r;
-    hi[t] = m;
     if (blockIdx.x == 0) H[((long)b * (JM + 1) + t) * JM + j] = mk(r, m);
+    // the update uses the stored (unnormalised) vectors: fold their scale in
+    const double sc = (double)vscale[(long)t * B + b].x;
+    hr[t] = r * sc;
+    hi[t] = m * sc;
   }
   __syncthreads();
   const long off = (long)b * n;
@@ -92,21 +110,40 @@ __global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, i
   const long e0 = (long)blockIdx.x * chunk;
   const long e1 = min(n, e0 + chunk);
   double acc = 0.0;
-  for (long e = e0 + t; e < e1; e += KT) {
-    const cplx<T> w = W[e];
-    double wx = w.x, wy = w.y;
+  constexpr int UNR = 4;
+  for (long eb = e0 + t; eb < e1; eb += UNR * KT) {
+    double wx[UNR], wy[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long e = eb + u * KT;
+      const cplx<T> w = e < e1 ? W[e] : mk((T)0, (T)0);
+      wx[u] = w.x;
+      wy[u] = w.y;
+    }
 #pragma unroll
     for (int i = 0; i <= JM; ++i) {
       if (i <= j) {
-        const cplx<T> v = V[(long)i * vs + off + e];
-        const double vx = v.x, vy = v.y;
-        wx -= hr[i] * vx - hi[i] * vy;
-        wy -= hr[i] * vy + hi[i] * vx;
+        const cplx<T>* Vi = V + (long)i * vs + off;
+        const double a = hr[i], bb = hi[i];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const long e = eb + u * KT;
+          const cplx<T> v = e < e1 ? Vi[e] : mk((T)0, (T)0);
+          const double vx = v.x, vy = v.y;
+          wx[u] -= a * vx - bb * vy;
+          wy[u] -= a * vy + bb * vx;
+        }
       }
     }
-    const cplx<T> o = mk((T)wx, (T)wy);
-    W[e] = o;
-    acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const long e = eb + u * KT;
+      if (e < e1) {
+        const cplx<T> o = mk((T)wx[u], (T)wy[u]);
+        W[e] = o;
+        acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+      }
+    }
   }
   const double s = block_sum<KT>(acc, red);
   if (t == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
@@ -119,7 +156,7 @@ __global__ void __launch_bounds__(1024) k_givens(int j, int B, int nblk, int* __
                                                  const double* __restrict__ nrmp, c128* __restrict__ H,
                                                  double* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ gv,
                                                  const double* __restrict__ target, int* __restrict__ ncol,
-                                                 int* __restrict__ iters, cplx<T>* __restrict__ scal,
+                                                 int* __restrict__ iters, cplx<T>* __restrict__ vscale_next,
                                                  int* __restrict__ counters) {
   __shared__ double red[1024 / 64];
   double cnt = 0.0;
@@ -162,25 +199,12 @@ __global__ void __launch_bounds__(1024) k_givens(int j, int B, int nblk, int* __
     if (res <= target[b] || !(hn > 1e-300) || nu == 0.0) {
       active[b] = 0;
     } else {
-      scal[b] = mk((T)(1.0 / hn), (T)0);
+      vscale_next[b] = mk((T)(1.0 / hn), (T)0);
       cnt += 1.0;
     }
   }
   const double tot = block_sum<1024>(cnt, red);
   if (threadIdx.x == 0) counters[0] = (int)tot;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(KT) k_scale_basis(cplx<T>* __restrict__ W, long n, const int* __restrict__ active,
-                                                    const cplx<T>* __restrict__ scal) {
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  const T s = scal[b].x;
-  cplx<T>* w = W + (long)b * n;
-  for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
-    const cplx<T> v = w[e];
-    w[e] = mk(v.x * s, v.y * s);
-  }
 }
 
 // |x_b|^2 partial sums of an FP64 array [B][n]
@@ -248,9 +272,11 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
 // V0_b = (T)(r_b / |r_b|)
 template <typename T>
 __global__ void __launch_bounds__(KT) k_start_basis(const c128* __restrict__ r, cplx<T>* __restrict__ V0, long n,
-                                                    const int* __restrict__ active, const double* __restrict__ rscale) {
+                                                    const int* __restrict__ active, const double* __restrict__ rscale,
+                                                    cplx<T>* __restrict__ vscale0) {
   const int b = blockIdx.y;
   if (!active[b]) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) vscale0[b] = mk((T)1, (T)0);
   const double s = rscale[b];
   const c128* rb = r + (long)b * n;
   cplx<T>* vb = V0 + (long)b * n;
@@ -282,15 +308,17 @@ __global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __r
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, long vs, long n,
                                                 const int* __restrict__ ncol, const c128* __restrict__ y,
-                                                const double* __restrict__ rnorm, c128* __restrict__ x) {
+                                                const double* __restrict__ rnorm, const cplx<T>* __restrict__ vscale,
+                                                int B, c128* __restrict__ x) {
   const int b = blockIdx.y;
   const int k = ncol[b];
   if (k == 0) return;
   __shared__ double yr[JM], yi[JM];
   if (threadIdx.x < k) {
     const c128 v = y[(long)b * JM + threadIdx.x];
-    yr[threadIdx.x] = rnorm[b] * v.x;
-    yi[threadIdx.x] = rnorm[b] * v.y;
+    const double sc = rnorm[b] * (double)vscale[(long)threadIdx.x * B + b].x;
+    yr[threadIdx.x] = sc * v.x;
+    yi[threadIdx.x] = sc * v.y;
   }
   __syncthreads();
   const long off = (long)b * n;
@@ -365,7 +393,8 @@ void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double i
 
 template <typename T>
 void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st) {
-  hipLaunchKernelGGL((k_start_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, r, s.V, s.n, s.active, s.rscale);
+  hipLaunchKernelGGL((k_start_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, r, s.V, s.n, s.active, s.rscale,
+                     s.vscale);
   FWI_LAUNCH_CHECK();
 }
 
@@ -377,20 +406,17 @@ void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st) {
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;
   prof_begin(KC_DOTS + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                          s.chunk, s.active, s.dotp, s.nblk));
+                                          s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
   FWI_LAUNCH_CHECK();
   prof_end(KC_DOTS + po, st, act * (j + 2) * vb);
   prof_begin(KC_ORTH + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                          s.chunk, s.active, s.dotp, s.nblk, s.H, s.nrmp));
+                                          s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk, s.H, s.nrmp));
   FWI_LAUNCH_CHECK();
   prof_end(KC_ORTH + po, st, act * (j + 3) * vb);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
-                                          s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters, s.scal,
-                                          s.counters));
-  FWI_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_scale_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V + (long)(j + 1) * vs, s.n,
-                     s.active, s.scal);
+                                          s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters,
+                                          s.vscale + (long)(j + 1) * s.B, s.counters));
   FWI_LAUNCH_CHECK();
 }
 
@@ -400,7 +426,7 @@ void krylov_finish_cycle(const KrylovState<T>& s, c128* x, hipStream_t st) {
                                           s.H, s.gv, s.y));
   FWI_LAUNCH_CHECK();
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_xupdate<T, JMC>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V,
-                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, x));
+                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, s.vscale, s.B, x));
   FWI_LAUNCH_CHECK();
 }
 

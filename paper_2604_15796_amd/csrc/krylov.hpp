@@ -26,7 +26,7 @@ struct KrylovState {
   double* bnorm = nullptr;     // [B]
   double* target = nullptr;    // [B] relative stopping target of the cycle
   double* rscale = nullptr;    // [B] 1/rnorm
-  cplx<T>* scal = nullptr;     // [B] normalisation of the newest basis vector
+  cplx<T>* vscale = nullptr;   // [JM+1][B] basis vector i of RHS b = vscale * stored V_i
   int* active = nullptr;       // [B]
   int* ncol = nullptr;         // [B]
   int* iters = nullptr;        // [B] accumulated iterations

@@ -1,0 +1,241 @@
+"""Full-size GPU checks at every workload configuration.
+
+Sampled outputs the oracle computes one by one (fields of chosen transmits),
+plus properties that hold at any size: reciprocity of the data, equality of
+the adjoint-solve gradient with the product-formula J^H r, directional and
+per-pixel central differences of the misfit, and the mixed-precision form
+against the plain FP64 solve (bars: fields 1e-5, gradients 1e-4).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fwi_oracle as O
+from paper_2604_15796_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2604_15796_amd import fwi
+    return fwi
+
+
+@pytest.fixture(scope="module")
+def ctx(F):
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def t(x, dtype=None):
+    x = torch.as_tensor(np.ascontiguousarray(x)).to(DEV)
+    return x if dtype is None else x.to(dtype)
+
+
+def rel(a, b, floor=0.0):
+    """Relative error; `floor` bounds the denominator from below (for a
+    reference that can be exactly zero, e.g. a fully shrunk TV variable)."""
+    a = a.detach().cpu().numpy() if torch.is_tensor(a) else np.asarray(a)
+    b = b.detach().cpu().numpy() if torch.is_tensor(b) else np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), floor, 1e-300))
+
+
+def mixed(F, **kw):
+    o = dict(precision=F.FWI_FP32_REFINE, rtol=1e-6, restart=16, inner_rtol=1e-3)
+    o.update(kw)
+    return F.SolveOptions(**o)
+
+
+def plain(F, **kw):
+    o = dict(precision=F.FWI_FP64, rtol=1e-12, restart=32)
+    o.update(kw)
+    return F.SolveOptions(**o)
+
+
+def oracle_fields(p, m, pairs):
+    """Oracle fields of (frequency index, transmit) pairs, solved one by one."""
+    cen = O.cell_centres(p.dim, p.nx, p.ny, p.nz, p.dx)
+    out = []
+    for l, i in pairs:
+        k = O.wavenumber(p.freqs[l], p.c0)
+        P0 = O.incident_fields(k, cen, p.elems[i:i + 1], p.dim)
+        out.append(O.solve(k, m, P0, p.dim, p.nx, p.ny, p.nz, p.dx)[0])
+    return out
+
+
+# ---------------------------------------------------------------- config 0 ---
+
+def test_cfg0_plain_fp64_gradient_vs_oracle(ctx, F):
+    p = W.config0()
+    d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    phi, gm, gc, ga, st = ctx.adjoint_gradient(p, t(p.c), t(p.alpha), t(d_obs), plain(F))
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs,
+                                               p.elems)
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert rel(gm, rg) < 1e-9 and rel(gc, rgc) < 1e-9 and rel(ga, rga) < 1e-9
+    assert st["solves"] == 32 and st["unconverged"] == 0
+
+
+# ---------------------------------------------------------------- config 1 ---
+
+@pytest.fixture(scope="module")
+def cfg1(ctx, F):
+    p = W.config1()
+    ctx.autotune(p, F.FWI_FP32_REFINE, B=p.nf * p.ne, reps=2)
+    ctx.autotune(p, F.FWI_FP64, B=p.nf * p.ne, reps=1)
+    c, a = t(p.c), t(p.alpha)
+    d_obs, _ = ctx.forward(p, t(p.extra["c_obs"]), a, plain(F))
+    return p, c, a, d_obs
+
+
+def test_cfg1_fields_sampled_vs_oracle(ctx, F, cfg1):
+    p, c, a, _ = cfg1
+    _, fields, st = ctx.forward(p, c, a, mixed(F), fields=True)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    pairs = [(0, 0), (3, 31), (7, 63)]
+    for (l, i), ref in zip(pairs, oracle_fields(p, m, pairs)):
+        assert rel(fields[l, i], ref) < 1e-5, (l, i)
+    assert st["unconverged"] == 0
+
+
+def test_cfg1_gradient_mixed_vs_fp64_and_properties(ctx, F, cfg1):
+    p, c, a, d_obs = cfg1
+    phi32, g32, _, _, _ = ctx.adjoint_gradient(p, c, a, d_obs, mixed(F))
+    phi64, g64, _, _, _ = ctx.adjoint_gradient(p, c, a, d_obs, plain(F))
+    assert rel(g32, g64) < 1e-4
+    assert abs(phi32 - phi64) < 1e-4 * phi64
+    # the adjoint-solve gradient equals J^H r from the product formula (Eq. 17)
+    data, fields, _ = ctx.forward(p, c, a, plain(F), fields=True)
+    jhr = ctx.jacobian_adjoint_apply(p, fields, data - d_obs)
+    assert rel(g64, jhr) < 1e-8
+    # reciprocity of the data
+    assert rel(data, data.transpose(1, 2)) < 1e-9
+
+
+def test_cfg1_directional_derivative(ctx, F, cfg1):
+    """(phi(m + h dm) - phi(m - h dm)) / 2h = Re <g, dm> (FP64, full size)."""
+    p, c, a, d_obs = cfg1
+    m = t(O.contrast(p.c, p.alpha, p.c0))
+    dm = t(W.random_complex(12, p.shape, 1e-3))
+    g, _ = ctx.vjp(p, m, ctx.forward_m(p, m, plain(F))[0] - d_obs, plain(F))
+    h = 1e-3
+    fp = 0.5 * float(torch.sum(torch.abs(ctx.forward_m(p, m + h * dm, plain(F))[0] - d_obs) ** 2))
+    fm = 0.5 * float(torch.sum(torch.abs(ctx.forward_m(p, m - h * dm, plain(F))[0] - d_obs) ** 2))
+    fd = (fp - fm) / (2 * h)
+    an = float(torch.real(torch.sum(torch.conj(g) * dm.reshape(-1))))
+    assert abs(fd - an) < 1e-5 * abs(an)
+
+
+# ---------------------------------------------------------------- config 3 ---
+
+@pytest.fixture(scope="module")
+def cfg3(ctx, F):
+    p = W.config3()
+    ctx.autotune(p, F.FWI_FP64, B=4 * p.ne, reps=1)
+    ctx.autotune(p, F.FWI_FP32_REFINE, B=4 * p.ne, reps=1)
+    a = t(p.alpha)
+    d_obs, _ = ctx.forward(p, t(p.c), a, plain(F, max_rhs=4 * p.ne, rtol=1e-13))
+    return p, d_obs
+
+
+def test_cfg3_gradient_central_differences_20_pixels(ctx, F, cfg3):
+    """Gradient w.r.t. m at an intermediate model checked by central
+    differences of the misfit at 20 seeded random pixels (full size, FP64)."""
+    p, d_obs = cfg3
+    o = plain(F, max_rhs=4 * p.ne, rtol=1e-13)
+    m_true = O.contrast(p.c, p.alpha, p.c0)
+    m0 = t(0.5 * m_true)
+    data0 = ctx.forward_m(p, m0, o)[0]
+    g, _ = ctx.vjp(p, m0, data0 - d_obs, o)
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(3)
+    inside = np.flatnonzero(np.abs(m_true.ravel()) > 0)
+    idx = np.concatenate([rng.choice(inside, 10, replace=False), rng.choice(p.n, 10, replace=False)])
+    h = 1e-6
+    gmax = np.abs(g).max()
+    for k in idx:
+        for unit, part in ((1.0, np.real), (1j, np.imag)):
+            e = torch.zeros(p.n, dtype=torch.complex128, device=DEV)
+            e[k] = unit * h
+            e = e.reshape(p.shape)
+            fp = 0.5 * float(torch.sum(torch.abs(ctx.forward_m(p, m0 + e, o)[0] - d_obs) ** 2))
+            fm = 0.5 * float(torch.sum(torch.abs(ctx.forward_m(p, m0 - e, o)[0] - d_obs) ** 2))
+            assert abs((fp - fm) / (2 * h) - part(g[k])) < 1e-4 * gmax, (k, unit)
+
+
+def test_cfg3_admm_step_full_grid_subset_vs_oracle(ctx, F):
+    """One ADMM step at the full 384^2 grid on a frequency/element subset
+    (2 frequencies x 8 elements) against the oracle."""
+    p = W.config3()
+    sub = W.Problem("cfg3_subset", 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs[[0, 6]], p.elems[::16], p.c, p.alpha)
+    d_obs, _, _ = O.forward(p.c, p.alpha, 2, sub.nx, 1, sub.nz, sub.dx, sub.c0, sub.freqs, sub.elems)
+    m0 = np.zeros(sub.shape, complex)
+    g0 = O.tv_grad(m0)
+    u0 = np.zeros_like(g0)
+    s = 1.0 / float(np.sum(np.abs(d_obs) ** 2))
+    ex = p.extra
+    rm, rg, ru, rep = O.admm_step(m0, g0, u0, m0, d_obs, 2, sub.nx, 1, sub.nz, sub.dx, sub.c0, sub.freqs,
+                                  sub.elems, ex["lam"], ex["rho"], ex["gamma"], ex["n_cg"], data_scale=s)
+    mt, gt, ut = t(m0), t(g0), t(u0)
+    grep, _ = ctx.tv_admm_step(sub, mt, gt, ut, t(d_obs), ex["lam"], ex["rho"], ex["gamma"], ex["n_cg"],
+                               m_ref=t(m0), data_scale=s, opts=plain(F))
+    # lambda/rho = 0.1 exceeds every |grad m| after one step, so g is exactly 0
+    scale = float(np.linalg.norm(O.tv_grad(rm)))
+    assert rel(mt, rm) < 1e-8 and rel(gt, rg, floor=scale) < 1e-8 and rel(ut, ru, floor=scale) < 1e-8
+    assert abs(grep["misfit"] - rep["misfit"]) < 1e-9 * rep["misfit"]
+
+
+def test_cfg3_five_admm_iterations_mixed(ctx, F, cfg3):
+    """Algorithm 1 for five iterations at full size in the mixed-precision form:
+    finite iterates and a decreasing data misfit."""
+    p, d_obs = cfg3
+    ex = p.extra
+    m = torch.zeros(p.shape, dtype=torch.complex128, device=DEV)
+    g = torch.zeros((2,) + p.shape, dtype=torch.complex128, device=DEV)
+    u = torch.zeros_like(g)
+    mref = torch.zeros_like(m)
+    misfits = []
+    for k in range(ex["admm_steps"]):
+        rep, st = ctx.tv_admm_step(p, m, g, u, d_obs, ex["lam"], ex["rho"], ex["gamma"], ex["n_cg"], m_ref=mref,
+                                   opts=mixed(F, max_rhs=4 * p.ne))
+        misfits.append(rep["misfit"])
+        assert np.isfinite(rep["tv"]) and np.isfinite(rep["dm_norm"])
+        assert st["unconverged"] == 0
+    assert bool(torch.isfinite(torch.view_as_real(m)).all())
+    assert misfits[-1] < misfits[0], misfits
+
+
+# ---------------------------------------------------------------- config 4 ---
+
+@pytest.fixture(scope="module")
+def cfg4(ctx, F):
+    p = W.config4()
+    ctx.autotune(p, F.FWI_FP32_REFINE, B=p.ne, reps=1)
+    ctx.autotune(p, F.FWI_FP64, B=p.ne, reps=1)
+    return p
+
+
+def test_cfg4_3d_fields_sampled_vs_oracle(ctx, F, cfg4):
+    p = cfg4
+    _, fields, st = ctx.forward(p, t(p.c), t(p.alpha), mixed(F, max_rhs=p.ne), fields=True)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    pairs = [(0, 20)]
+    for (l, i), ref in zip(pairs, oracle_fields(p, m, pairs)):
+        assert rel(fields[l, i], ref) < 1e-5
+    assert st["unconverged"] == 0
+
+
+def test_cfg4_3d_gradient_recompute_mixed_vs_fp64(ctx, F, cfg4):
+    """Per-frequency streaming (fields recomputed per frequency, never all
+    stored): mixed-precision gradient against the FP64 one."""
+    p = cfg4
+    c, a = t(p.c), t(p.alpha)
+    d_obs, _ = ctx.forward(p, t(p.extra["c_obs"]), a, plain(F, max_rhs=p.ne))
+    phi32, g32, _, _, st = ctx.adjoint_gradient(p, c, a, d_obs, mixed(F, max_rhs=p.ne))
+    phi64, g64, _, _, _ = ctx.adjoint_gradient(p, c, a, d_obs, plain(F, max_rhs=p.ne, rtol=1e-10))
+    assert rel(g32, g64) < 1e-4
+    assert abs(phi32 - phi64) < 1e-4 * phi64
+    assert st["solves"] == 2 * p.nf * p.ne
