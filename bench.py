@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile variants")
     ap.add_argument("--cpu-solves", type=int, default=6, help="oracle forward solves in the CPU sample")
+    ap.add_argument("--workload", default="gradient-256", choices=["gradient-256", "uneven-batch"],
+                    help="gradient-256: the headline workload; uneven-batch: 32 instances of different grids, "
+                         "element and frequency counts through the graph-replayed batched path")
     ap.add_argument("--counter-sample", action="store_true",
                     help="short run for hardware-counter passes: warmup, one step, then a plain copy of "
                          "known size (the incident-field cache) for calibrating FETCH_SIZE / WRITE_SIZE")
@@ -62,6 +65,8 @@ def main():
     import torch
     from paper_2604_15796_amd import fwi, workloads as W
 
+    if args.workload == "uneven-batch":
+        return bench_uneven(args)
     dev = torch.device("cuda", 0)
     p = W.config1()
     prob = fwi.ProblemArgs(p)
@@ -183,6 +188,63 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_uneven(args):
+    """32 uneven instances (N in {128..512}, 32-128 elements, 1-4 frequencies)
+    solved together: one step = forward + adjoint solves and gradients of all
+    instances through graph-replayed refinement cycles."""
+    import torch
+    from paper_2604_15796_amd import fwi, workloads as W
+
+    dev = torch.device("cuda", 0)
+    insts = W.config2()
+    ctx = fwi.Context(0)
+    cs = [torch.as_tensor(p.c).to(dev) for p in insts]
+    al = [torch.as_tensor(p.alpha).to(dev) for p in insts]
+    obs = [torch.as_tensor(W.perturb_sos(p.c, seed=200 + k)).to(dev) for k, p in enumerate(insts)]
+    d_obs, _ = ctx.forward_batch(insts, obs, al, fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=16))
+    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
+                             inner_rtol=args.inner_rtol)
+    solves = sum(2 * p.nf * p.ne for p in insts)
+
+    def step():
+        return ctx.adjoint_gradient_batch(insts, cs, al, d_obs, mixed)
+
+    # fixed (built-in) tiles first, then autotune each distinct grid size
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    fixed_ms = (time.perf_counter() - t0) * 1e3
+    tune = {}
+    for p in insts:
+        if p.nx in tune:
+            continue
+        tune[p.nx] = {"c64": ctx.autotune(p, fwi.FWI_FP32_REFINE, B=p.nf * p.ne, reps=2),
+                      "c128": ctx.autotune(p, fwi.FWI_FP64, B=p.nf * p.ne, reps=1)}
+    for w in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for k in range(args.steps):
+        st = step()[2]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {"metric": METRIC, "value": round(solves / (ms * 1e-3), 2), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": "uneven batch: 32 2D instances, N in {128..512}, 32-128 elements, "
+                                  "1-4 frequencies in 0.3-1.5 MHz, forward+adjoint gradients",
+                      "instances": len(insts), "solves_per_step": solves, "rtol": args.rtol,
+                      "restart": args.restart, "path": "graph-replayed refinement cycles"},
+           "batch": st,
+           "autotune": {"fixed_tiles_ms_per_step": round(fixed_ms, 3), "autotuned_ms_per_step": round(ms, 3),
+                        "passes": {str(k): v for k, v in tune.items()}}}
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -183,6 +183,32 @@ int fwi_tv_admm_step(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_param
                      void* g_inout, void* u_inout, const void* m_ref, const void* d_obs,
                      const fwi_solve_opts* opts, fwi_admm_report* report, fwi_stats* stats);
 
+/* ---------------------------------------------------------- uneven batches */
+/* Many independent problems (grids, element counts and frequency counts may
+ * all differ) solved together. One refinement cycle of every instance of a
+ * wave is captured into one hipGraph (a branch per instance, convergence masks
+ * instead of host checks inside the cycle) and the graph is replayed until
+ * every right-hand side has converged; instances are grouped into waves that
+ * fit 60% of free device memory. Tile variants follow the context's tuning
+ * table (fwi_autotune per grid size). Arrays are per instance, as in
+ * fwi_adjoint_gradient / fwi_forward; misfit_out is host [ninst]. The caller
+ * workspace, if set, must hold the largest wave (else FWI_E_NOMEM). */
+typedef struct fwi_batch_stats {
+  int waves;               /* instance groups solved one after another */
+  int graph_launches;      /* replays of captured cycle graphs */
+  int iterations;          /* max Krylov iterations over all RHS */
+  int unconverged;         /* RHS that did not reach rtol */
+  double max_rel_residual; /* max FP64 relative residual at exit */
+  long long solves;        /* right-hand sides solved (forward + adjoint) */
+  double t_setup_ms, t_solve_ms, t_total_ms;
+} fwi_batch_stats;
+int fwi_adjoint_gradient_batch(fwi_ctx* ctx, int ninst, const fwi_problem* probs, const double* const* c,
+                               const double* const* alpha, const void* const* d_obs, const fwi_solve_opts* opts,
+                               double* misfit_out, void* const* grad_m_out, fwi_batch_stats* stats);
+int fwi_forward_batch(fwi_ctx* ctx, int ninst, const fwi_problem* probs, const double* const* c,
+                      const double* const* alpha, const fwi_solve_opts* opts, void* const* data_out,
+                      fwi_batch_stats* stats);
+
 /* ------------------------------------------------- building blocks (parity) */
 /* y = A_l x for B vectors (Eq. 5 discretised): y_b = x_b - k_l^2 sum W m x_b.
  * precision FWI_FP64: x, y complex128; FWI_FP32_REFINE: complex64 (one FP32

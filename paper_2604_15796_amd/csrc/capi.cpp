@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <set>
 #include <sstream>
 #include <string>
@@ -198,6 +199,18 @@ struct fwi_ctx {
   int* d_int = nullptr;        // device scratch for checks
   EventProfiler prof;
   FftTuning tune;
+  std::map<std::string, ProblemCache> bcache;  // caches of the batched entry point
+  hipStream_t cap_stream = nullptr;            // capture stream of the batched entry point
+  std::vector<hipStream_t> branch;             // one per instance of a wave (default priority)
+  std::vector<hipEvent_t> branch_ev;
+  hipEvent_t fork_ev = nullptr;
+  ~fwi_ctx() {
+    for (auto& kv : bcache) kv.second.release();
+    for (hipStream_t st : branch) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : branch_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -300,13 +313,10 @@ void make_twiddles(fwi_ctx* c) {
 
 // --------------------------------------------------------- cache build ---
 // Green spectra (FP64 FFT of the circulant table, cast to FP32 as well) and
-// incident fields of every frequency; reused while the problem is unchanged.
-double ensure_cache(fwi_ctx* c, const fwi_problem* p) {
-  const std::string key = problem_key(p);
-  if (key == c->pc.key) return 0.0;
+// incident fields of every frequency, built into `pc`.
+double build_cache(fwi_ctx* c, const fwi_problem* p, ProblemCache& pc, const std::string& key) {
   const double t0 = now_ms();
-  c->pc.release();
-  ProblemCache& pc = c->pc;
+  pc.release();
   pc.g = make_geo(p);
   pc.nf = p->nf;
   pc.ne = p->ne;
@@ -347,6 +357,13 @@ double ensure_cache(fwi_ctx* c, const fwi_problem* p) {
   FWI_HIP(hipFree(work));
   pc.key = key;
   return now_ms() - t0;
+}
+
+// The single-problem cache used by the per-problem entry points.
+double ensure_cache(fwi_ctx* c, const fwi_problem* p) {
+  const std::string key = problem_key(p);
+  if (key == c->pc.key) return 0.0;
+  return build_cache(c, p, c->pc, key);
 }
 
 // ----------------------------------------------------------- workspace ---
@@ -918,6 +935,305 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   return finish_rc(R.tot);
 }
 
+
+// ------------------------------------------------------- uneven batches ---
+// Many independent problems (different grids, element and frequency counts)
+// solved together: one refinement cycle of every instance of a wave is
+// captured into one hipGraph (one branch per instance, convergence masks
+// instead of host checks inside the cycle) and replayed until every RHS of
+// every instance has converged. Instances are grouped into waves that fit a
+// memory budget.
+template <typename T>
+struct BatchInst {
+  const fwi_problem* p = nullptr;
+  Geo g;
+  ProblemCache* pc = nullptr;
+  int B = 0;
+  long n = 0;
+  size_t bytes = 0;
+  CallBufs cb;
+  SolveBufs<T> sb;
+  hipStream_t st = nullptr;
+  hipEvent_t join = nullptr;
+  const double* c = nullptr;
+  const double* alpha = nullptr;
+  const c128* dobs = nullptr;
+  c128* grad = nullptr;
+  c128* data_out = nullptr;
+};
+
+template <typename T>
+void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cyc, const fwi_solve_opts& o,
+                   hipStream_t st) {
+  const bool fp32 = std::is_same<T, float>::value;
+  KrylovState<T>& ks = I.sb.ks;
+  SolveBufs<T>& s = I.sb;
+  const ProblemCache& pc = *I.pc;
+  const cplx<T>* mT = fp32 ? (const cplx<T>*)I.cb.m32 : (const cplx<T>*)I.cb.m64;
+  const cplx<T>* gT = fp32 ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
+  const long vs = ks.vstride();
+  const c128* r = rhs;
+  if (cyc > 0) {
+    launch_vie<double>(I.g, c->tw, ks.B, x, nullptr, nullptr, I.cb.m64, pc.ghat64, pc.rhs_freq, s.U1_64, s.U2_64,
+                       s.r64, rhs, EPI_RESID, st);
+    r = s.r64;
+  }
+  krylov_norms(ks, r, st);
+  krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
+  krylov_start_basis(ks, r, st);
+  for (int j = 0; j < ks.JM; ++j) {
+    launch_vie<T>(I.g, c->tw, ks.B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, gT,
+                  pc.rhs_freq, s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
+    krylov_arnoldi(ks, j, st);
+  }
+  krylov_finish_cycle(ks, x, st);
+}
+
+template <typename T, class RhsOf, class XOf>
+hipGraphExec_t capture_cycle(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int cyc, const fwi_solve_opts& o,
+                             RhsOf&& rhs_of, XOf&& x_of) {
+  hipStream_t main = c->cap_stream;
+  FWI_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+  try {
+    FWI_HIP(hipEventRecord(c->fork_ev, main));
+    for (BatchInst<T>* I : wave) {
+      FWI_HIP(hipStreamWaitEvent(I->st, c->fork_ev, 0));
+      enqueue_cycle<T>(c, *I, rhs_of(*I), x_of(*I), cyc, o, I->st);
+      FWI_HIP(hipEventRecord(I->join, I->st));
+      FWI_HIP(hipStreamWaitEvent(main, I->join, 0));
+    }
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(main, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t graph = nullptr;
+  FWI_HIP(hipStreamEndCapture(main, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  FWI_HIP(e);
+  return exec;
+}
+
+struct BatchTotals {
+  int graph_launches = 0, iters = 0, unconverged = 0, waves = 0;
+  double maxrel = 0.0, t_solve = 0.0;
+  long long solves = 0;
+};
+
+// Solve every instance of the wave for rhs_of(I) into x_of(I).
+template <typename T, class RhsOf, class XOf>
+void batch_solve(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int* ctr_dev, const fwi_solve_opts& o,
+                 RhsOf&& rhs_of, XOf&& x_of, BatchTotals& tot) {
+  hipStream_t main = c->cap_stream;
+  const bool fp32 = std::is_same<T, float>::value;
+  const int max_cycles = fp32 ? o.max_refine : (o.max_iter + o.restart - 1) / o.restart + 1;
+  const double t0 = now_ms();
+  for (BatchInst<T>* I : wave) {
+    launch_fill_zero_c128((long)I->B * I->n, x_of(*I), main);
+    krylov_reset_iters(I->sb.ks, main);
+  }
+  hipGraphExec_t g0 = capture_cycle<T>(c, wave, 0, o, rhs_of, x_of);
+  hipGraphExec_t gN = nullptr;
+  try {
+    gN = capture_cycle<T>(c, wave, 1, o, rhs_of, x_of);
+    const int W = (int)wave.size();
+    std::vector<int> ctr(2 * W);
+    for (int cyc = 0;; ++cyc) {
+      FWI_HIP(hipGraphLaunch(cyc == 0 ? g0 : gN, main));
+      tot.graph_launches += 1;
+      FWI_HIP(hipMemcpyAsync(ctr.data(), ctr_dev, sizeof(int) * 2 * W, hipMemcpyDeviceToHost, main));
+      FWI_HIP(hipStreamSynchronize(main));
+      int active = 0;
+      for (int i = 0; i < W; ++i) active += ctr[2 * i + 1];  // RHS active at the start of this cycle
+      if (active == 0) break;
+      if (cyc >= max_cycles) {
+        tot.unconverged += active;
+        break;
+      }
+    }
+  } catch (...) {
+    if (g0) (void)hipGraphExecDestroy(g0);
+    if (gN) (void)hipGraphExecDestroy(gN);
+    throw;
+  }
+  FWI_HIP(hipGraphExecDestroy(g0));
+  FWI_HIP(hipGraphExecDestroy(gN));
+  for (BatchInst<T>* I : wave) {
+    std::vector<int> it(I->B);
+    double mr = 0.0;
+    FWI_HIP(hipMemcpyAsync(it.data(), I->sb.ks.iters, sizeof(int) * I->B, hipMemcpyDeviceToHost, main));
+    FWI_HIP(hipMemcpyAsync(&mr, I->sb.ks.maxrel, sizeof(double), hipMemcpyDeviceToHost, main));
+    FWI_HIP(hipStreamSynchronize(main));
+    for (int v : it) tot.iters = std::max(tot.iters, v);
+    if (!std::isfinite(mr)) throw Error(FWI_E_NONFINITE, "non-finite residual in a batched solve");
+    tot.maxrel = std::max(tot.maxrel, mr);
+    tot.solves += I->B;
+  }
+  tot.t_solve += now_ms() - t0;
+}
+
+template <typename T>
+int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* const* cc, const double* const* alpha,
+               const void* const* dobs, const fwi_solve_opts* opts, double* misfit_out, void* const* grad_out,
+               void* const* data_out, fwi_batch_stats* stats) {
+  const double t0 = now_ms();
+  tl_prof = nullptr;  // no event records inside captured graphs
+  if (ninst < 1 || !probs || !cc || !opts) throw Error(FWI_E_INVAL, "bad batch arguments");
+  const bool gradient = dobs != nullptr;
+  if (gradient && !grad_out && !misfit_out) throw Error(FWI_E_INVAL, "no batch outputs");
+  if (!gradient && !data_out) throw Error(FWI_E_INVAL, "no batch outputs");
+  std::string msg;
+  int rc = validate_opts(opts, msg);
+  if (rc) throw Error(rc, msg);
+  fwi_solve_opts o = *opts;
+  o.max_rhs = 0;               // every instance solves all its frequencies at once
+  o.reciprocity_adjoint = 0;
+  // caches and plans
+  double t_setup = 0.0;
+  std::vector<BatchInst<T>> inst(ninst);
+  std::set<std::string> keys;
+  for (int i = 0; i < ninst; ++i) {
+    rc = validate_problem(&probs[i], msg);
+    if (rc) throw Error(rc, "instance " + std::to_string(i) + ": " + msg);
+    if (!cc[i]) throw Error(FWI_E_INVAL, "instance " + std::to_string(i) + ": c is NULL");
+    if (gradient && !dobs[i]) throw Error(FWI_E_INVAL, "instance " + std::to_string(i) + ": d_obs is NULL");
+    if (!gradient && !data_out[i]) throw Error(FWI_E_INVAL, "instance " + std::to_string(i) + ": no output");
+    const std::string key = problem_key(&probs[i]);
+    keys.insert(key);
+    ProblemCache& pc = c->bcache[key];
+    if (pc.key != key) t_setup += build_cache(c, &probs[i], pc, key);
+    BatchInst<T>& I = inst[i];
+    I.p = &probs[i];
+    I.g = make_geo(&probs[i]);
+    I.pc = &pc;
+    I.B = probs[i].nf * probs[i].ne;
+    I.n = I.g.n();
+    I.c = cc[i];
+    I.alpha = alpha ? alpha[i] : nullptr;
+    I.dobs = gradient ? (const c128*)dobs[i] : nullptr;
+    I.grad = grad_out ? (c128*)grad_out[i] : nullptr;
+    I.data_out = data_out ? (c128*)data_out[i] : nullptr;
+    Arena dry;
+    plan_call<T>(dry, I.p, o, FWI_ENTRY_GRADIENT, I.cb, I.sb);
+    I.bytes = dry.used;
+  }
+  for (auto it = c->bcache.begin(); it != c->bcache.end();) {  // drop caches of earlier batches
+    if (!keys.count(it->first)) {
+      it->second.release();
+      it = c->bcache.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  // waves under a memory budget (60% of free device memory after the caches)
+  size_t free_b = 0, total_b = 0;
+  FWI_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t budget = std::max<size_t>((size_t)(0.6 * (double)(free_b + c->ws_int_bytes)), 1);
+  std::vector<std::vector<int>> waves;
+  size_t cur = 0;
+  for (int i = 0; i < ninst; ++i) {
+    if (waves.empty() || cur + inst[i].bytes > budget) {
+      waves.emplace_back();
+      cur = 0;
+    }
+    waves.back().push_back(i);
+    cur += inst[i].bytes;
+  }
+  size_t maxw = 0, maxn = 0;
+  for (auto& w : waves) {
+    size_t sum = 2 * sizeof(int) * w.size() + 256 * (w.size() + 1);
+    for (int i : w) sum += inst[i].bytes;
+    maxw = std::max(maxw, sum);
+    maxn = std::max(maxn, w.size());
+  }
+  // streams and events
+  if (!c->cap_stream) FWI_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (!c->fork_ev) FWI_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  while (c->branch.size() < maxn) {
+    hipStream_t st;
+    hipEvent_t ev;
+    FWI_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    FWI_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    c->branch.push_back(st);
+    c->branch_ev.push_back(ev);
+  }
+  hipStream_t main = c->cap_stream;
+  // order after the caller's earlier work
+  FWI_HIP(hipEventRecord(c->fork_ev, c->stream));
+  FWI_HIP(hipStreamWaitEvent(main, c->fork_ev, 0));
+  Arena a;
+  bind_workspace(c, a, maxw);
+  BatchTotals tot;
+  std::vector<double> misfits(ninst, 0.0);
+  for (auto& w : waves) {
+    a.used = 0;
+    int* ctr = a.take<int>(2 * w.size());
+    std::vector<BatchInst<T>*> wave;
+    for (size_t k = 0; k < w.size(); ++k) {
+      BatchInst<T>& I = inst[w[k]];
+      plan_call<T>(a, I.p, o, FWI_ENTRY_GRADIENT, I.cb, I.sb);
+      I.sb.ks.counters = ctr + 2 * k;
+      I.st = c->branch[k];
+      I.join = c->branch_ev[k];
+      wave.push_back(&I);
+    }
+    // contrast
+    for (BatchInst<T>* I : wave) {
+      launch_check_sos(I->n, I->c, I->alpha, c->d_int, main);
+      FWI_HIP(hipMemcpyAsync(c->h_int, c->d_int, 2 * sizeof(int), hipMemcpyDeviceToHost, main));
+      FWI_HIP(hipStreamSynchronize(main));
+      if (c->h_int[0] || c->h_int[1]) throw Error(FWI_E_NONFINITE, "invalid speed of sound / attenuation");
+      launch_contrast(I->n, I->p->c0, I->c, I->alpha, I->cb.m64, I->cb.m32, main);
+    }
+    // forward solves
+    batch_solve<T>(c, wave, ctr, o, [](BatchInst<T>& I) -> const c128* { return I.pc->P0; },
+                   [](BatchInst<T>& I) -> c128* { return I.cb.fields; }, tot);
+    for (BatchInst<T>* I : wave) {
+      const int ne = I->p->ne, nf = I->p->nf;
+      c128* data = I->data_out ? I->data_out : I->cb.data;
+      launch_gemm_nt(nf, I->cb.fields, (long)ne * I->n, ne, I->cb.m64, I->pc->P0, (long)ne * I->n, ne, I->n,
+                     I->pc->coef, I->cb.gpart, gemm_splits(I->n), data, main);
+      if (gradient) {
+        launch_residual((long)nf * ne * ne, data, I->dobs, I->cb.r, I->cb.misfits, main);
+        launch_gemm_cn(nf, I->cb.r, ne, ne, I->pc->P0, (long)ne * I->n, I->n, I->cb.S, (long)ne * I->n, main);
+      }
+    }
+    if (gradient) {
+      batch_solve<T>(c, wave, ctr, o, [](BatchInst<T>& I) -> const c128* { return I.cb.S; },
+                     [](BatchInst<T>& I) -> c128* { return I.cb.lam; }, tot);
+      for (size_t k = 0; k < wave.size(); ++k) {
+        BatchInst<T>* I = wave[k];
+        launch_gradient_accum(I->n, I->p->nf, I->p->ne, I->cb.fields, I->cb.lam, I->pc->k2, I->cb.gpart, kGradSeg,
+                              1, I->cb.gacc, main);
+        launch_grad_chain(I->n, I->cb.gacc, std::pow(I->g.dx, I->g.dim), I->g.c0, nullptr, nullptr, I->grad,
+                          nullptr, nullptr, main);
+        FWI_HIP(hipMemcpyAsync(&misfits[w[k]], I->cb.misfits, sizeof(double), hipMemcpyDeviceToHost, main));
+      }
+    }
+    FWI_HIP(hipStreamSynchronize(main));
+    tot.waves += 1;
+  }
+  // later work on the caller's stream follows this call
+  FWI_HIP(hipEventRecord(c->fork_ev, main));
+  FWI_HIP(hipStreamWaitEvent(c->stream, c->fork_ev, 0));
+  if (misfit_out)
+    for (int i = 0; i < ninst; ++i) misfit_out[i] = misfits[i];
+  if (stats) {
+    stats->waves = tot.waves;
+    stats->graph_launches = tot.graph_launches;
+    stats->iterations = tot.iters;
+    stats->unconverged = tot.unconverged;
+    stats->max_rel_residual = tot.maxrel;
+    stats->solves = tot.solves;
+    stats->t_setup_ms = t_setup;
+    stats->t_solve_ms = tot.t_solve;
+    stats->t_total_ms = now_ms() - t0;
+  }
+  return tot.unconverged ? FWI_E_NOCONV : FWI_OK;
+}
 }  // namespace
 
 // ===================================================================== ABI ===
@@ -1364,6 +1680,28 @@ int fwi_set_tuning(fwi_ctx* c, const signed char* in, int count) {
   if (count != (int)sizeof(FftTuning::v)) return FWI_E_INVAL;
   std::memcpy(c->tune.v, in, sizeof(FftTuning::v));
   return FWI_OK;
+}
+
+int fwi_adjoint_gradient_batch(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* const* cc,
+                               const double* const* alpha, const void* const* d_obs, const fwi_solve_opts* o,
+                               double* misfit_out, void* const* grad_m_out, fwi_batch_stats* stats) {
+  return guarded(c, [&] {
+    if (!o || !d_obs) throw Error(FWI_E_INVAL, "bad batch arguments");
+    return o->precision == FWI_FP32_REFINE
+               ? batch_impl<float>(c, ninst, probs, cc, alpha, d_obs, o, misfit_out, grad_m_out, nullptr, stats)
+               : batch_impl<double>(c, ninst, probs, cc, alpha, d_obs, o, misfit_out, grad_m_out, nullptr, stats);
+  });
+}
+
+int fwi_forward_batch(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* const* cc,
+                      const double* const* alpha, const fwi_solve_opts* o, void* const* data_out,
+                      fwi_batch_stats* stats) {
+  return guarded(c, [&] {
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? batch_impl<float>(c, ninst, probs, cc, alpha, nullptr, o, nullptr, nullptr, data_out, stats)
+               : batch_impl<double>(c, ninst, probs, cc, alpha, nullptr, o, nullptr, nullptr, data_out, stats);
+  });
 }
 
 }  // extern "C"

@@ -111,6 +111,10 @@ def lib():
         "fwi_profile": (ip, [vp, C.c_uint]),
         "fwi_profile_read": (ip, [vp, ip, dp, C.POINTER(C.c_longlong), dp]),
         "fwi_autotune": (ip, [vp, pp, ip, ip, ip, C.POINTER(CTuneReport)]),
+        "fwi_adjoint_gradient_batch": (ip, [vp, ip, pp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), op, dp,
+                                            C.POINTER(vp), C.POINTER(CBatchStats)]),
+        "fwi_forward_batch": (ip, [vp, ip, pp, C.POINTER(vp), C.POINTER(vp), op, C.POINTER(vp),
+                                   C.POINTER(CBatchStats)]),
         "fwi_get_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
         "fwi_set_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
     }
@@ -127,13 +131,23 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_tv_admm_step",
             "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
-            "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning"]
+            "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
+            "fwi_forward_batch"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
 _BASE_CLASSES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv", "dots", "orth"]
 # class k: complex64 launches; class k + 7: complex128 launches
 KERNEL_CLASSES = [f"{c}_c64" for c in _BASE_CLASSES] + [f"{c}_c128" for c in _BASE_CLASSES]
+
+
+class CBatchStats(C.Structure):
+    _fields_ = [("waves", C.c_int), ("graph_launches", C.c_int), ("iterations", C.c_int), ("unconverged", C.c_int),
+                ("max_rel_residual", C.c_double), ("solves", C.c_longlong), ("t_setup_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class CTuneReport(C.Structure):
@@ -371,6 +385,47 @@ class Context:
             return
         buf = (C.c_byte * TUNING_BYTES).from_buffer_copy(bytes(table))
         self._check(self.L.fwi_set_tuning(self.h, buf, TUNING_BYTES))
+
+    # ----------------------------------------------------------- batches ---
+    def _batch_args(self, probs, cs, alphas):
+        pas = [p if isinstance(p, ProblemArgs) else ProblemArgs(p) for p in probs]
+        arr = (CProblem * len(pas))(*[pa.c for pa in pas])
+        for pa, c_ in zip(pas, cs):
+            _check_dtype(c_, torch.float64, pa.shape, "c")
+        cp = (C.c_void_p * len(pas))(*[t.data_ptr() for t in cs])
+        ap = None
+        if alphas is not None:
+            ap = (C.c_void_p * len(pas))(*[t.data_ptr() for t in alphas])
+        return pas, arr, cp, ap
+
+    def forward_batch(self, probs, cs, alphas=None, opts=None, allow_noconv=False):
+        """Data of many problems of different shapes, solved together (list of [nf, ne, ne])."""
+        pas, arr, cp, ap = self._batch_args(probs, cs, alphas)
+        o = (opts or SolveOptions()).c()
+        outs = [torch.empty((pa.nf, pa.ne, pa.ne), dtype=torch.complex128, device=self.device) for pa in pas]
+        op_ = (C.c_void_p * len(pas))(*[t.data_ptr() for t in outs])
+        st = CBatchStats()
+        self._stream()
+        self._internal_workspace()
+        rc = self.L.fwi_forward_batch(self.h, len(pas), arr, cp, ap, C.byref(o), op_, C.byref(st))
+        self._check(rc, allow_noconv)
+        return outs, st.as_dict()
+
+    def adjoint_gradient_batch(self, probs, cs, alphas, d_obs, opts=None, allow_noconv=False):
+        """(misfits [ninst], gradients list of [n] complex, stats) for many problems."""
+        pas, arr, cp, ap = self._batch_args(probs, cs, alphas)
+        o = (opts or SolveOptions()).c()
+        dp_ = (C.c_void_p * len(pas))(*[t.data_ptr() for t in d_obs])
+        grads = [torch.empty(pa.n, dtype=torch.complex128, device=self.device) for pa in pas]
+        gp = (C.c_void_p * len(pas))(*[t.data_ptr() for t in grads])
+        mis = (C.c_double * len(pas))()
+        st = CBatchStats()
+        self._stream()
+        self._internal_workspace()
+        rc = self.L.fwi_adjoint_gradient_batch(self.h, len(pas), arr, cp, ap, dp_, C.byref(o), mis, gp,
+                                               C.byref(st))
+        self._check(rc, allow_noconv)
+        return list(mis), grads, st.as_dict()
 
     # ---------------------------------------------------- building blocks ---
     def apply_operator(self, prob, m, freq_index, x, precision=FWI_FP64):

@@ -239,3 +239,28 @@ def test_cfg4_3d_gradient_recompute_mixed_vs_fp64(ctx, F, cfg4):
     assert rel(g32, g64) < 1e-4
     assert abs(phi32 - phi64) < 1e-4 * phi64
     assert st["solves"] == 2 * p.nf * p.ne
+
+
+# ---------------------------------------------------------------- config 2 ---
+
+def test_cfg2_uneven_batch_graph_vs_eager(ctx, F):
+    """32 uneven instances through the graph-replayed batch in the mixed form:
+    every instance converges, and sampled instances equal the eager per-problem
+    path bit for bit (same arithmetic)."""
+    insts = W.config2()
+    cs = [t(p.c) for p in insts]
+    al = [t(p.alpha) for p in insts]
+    obs = [t(W.perturb_sos(p.c, seed=200 + k)) for k, p in enumerate(insts)]
+    d_obs, _ = ctx.forward_batch(insts, obs, al, plain(F, restart=16))
+    o = mixed(F)
+    mis, grads, st = ctx.adjoint_gradient_batch(insts, cs, al, d_obs, o)
+    assert st["unconverged"] == 0 and st["solves"] == sum(2 * p.nf * p.ne for p in insts)
+    for k in (0, 7, 31):
+        phi, g, _, _, _ = ctx.adjoint_gradient(insts[k], cs[k], al[k], d_obs[k], o)
+        assert rel(grads[k], g) < 1e-13 and abs(mis[k] - phi) <= 1e-13 * phi
+    # sampled forward fields of one instance against the oracle
+    p = insts[3]
+    _, fields, _ = ctx.forward(p, cs[3], al[3], o, fields=True)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    for (l, i), ref in zip([(0, 0)], oracle_fields(p, m, [(0, 0)])):
+        assert rel(fields[l, i], ref) < 1e-5

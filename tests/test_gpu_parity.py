@@ -271,3 +271,45 @@ def test_autograd_gradcheck_tiny(ctx, F):
     opts = F.SolveOptions(rtol=1e-14, restart=32)
     assert torch.autograd.gradcheck(lambda z: F.fwi_data(z, ctx, p, opts), (m,), eps=1e-7, atol=1e-9,
                                     rtol=1e-6, fast_mode=True)
+
+
+# ------------------------------------------------------- uneven batches ---
+
+def _uneven_instances():
+    a = W.small2d(seed=41, nx=24, nz=20, ne=4, nf=2)
+    b = W.small2d(seed=42, nx=40, nz=33, ne=6, nf=1, f_lo=0.9e6, f_hi=0.9e6)
+    c = W.small2d(seed=43, nx=33, nz=48, ne=5, nf=3)
+    return [a, b, c]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_gradient_matches_eager_path_and_oracle(ctx, F, prec):
+    """The graph-replayed uneven batch gives the per-problem eager results
+    (identical arithmetic), twice in a row bit for bit, and matches the oracle."""
+    insts = _uneven_instances()
+    d_obs = [O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)[0] for p in insts]
+    cs = [dev(p.c, torch.float64) for p in insts]
+    al = [dev(p.alpha, torch.float64) for p in insts]
+    dd = [dev(d) for d in d_obs]
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16)
+    mis, grads, st = ctx.adjoint_gradient_batch(insts, cs, al, dd, opts)
+    mis2, grads2, st2 = ctx.adjoint_gradient_batch(insts, cs, al, dd, opts)
+    assert st["solves"] == sum(2 * p.nf * p.ne for p in insts) and st["unconverged"] == 0
+    assert st["graph_launches"] >= 2
+    for i, p in enumerate(insts):
+        assert torch.equal(grads[i], grads2[i]) and mis[i] == mis2[i]
+        phi, g, _, _, _ = ctx.adjoint_gradient(p, cs[i], al[i], dd[i], opts)
+        assert relerr(host(grads[i]), host(g)) < 1e-13 and abs(mis[i] - phi) <= 1e-13 * phi
+        rphi, rg, _, _, _ = O.adjoint_gradient(p.c, p.alpha, d_obs[i], 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs,
+                                               p.elems)
+        assert relerr(host(grads[i]), rg) < 1e-9 and abs(mis[i] - rphi) < 1e-9 * rphi
+
+
+def test_batch_forward_matches_oracle(ctx, F):
+    insts = _uneven_instances()
+    data, st = ctx.forward_batch(insts, [dev(p.c, torch.float64) for p in insts],
+                                 [dev(p.alpha, torch.float64) for p in insts],
+                                 F.SolveOptions(precision=1, rtol=1e-12, restart=8))
+    for i, p in enumerate(insts):
+        rd, _, _ = O.forward(p.c, p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+        assert relerr(host(data[i]), rd) < 1e-10
