@@ -28,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "forward+adjoint solves/s at 1e-5 rel err vs FP64 plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-
+# calibrated) for the exact kernel variant named; reported only while the timed
+# dominant class runs that variant (profiles/gradient256_hbm_traffic.md).
+MEASURED_TRAFFIC = {("conv_c64", 1): {"kernel": "k_strided<float, 512, 16, 256, 2>", "bytes_per_launch": 946.3e6}}
 
 
 def parse():
@@ -144,8 +148,11 @@ def main():
     value = solves_per_step / (ms_step * 1e-3)
     log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
+    chosen = tune.get("c64", {}).get(dominant.replace("_c64", ""), {}).get("chosen", 1)
+    meas = MEASURED_TRAFFIC.get((dominant, chosen))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": meas["bytes_per_launch"] if meas else None,
+                "traffic_kernel": meas["kernel"] if meas else None,
                 "kernel": dominant, "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
                 "bytes_per_launch": prof["bytes"] / prof["launches"], "launches": prof["launches"]}
 

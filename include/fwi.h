@@ -259,8 +259,8 @@ int fwi_profile_read(const fwi_ctx* ctx, int cls, double* total_ms, long long* l
 
 /* ------------------------------------------------------------- autotuner */
 /* Each FFT pass of the operator exists in three tile variants (row passes:
- * 2048 / 4096 / 8192 points per workgroup; strided passes: 4 / 8 / 16 columns
- * per workgroup). fwi_autotune times every variant of every pass on the device
+ * 2048 / 4096 / 8192 points per workgroup; strided passes: 8 columns x 256
+ * threads, 16 x 256, 16 x 512 per workgroup). fwi_autotune times every variant of every pass on the device
  * for this problem's grid with B right-hand sides (reps launches each, HIP
  * events) and stores the fastest per (pass, precision, padded length) in the
  * context; later calls use it. Report rows: 0 row forward, 1 convolution,

@@ -31,8 +31,8 @@ thread_local int tl_force_variant = -1;
 
 int default_variant(int pass, bool dbl, int L) {
   (void)L;
-  if (pass == PK_ROW_FWD || pass == PK_ROW_INV) return dbl ? 0 : 1;  // 2048 / 4096 points
-  return dbl ? 1 : 2;                                                  // 8 / 16 columns
+  if (pass == PK_ROW_FWD || pass == PK_ROW_INV) return 0;  // 2048 points per workgroup
+  return dbl ? 0 : 1;                                        // (8, 256) / (16, 256) columns, threads
 }
 
 int tune_variant(int pass, bool dbl, int L) {

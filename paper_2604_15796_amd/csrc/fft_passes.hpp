@@ -12,6 +12,11 @@ namespace fwi {
 
 constexpr int NT = 256;
 constexpr int kLdsMax = 160 * 1024;
+// 2D intermediate layout: columns grouped in tiles of CTILE, each tile stored
+// depth-major ([b][Lx/CTILE][nz][CTILE]) so the column pass streams contiguous
+// blocks and the row passes touch runs of (rows per workgroup) x CTILE points.
+constexpr int CTILE = 16;
+constexpr bool kTiled2D = false;  // measured: no gain for the column pass, slower row passes
 
 // rows per workgroup of variant v: 2048 / 4096 / 8192 points
 template <typename T, int L, int V>
@@ -21,10 +26,15 @@ __host__ __device__ constexpr int row_nl() {
   // keep the workgroup inside the LDS budget
   return nl0 * (L + L / 8) * (int)sizeof(cplx<T>) <= kLdsMax - 4096 ? nl0 : (nl0 / 2 > 0 ? nl0 / 2 : 1);
 }
-// columns per workgroup of variant v: 4 / 8 / 16 (halved while over budget)
+// strided-pass variants: (columns, threads) = (8, 256), (16, 256), (16, 512);
+// columns are halved while the tile is over the LDS budget
+template <int V>
+__host__ __device__ constexpr int col_nt() {
+  return V == 2 ? 512 : 256;
+}
 template <typename T, int L, int V>
 __host__ __device__ constexpr int col_nl() {
-  constexpr int nl0 = V == 0 ? 4 : V == 1 ? 8 : 16;
+  constexpr int nl0 = V == 0 ? 8 : 16;
   constexpr int lp = L + L / 8;
   return nl0 * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0
        : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0 / 2 : nl0 / 4;
@@ -42,6 +52,7 @@ struct RowFwdArgs {
   long nrows;
   int rows_per_rhs, nin;
   long in_stride;
+  int tile;              // 0: rows of length L; CTILE: column-tiled output (2D)
 };
 
 template <typename T, int L, int NLV>
@@ -49,6 +60,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ long s_x[C::NL];
+  __shared__ long s_o[C::NL];
   __shared__ int s_m[C::NL];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
@@ -58,9 +70,11 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     int ok = g < a.nrows;
     const long b = ok ? g / a.rows_per_rhs : 0;
     if (ok && a.active && !a.active[b]) ok = 0;
+    const long z = g - b * a.rows_per_rhs;
     s_ok[l] = ok;
     s_x[l] = g * a.in_stride;
-    s_m[l] = (int)(g - b * a.rows_per_rhs) * a.nin;
+    s_o[l] = a.tile ? b * a.rows_per_rhs * (long)L + z * a.tile : g * (long)L;
+    s_m[l] = (int)z * a.nin;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
@@ -71,8 +85,11 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     if (a.scale) v = v * s_s[line];
     return v;
   };
+  const long tstride = (long)a.rows_per_rhs * a.tile;  // elements per column tile
   auto snk = [&](int line, int p, cplx<T> v) {
-    if (s_ok[line]) a.out[(g0 + line) * L + p] = v;
+    if (!s_ok[line]) return;
+    if (a.tile) a.out[s_o[line] + (p / CTILE) * tstride + (p % CTILE)] = v;
+    else a.out[s_o[line] + p] = v;
   };
   fft_line_transform<C, 0>(a.tw, sh, src, snk);
 }
@@ -89,6 +106,7 @@ struct RowInvArgs {
   const cplx<T>* tw;
   long nrows;
   int rows_per_rhs, nout;
+  int tile;              // 0: rows of length L; CTILE: column-tiled input (2D)
 };
 
 template <typename T, int L, int NLV, int EPI>
@@ -97,19 +115,24 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
+  __shared__ long s_i[C::NL];
   const long g0 = (long)blockIdx.x * C::NL;
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
     int ok = g < a.nrows;
     const long b = ok ? g / a.rows_per_rhs : 0;
     if (ok && a.active && !a.active[b]) ok = 0;
+    const long z = g - b * a.rows_per_rhs;
     s_ok[l] = ok;
+    s_i[l] = a.tile ? b * a.rows_per_rhs * (long)L + z * a.tile : g * (long)L;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
+  const long tstride = (long)a.rows_per_rhs * a.tile;
   auto src = [&](int line, int p) -> cplx<T> {
     if (!s_ok[line]) return mk((T)0, (T)0);
-    return a.in[(g0 + line) * L + p];
+    if (a.tile) return a.in[s_i[line] + (p / CTILE) * tstride + (p % CTILE)];
+    return a.in[s_i[line] + p];
   };
   auto snk = [&](int line, int p, cplx<T> v) {
     if (!s_ok[line] || p >= a.nout) return;
@@ -142,46 +165,74 @@ struct StridedArgs {
   int nlines;             // lines per plane
   int planes_per_rhs;
   int lin, lout;          // nonzero input points, output points kept
+  long nplanes;           // planes in the launch
+  int tile;               // 0: line l at offset l; CTILE: line l in tile l / CTILE (pstride = CTILE)
+  long tile_stride;       // elements per column tile (tiled layout)
+  long gpstride;          // Ghat stride between points of a line (conv)
 };
 
-template <typename T, int L, int NLV, int MODE>  // MODE 0 forward, 1 inverse, 2 convolution
-__global__ void __launch_bounds__(NT) k_strided(StridedArgs<T> a) {
-  using C = LineCfg<T, L, NLV, NT, true>;
+constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolution pass
+
+template <typename T, int L, int NLV, int NTV, int MODE>  // MODE 0 forward, 1 inverse, 2 convolution
+__global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
+  using C = LineCfg<T, L, NLV, NTV, true>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
-  const long plane = blockIdx.y;
-  const int b = (int)(plane / a.planes_per_rhs);
-  if (a.active && !a.active[b]) return;  // uniform per workgroup
   const int line0 = blockIdx.x * C::NL;
-  const cplx<T>* ip = a.in + plane * a.in_ps + line0;
-  cplx<T>* op = a.out + plane * a.out_ps + line0;
   const int nl = a.nlines - line0;
-  auto src = [&](int line, int p) -> cplx<T> {
-    if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
-    return ip[p * a.pstride + line];
-  };
-  auto snk = [&](int line, int p, cplx<T> v) {
-    if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
-  };
   if constexpr (MODE == 2) {
-    // prefetch this thread's kernel-spectrum values; the loads complete while
-    // the forward stages run
+    // CONV_RPW consecutive planes (right-hand sides) per workgroup share the
+    // kernel-spectrum tile, which is prefetched into registers once per
+    // frequency; the loads complete while the forward stages run
     using Map = ConvMidMap<C>;
-    const cplx<T>* gp = a.ghat + (long)a.rhs_freq[b] * a.gstride + line0;
     cplx<T> gpre[Map::TT][Map::R];
+    int fcur = -1;
+    for (int q = 0; q < CONV_RPW; ++q) {
+      const long plane = (long)blockIdx.y * CONV_RPW + q;
+      if (plane >= a.nplanes) break;
+      const int b = (int)(plane / a.planes_per_rhs);
+      if (a.active && !a.active[b]) continue;  // uniform per workgroup
+      const int f = a.rhs_freq[b];
+      if (f != fcur) {
+        const cplx<T>* gp = a.ghat + (long)f * a.gstride + line0;
 #pragma unroll
-    for (int t = 0; t < Map::TT; ++t)
+        for (int t = 0; t < Map::TT; ++t)
 #pragma unroll
-      for (int r = 0; r < Map::R; ++r) {
-        int line, p;
-        gpre[t][r] = (Map::at(t, r, line, p) && line < nl) ? gp[p * a.pstride + line] : mk((T)0, (T)0);
+          for (int r = 0; r < Map::R; ++r) {
+            int line, p;
+            gpre[t][r] = (Map::at(t, r, line, p) && line < nl) ? gp[p * a.gpstride + line] : mk((T)0, (T)0);
+          }
+        fcur = f;
       }
-    auto gh = [&](int t, int r, int, int) -> cplx<T> { return gpre[t][r]; };
-    fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+      const long loff = a.tile ? (line0 / a.tile) * a.tile_stride + line0 % a.tile : line0;
+      const cplx<T>* ip = a.in + plane * a.in_ps + loff;
+      cplx<T>* op = a.out + plane * a.out_ps + loff;
+      auto src = [&](int line, int p) -> cplx<T> {
+        if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
+        return ip[p * a.pstride + line];
+      };
+      auto snk = [&](int line, int p, cplx<T> v) {
+        if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
+      };
+      auto gh = [&](int t, int r, int, int) -> cplx<T> { return gpre[t][r]; };
+      fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+      __syncthreads();  // LDS is reused by the next plane
+    }
   } else {
+    const long plane = blockIdx.y;
+    const int b = (int)(plane / a.planes_per_rhs);
+    if (a.active && !a.active[b]) return;  // uniform per workgroup
+    const cplx<T>* ip = a.in + plane * a.in_ps + line0;
+    cplx<T>* op = a.out + plane * a.out_ps + line0;
+    auto src = [&](int line, int p) -> cplx<T> {
+      if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
+      return ip[p * a.pstride + line];
+    };
+    auto snk = [&](int line, int p, cplx<T> v) {
+      if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
+    };
     fft_line_transform<C, MODE>(a.tw, sh, src, snk);
   }
 }
-
 
 // ---------------------------------------------------------------- dispatch ---
 template <typename T, int L, int V>
@@ -205,12 +256,16 @@ void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
 template <typename T, int L, int V>
 void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
   constexpr int NL = col_nl<T, L, V>();
+  constexpr int NTV = col_nt<V>();
   if (planes == 0) return;
-  if (planes > 65535) throw Error(-6, "too many planes for one strided pass");
-  dim3 grid((a.nlines + NL - 1) / NL, (unsigned)planes);
-  if (mode == 0) hipLaunchKernelGGL((k_strided<T, L, NL, 0>), grid, dim3(NT), 0, st, a);
-  else if (mode == 1) hipLaunchKernelGGL((k_strided<T, L, NL, 1>), grid, dim3(NT), 0, st, a);
-  else hipLaunchKernelGGL((k_strided<T, L, NL, 2>), grid, dim3(NT), 0, st, a);
+  StridedArgs<T> args = a;
+  args.nplanes = planes;
+  const long gy = mode == 2 ? (planes + CONV_RPW - 1) / CONV_RPW : planes;
+  if (gy > 65535) throw Error(-6, "too many planes for one strided pass");
+  dim3 grid((a.nlines + NL - 1) / NL, (unsigned)gy);
+  if (mode == 0) hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 0>), grid, dim3(NTV), 0, st, args);
+  else if (mode == 1) hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 1>), grid, dim3(NTV), 0, st, args);
+  else hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 2>), grid, dim3(NTV), 0, st, args);
   FWI_LAUNCH_CHECK();
 }
 
@@ -275,6 +330,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.rows_per_rhs = (int)rows_per_rhs;
   f.nin = g.nx;
   f.in_stride = g.nx;
+  f.tile = (g.dim == 2 && kTiled2D) ? CTILE : 0;
   prof_begin(KC_ROW_FWD + po, st);
   row_fwd_call<T>(g.Lx, f, st);
   prof_end(KC_ROW_FWD + po, st, act * (n + g.u1()) * es + n * es);
@@ -288,8 +344,11 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.rhs_freq = rhs_freq;
     s.active = active;
     s.in_ps = s.out_ps = (long)g.nz * g.Lx;
-    s.pstride = g.Lx;
+    s.tile = kTiled2D ? CTILE : 0;
+    s.tile_stride = (long)g.nz * CTILE;
+    s.pstride = kTiled2D ? CTILE : g.Lx;
     s.gstride = g.npad();
+    s.gpstride = g.Lx;
     s.nlines = g.Lx;
     s.planes_per_rhs = 1;
     s.lin = s.lout = g.nz;
@@ -324,6 +383,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     c.in_ps = c.out_ps = (long)g.nz * g.Ly * g.Lx;
     c.pstride = (long)g.Ly * g.Lx;
     c.gstride = g.npad();
+    c.gpstride = (long)g.Ly * g.Lx;
     c.nlines = g.Ly * g.Lx;
     c.planes_per_rhs = 1;
     c.lin = c.lout = g.nz;
@@ -359,6 +419,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   r.nrows = rows_per_rhs * B;
   r.rows_per_rhs = (int)rows_per_rhs;
   r.nout = g.nx;
+  r.tile = (g.dim == 2 && kTiled2D) ? CTILE : 0;
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
   prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() + (epi == EPI_RESID ? 3.0 : 2.0) * n) * es);

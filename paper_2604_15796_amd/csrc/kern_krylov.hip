@@ -7,8 +7,10 @@ namespace fwi {
 
 constexpr int KT = 256;  // threads per block of the vector kernels
 
+// Blocks per RHS of the Arnoldi kernels: chunks of 16384 elements (64 per
+// thread), enough to amortise each block's reduction.
 int krylov_nblk(long n) {
-  long nb = (n + 4095) / 4096;
+  long nb = (n + 16383) / 16384;
   return (int)(nb < 1 ? 1 : nb);
 }
 
