@@ -313,3 +313,74 @@ def test_batch_forward_matches_oracle(ctx, F):
     for i, p in enumerate(insts):
         rd, _, _ = O.forward(p.c, p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
         assert relerr(host(data[i]), rd) < 1e-10
+
+
+# ------------------------------------------------- failure handling, misc ---
+
+def test_noconv_is_reported_with_outputs(ctx, F):
+    p = W.small2d(seed=51, nx=24, nz=20, ne=3, nf=1)
+    opts = F.SolveOptions(rtol=1e-14, restart=8, max_iter=1)
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward(p, dev(p.c, torch.float64), None, opts)
+    assert e.value.code == F.FWI_E_NOCONV
+    data, st = ctx.forward(p, dev(p.c, torch.float64), None, opts, allow_noconv=True)
+    assert st["unconverged"] > 0 and bool(torch.isfinite(torch.view_as_real(data)).all())
+
+
+def test_nonfinite_and_invalid_inputs(ctx, F):
+    p = W.small2d(seed=52, nx=24, nz=20, ne=3, nf=1)
+    c = p.c.copy()
+    c[3, 4] = np.nan
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward(p, dev(c, torch.float64))
+    assert e.value.code == F.FWI_E_NONFINITE
+    c[3, 4] = -1.0
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward(p, dev(c, torch.float64))
+    assert e.value.code == F.FWI_E_NONFINITE
+    m = np.zeros(p.shape, complex)
+    m[0, 0] = np.inf
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward_m(p, dev(m))
+    assert e.value.code == F.FWI_E_NONFINITE
+    bad = W.small2d(seed=52, nx=24, nz=20, ne=3, nf=1)
+    bad.elems = bad.elems.copy()
+    bad.elems[0, 2] = 1e-4
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward(bad, dev(bad.c, torch.float64))
+    assert e.value.code == F.FWI_E_UNSUPPORTED
+
+
+def test_deterministic_and_workspace_modes(ctx, F):
+    """Run-to-run bitwise reproducibility (fixed-order reductions, no float
+    atomics) and identical results with library-owned vs torch workspace."""
+    p = W.small2d(seed=53, nx=40, nz=36, ne=5, nf=2)
+    d_obs = dev(W.random_data(1, p.nf, p.ne, 1e-4))
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    for prec in (0, 1):
+        opts = F.SolveOptions(precision=prec, rtol=1e-10, restart=16)
+        r1 = ctx.adjoint_gradient(p, c, a, d_obs, opts)
+        r2 = ctx.adjoint_gradient(p, c, a, d_obs, opts)
+        assert torch.equal(r1[1], r2[1]) and r1[0] == r2[0]
+        other = F.Context(0, use_torch_workspace=False)
+        r3 = other.adjoint_gradient(p, c, a, d_obs, opts)
+        other.close()
+        assert torch.equal(r1[1], r3[1]) and r1[0] == r3[0]
+
+
+def test_caller_workspace_too_small(ctx, F):
+    p = W.small2d(seed=54, nx=24, nz=20, ne=3, nf=1)
+    small = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    ctx.L.fwi_set_workspace(ctx.h, ctypes_ptr(small), small.numel())
+    o = F.SolveOptions().c()
+    out = torch.empty((1, 3, 3), dtype=torch.complex128, device=DEV)
+    import ctypes as C
+    rc = ctx.L.fwi_forward(ctx.h, F.ProblemArgs(p).ref(), ctypes_ptr(dev(p.c, torch.float64)), None, C.byref(o),
+                           ctypes_ptr(out), None, None)
+    assert rc == F.FWI_E_NOMEM
+    ctx.L.fwi_set_workspace(ctx.h, None, 0)
+
+
+def ctypes_ptr(t):
+    import ctypes as C
+    return C.c_void_p(t.data_ptr())
