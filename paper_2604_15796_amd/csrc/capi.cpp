@@ -1128,26 +1128,41 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
       ++it;
     }
   }
-  // waves under a memory budget (60% of free device memory after the caches)
+  // waves under a memory budget (60% of free device memory after the caches);
+  // if the workspace still cannot be allocated, the budget is halved until
+  // every wave holds one instance
   size_t free_b = 0, total_b = 0;
   FWI_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t budget = std::max<size_t>((size_t)(0.6 * (double)(free_b + c->ws_int_bytes)), 1);
+  size_t budget = std::max<size_t>((size_t)(0.6 * (double)(free_b + c->ws_int_bytes)), 1);
   std::vector<std::vector<int>> waves;
-  size_t cur = 0;
-  for (int i = 0; i < ninst; ++i) {
-    if (waves.empty() || cur + inst[i].bytes > budget) {
-      waves.emplace_back();
-      cur = 0;
-    }
-    waves.back().push_back(i);
-    cur += inst[i].bytes;
-  }
   size_t maxw = 0, maxn = 0;
-  for (auto& w : waves) {
-    size_t sum = 2 * sizeof(int) * w.size() + 256 * (w.size() + 1);
-    for (int i : w) sum += inst[i].bytes;
-    maxw = std::max(maxw, sum);
-    maxn = std::max(maxn, w.size());
+  Arena a;
+  for (;;) {
+    waves.clear();
+    size_t cur = 0;
+    for (int i = 0; i < ninst; ++i) {
+      if (waves.empty() || cur + inst[i].bytes > budget) {
+        waves.emplace_back();
+        cur = 0;
+      }
+      waves.back().push_back(i);
+      cur += inst[i].bytes;
+    }
+    maxw = 0;
+    maxn = 0;
+    for (auto& w : waves) {
+      size_t sum = 2 * sizeof(int) * w.size() + 256 * (w.size() + 1);
+      for (int i : w) sum += inst[i].bytes;
+      maxw = std::max(maxw, sum);
+      maxn = std::max(maxn, w.size());
+    }
+    try {
+      bind_workspace(c, a, maxw);
+      break;
+    } catch (const Error& e) {
+      if (e.code != FWI_E_NOMEM || c->ws_ext || maxn <= 1) throw;
+      budget = maxw / 2;
+    }
   }
   // streams and events
   if (!c->cap_stream) FWI_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -1164,8 +1179,6 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
   // order after the caller's earlier work
   FWI_HIP(hipEventRecord(c->fork_ev, c->stream));
   FWI_HIP(hipStreamWaitEvent(main, c->fork_ev, 0));
-  Arena a;
-  bind_workspace(c, a, maxw);
   BatchTotals tot;
   std::vector<double> misfits(ninst, 0.0);
   for (auto& w : waves) {

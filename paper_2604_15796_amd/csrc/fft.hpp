@@ -11,8 +11,9 @@
 // global memory directly (cropping is a store predicate), so a pass costs one
 // read and one write of its data in HBM and S-1 LDS exchanges in between.
 //
-// Lengths are 2^a 3^b (32 ... 1024) with radices 8, 6, 4, 3; every plan starts
-// with radix 8, which makes the zero half of a padded input a whole set of
+// Lengths are 2^a 3^b (32 ... 1024) with radices 8, 6, 4, 3, or 16 and 32 for
+// tiles with many points per thread; every plan starts with a radix of at
+// least 8, which makes the zero half of a padded input a whole set of
 // predicated-off loads, and the inverse plan is the reverse of the forward one.
 #pragma once
 
@@ -21,14 +22,26 @@
 namespace fwi {
 
 // ---------------------------------------------------------------- plans ---
-__host__ __device__ constexpr int plan_stages(int L) {
-  return L == 32 || L == 48 || L == 64 ? 2
+// Two plan families: radices 8/6/4/3 (any tile), and for tiles holding at
+// least big_ppt(L) points per thread, radices 16/32 with fewer stages (fewer
+// LDS exchanges and barriers).
+__host__ __device__ constexpr int big_ppt(int L) {
+  return L == 512 || L == 1024 ? 32 : (L == 128 || L == 256 || L == 768) ? 16 : 1 << 30;
+}
+__host__ __device__ constexpr int plan_stages(int L, bool big = false) {
+  return big ? (L == 768 ? 3 : 2)
+       : L == 32 || L == 48 || L == 64 ? 2
        : L == 96 || L == 128 || L == 192 || L == 256 || L == 384 || L == 512 ? 3
        : L == 768 || L == 1024 ? 4 : 0;
 }
-__host__ __device__ constexpr int plan_radix(int L, int s) {
+__host__ __device__ constexpr int plan_radix(int L, int s, bool big = false) {
   // forward plan, stage s
-  return s == 0 ? 8
+  return big ? (L == 128 ? (s == 0 ? 16 : 8)
+              : L == 256 ? 16
+              : L == 512 ? (s == 0 ? 16 : 32)
+              : L == 768 ? (s == 2 ? 3 : 16)
+              : L == 1024 ? 32 : 0)
+       : s == 0 ? 8
        : L == 32 ? 4
        : L == 48 ? 6
        : L == 64 ? 8
@@ -42,8 +55,18 @@ __host__ __device__ constexpr int plan_radix(int L, int s) {
        : L == 1024 ? (s == 1 ? 8 : 4) : 0;
 }
 // radix of stage s of the plan in direction dir (0: forward order, 1: reversed)
-__host__ __device__ constexpr int stage_radix(int L, int dir, int s) {
-  return dir == 0 ? plan_radix(L, s) : plan_radix(L, plan_stages(L) - 1 - s);
+__host__ __device__ constexpr int stage_radix(int L, int dir, int s, bool big = false) {
+  return dir == 0 ? plan_radix(L, s, big) : plan_radix(L, plan_stages(L, big) - 1 - s, big);
+}
+
+// exp(sgn 2 pi i m / 32) for compile-time m (after unrolling)
+__host__ __device__ constexpr double cos32(int m) {
+  constexpr double t[32] = {1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452, 0.7071067811865476, 0.5555702330196023, 0.38268343236508984, 0.19509032201612833, 6.123233995736766e-17, -0.1950903220161282, -0.3826834323650897, -0.555570233019602, -0.7071067811865475, -0.8314696123025453, -0.9238795325112867, -0.9807852804032304, -1.0, -0.9807852804032304, -0.9238795325112868, -0.8314696123025455, -0.7071067811865477, -0.5555702330196022, -0.38268343236509034, -0.19509032201612866, -1.8369701987210297e-16, 0.1950903220161283, 0.38268343236509, 0.5555702330196018, 0.7071067811865474, 0.8314696123025452, 0.9238795325112865, 0.9807852804032303};
+  return t[m & 31];
+}
+__host__ __device__ constexpr double sin32(int m) {
+  constexpr double t[32] = {0.0, 0.19509032201612825, 0.3826834323650898, 0.5555702330196022, 0.7071067811865475, 0.8314696123025452, 0.9238795325112867, 0.9807852804032304, 1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025455, 0.7071067811865476, 0.5555702330196022, 0.3826834323650899, 0.1950903220161286, 1.2246467991473532e-16, -0.19509032201612836, -0.38268343236508967, -0.555570233019602, -0.7071067811865475, -0.8314696123025452, -0.9238795325112865, -0.9807852804032303, -1.0, -0.9807852804032304, -0.9238795325112866, -0.8314696123025455, -0.7071067811865477, -0.5555702330196022, -0.3826834323650904, -0.19509032201612872};
+  return t[m & 31];
 }
 
 // ------------------------------------------------------------ butterflies ---
@@ -55,6 +78,11 @@ __device__ __forceinline__ void dft2(cplx<T>& a, cplx<T>& b) {
   a = a + b;
   b = t;
 }
+
+template <int R1, int R2, typename T>
+__device__ __forceinline__ void dft_ct(cplx<T>* v, int sgn);
+template <typename T>
+__device__ __forceinline__ cplx<T> rot32(cplx<T> a, int m, int sgn);
 
 template <int R, typename T>
 __device__ __forceinline__ void dft(cplx<T>* v, int sgn) {
@@ -93,6 +121,10 @@ __device__ __forceinline__ void dft(cplx<T>* v, int sgn) {
     v[4] = e[1] - t1;
     v[2] = e[2] + t2;
     v[5] = e[2] - t2;
+  } else if constexpr (R == 16) {
+    dft_ct<4, 4>(v, sgn);
+  } else if constexpr (R == 32) {
+    dft_ct<8, 4>(v, sgn);
   } else if constexpr (R == 8) {
     // 8 = 2 x 4: even / odd length-4 DFTs, then X_q = E_q + w8^q O_q
     cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
@@ -112,6 +144,67 @@ __device__ __forceinline__ void dft(cplx<T>* v, int sgn) {
     v[6] = e[2] - t2;
     v[3] = e[3] + t3;
     v[7] = e[3] - t3;
+  }
+}
+
+// Length R1*R2 DFT by one Cooley-Tukey split: n = R2 n1 + n2, k = k1 + R1 k2;
+// R1-point DFTs over n1, internal twiddles w_R^{n2 k1} (compile-time
+// constants), R2-point DFTs over n2.
+template <int R1, int R2, typename T>
+__device__ __forceinline__ void dft_ct(cplx<T>* v, int sgn) {
+  constexpr int R = R1 * R2;
+  cplx<T> a[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) a[n2][n1] = v[R2 * n1 + n2];
+    dft<R1>(a[n2], sgn);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      a[n2][k1] = rot32(a[n2][k1], n2 * k1 * (32 / R), sgn);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cplx<T> b[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) b[n2] = a[n2][k1];
+    dft<R2>(b, sgn);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
+  }
+}
+
+// a * exp(sgn 2 pi i m / 32) for a compile-time m (after unrolling)
+template <typename T>
+__device__ __forceinline__ cplx<T> rot32(cplx<T> a, int m, int sgn) {
+  m &= 31;
+  if (m == 0) return a;
+  if (m == 8) return mul_i(a, sgn);
+  if (m == 16) return mk(-a.x, -a.y);
+  if (m == 24) return mul_i(a, -sgn);
+  return a * mk((T)cos32(m), (T)(sgn * sin32(m)));
+}
+
+// Length-R DFT of a vector whose legs R/2 .. R-1 are zero (a first stage over
+// zero-padded data): even outputs are the R/2-point DFT of the nonzero half,
+// odd outputs the R/2-point DFT of it times w_R^r.
+template <int R, typename T>
+__device__ __forceinline__ void dft_half_in(cplx<T>* v, int sgn) {
+  static_assert(R == 8 || R == 16 || R == 32, "half-input DFT radix");
+  constexpr int H = R / 2;
+  cplx<T> e[H], o[H];
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    e[r] = v[r];
+    o[r] = rot32(v[r], r * (32 / R), sgn);
+  }
+  dft<H>(e, sgn);
+  dft<H>(o, sgn);
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    v[2 * m] = e[m];
+    v[2 * m + 1] = o[m];
   }
 }
 
@@ -137,6 +230,32 @@ __device__ __forceinline__ void apply_twiddles(cplx<T>* v, cplx<T> w1) {
   }
 }
 
+// Radix 16 / 32: w^r = (w^8)^(r div 8) w^(r mod 8) from two table values.
+template <int R, typename T>
+__device__ __forceinline__ void apply_twiddles_big(cplx<T>* v, cplx<T> w1, cplx<T> w8) {
+  cplx<T> p[8];
+  p[1] = w1;
+  p[2] = w1 * w1;
+  p[3] = p[2] * w1;
+  p[4] = p[2] * p[2];
+  p[5] = p[4] * w1;
+  p[6] = p[4] * p[2];
+  p[7] = p[4] * p[3];
+  cplx<T> q[R / 8];
+  if constexpr (R / 8 > 1) q[1] = w8;
+  if constexpr (R / 8 > 2) {
+    q[2] = w8 * w8;
+    q[3] = q[2] * w8;
+  }
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int lo = r & 7, hi = r >> 3;
+    if (hi == 0) v[r] = v[r] * p[lo];
+    else if (lo == 0) v[r] = v[r] * q[hi];
+    else v[r] = v[r] * (q[hi] * p[lo]);
+  }
+}
+
 // --------------------------------------------------------- line config ---
 // NL lines of length L per workgroup of NT threads. LF (line-fastest): the
 // butterfly index b maps to (line = b % NL, j = b / NL) and LDS holds point p of
@@ -154,94 +273,130 @@ struct LineCfg {
   static constexpr int L = L_, NL = NL_, NT = NT_;
   static constexpr bool LF = LF_;
   static constexpr int LP = L + L / 8;  // padded line length (points)
+  static constexpr bool BIG = NL * L / NT >= big_ppt(L);  // radix-16/32 plan
   static constexpr int LDS_ELEMS = NL * LP;
   __device__ static __forceinline__ int lds(int line, int p) {
     return LF ? (p + (p >> 3)) * NL + line : line * LP + p + (p >> 3);
   }
+  // LDS index of point pb + ro, where ro is a compile-time offset and ro or pb
+  // is a multiple of 8: the padding term splits and ro becomes an immediate
+  // offset of the LDS instruction.
+  __device__ static __forceinline__ int lds(int line, int pb, int ro) {
+    return lds(line, pb) + (ro + (ro >> 3)) * (LF ? NL : 1);
+  }
+  // (line, j) of butterfly t of this thread in a radix-R stage; the butterfly
+  // index is threadIdx.x + t NT.
   template <int R>
-  __device__ static __forceinline__ void split(int b, int& line, int& j) {
+  __device__ static __forceinline__ void split(int t, int& line, int& j) {
     if constexpr (LF) {
-      line = b % NL;
-      j = b / NL;
+      static_assert(NT % NL == 0, "lines must divide the workgroup");
+      line = (int)threadIdx.x % NL;  // fixed for the thread
+      j = (int)threadIdx.x / NL + t * (NT / NL);
+    } else if constexpr (NT % (L / R) == 0) {
+      j = (int)threadIdx.x % (L / R);
+      line = (int)threadIdx.x / (L / R) + t * (NT / (L / R));
     } else {
+      const int b = (int)threadIdx.x + t * NT;
       j = b % (L / R);
       line = b / (L / R);
     }
   }
 };
 
-// One Stockham stage: loads R points per butterfly through src(line, p), then
-// (after an optional barrier) twiddles, transforms and stores through
-// snk(line, p, value). Twiddle table tw[m] = exp(-2 pi i m / L).
-template <class C, int R, int Ns, bool SYNC, class Src, class Snk>
+// One Stockham stage: loads R points per butterfly through src(line, pb, ro),
+// then (after an optional barrier) twiddles, transforms and stores through
+// snk(line, pb, ro, value); the point index is pb + ro with ro a compile-time
+// offset (see LineCfg::lds). Twiddle table tw[m] = exp(-2 pi i m / L).
+// HIN: legs R/2 .. R-1 are zero and not loaded (first stage over zero-padded
+// data). HOUT: only legs 0 .. R/2-1 are stored (last stage of a cropped
+// transform), so the rest of the butterfly is never computed.
+template <class C, int R, int Ns, bool SYNC, bool HIN, bool HOUT, class Src, class Snk>
 __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __restrict__ tw, Src&& src, Snk&& snk) {
   using T = typename C::T;
   constexpr int L = C::L, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
+  static_assert(!HIN || Ns == 1, "zero legs only in a first stage");
+  static_assert(!HOUT || Ns * R == L, "cropping only in a last stage");
+  constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
+  constexpr bool RD_SPLIT = (L / R) % 8 == 0;
+  constexpr bool WR_SPLIT = Ns % 8 == 0 || (Ns == 1 && R % 8 == 0);
   cplx<T> v[TT][R];
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
-    const int b = threadIdx.x + t * C::NT;
-    if (NB % C::NT == 0 || b < NB) {
+    if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
-      C::template split<R>(b, line, j);
+      C::template split<R>(t, line, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[t][r] = src(line, j + r * (L / R));
+      for (int r = 0; r < RIN; ++r)
+        v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
     }
   }
   if constexpr (SYNC) __syncthreads();
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
-    const int b = threadIdx.x + t * C::NT;
-    if (NB % C::NT == 0 || b < NB) {
+    if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
-      C::template split<R>(b, line, j);
+      C::template split<R>(t, line, j);
       const int k = j % Ns;
       if constexpr (Ns > 1) {
         cplx<T> w1 = tw[k * (L / (Ns * R))];
         if (sgn > 0) w1.y = -w1.y;
-        apply_twiddles<R>(v[t], w1);
+        if constexpr (R > 8) {
+          cplx<T> w8 = tw[8 * k * (L / (Ns * R))];
+          if (sgn > 0) w8.y = -w8.y;
+          apply_twiddles_big<R>(v[t], w1, w8);
+        } else {
+          apply_twiddles<R>(v[t], w1);
+        }
       }
-      dft<R>(v[t], sgn);
+      if constexpr (HIN) dft_half_in<R>(v[t], sgn);
+      else dft<R>(v[t], sgn);
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) snk(line, base + r * Ns, v[t][r]);
+      for (int r = 0; r < ROUT; ++r) {
+        if constexpr (WR_SPLIT) snk(line, base, r * Ns, v[t][r]);
+        else snk(line, base + r * Ns, 0, v[t][r]);
+      }
     }
   }
 }
 
 // Middle of a convolution: last forward stage (radix R, Ns = L/R), pointwise
-// multiply by the kernel spectrum gh(line, p), first inverse stage (radix R,
-// Ns = 1). The last forward stage leaves butterfly j holding points
+// multiply by the kernel spectrum gh(t, r, line, p), first inverse stage
+// (radix R, Ns = 1). The last forward stage leaves butterfly j holding points
 // j + r L/R, which are exactly the inputs of inverse butterfly j.
 template <class C, int R, class Src, class Gh, class Snk>
 __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restrict__ tw, Src&& src, Gh&& gh, Snk&& snk) {
   using T = typename C::T;
   constexpr int L = C::L, Ns = L / R, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
+  constexpr bool RD_SPLIT = (L / R) % 8 == 0;
   cplx<T> v[TT][R];
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
-    const int b = threadIdx.x + t * C::NT;
-    if (NB % C::NT == 0 || b < NB) {
+    if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
-      C::template split<R>(b, line, j);
+      C::template split<R>(t, line, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[t][r] = src(line, j + r * (L / R));
+      for (int r = 0; r < R; ++r)
+        v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
-    const int b = threadIdx.x + t * C::NT;
-    if (NB % C::NT == 0 || b < NB) {
+    if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
-      C::template split<R>(b, line, j);
-      apply_twiddles<R>(v[t], tw[j]);  // k = j < Ns, twiddle step 1
+      C::template split<R>(t, line, j);
+      if constexpr (R > 8) apply_twiddles_big<R>(v[t], tw[j], tw[8 * j]);  // k = j < Ns, step 1
+      else apply_twiddles<R>(v[t], tw[j]);
       dft<R>(v[t], -1);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[t][r] = v[t][r] * gh(t, r, line, j + r * Ns);
       dft<R>(v[t], +1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) snk(line, j * R + r, v[t][r]);
+      for (int r = 0; r < R; ++r) {
+        if constexpr (R % 8 == 0) snk(line, j * R, r, v[t][r]);
+        else snk(line, j * R + r, 0, v[t][r]);
+      }
     }
   }
 }
@@ -250,78 +405,83 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
 template <class C, int dir, int s, int Ns>
 __device__ __forceinline__ void fft_mid_stages(int sgn, const cplx<typename C::T>* __restrict__ tw,
                                                cplx<typename C::T>* sh) {
-  constexpr int S = plan_stages(C::L);
+  constexpr int S = plan_stages(C::L, C::BIG);
   if constexpr (s < S - 1) {
-    constexpr int R = stage_radix(C::L, dir, s);
-    fft_stage<C, R, Ns, true>(
-        sgn, tw, [&](int line, int p) { return sh[C::lds(line, p)]; },
-        [&](int line, int p, cplx<typename C::T> v) { sh[C::lds(line, p)] = v; });
+    constexpr int R = stage_radix(C::L, dir, s, C::BIG);
+    fft_stage<C, R, Ns, true, false, false>(
+        sgn, tw, [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; },
+        [&](int line, int pb, int ro, cplx<typename C::T> v) { sh[C::lds(line, pb, ro)] = v; });
     __syncthreads();
     fft_mid_stages<C, dir, s + 1, Ns * R>(sgn, tw, sh);
   }
 }
 
 // Ns before stage s of direction dir
-template <int L, int dir, int s>
+template <int L, bool BIG, int dir, int s>
 __host__ __device__ constexpr int ns_before() {
   if constexpr (s == 0) return 1;
-  else return ns_before<L, dir, s - 1>() * stage_radix(L, dir, s - 1);
+  else return ns_before<L, BIG, dir, s - 1>() * stage_radix(L, dir, s - 1, BIG);
 }
 
 // Full forward/inverse transform: first stage from src (global), middle stages
 // in LDS, last stage to snk (global). dir 0 = forward plan (sgn -1), 1 = inverse.
-template <class C, int dir, class Src, class Snk>
+// HIN / HOUT as in fft_stage, for the first / last stage.
+template <class C, int dir, bool HIN, bool HOUT, class Src, class Snk>
 __device__ __forceinline__ void fft_line_transform(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* sh,
                                                    Src&& src, Snk&& snk) {
   using T = typename C::T;
-  constexpr int S = plan_stages(C::L);
+  constexpr int S = plan_stages(C::L, C::BIG);
   const int sgn = dir == 0 ? -1 : +1;
-  constexpr int R0 = stage_radix(C::L, dir, 0);
-  fft_stage<C, R0, 1, false>(sgn, tw, src, [&](int line, int p, cplx<T> v) { sh[C::lds(line, p)] = v; });
+  constexpr int R0 = stage_radix(C::L, dir, 0, C::BIG);
+  fft_stage<C, R0, 1, false, HIN, false>(
+      sgn, tw, src, [&](int line, int pb, int ro, cplx<T> v) { sh[C::lds(line, pb, ro)] = v; });
   __syncthreads();
   fft_mid_stages<C, dir, 1, R0>(sgn, tw, sh);
-  constexpr int RL = stage_radix(C::L, dir, S - 1);
-  constexpr int NsL = ns_before<C::L, dir, S - 1>();
-  fft_stage<C, RL, NsL, false>(sgn, tw, [&](int line, int p) { return sh[C::lds(line, p)]; }, snk);
+  constexpr int RL = stage_radix(C::L, dir, S - 1, C::BIG);
+  constexpr int NsL = ns_before<C::L, C::BIG, dir, S - 1>();
+  fft_stage<C, RL, NsL, false, false, HOUT>(
+      sgn, tw, [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; }, snk);
 }
 
 // Points of the convolution middle stage held by this thread: butterfly t,
 // leg r -> (line, p). Used to prefetch the kernel spectrum into registers.
 template <class C>
 struct ConvMidMap {
-  static constexpr int S = plan_stages(C::L);
-  static constexpr int R = stage_radix(C::L, 0, S - 1);
+  static constexpr int S = plan_stages(C::L, C::BIG);
+  static constexpr int R = stage_radix(C::L, 0, S - 1, C::BIG);
   static constexpr int NB = C::NL * (C::L / R);
   static constexpr int TT = (NB + C::NT - 1) / C::NT;
   __device__ static __forceinline__ bool at(int t, int r, int& line, int& p) {
-    const int b = threadIdx.x + t * C::NT;
-    if (!(NB % C::NT == 0 || b < NB)) return false;
+    if (!(NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB)) return false;
     int j;
-    C::template split<R>(b, line, j);
+    C::template split<R>(t, line, j);
     p = j + r * (C::L / R);
     return true;
   }
 };
 
-// Convolution along a line: forward (from src), multiply by gh, inverse (to snk).
+// Convolution along a line: forward (from src), multiply by gh, inverse (to
+// snk). The input occupies at most the first half of the line and only the
+// first half of the output is kept (linear convolution by zero padding).
 template <class C, class Src, class Gh, class Snk>
 __device__ __forceinline__ void fft_line_convolve(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* sh,
                                                   Src&& src, Gh&& gh, Snk&& snk) {
   using T = typename C::T;
-  constexpr int S = plan_stages(C::L);
-  constexpr int R0 = stage_radix(C::L, 0, 0);
-  fft_stage<C, R0, 1, false>(-1, tw, src, [&](int line, int p, cplx<T> v) { sh[C::lds(line, p)] = v; });
+  constexpr int S = plan_stages(C::L, C::BIG);
+  constexpr int R0 = stage_radix(C::L, 0, 0, C::BIG);
+  auto to_lds = [&](int line, int pb, int ro, cplx<T> v) { sh[C::lds(line, pb, ro)] = v; };
+  auto from_lds = [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; };
+  fft_stage<C, R0, 1, false, true, false>(-1, tw, src, to_lds);
   __syncthreads();
   fft_mid_stages<C, 0, 1, R0>(-1, tw, sh);
-  constexpr int RL = stage_radix(C::L, 0, S - 1);
-  fft_conv_mid<C, RL>(tw, [&](int line, int p) { return sh[C::lds(line, p)]; }, gh,
-                      [&](int line, int p, cplx<T> v) { sh[C::lds(line, p)] = v; });
+  constexpr int RL = stage_radix(C::L, 0, S - 1, C::BIG);
+  fft_conv_mid<C, RL>(tw, from_lds, gh, to_lds);
   __syncthreads();
   // inverse plan is the reverse of the forward plan; its first stage (radix RL) is done
   fft_mid_stages<C, 1, 1, RL>(+1, tw, sh);
-  constexpr int RI = stage_radix(C::L, 1, S - 1);
-  constexpr int NsI = ns_before<C::L, 1, S - 1>();
-  fft_stage<C, RI, NsI, false>(+1, tw, [&](int line, int p) { return sh[C::lds(line, p)]; }, snk);
+  constexpr int RI = stage_radix(C::L, 1, S - 1, C::BIG);
+  constexpr int NsI = ns_before<C::L, C::BIG, 1, S - 1>();
+  fft_stage<C, RI, NsI, false, false, true>(+1, tw, from_lds, snk);
 }
 
 }  // namespace fwi

@@ -5,6 +5,9 @@
 // the tuning table that the on-device autotuner fills.
 #pragma once
 
+#include <algorithm>
+
+#include "bufview.hpp"
 #include "fft.hpp"
 #include "internal.hpp"
 
@@ -12,11 +15,7 @@ namespace fwi {
 
 constexpr int NT = 256;
 constexpr int kLdsMax = 160 * 1024;
-// 2D intermediate layout: columns grouped in tiles of CTILE, each tile stored
-// depth-major ([b][Lx/CTILE][nz][CTILE]) so the column pass streams contiguous
-// blocks and the row passes touch runs of (rows per workgroup) x CTILE points.
-constexpr int CTILE = 16;
-constexpr bool kTiled2D = false;  // measured: no gain for the column pass, slower row passes
+constexpr long kNarrowMax = 0x7fffffffL;  // bytes a 32-bit buffer view can cover
 
 // rows per workgroup of variant v: 2048 / 4096 / 8192 points
 template <typename T, int L, int V>
@@ -52,15 +51,14 @@ struct RowFwdArgs {
   long nrows;
   int rows_per_rhs, nin;
   long in_stride;
-  int tile;              // 0: rows of length L; CTILE: column-tiled output (2D)
 };
 
-template <typename T, int L, int NLV>
+// HIN: nin <= L/2, so the upper half of every padded row is skipped
+template <typename T, int L, int NLV, bool HIN>
 __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ long s_x[C::NL];
-  __shared__ long s_o[C::NL];
   __shared__ int s_m[C::NL];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
@@ -73,25 +71,22 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     const long z = g - b * a.rows_per_rhs;
     s_ok[l] = ok;
     s_x[l] = g * a.in_stride;
-    s_o[l] = a.tile ? b * a.rows_per_rhs * (long)L + z * a.tile : g * (long)L;
     s_m[l] = (int)z * a.nin;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
-  auto src = [&](int line, int p) -> cplx<T> {
+  auto src = [&](int line, int pb, int ro) -> cplx<T> {
+    const int p = pb + ro;
     if (!s_ok[line] || p >= a.nin) return mk((T)0, (T)0);
     cplx<T> v = a.x[s_x[line] + p];
     if (a.m) v = v * a.m[s_m[line] + p];
     if (a.scale) v = v * s_s[line];
     return v;
   };
-  const long tstride = (long)a.rows_per_rhs * a.tile;  // elements per column tile
-  auto snk = [&](int line, int p, cplx<T> v) {
-    if (!s_ok[line]) return;
-    if (a.tile) a.out[s_o[line] + (p / CTILE) * tstride + (p % CTILE)] = v;
-    else a.out[s_o[line] + p] = v;
+  auto snk = [&](int line, int pb, int ro, cplx<T> v) {
+    if (s_ok[line]) a.out[(g0 + line) * L + pb + ro] = v;
   };
-  fft_line_transform<C, 0>(a.tw, sh, src, snk);
+  fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
 }
 
 // ------------------------------------------------------------- row pass 3 ---
@@ -105,8 +100,7 @@ struct RowInvArgs {
   cplx<T>* y;            // [rows][nout]
   const cplx<T>* tw;
   long nrows;
-  int rows_per_rhs, nout;
-  int tile;              // 0: rows of length L; CTILE: column-tiled input (2D)
+  int rows_per_rhs, nout;  // nout <= L/2 (cropped output)
 };
 
 template <typename T, int L, int NLV, int EPI>
@@ -115,26 +109,22 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
-  __shared__ long s_i[C::NL];
   const long g0 = (long)blockIdx.x * C::NL;
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
     int ok = g < a.nrows;
     const long b = ok ? g / a.rows_per_rhs : 0;
     if (ok && a.active && !a.active[b]) ok = 0;
-    const long z = g - b * a.rows_per_rhs;
     s_ok[l] = ok;
-    s_i[l] = a.tile ? b * a.rows_per_rhs * (long)L + z * a.tile : g * (long)L;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
-  const long tstride = (long)a.rows_per_rhs * a.tile;
-  auto src = [&](int line, int p) -> cplx<T> {
+  auto src = [&](int line, int pb, int ro) -> cplx<T> {
     if (!s_ok[line]) return mk((T)0, (T)0);
-    if (a.tile) return a.in[s_i[line] + (p / CTILE) * tstride + (p % CTILE)];
-    return a.in[s_i[line] + p];
+    return a.in[(g0 + line) * L + pb + ro];
   };
-  auto snk = [&](int line, int p, cplx<T> v) {
+  auto snk = [&](int line, int pb, int ro, cplx<T> v) {
+    const int p = pb + ro;
     if (!s_ok[line] || p >= a.nout) return;
     const long o = (g0 + line) * a.nout + p;
     if constexpr (EPI == EPI_VIE) {
@@ -147,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
       a.y[o] = v;
     }
   };
-  fft_line_transform<C, 1>(a.tw, sh, src, snk);
+  fft_line_transform<C, 1, false, true>(a.tw, sh, src, snk);
 }
 
 // --------------------------------------------------------- strided passes ---
@@ -166,19 +156,28 @@ struct StridedArgs {
   int planes_per_rhs;
   int lin, lout;          // nonzero input points, output points kept
   long nplanes;           // planes in the launch
-  int tile;               // 0: line l at offset l; CTILE: line l in tile l / CTILE (pstride = CTILE)
-  long tile_stride;       // elements per column tile (tiled layout)
   long gpstride;          // Ghat stride between points of a line (conv)
 };
 
 constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolution pass
 
-template <typename T, int L, int NLV, int NTV, int MODE>  // MODE 0 forward, 1 inverse, 2 convolution
+// MODE 0 forward, 1 inverse, 2 convolution. HALF: the input occupies at most
+// the first half of a line (mode 0), only the first half of the output is kept
+// (mode 1); the convolution always has both. WIDE: 64-bit addressing for
+// planes of 2 GiB or more; otherwise every plane is a 32-bit buffer view whose
+// bounds do the zero padding and cropping.
+template <typename T, int L, int NLV, int NTV, int MODE, bool HALF, bool WIDE>
 __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
   using C = LineCfg<T, L, NLV, NTV, true>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
+  constexpr unsigned ES = sizeof(cplx<T>);
   const int line0 = blockIdx.x * C::NL;
   const int nl = a.nlines - line0;
+  // line-fastest mapping: the thread's line is fixed; a line past the plane
+  // gets an offset past every view (its loads read zero, its stores drop)
+  const int myline = (int)threadIdx.x % C::NL;
+  const unsigned loff = myline < nl ? (unsigned)(line0 + myline) * ES : kBufferOut;
+  const unsigned ps8 = (unsigned)a.pstride * ES;
   if constexpr (MODE == 2) {
     // CONV_RPW consecutive planes (right-hand sides) per workgroup share the
     // kernel-spectrum tile, which is prefetched into registers once per
@@ -193,44 +192,76 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
       if (a.active && !a.active[b]) continue;  // uniform per workgroup
       const int f = a.rhs_freq[b];
       if (f != fcur) {
-        const cplx<T>* gp = a.ghat + (long)f * a.gstride + line0;
+        if constexpr (WIDE) {
+          const cplx<T>* gp = a.ghat + (long)f * a.gstride + line0;
 #pragma unroll
-        for (int t = 0; t < Map::TT; ++t)
+          for (int t = 0; t < Map::TT; ++t)
 #pragma unroll
-          for (int r = 0; r < Map::R; ++r) {
-            int line, p;
-            gpre[t][r] = (Map::at(t, r, line, p) && line < nl) ? gp[p * a.gpstride + line] : mk((T)0, (T)0);
-          }
+            for (int r = 0; r < Map::R; ++r) {
+              int line, p;
+              gpre[t][r] = (Map::at(t, r, line, p) && line < nl) ? gp[p * a.gpstride + line] : mk((T)0, (T)0);
+            }
+        } else {
+          const unsigned gps8 = (unsigned)a.gpstride * ES;
+          const BufView gv(a.ghat + (long)f * a.gstride, (unsigned)L * gps8);
+#pragma unroll
+          for (int t = 0; t < Map::TT; ++t)
+#pragma unroll
+            for (int r = 0; r < Map::R; ++r) {
+              int line, p;
+              if (Map::at(t, r, line, p)) gpre[t][r] = gv.ld<T>(loff + (unsigned)p * gps8);
+            }
+        }
         fcur = f;
       }
-      const long loff = a.tile ? (line0 / a.tile) * a.tile_stride + line0 % a.tile : line0;
-      const cplx<T>* ip = a.in + plane * a.in_ps + loff;
-      cplx<T>* op = a.out + plane * a.out_ps + loff;
-      auto src = [&](int line, int p) -> cplx<T> {
-        if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
-        return ip[p * a.pstride + line];
-      };
-      auto snk = [&](int line, int p, cplx<T> v) {
-        if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
-      };
       auto gh = [&](int t, int r, int, int) -> cplx<T> { return gpre[t][r]; };
-      fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+      if constexpr (WIDE) {
+        const cplx<T>* ip = a.in + plane * a.in_ps + line0;
+        cplx<T>* op = a.out + plane * a.out_ps + line0;
+        auto src = [&](int line, int pb, int ro) -> cplx<T> {
+          const int p = pb + ro;
+          if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
+          return ip[p * a.pstride + line];
+        };
+        auto snk = [&](int line, int pb, int ro, cplx<T> v) {
+          const int p = pb + ro;
+          if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
+        };
+        fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+      } else {
+        const BufView iv(a.in + plane * a.in_ps, (unsigned)a.lin * ps8);
+        const BufView ov(a.out + plane * a.out_ps, (unsigned)a.lout * ps8);
+        auto src = [&](int, int pb, int ro) { return iv.ld<T>(loff + (unsigned)(pb + ro) * ps8); };
+        auto snk = [&](int, int pb, int ro, cplx<T> v) { ov.st<T>(loff + (unsigned)(pb + ro) * ps8, v); };
+        fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+      }
       __syncthreads();  // LDS is reused by the next plane
     }
   } else {
     const long plane = blockIdx.y;
     const int b = (int)(plane / a.planes_per_rhs);
     if (a.active && !a.active[b]) return;  // uniform per workgroup
-    const cplx<T>* ip = a.in + plane * a.in_ps + line0;
-    cplx<T>* op = a.out + plane * a.out_ps + line0;
-    auto src = [&](int line, int p) -> cplx<T> {
-      if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
-      return ip[p * a.pstride + line];
-    };
-    auto snk = [&](int line, int p, cplx<T> v) {
-      if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
-    };
-    fft_line_transform<C, MODE>(a.tw, sh, src, snk);
+    constexpr bool HIN = MODE == 0 && HALF, HOUT = MODE == 1 && HALF;
+    if constexpr (WIDE) {
+      const cplx<T>* ip = a.in + plane * a.in_ps + line0;
+      cplx<T>* op = a.out + plane * a.out_ps + line0;
+      auto src = [&](int line, int pb, int ro) -> cplx<T> {
+        const int p = pb + ro;
+        if (p >= a.lin || line >= nl) return mk((T)0, (T)0);
+        return ip[p * a.pstride + line];
+      };
+      auto snk = [&](int line, int pb, int ro, cplx<T> v) {
+        const int p = pb + ro;
+        if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
+      };
+      fft_line_transform<C, MODE, HIN, HOUT>(a.tw, sh, src, snk);
+    } else {
+      const BufView iv(a.in + plane * a.in_ps, (unsigned)a.lin * ps8);
+      const BufView ov(a.out + plane * a.out_ps, (unsigned)a.lout * ps8);
+      auto src = [&](int, int pb, int ro) { return iv.ld<T>(loff + (unsigned)(pb + ro) * ps8); };
+      auto snk = [&](int, int pb, int ro, cplx<T> v) { ov.st<T>(loff + (unsigned)(pb + ro) * ps8, v); };
+      fft_line_transform<C, MODE, HIN, HOUT>(a.tw, sh, src, snk);
+    }
   }
 }
 
@@ -240,7 +271,13 @@ void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
   constexpr int NL = row_nl<T, L, V>();
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
-  hipLaunchKernelGGL((k_row_fwd<T, L, NL>), dim3(grid), dim3(NT), 0, st, a);
+  if (2 * a.nin <= L) {
+    hipLaunchKernelGGL((k_row_fwd<T, L, NL, true>), dim3(grid), dim3(NT), 0, st, a);
+  } else if constexpr (sizeof(T) == 8) {
+    hipLaunchKernelGGL((k_row_fwd<T, L, NL, false>), dim3(grid), dim3(NT), 0, st, a);
+  } else {
+    throw Error(-6, "complex64 row transforms need zero-padded rows");
+  }
   FWI_LAUNCH_CHECK();
 }
 template <typename T, int L, int V>
@@ -248,24 +285,59 @@ void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
   constexpr int NL = row_nl<T, L, V>();
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
+  if (2 * a.nout > L) throw Error(-6, "inverse row transform must crop to half a padded row");
   if (epi == EPI_VIE) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
   else if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
   else hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
   FWI_LAUNCH_CHECK();
 }
+template <typename T, int L, int V, int MODE, bool HALF, bool WIDE>
+void launch_strided_k(const StridedArgs<T>& a, dim3 grid, hipStream_t st) {
+  constexpr int NL = col_nl<T, L, V>();
+  constexpr int NTV = col_nt<V>();
+  hipLaunchKernelGGL((k_strided<T, L, NL, NTV, MODE, HALF, WIDE>), grid, dim3(NTV), 0, st, a);
+}
 template <typename T, int L, int V>
 void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {
   constexpr int NL = col_nl<T, L, V>();
-  constexpr int NTV = col_nt<V>();
   if (planes == 0) return;
   StridedArgs<T> args = a;
   args.nplanes = planes;
   const long gy = mode == 2 ? (planes + CONV_RPW - 1) / CONV_RPW : planes;
   if (gy > 65535) throw Error(-6, "too many planes for one strided pass");
   dim3 grid((a.nlines + NL - 1) / NL, (unsigned)gy);
-  if (mode == 0) hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 0>), grid, dim3(NTV), 0, st, args);
-  else if (mode == 1) hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 1>), grid, dim3(NTV), 0, st, args);
-  else hipLaunchKernelGGL((k_strided<T, L, NL, NTV, 2>), grid, dim3(NTV), 0, st, args);
+  // 32-bit views need every offset of a line point (p < L) below 2^31, so that
+  // an out-of-plane line (offset kBufferOut + ...) cannot wrap into range
+  const long es = sizeof(cplx<T>);
+  const long span = (long)L * std::max(a.pstride, mode == 2 ? a.gpstride : 0L) * es + (long)a.nlines * es;
+  const bool wide = span > kNarrowMax;
+  const bool hin = 2 * a.lin <= L, hout = 2 * a.lout <= L;
+  if (mode == 2) {
+    if (!hin || !hout) throw Error(-6, "convolution lines must be zero-padded to twice their length");
+    // 64-bit path: one tile variant only
+    if (wide) launch_strided_k<T, L, 0, 2, true, true>(args, dim3((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y), st);
+    else launch_strided_k<T, L, V, 2, true, false>(args, grid, st);
+  } else if (mode == 0) {
+    if (wide) {
+      if constexpr (sizeof(T) == 8) {
+        const dim3 g0((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y);
+        if (hin) launch_strided_k<T, L, 0, 0, true, true>(args, g0, st);
+        else launch_strided_k<T, L, 0, 0, false, true>(args, g0, st);
+      } else {
+        throw Error(-6, "complex64 strided pass over a plane of 2 GiB or more");
+      }
+    } else if (hin) {
+      launch_strided_k<T, L, V, 0, true, false>(args, grid, st);
+    } else if constexpr (sizeof(T) == 8) {
+      launch_strided_k<T, L, V, 0, false, false>(args, grid, st);
+    } else {
+      throw Error(-6, "complex64 strided transforms need zero-padded lines");
+    }
+  } else {
+    if (!hout) throw Error(-6, "inverse strided transform must crop to half a line");
+    if (wide) launch_strided_k<T, L, 0, 1, true, true>(args, dim3((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y), st);
+    else launch_strided_k<T, L, V, 1, true, false>(args, grid, st);
+  }
   FWI_LAUNCH_CHECK();
 }
 
@@ -330,7 +402,6 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.rows_per_rhs = (int)rows_per_rhs;
   f.nin = g.nx;
   f.in_stride = g.nx;
-  f.tile = (g.dim == 2 && kTiled2D) ? CTILE : 0;
   prof_begin(KC_ROW_FWD + po, st);
   row_fwd_call<T>(g.Lx, f, st);
   prof_end(KC_ROW_FWD + po, st, act * (n + g.u1()) * es + n * es);
@@ -344,9 +415,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.rhs_freq = rhs_freq;
     s.active = active;
     s.in_ps = s.out_ps = (long)g.nz * g.Lx;
-    s.tile = kTiled2D ? CTILE : 0;
-    s.tile_stride = (long)g.nz * CTILE;
-    s.pstride = kTiled2D ? CTILE : g.Lx;
+    s.pstride = g.Lx;
     s.gstride = g.npad();
     s.gpstride = g.Lx;
     s.nlines = g.Lx;
@@ -419,7 +488,6 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   r.nrows = rows_per_rhs * B;
   r.rows_per_rhs = (int)rows_per_rhs;
   r.nout = g.nx;
-  r.tile = (g.dim == 2 && kTiled2D) ? CTILE : 0;
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
   prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() + (epi == EPI_RESID ? 3.0 : 2.0) * n) * es);
