@@ -395,7 +395,7 @@ void bind_workspace(fwi_ctx* c, Arena& a, size_t need) {
 template <typename T>
 struct SolveBufs {
   KrylovState<T> ks;
-  c128* r64 = nullptr;
+  double* rowpart = nullptr;  // [B][nz*ny] residual norm partials
   cplx<T>* U1 = nullptr;
   cplx<T>* U2 = nullptr;
   c128* U1_64 = nullptr;
@@ -429,7 +429,7 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.iters = a.take<int>(B);
   k.counters = a.take<int>(2);
   k.maxrel = a.take<double>(1);
-  s.r64 = a.take<c128>((size_t)B * n);
+  s.rowpart = a.take<double>((size_t)B * g.nz * g.ny);
   s.U1 = a.take<cplx<T>>((size_t)B * g.u1());
   s.U2 = g.dim == 3 ? a.take<cplx<T>>((size_t)B * g.u2()) : nullptr;
   if (std::is_same<T, float>::value) {
@@ -462,6 +462,20 @@ struct SolveTotals {
 // Each cycle starts from the true FP64 residual r = b - A x, normalises it,
 // runs at most `restart` Arnoldi steps per RHS (stopping each RHS at its
 // target) and adds the correction to the FP64 solution x.
+// r = b - A x in FP64 for every RHS; the epilogue stores r into V_0 of the
+// basis (rounded to the basis precision) and one |r|^2 partial per grid row.
+template <typename T>
+void launch_residual_basis(const Geo& g, const Twiddles& tw, int B, const c128* x64, const c128* m64,
+                           const c128* ghat64, const int* rhs_freq, SolveBufs<T>& s, const c128* b64,
+                           hipStream_t st) {
+  if (std::is_same<T, float>::value)
+    launch_vie<double>(g, tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64, nullptr, b64,
+                       EPI_RESID32, st, reinterpret_cast<c64*>(s.ks.V), s.rowpart);
+  else
+    launch_vie<double>(g, tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64,
+                       reinterpret_cast<c128*>(s.ks.V), b64, EPI_RESID, st, nullptr, s.rowpart);
+}
+
 template <typename T>
 SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* mT, const c128* ghat64,
                       const cplx<T>* ghatT, int B, const c128* b64, const int* rhs_freq, c128* x64,
@@ -476,19 +490,19 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   const double t0 = now_ms();
   SolveTotals res;
   res.solves = B;
-  launch_fill_zero_c128((long)B * ks.n, x64, st);
   krylov_reset_iters(ks, st);
   int total = 0, cyc = 0;
+  bool x_written = false;
   for (;; ++cyc) {
-    const c128* r = b64;
-    if (cyc > 0) {
+    if (cyc == 0) {
+      krylov_start_norm(ks, b64, st);  // x_0 = 0: r = b
+    } else {
+      // FP64 residual; its epilogue writes V_0 (unscaled) and per-row norms
       tl_active = B;
-      launch_vie<double>(g, c->tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64, s.r64, b64,
-                         EPI_RESID, st);
-      r = s.r64;
+      launch_residual_basis(g, c->tw, B, x64, m64, ghat64, rhs_freq, s, b64, st);
+      krylov_rows_norm(ks, s.rowpart, g.nz * g.ny, st);
       res.matvecs += B;
     }
-    krylov_norms(ks, r, st);
     krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
     FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
     FWI_HIP(hipMemcpyAsync(c->h_dbl, ks.maxrel, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -502,7 +516,6 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       res.unconverged = nact;
       break;
     }
-    krylov_start_basis(ks, r, st);
     for (int j = 0; j < ks.JM; ++j) {
       launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, ghatT, rhs_freq,
                     s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
@@ -516,8 +529,10 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       }
       if (total >= o.max_iter) break;
     }
-    krylov_finish_cycle(ks, x64, st);
+    krylov_finish_cycle(ks, x64, cyc == 0, st);
+    x_written = true;
   }
+  if (!x_written) launch_fill_zero_c128((long)B * ks.n, x64, st);  // nothing to solve: x = 0
   res.cycles = cyc;
   std::vector<int> it(B);
   FWI_HIP(hipMemcpyAsync(it.data(), ks.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
@@ -972,21 +987,19 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   const cplx<T>* mT = fp32 ? (const cplx<T>*)I.cb.m32 : (const cplx<T>*)I.cb.m64;
   const cplx<T>* gT = fp32 ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
   const long vs = ks.vstride();
-  const c128* r = rhs;
-  if (cyc > 0) {
-    launch_vie<double>(I.g, c->tw, ks.B, x, nullptr, nullptr, I.cb.m64, pc.ghat64, pc.rhs_freq, s.U1_64, s.U2_64,
-                       s.r64, rhs, EPI_RESID, st);
-    r = s.r64;
+  if (cyc == 0) {
+    krylov_start_norm(ks, rhs, st);
+  } else {
+    launch_residual_basis(I.g, c->tw, ks.B, x, I.cb.m64, pc.ghat64, pc.rhs_freq, s, rhs, st);
+    krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
   }
-  krylov_norms(ks, r, st);
   krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
-  krylov_start_basis(ks, r, st);
   for (int j = 0; j < ks.JM; ++j) {
     launch_vie<T>(I.g, c->tw, ks.B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, gT,
                   pc.rhs_freq, s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
     krylov_arnoldi(ks, j, st);
   }
-  krylov_finish_cycle(ks, x, st);
+  krylov_finish_cycle(ks, x, cyc == 0, st);
 }
 
 template <typename T, class RhsOf, class XOf>
@@ -1031,10 +1044,7 @@ void batch_solve(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int* ctr_dev, con
   const bool fp32 = std::is_same<T, float>::value;
   const int max_cycles = fp32 ? o.max_refine : (o.max_iter + o.restart - 1) / o.restart + 1;
   const double t0 = now_ms();
-  for (BatchInst<T>* I : wave) {
-    launch_fill_zero_c128((long)I->B * I->n, x_of(*I), main);
-    krylov_reset_iters(I->sb.ks, main);
-  }
+  for (BatchInst<T>* I : wave) krylov_reset_iters(I->sb.ks, main);  // x is written by the first cycle
   hipGraphExec_t g0 = capture_cycle<T>(c, wave, 0, o, rhs_of, x_of);
   hipGraphExec_t gN = nullptr;
   try {

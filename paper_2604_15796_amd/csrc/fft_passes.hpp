@@ -101,14 +101,23 @@ struct RowInvArgs {
   const cplx<T>* tw;
   long nrows;
   int rows_per_rhs, nout;  // nout <= L/2 (cropped output)
+  c64* y32;              // EPI_RESID32 output [rows][nout]
+  double* rowpart;       // EPI_RESID / EPI_RESID32: [rows] sum of |residual|^2
 };
 
 template <typename T, int L, int NLV, int EPI>
 __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
+  constexpr bool RESID = EPI == EPI_RESID || EPI == EPI_RESID32;
+  // last stage: butterfly j < NsL of a line stores points j + r NsL, so
+  // (line, p mod NsL) names one thread: per-row sums need no atomics
+  constexpr int NsL = L / stage_radix(L, 1, plan_stages(L, C::BIG) - 1, C::BIG);
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
+  __shared__ double s_part[RESID ? C::NL * NsL : 1];
+  if constexpr (RESID)
+    for (int i = threadIdx.x; i < C::NL * NsL; i += NT) s_part[i] = 0.0;
   const long g0 = (long)blockIdx.x * C::NL;
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
@@ -131,13 +140,24 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
       cplx<T> xv = a.x[o];
       if (a.scale) xv = xv * s_s[line];
       a.y[o] = xv - v;
-    } else if constexpr (EPI == EPI_RESID) {
-      a.y[o] = a.rhs[o] - (a.x[o] - v);
+    } else if constexpr (RESID) {
+      const cplx<T> r = a.rhs[o] - (a.x[o] - v);
+      if constexpr (EPI == EPI_RESID) a.y[o] = r;
+      else a.y32[o] = mk((float)r.x, (float)r.y);
+      s_part[line * NsL + p % NsL] += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
     } else {
       a.y[o] = v;
     }
   };
   fft_line_transform<C, 1, false, true>(a.tw, sh, src, snk);
+  if constexpr (RESID) {
+    __syncthreads();
+    if (threadIdx.x < C::NL && s_ok[threadIdx.x]) {
+      double s = 0.0;
+      for (int i = 0; i < NsL; ++i) s += s_part[threadIdx.x * NsL + i];
+      a.rowpart[g0 + threadIdx.x] = s;
+    }
+  }
 }
 
 // --------------------------------------------------------- strided passes ---
@@ -286,9 +306,16 @@ void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
   if (2 * a.nout > L) throw Error(-6, "inverse row transform must crop to half a padded row");
-  if (epi == EPI_VIE) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
-  else if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
-  else hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
+  if (epi == EPI_VIE) {
+    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
+  } else if (epi == EPI_COPY) {
+    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
+  } else if constexpr (sizeof(T) == 8) {
+    if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID32>), dim3(grid), dim3(NT), 0, st, a);
+  } else {
+    throw Error(-6, "residual epilogue needs the complex128 operator");
+  }
   FWI_LAUNCH_CHECK();
 }
 template <typename T, int L, int V, int MODE, bool HALF, bool WIDE>
@@ -383,7 +410,7 @@ void row_inv_call(int L, const RowInvArgs<T>& a, int epi, hipStream_t st) {
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st) {
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const double act = (double)(active && tl_active > 0 && tl_active < B ? tl_active : B);
@@ -488,9 +515,17 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   r.nrows = rows_per_rhs * B;
   r.rows_per_rhs = (int)rows_per_rhs;
   r.nout = g.nx;
+  r.y32 = y32;
+  r.rowpart = rowpart;
+  // per RHS: the x-pass intermediate, then x and y (VIE), or x, rhs, the
+  // residual (complex128 or complex64) and one norm partial per row
+  const double rows = (double)g.nz * g.ny;
+  const double epi_bytes = epi == EPI_RESID     ? 3.0 * n * es + 8.0 * rows
+                           : epi == EPI_RESID32 ? (2.0 * es + 8.0) * n + 8.0 * rows
+                                                : 2.0 * n * es;
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
-  prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() + (epi == EPI_RESID ? 3.0 : 2.0) * n) * es);
+  prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() * es + epi_bytes));
 }
 
 #ifdef FWI_FFT_WITH_FULL

@@ -95,11 +95,13 @@ struct Geo {
   long u2() const { return dim == 3 ? (long)nz * Ly * Lx : 0; }
 };
 
-enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2 };
+enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3 };
 
 // y = A x for B right-hand sides (Eq. 5 discretised):
 //   EPI_VIE  : y_b = s_b x_b - conv(m * s_b x_b)
-//   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored)
+//   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored), and
+//              rowpart[row] = sum over the row of |y_b|^2 (rows of nx points)
+//   EPI_RESID32: the same residual rounded to complex64 into y32 (y unused)
 // x, y, rhs: [B][n]; scale: [B] or null; active: [B] or null (inactive RHS are
 // skipped and their y left untouched); ghat: [nf][npad] spectra with k^2 and
 // 1/npad folded in; rhs_freq: [B] frequency index per RHS; U1 [B][u1],
@@ -107,7 +109,7 @@ enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2 };
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st);
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr, double* rowpart = nullptr);
 
 // Forward FFT of a full padded grid [Lz][Ly][Lx] (no padding, no crop), in place
 // through `work` of the same size: out = FFT(in). Used for the Green spectrum.

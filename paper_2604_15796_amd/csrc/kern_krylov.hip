@@ -210,15 +210,37 @@ __global__ void __launch_bounds__(1024) k_givens(int j, int B, int nblk, int* __
 }
 
 // |x_b|^2 partial sums of an FP64 array [B][n]
-__global__ void __launch_bounds__(KT) k_norm_partial(const c128* __restrict__ x, long n, int chunk,
-                                                     double* __restrict__ nrmp, int nblk) {
+// First cycle (x_0 = 0, r = b): V_0 = (T) b, unscaled, and nrmp[b][blk] =
+// |b|^2 over the block's chunk (FP64, fixed order).
+template <typename T>
+__global__ void __launch_bounds__(KT) k_start_norm(const c128* __restrict__ x, cplx<T>* __restrict__ V0, long n,
+                                                   int chunk, double* __restrict__ nrmp, int nblk) {
   __shared__ double red[KT / 64];
   const int b = blockIdx.y;
   const long e0 = (long)blockIdx.x * chunk;
   const long e1 = min(n, e0 + chunk);
   const c128* xb = x + (long)b * n;
+  cplx<T>* vb = V0 + (long)b * n;
   double acc = 0.0;
-  for (long e = e0 + threadIdx.x; e < e1; e += KT) acc += norm2(xb[e]);
+  for (long e = e0 + threadIdx.x; e < e1; e += KT) {
+    const c128 v = xb[e];
+    vb[e] = mk((T)v.x, (T)v.y);
+    acc += norm2(v);
+  }
+  const double s = block_sum<KT>(acc, red);
+  if (threadIdx.x == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
+}
+
+// nrmp[b][blk] = sum of the block's share of the per-row partials of RHS b.
+__global__ void __launch_bounds__(KT) k_rows_norm(const double* __restrict__ rowpart, int rows, int per,
+                                                  double* __restrict__ nrmp, int nblk) {
+  __shared__ double red[KT / 64];
+  const int b = blockIdx.y;
+  const int r0 = blockIdx.x * per;
+  const int r1 = min(rows, r0 + per);
+  const double* rp = rowpart + (long)b * rows;
+  double acc = 0.0;
+  for (int r = r0 + threadIdx.x; r < r1; r += KT) acc += rp[r];
   const double s = block_sum<KT>(acc, red);
   if (threadIdx.x == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
 }
@@ -230,7 +252,8 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
                                                      double* __restrict__ bnorm, double* __restrict__ target,
                                                      double* __restrict__ rscale, int* __restrict__ active,
                                                      int* __restrict__ ncol, c128* __restrict__ gv,
-                                                     int* __restrict__ counters, double* __restrict__ maxrel) {
+                                                     int* __restrict__ counters, double* __restrict__ maxrel,
+                                                     cplx<T>* __restrict__ vscale0) {
   __shared__ double red[1024 / 64];
   __shared__ double redm[1024 / 64];
   double cnt = 0.0, mx = 0.0;
@@ -253,6 +276,7 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
       if (inner_rtol > tg) tg = inner_rtol;
       target[b] = tg;
       rscale[b] = 1.0 / rn;
+      vscale0[b] = mk((T)(1.0 / rn), (T)0);  // V_0 holds r unscaled
     }
   }
   const double tot = block_sum<1024>(cnt, red);
@@ -268,23 +292,6 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
     maxrel[0] = mm;
     counters[0] = (int)tot;
     counters[1] = (int)tot;
-  }
-}
-
-// V0_b = (T)(r_b / |r_b|)
-template <typename T>
-__global__ void __launch_bounds__(KT) k_start_basis(const c128* __restrict__ r, cplx<T>* __restrict__ V0, long n,
-                                                    const int* __restrict__ active, const double* __restrict__ rscale,
-                                                    cplx<T>* __restrict__ vscale0) {
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) vscale0[b] = mk((T)1, (T)0);
-  const double s = rscale[b];
-  const c128* rb = r + (long)b * n;
-  cplx<T>* vb = V0 + (long)b * n;
-  for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
-    const c128 v = rb[e];
-    vb[e] = mk((T)(v.x * s), (T)(v.y * s));
   }
 }
 
@@ -306,15 +313,20 @@ __global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __r
   }
 }
 
-// x_b += |r_b| sum_{i < ncol_b} y_i V_i  (FP64 accumulation)
+// x_b += |r_b| sum_{i < ncol_b} y_i V_i  (FP64 accumulation); first: x_b is
+// not read (the first cycle starts from x = 0), and RHS that did no step get 0.
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, long vs, long n,
                                                 const int* __restrict__ ncol, const c128* __restrict__ y,
                                                 const double* __restrict__ rnorm, const cplx<T>* __restrict__ vscale,
-                                                int B, c128* __restrict__ x) {
+                                                int B, c128* __restrict__ x, int first) {
   const int b = blockIdx.y;
   const int k = ncol[b];
-  if (k == 0) return;
+  if (k == 0) {
+    if (first)
+      for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) x[(long)b * n + e] = mk(0.0, 0.0);
+    return;
+  }
   __shared__ double yr[JM], yi[JM];
   if (threadIdx.x < k) {
     const c128 v = y[(long)b * JM + threadIdx.x];
@@ -325,7 +337,7 @@ __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, l
   __syncthreads();
   const long off = (long)b * n;
   for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
-    c128 acc = x[off + e];
+    c128 acc = first ? mk(0.0, 0.0) : x[off + e];
 #pragma unroll
     for (int i = 0; i < JM; ++i) {
       if (i < k) {
@@ -380,8 +392,15 @@ static unsigned vec_blocks(long n) {
   }
 
 template <typename T>
-void krylov_norms(const KrylovState<T>& s, const c128* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_norm_partial, dim3(s.nblk, s.B), dim3(KT), 0, st, x, s.n, s.chunk, s.nrmp, s.nblk);
+void krylov_start_norm(const KrylovState<T>& s, const c128* b, hipStream_t st) {
+  hipLaunchKernelGGL((k_start_norm<T>), dim3(s.nblk, s.B), dim3(KT), 0, st, b, s.V, s.n, s.chunk, s.nrmp, s.nblk);
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, hipStream_t st) {
+  const int per = (rows + s.nblk - 1) / s.nblk;
+  hipLaunchKernelGGL(k_rows_norm, dim3(s.nblk, s.B), dim3(KT), 0, st, rowpart, rows, per, s.nrmp, s.nblk);
   FWI_LAUNCH_CHECK();
 }
 
@@ -389,14 +408,7 @@ template <typename T>
 void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st) {
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_cycle_init<T, JMC>), dim3(1), dim3(1024), 0, st, s.B, s.nblk, first, rtol,
                                           inner_rtol, s.nrmp, s.rnorm, s.bnorm, s.target, s.rscale, s.active, s.ncol,
-                                          s.gv, s.counters, s.maxrel));
-  FWI_LAUNCH_CHECK();
-}
-
-template <typename T>
-void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st) {
-  hipLaunchKernelGGL((k_start_basis<T>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, r, s.V, s.n, s.active, s.rscale,
-                     s.vscale);
+                                          s.gv, s.counters, s.maxrel, s.vscale));
   FWI_LAUNCH_CHECK();
 }
 
@@ -423,12 +435,12 @@ void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st) {
 }
 
 template <typename T>
-void krylov_finish_cycle(const KrylovState<T>& s, c128* x, hipStream_t st) {
+void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st) {
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_backsolve<JMC>), dim3((s.B + 63) / 64), dim3(64), 0, st, s.B, s.ncol,
                                           s.H, s.gv, s.y));
   FWI_LAUNCH_CHECK();
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_xupdate<T, JMC>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V,
-                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, s.vscale, s.B, x));
+                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, s.vscale, s.B, x, first));
   FWI_LAUNCH_CHECK();
 }
 
@@ -439,11 +451,11 @@ void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
 }
 
 #define FWI_INST(T)                                                                            \
-  template void krylov_norms<T>(const KrylovState<T>&, const c128*, hipStream_t);              \
+  template void krylov_start_norm<T>(const KrylovState<T>&, const c128*, hipStream_t);         \
+  template void krylov_rows_norm<T>(const KrylovState<T>&, const double*, int, hipStream_t);   \
   template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
-  template void krylov_start_basis<T>(const KrylovState<T>&, const c128*, hipStream_t);        \
   template void krylov_arnoldi<T>(const KrylovState<T>&, int, hipStream_t);                    \
-  template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, hipStream_t);             \
+  template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, int, hipStream_t);        \
   template void krylov_reset_iters<T>(const KrylovState<T>&, hipStream_t);
 FWI_INST(float)
 FWI_INST(double)

@@ -37,16 +37,21 @@ struct KrylovState {
 
 int krylov_nblk(long n);
 
+// First cycle: V_0 = (T) b (stored unscaled) and the norm partials of b.
 template <typename T>
-void krylov_norms(const KrylovState<T>& s, const c128* x, hipStream_t st);  // -> nrmp
+void krylov_start_norm(const KrylovState<T>& s, const c128* b, hipStream_t st);  // -> V_0, nrmp
+// Later cycles: V_0 was written by the residual epilogue of the operator
+// together with one |r|^2 partial per grid row; fold those into nrmp.
+template <typename T>
+void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, hipStream_t st);
+// Norms, activity, stopping targets and the scale of V_0 (1 / |r|).
 template <typename T>
 void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st);
 template <typename T>
-void krylov_start_basis(const KrylovState<T>& s, const c128* r, hipStream_t st);
-template <typename T>
 void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st);  // dots, orth, givens, normalise
+// Back-substitution and x update; first: x is written, not read (x_0 = 0).
 template <typename T>
-void krylov_finish_cycle(const KrylovState<T>& s, c128* x, hipStream_t st);  // backsolve + x update
+void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st);
 template <typename T>
 void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st);
 
