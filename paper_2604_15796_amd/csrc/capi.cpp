@@ -574,7 +574,7 @@ struct CallBufs {
 constexpr int kGradSeg = 16;
 
 int gemm_splits(long n) {
-  long s = (n + 2047) / 2048;
+  long s = (n + 1023) / 1024;
   return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
 }
 

@@ -49,6 +49,15 @@ template <typename T>
 __host__ __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
   return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+// acc + a * b as four fused multiply-adds
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> cfma(cplx<T> a, cplx<T> b, cplx<T> acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
 template <typename T>
 __host__ __device__ __forceinline__ T norm2(cplx<T> a) {
   return a.x * a.x + a.y * a.y;

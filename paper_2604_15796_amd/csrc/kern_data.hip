@@ -15,8 +15,12 @@ namespace fwi {
 constexpr double PI = 3.14159265358979323846;
 
 // ------------------------------------------------------------- gemm (NT) ---
-constexpr int GT = 32;  // output tile
-constexpr int GK = 32;  // k step
+// 64 x 64 output tile per block, 256 threads each holding a 4 x 4 complex
+// register block (rows ty + 16a, columns tx + 16b): every A and Bm element of a
+// split is read from HBM once per output tile, and each LDS value feeds four
+// complex FMAs.
+constexpr int GT = 64;  // output tile
+constexpr int GK = 16;  // k step
 
 // part[ks][l][i][j] = sum over the split's k range of A[l][i][k] w[k] Bm[l][j][k]
 __global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, long a_ls, int ni,
@@ -32,42 +36,65 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, lon
   const int ty = t / 16, tx = t % 16;
   const c128* Al = A + l * a_ls;
   const c128* Bl = Bm + l * b_ls;
-  c128 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = mk(0.0, 0.0);
+  c128 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
   const long k0 = ks * kchunk;
   const long k1 = min(n, k0 + kchunk);
-  for (long kb = k0; kb < k1; kb += GK) {
-    // load 32x32 tiles of A (rows ti*32..) and Bm (rows tj*32..), k in [kb, kb+32)
-    for (int e = t; e < GT * GK; e += 256) {
+  // 64 x 16 tiles of A (rows ti*64 ..) and Bm (rows tj*64 ..), k in [kb, kb+16);
+  // the next tile is loaded into registers while the current one is used
+  // (raw loads only: the weight is applied at the LDS store, so no load is
+  // waited for before the current tile's products)
+  // Loads use clamped indices and are masked at the LDS store, so nothing
+  // waits for them before the current tile's products.
+  constexpr int Q = GT * GK / 256;
+  c128 ra[Q], rb[Q], rw[Q];
+  bool va[Q], vb[Q];
+  auto fetch = [&](long kb) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = t + q * 256;
       const int r = e / GK, c = e % GK;
       const long k = kb + c;
       const int ia = ti * GT + r, jb = tj * GT + r;
-      c128 va = mk(0.0, 0.0), vb = mk(0.0, 0.0);
-      if (k < k1) {
-        if (ia < ni) {
-          va = Al[(long)ia * n + k];
-          if (w) va = va * w[k];
-        }
-        if (jb < nj) vb = Bl[(long)jb * n + k];
-      }
-      sa[r][c] = va;
-      sb[r][c] = vb;
+      va[q] = k < k1 && ia < ni;
+      vb[q] = k < k1 && jb < nj;
+      const long kc = k < k1 ? k : k1 - 1;
+      ra[q] = Al[(long)(ia < ni ? ia : ni - 1) * n + kc];
+      rb[q] = Bl[(long)(jb < nj ? jb : nj - 1) * n + kc];
+      rw[q] = w ? w[kc] : mk(1.0, 0.0);
+    }
+  };
+  if (k0 < k1) fetch(k0);
+  for (long kb = k0; kb < k1; kb += GK) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = t + q * 256;
+      sa[e / GK][e % GK] = va[q] ? ra[q] * rw[q] : mk(0.0, 0.0);
+      sb[e / GK][e % GK] = vb[q] ? rb[q] : mk(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll 8
+    if (kb + GK < k1) fetch(kb + GK);
+#pragma unroll 4
     for (int c = 0; c < GK; ++c) {
-      const c128 a0 = sa[ty][c], a1 = sa[ty + 16][c];
-      const c128 b0 = sb[tx][c], b1 = sb[tx + 16][c];
-      acc[0][0] = acc[0][0] + a0 * b0;
-      acc[0][1] = acc[0][1] + a0 * b1;
-      acc[1][0] = acc[1][0] + a1 * b0;
-      acc[1][1] = acc[1][1] + a1 * b1;
+      c128 av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = sa[ty + 16 * a][c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = sb[tx + 16 * b][c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = cfma(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
       const int i = ti * GT + ty + 16 * a, j = tj * GT + tx + 16 * b;
       if (i < ni && j < nj) part[(((long)ks * nf + l) * ni + i) * nj + j] = acc[a][b];
     }
@@ -85,34 +112,88 @@ __global__ void k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, 
 }
 
 // ------------------------------------------------------------- gemm (NN) ---
-constexpr int NI = 16;  // rows of M per block
+// S[l][i][n] = sum_j conj(M[l][i][j]) P[l][j][n]: 64 (i) x 64 (n) output tile
+// per block, 4 x 4 complex register block per thread, j in steps of 16 through
+// LDS; each P element is read from HBM once per 64 rows of S.
+constexpr int CT = 64;  // output tile (rows of S, points n)
+constexpr int CK = 16;  // j step
 
-// S[l][i][n] = sum_j conj(M[l][i][j]) P[l][j][n]   (i in a 16-row tile, one n per thread)
 __global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int ni, int nj,
                                                  const c128* __restrict__ P, long p_ls, long n,
                                                  c128* __restrict__ S, long s_ls) {
-  extern __shared__ c128 sm[];  // [NI][nj]
+  __shared__ c128 sm[CT][CK + 1];   // conj(M) tile [i][j]
+  __shared__ c128 sp[CK][CT + 1];   // P tile [j][n]
   const int l = blockIdx.z;
-  const int i0 = blockIdx.y * NI;
-  for (int e = threadIdx.x; e < NI * nj; e += 256) {
-    const int r = e / nj, c = e % nj;
-    sm[e] = (i0 + r < ni) ? conj(M[((long)l * ni + i0 + r) * nj + c]) : mk(0.0, 0.0);
-  }
-  __syncthreads();
-  const long e = (long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  c128 acc[NI];
-#pragma unroll
-  for (int r = 0; r < NI; ++r) acc[r] = mk(0.0, 0.0);
+  const int i0 = blockIdx.y * CT;
+  const long n0 = (long)blockIdx.x * CT;
+  const int t = threadIdx.x;
+  const int ty = t / 16, tx = t % 16;
+  const c128* Ml = M + (long)l * ni * nj;
   const c128* Pl = P + l * p_ls;
-  for (int j = 0; j < nj; ++j) {
-    const c128 p = Pl[(long)j * n + e];
+  c128 acc[4][4];
 #pragma unroll
-    for (int r = 0; r < NI; ++r) acc[r] = acc[r] + sm[r * nj + j] * p;
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+  // M tile (row-major [i][j]) and P tile (n fastest, coalesced); the next pair
+  // is loaded into registers while the current one is used
+  // (clamped loads, masked at the LDS store: nothing waits for them early)
+  constexpr int Q = CT * CK / 256;
+  c128 rm[Q], rp[Q];
+  bool vm[Q], vp[Q];
+  auto fetch = [&](int jb) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = t + q * 256;
+      {
+        const int r = e / CK, c = e % CK;
+        const int i = i0 + r, j = jb + c;
+        vm[q] = i < ni && j < nj;
+        rm[q] = Ml[(long)(i < ni ? i : ni - 1) * nj + (j < nj ? j : nj - 1)];
+      }
+      {
+        const int r = e / CT, c = e % CT;
+        const int j = jb + r;
+        const long nn = n0 + c;
+        vp[q] = j < nj && nn < n;
+        rp[q] = Pl[(long)(j < nj ? j : nj - 1) * n + (nn < n ? nn : n - 1)];
+      }
+    }
+  };
+  fetch(0);
+  for (int jb = 0; jb < nj; jb += CK) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = t + q * 256;
+      sm[e / CK][e % CK] = vm[q] ? conj(rm[q]) : mk(0.0, 0.0);
+      sp[e / CT][e % CT] = vp[q] ? rp[q] : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (jb + CK < nj) fetch(jb + CK);
+#pragma unroll 4
+    for (int c = 0; c < CK; ++c) {
+      c128 mv[4], pv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) mv[a] = sm[ty + 16 * a][c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) pv[b] = sp[c][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = cfma(mv[a], pv[b], acc[a][b]);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < NI; ++r)
-    if (i0 + r < ni) S[l * s_ls + (long)(i0 + r) * n + e] = acc[r];
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ty + 16 * a;
+    if (i >= ni) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const long nn = n0 + tx + 16 * b;
+      if (nn < n) S[l * s_ls + (long)i * n + nn] = acc[a][b];
+    }
+  }
 }
 
 // ------------------------------------------------------------- residual ---
@@ -339,9 +420,7 @@ void launch_gemm_nt(int nf, const c128* A, long a_ls, int ni, const c128* w, con
 
 void launch_gemm_cn(int nf, const c128* M, int ni, int nj, const c128* P, long p_ls, long n, c128* S, long s_ls,
                     hipStream_t st) {
-  const size_t lds = sizeof(c128) * NI * nj;
-  if (lds > 64 * 1024) throw Error(-6, "too many elements for the adjoint-source kernel");
-  hipLaunchKernelGGL(k_gemm_cn, dim3((unsigned)((n + 255) / 256), (ni + NI - 1) / NI, nf), dim3(256), lds, st, M, ni,
+  hipLaunchKernelGGL(k_gemm_cn, dim3((unsigned)((n + CT - 1) / CT), (ni + CT - 1) / CT, nf), dim3(256), 0, st, M, ni,
                      nj, P, p_ls, n, S, s_ls);
   FWI_LAUNCH_CHECK();
 }
