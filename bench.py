@@ -28,10 +28,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "forward+adjoint solves/s at 1e-5 rel err vs FP64 plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-
-# calibrated) for the exact kernel variant named; reported only while the timed
-# dominant class runs that variant (profiles/gradient256_hbm_traffic.md).
-MEASURED_TRAFFIC = {("conv_c64", 1): {"kernel": "k_strided<float, 512, 16, 256, 2>", "bytes_per_launch": 946.3e6}}
+# MI355X FP32 vector peak (published, counts packed dual-FP32 FMAs) and the
+# peak without packed FP32, which this build does not use: 256 CUs x 4 SIMD x
+# 16 lanes x 2 flop (FMA) x 2.4 GHz.
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
+# Per-dispatch figures of the counter sample (rocprofv3, same tuning table as
+# the timed run: `--counter-sample --tuning <tuning_hex>`), for the exact
+# kernel named: HBM traffic from FETCH_SIZE / WRITE_SIZE scaled by a plain copy
+# of known size, and the VALU busy fraction from SQ_ACTIVE_INST_VALU over
+# GRBM_GUI_ACTIVE. Reported only while the timed dominant class runs that
+# kernel (profiles/gradient256_hbm_traffic.md, profiles/gradient256_valu.md).
+MEASURED = {"k_strided<float, 512, 16, 512, 2, true, false>": {"traffic": 907.5e6, "valu_busy": 0.73}}
 
 
 def parse():
@@ -50,6 +58,8 @@ def parse():
     ap.add_argument("--workload", default="gradient-256", choices=["gradient-256", "uneven-batch"],
                     help="gradient-256: the headline workload; uneven-batch: 32 instances of different grids, "
                          "element and frequency counts through the graph-replayed batched path")
+    ap.add_argument("--tuning", default=None,
+                    help="hex tuning table (as printed in tuning_hex) to use instead of autotuning")
     ap.add_argument("--counter-sample", action="store_true",
                     help="short run for hardware-counter passes: warmup, one step, then a plain copy of "
                          "known size (the incident-field cache) for calibrating FETCH_SIZE / WRITE_SIZE")
@@ -86,7 +96,9 @@ def main():
     # autotune the FFT-pass tiles for this grid (untimed set-up), then time one
     # step with the built-in tiles for the "fixed vs autotuned" comparison
     tune = {}
-    if not args.no_tune:
+    if args.tuning:
+        ctx.set_tuning(bytes.fromhex(args.tuning))
+    elif not args.no_tune:
         tune["c64"] = ctx.autotune(prob, fwi.FWI_FP32_REFINE, B=p.nf * p.ne, reps=3)
         tune["c128"] = ctx.autotune(prob, fwi.FWI_FP64, B=p.nf * p.ne, reps=2)
         log(f"autotune: {tune}")
@@ -147,14 +159,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = solves_per_step / (ms_step * 1e-3)
     log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
-    achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9
-    chosen = tune.get("c64", {}).get(dominant.replace("_c64", ""), {}).get("chosen", 1)
-    meas = MEASURED_TRAFFIC.get((dominant, chosen))
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": meas["bytes_per_launch"] if meas else None,
-                "traffic_kernel": meas["kernel"] if meas else None,
-                "kernel": dominant, "avg_launch_us": round(prof["ms"] * 1e3 / prof["launches"], 2),
-                "bytes_per_launch": prof["bytes"] / prof["launches"], "launches": prof["launches"]}
+    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -166,7 +171,8 @@ def main():
                       "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
            "roofline": roofline,
            "autotune": {"fixed_tiles_ms_per_step": None if fixed_ms is None else round(fixed_ms, 3),
-                        "autotuned_ms_per_step": round(ms_step, 3), "passes": tune},
+                        "autotuned_ms_per_step": round(ms_step, 3), "passes": tune,
+                        "tuning_hex": ctx.get_tuning().hex()},
            "solver": {"iterations_max": stats["iterations"], "refinements": stats["cycles"],
                       "matvecs_per_step": stats["matvecs"], "max_rel_residual": stats["max_rel_residual"]}}
 
@@ -197,6 +203,59 @@ def main():
         out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+# strided-pass tile variants (columns, threads), as in the library: 8 x 256,
+# 16 x 256, 16 x 512, columns halved while the tile is over 160 KiB of LDS
+def strided_tile(L, es, v):
+    nl0 = 8 if v == 0 else 16
+    lp = L + L // 8
+    nl = nl0 if nl0 * lp * es <= 160 * 1024 else (nl0 // 2 if nl0 // 2 * lp * es <= 160 * 1024 else nl0 // 4)
+    return nl, (512 if v == 2 else 256)
+
+
+def roofline_entry(fwi, ctx, prob, p, dominant, prof):
+    """Roofline of the dominant kernel class over the timed launches.
+
+    The 2D convolution pass (forward FFT, spectrum product, inverse FFT along
+    each padded column) is bound by FP32 vector issue, not HBM: its algorithmic
+    work is the nominal 5 L log2 L flops per length-L complex FFT, two per
+    column, plus 6 L for the product; its algorithmic bytes (read and write of
+    each RHS's half-padded plane, spectra once per frequency) are reported as
+    the secondary HBM figure. Other classes are HBM-bound streaming kernels.
+    """
+    launches = prof["launches"]
+    sec = prof["ms"] * 1e-3
+    achieved_gbs = prof["bytes"] / sec / 1e9
+    hbm = {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": prof["bytes"] / launches}
+    table = ctx.get_tuning()
+    entry = {"kernel": dominant, "avg_launch_us": round(prof["ms"] * 1e3 / launches, 2), "launches": launches}
+    if dominant == "conv_c64" and p.dim == 2:
+        Lz, Lx = ctx.padded_shape(prob)
+        es = 8
+        li = [32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024].index(Lz)
+        v = table[(2 * 2 + 0) * 11 + li]  # pass PK_CONV, complex64, length index
+        v = 2 if v in (255, -1) else v     # unset: built-in default of the complex64 convolution pass
+        nl, nt = strided_tile(Lz, es, v)
+        name = f"k_strided<float, {Lz}, {nl}, {nt}, 2, true, false>"
+        gbytes = p.nf * Lz * Lx * es                     # spectra read once per launch
+        per_rhs_bytes = 2.0 * p.nz * Lx * es             # half-padded plane in and out
+        per_rhs_flops = Lx * (2 * 5 * Lz * np.log2(Lz) + 6 * Lz)
+        rhs = (prof["bytes"] - launches * gbytes) / per_rhs_bytes
+        flops = rhs * per_rhs_flops
+        tf = flops / sec / 1e12
+        m = MEASURED.get(name, {})
+        entry.update({"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+                      "peak_unpacked_fp32": FP32_UNPACKED_PEAK_TFLOPS,
+                      "frac_unpacked": round(tf / FP32_UNPACKED_PEAK_TFLOPS, 4),
+                      "flops_per_launch": flops / launches, "kernel_name": name,
+                      "traffic": m.get("traffic"), "valu_busy": m.get("valu_busy"), "hbm": hbm})
+    else:
+        entry.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "traffic": None})
+    return entry
 
 
 def bench_uneven(args):

@@ -260,11 +260,13 @@ int fwi_profile_read(const fwi_ctx* ctx, int cls, double* total_ms, long long* l
 /* ------------------------------------------------------------- autotuner */
 /* Each FFT pass of the operator exists in three tile variants (row passes:
  * 2048 / 4096 / 8192 points per workgroup; strided passes: 8 columns x 256
- * threads, 16 x 256, 16 x 512 per workgroup). fwi_autotune times every variant of every pass on the device
- * for this problem's grid with B right-hand sides (reps launches each, HIP
- * events) and stores the fastest per (pass, precision, padded length) in the
- * context; later calls use it. Report rows: 0 row forward, 1 convolution,
- * 2 row inverse, 3 / 4 elevation forward / inverse (3D). */
+ * threads, 16 x 256, 16 x 512 per workgroup). fwi_autotune times every
+ * variant of every pass on the device for this problem's grid with B
+ * right-hand sides (reps launches each, HIP events) and stores the fastest per
+ * (pass, precision, padded length) in the context; a variant replaces the
+ * built-in default only if it is at least 2% faster. Later calls use the
+ * table. Report rows: 0 row forward, 1 convolution, 2 row inverse, 3 / 4
+ * elevation forward / inverse (3D, tuned on their summed time). */
 typedef struct fwi_tune_report {
   double variant_ms[5][3];  /* mean time per launch of each variant [ms] */
   int variant[5];           /* chosen variant */

@@ -32,7 +32,17 @@ thread_local int tl_force_variant = -1;
 int default_variant(int pass, bool dbl, int L) {
   (void)L;
   if (pass == PK_ROW_FWD || pass == PK_ROW_INV) return 0;  // 2048 points per workgroup
-  return dbl ? 0 : 1;                                        // (8, 256) / (16, 256) columns, threads
+  if (pass == PK_CONV && !dbl) return 2;                     // (16, 512) columns, threads
+  return dbl ? 0 : 1;                                        // (8, 256) / (16, 256)
+}
+
+// Fastest variant by measured time; another variant replaces the default only
+// if it is at least 2% faster (timing noise does not flip the choice).
+int pick_variant(const double* t, int dflt) {
+  int best = dflt;
+  for (int v = 0; v < kNumVariants; ++v)
+    if (v != best && t[v] > 0.0 && t[v] < 0.98 * t[best]) best = v;
+  return best;
 }
 
 int tune_variant(int pass, bool dbl, int L) {
@@ -1668,21 +1678,19 @@ int fwi_autotune(fwi_ctx* c, const fwi_problem* p, int precision, int B, int rep
       if (kinds[k] < 0 || k == KC_Y_INV) continue;
       const double* tv = k == KC_Y_FWD ? strided_sum : t[k];
       if (tv[0] == 0.0) continue;
-      int best = 0;
-      for (int v = 1; v < kNumVariants; ++v)
-        if (tv[v] < tv[best]) best = v;
-      c->tune.v[kinds[k]][dbl ? 1 : 0][length_index(lens[k])] = (signed char)best;
+      c->tune.v[kinds[k]][dbl ? 1 : 0][length_index(lens[k])] =
+          (signed char)pick_variant(tv, default_variant(kinds[k], dbl, lens[k]));
     }
     if (rep) {
       for (int k = 0; k < 5; ++k) {
-        int best = 0;
-        for (int v = 0; v < kNumVariants; ++v) {
-          rep->variant_ms[k][v] = t[k][v];
-          if (t[k][v] < t[k][best]) best = v;
-        }
-        rep->variant[k] = best;
+        for (int v = 0; v < kNumVariants; ++v) rep->variant_ms[k][v] = t[k][v];
         rep->default_variant[k] = kinds[k] >= 0 ? default_variant(kinds[k], dbl, lens[k]) : -1;
+        rep->variant[k] = t[k][0] > 0.0 ? pick_variant(t[k], rep->default_variant[k] >= 0 ? rep->default_variant[k] : 0)
+                                         : -1;
       }
+      // the elevation passes are tuned on their summed time
+      if (strided_sum[0] > 0.0) rep->variant[KC_Y_FWD] = rep->variant[KC_Y_INV] =
+          pick_variant(strided_sum, default_variant(PK_STRIDED, dbl, g.Ly));
     }
     return FWI_OK;
   });
