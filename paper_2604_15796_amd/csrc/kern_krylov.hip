@@ -7,12 +7,19 @@ namespace fwi {
 
 constexpr int KT = 256;  // threads per block of the vector kernels
 
-// Blocks per RHS of the Arnoldi kernels: chunks of 16384 elements (64 per
-// thread), enough to amortise each block's reduction.
+// Blocks per RHS of the Arnoldi kernels: chunks of at most EPT * KT = 4096
+// elements, EPT per thread held in registers.
+constexpr int EPT = 16;
 int krylov_nblk(long n) {
-  long nb = (n + 16383) / 16384;
+  long nb = (n + EPT * KT - 1) / (EPT * KT);
   return (int)(nb < 1 ? 1 : nb);
 }
+
+// Both Arnoldi kernels keep the block's EPT elements per thread of the new
+// vector in registers and stream the basis vectors one after another, each
+// with EPT independent coalesced loads per thread (indices clamped, values
+// masked, so the loads are not behind branches); per-vector sums are reduced
+// wave by wave in a fixed order.
 
 // ------------------------------------------------------------------ dots ---
 // dotp[b][blk][i] = sum over the block's chunk of conj(V_i) . V_{j+1}, i <= j
@@ -22,54 +29,46 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
                                              int B, c128* __restrict__ dotp, int nblk) {
   const int b = blockIdx.y;
   if (!active[b]) return;
+  const int t = threadIdx.x;
   const long off = (long)b * n;
-  const cplx<T>* W = V + (long)(j + 1) * vs + off;
-  double ar[JM + 1], ai[JM + 1];
-#pragma unroll
-  for (int i = 0; i <= JM; ++i) ar[i] = ai[i] = 0.0;
   const long e0 = (long)blockIdx.x * chunk;
-  const long e1 = min(n, e0 + chunk);
-  // UNR elements per thread per trip: UNR independent loads of every vector in flight
-  constexpr int UNR = 4;
-  for (long eb = e0 + threadIdx.x; eb < e1; eb += UNR * KT) {
-    double wx[UNR], wy[UNR];
+  const int cnt = (int)min((long)chunk, n - e0);
+  const cplx<T>* W = V + (long)(j + 1) * vs + off + e0;
+  double wx[EPT], wy[EPT];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const long e = eb + u * KT;
-      const cplx<T> w = e < e1 ? W[e] : mk((T)0, (T)0);
-      wx[u] = w.x;
-      wy[u] = w.y;
-    }
-#pragma unroll
-    for (int i = 0; i <= JM; ++i) {
-      if (i <= j) {
-        const cplx<T>* Vi = V + (long)i * vs + off;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const long e = eb + u * KT;
-          const cplx<T> v = e < e1 ? Vi[e] : mk((T)0, (T)0);
-          const double vx = v.x, vy = v.y;
-          ar[i] += vx * wx[u] + vy * wy[u];
-          ai[i] += vx * wy[u] - vy * wx[u];
-        }
-      }
-    }
+  for (int q = 0; q < EPT; ++q) {
+    const int e = t + q * KT;
+    const cplx<T> w = W[e < cnt ? e : cnt - 1];
+    wx[q] = e < cnt ? (double)w.x : 0.0;
+    wy[q] = e < cnt ? (double)w.y : 0.0;
   }
   __shared__ double red[2][JM + 1][KT / 64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = t & 63, wvi = t >> 6;
+  for (int i = 0; i <= j; ++i) {
+    const cplx<T>* Vi = V + (long)i * vs + off + e0;
+    cplx<T> vv[EPT];  // all loads of the vector issued before any arithmetic
 #pragma unroll
-  for (int i = 0; i <= JM; ++i) {
-    if (i <= j) {
-      const double sc = (double)vscale[(long)i * B + b].x;  // stored V_i = basis vector / sc
-      const double r = sc * wave_sum(ar[i]), m = sc * wave_sum(ai[i]);
-      if (lane == 0) {
-        red[0][i][wv] = r;
-        red[1][i][wv] = m;
-      }
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + q * KT;
+      vv[q] = Vi[e < cnt ? e : cnt - 1];
+    }
+    double r = 0.0, m = 0.0;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double vx = vv[q].x, vy = vv[q].y;  // wx, wy are zero past the chunk
+      r = fma(vx, wx[q], r);
+      r = fma(vy, wy[q], r);
+      m = fma(vx, wy[q], m);
+      m = fma(-vy, wx[q], m);
+    }
+    r = wave_sum(r);
+    m = wave_sum(m);
+    if (lane == 0) {
+      red[0][i][wvi] = r;
+      red[1][i][wvi] = m;
     }
   }
   __syncthreads();
-  const int t = threadIdx.x;
   if (t <= j) {
     double r = 0.0, m = 0.0;
 #pragma unroll
@@ -77,7 +76,8 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
       r += red[0][t][w];
       m += red[1][t][w];
     }
-    dotp[((long)b * nblk + blockIdx.x) * (JM + 1) + t] = mk(r, m);
+    const double sc = (double)vscale[(long)t * B + b].x;  // stored V_i = basis vector / sc
+    dotp[((long)b * nblk + blockIdx.x) * (JM + 1) + t] = mk(sc * r, sc * m);
   }
 }
 
@@ -108,43 +108,43 @@ __global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, i
   }
   __syncthreads();
   const long off = (long)b * n;
-  cplx<T>* W = V + (long)(j + 1) * vs + off;
   const long e0 = (long)blockIdx.x * chunk;
-  const long e1 = min(n, e0 + chunk);
+  const int cnt = (int)min((long)chunk, n - e0);
+  cplx<T>* W = V + (long)(j + 1) * vs + off + e0;
+  double ax[EPT], ay[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = t + q * KT;
+    const cplx<T> w = W[e < cnt ? e : cnt - 1];
+    ax[q] = w.x;
+    ay[q] = w.y;
+  }
+  for (int i = 0; i <= j; ++i) {
+    const cplx<T>* Vi = V + (long)i * vs + off + e0;
+    const double a = hr[i], bb = hi[i];
+    cplx<T> vv[EPT];  // all loads of the vector issued before any arithmetic
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = t + q * KT;
+      vv[q] = Vi[e < cnt ? e : cnt - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const double vx = vv[q].x, vy = vv[q].y;
+      ax[q] = fma(-a, vx, ax[q]);
+      ax[q] = fma(bb, vy, ax[q]);
+      ay[q] = fma(-a, vy, ay[q]);
+      ay[q] = fma(-bb, vx, ay[q]);
+    }
+  }
   double acc = 0.0;
-  constexpr int UNR = 4;
-  for (long eb = e0 + t; eb < e1; eb += UNR * KT) {
-    double wx[UNR], wy[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const long e = eb + u * KT;
-      const cplx<T> w = e < e1 ? W[e] : mk((T)0, (T)0);
-      wx[u] = w.x;
-      wy[u] = w.y;
-    }
-#pragma unroll
-    for (int i = 0; i <= JM; ++i) {
-      if (i <= j) {
-        const cplx<T>* Vi = V + (long)i * vs + off;
-        const double a = hr[i], bb = hi[i];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const long e = eb + u * KT;
-          const cplx<T> v = e < e1 ? Vi[e] : mk((T)0, (T)0);
-          const double vx = v.x, vy = v.y;
-          wx[u] -= a * vx - bb * vy;
-          wy[u] -= a * vy + bb * vx;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const long e = eb + u * KT;
-      if (e < e1) {
-        const cplx<T> o = mk((T)wx[u], (T)wy[u]);
-        W[e] = o;
-        acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
-      }
+  for (int q = 0; q < EPT; ++q) {
+    const int e = t + q * KT;
+    if (e < cnt) {
+      const cplx<T> o = mk((T)ax[q], (T)ay[q]);
+      W[e] = o;
+      acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
     }
   }
   const double s = block_sum<KT>(acc, red);
