@@ -320,6 +320,7 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
   constexpr bool RD_SPLIT = (L / R) % 8 == 0;
   constexpr bool WR_SPLIT = Ns % 8 == 0 || (Ns == 1 && R % 8 == 0);
   cplx<T> v[TT][R];
+  cplx<T> tw1[TT], tw8[TT];  // twiddle table values, loaded with the data
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
@@ -328,6 +329,11 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
 #pragma unroll
       for (int r = 0; r < RIN; ++r)
         v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
+      if constexpr (Ns > 1) {
+        const int k = j % Ns;
+        tw1[t] = tw[k * (L / (Ns * R))];
+        if constexpr (R > 8) tw8[t] = tw[8 * k * (L / (Ns * R))];
+      }
     }
   }
   if constexpr (SYNC) __syncthreads();
@@ -338,10 +344,10 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
       C::template split<R>(t, line, j);
       const int k = j % Ns;
       if constexpr (Ns > 1) {
-        cplx<T> w1 = tw[k * (L / (Ns * R))];
+        cplx<T> w1 = tw1[t];
         if (sgn > 0) w1.y = -w1.y;
         if constexpr (R > 8) {
-          cplx<T> w8 = tw[8 * k * (L / (Ns * R))];
+          cplx<T> w8 = tw8[t];
           if (sgn > 0) w8.y = -w8.y;
           apply_twiddles_big<R>(v[t], w1, w8);
         } else {
@@ -370,6 +376,7 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
   constexpr int L = C::L, Ns = L / R, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
   constexpr bool RD_SPLIT = (L / R) % 8 == 0;
   cplx<T> v[TT][R];
+  cplx<T> tw1[TT], tw8[TT];  // twiddle table values, loaded with the data
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
     if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
@@ -378,6 +385,8 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
 #pragma unroll
       for (int r = 0; r < R; ++r)
         v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
+      tw1[t] = tw[j];  // k = j < Ns, step 1
+      if constexpr (R > 8) tw8[t] = tw[8 * j];
     }
   }
   __syncthreads();
@@ -386,8 +395,8 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
     if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
       C::template split<R>(t, line, j);
-      if constexpr (R > 8) apply_twiddles_big<R>(v[t], tw[j], tw[8 * j]);  // k = j < Ns, step 1
-      else apply_twiddles<R>(v[t], tw[j]);
+      if constexpr (R > 8) apply_twiddles_big<R>(v[t], tw1[t], tw8[t]);
+      else apply_twiddles<R>(v[t], tw1[t]);
       dft<R>(v[t], -1);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[t][r] = v[t][r] * gh(t, r, line, j + r * Ns);

@@ -39,6 +39,13 @@ __host__ __device__ constexpr int col_nl() {
        : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0 / 2 : nl0 / 4;
 }
 
+// true if any row of the workgroup is to be processed (uniform: LDS flags)
+__device__ __forceinline__ bool any_row(const int* s_ok, int nl) {
+  int any = 0;
+  for (int l = 0; l < nl; ++l) any |= s_ok[l];
+  return any != 0;
+}
+
 // ------------------------------------------------------------- row pass 1 ---
 template <typename T>
 struct RowFwdArgs {
@@ -66,22 +73,30 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
     int ok = g < a.nrows;
-    const long b = ok ? g / a.rows_per_rhs : 0;
+    const long gc = ok ? g : a.nrows - 1;  // rows past the end read the last row (not stored)
+    const long b = gc / a.rows_per_rhs;
     if (ok && a.active && !a.active[b]) ok = 0;
-    const long z = g - b * a.rows_per_rhs;
+    const long z = gc - b * a.rows_per_rhs;
     s_ok[l] = ok;
-    s_x[l] = g * a.in_stride;
+    s_x[l] = gc * a.in_stride;
     s_m[l] = (int)z * a.nin;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
+  if (!any_row(s_ok, C::NL)) return;  // converged right-hand sides: no traffic
+  // branch-free loads (clamped index, masked value), so every leg's loads can
+  // be in flight before the first product; without a contrast the x row
+  // stands in for m and the blend below makes the factor exactly 1
+  const T km = a.m ? (T)1 : (T)0;
+  const cplx<T>* mp = a.m ? a.m : a.x;
   auto src = [&](int line, int pb, int ro) -> cplx<T> {
     const int p = pb + ro;
-    if (!s_ok[line] || p >= a.nin) return mk((T)0, (T)0);
-    cplx<T> v = a.x[s_x[line] + p];
-    if (a.m) v = v * a.m[s_m[line] + p];
-    if (a.scale) v = v * s_s[line];
-    return v;
+    const int pc = p < a.nin ? p : a.nin - 1;
+    const cplx<T> xv = a.x[s_x[line] + pc];
+    const cplx<T> mv = mp[s_m[line] + pc];
+    const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
+    const cplx<T> v = xv * mf * s_s[line];
+    return p < a.nin ? v : mk((T)0, (T)0);
   };
   auto snk = [&](int line, int pb, int ro, cplx<T> v) {
     if (s_ok[line]) a.out[(g0 + line) * L + pb + ro] = v;
@@ -128,25 +143,27 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
   }
   __syncthreads();
-  auto src = [&](int line, int pb, int ro) -> cplx<T> {
-    if (!s_ok[line]) return mk((T)0, (T)0);
-    return a.in[(g0 + line) * L + pb + ro];
-  };
+  if (!any_row(s_ok, C::NL)) return;  // converged right-hand sides: no traffic
+  // rows past the end read the last row and are not stored; epilogue loads
+  // use clamped indices so they are not behind the store predicate
+  auto row = [&](int line) { return g0 + line < a.nrows ? g0 + line : a.nrows - 1; };
+  auto src = [&](int line, int pb, int ro) -> cplx<T> { return a.in[row(line) * L + pb + ro]; };
   auto snk = [&](int line, int pb, int ro, cplx<T> v) {
     const int p = pb + ro;
-    if (!s_ok[line] || p >= a.nout) return;
-    const long o = (g0 + line) * a.nout + p;
+    const bool st = s_ok[line] && p < a.nout;
+    const long o = row(line) * a.nout + (p < a.nout ? p : a.nout - 1);
     if constexpr (EPI == EPI_VIE) {
-      cplx<T> xv = a.x[o];
-      if (a.scale) xv = xv * s_s[line];
-      a.y[o] = xv - v;
+      const cplx<T> y = a.x[o] * s_s[line] - v;
+      if (st) a.y[o] = y;
     } else if constexpr (RESID) {
       const cplx<T> r = a.rhs[o] - (a.x[o] - v);
-      if constexpr (EPI == EPI_RESID) a.y[o] = r;
-      else a.y32[o] = mk((float)r.x, (float)r.y);
-      s_part[line * NsL + p % NsL] += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      if (st) {
+        if constexpr (EPI == EPI_RESID) a.y[o] = r;
+        else a.y32[o] = mk((float)r.x, (float)r.y);
+        s_part[line * NsL + p % NsL] += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+      }
     } else {
-      a.y[o] = v;
+      if (st) a.y[o] = v;
     }
   };
   fft_line_transform<C, 1, false, true>(a.tw, sh, src, snk);
