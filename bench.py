@@ -206,11 +206,12 @@ def main():
 
 
 # strided-pass tile variants (columns, threads), as in the library: 8 x 256,
-# 16 x 256, 16 x 512, columns halved while the tile is over 160 KiB of LDS
+# 16 x 256, 16 x 512, columns halved while the tile is over 80 KiB of LDS
 def strided_tile(L, es, v):
     nl0 = 8 if v == 0 else 16
     lp = L + L // 8
-    nl = nl0 if nl0 * lp * es <= 160 * 1024 else (nl0 // 2 if nl0 // 2 * lp * es <= 160 * 1024 else nl0 // 4)
+    lim = 80 * 1024
+    nl = nl0 if nl0 * lp * es <= lim else (nl0 // 2 if nl0 // 2 * lp * es <= lim else nl0 // 4)
     return nl, (512 if v == 2 else 256)
 
 

@@ -260,7 +260,8 @@ int fwi_profile_read(const fwi_ctx* ctx, int cls, double* total_ms, long long* l
 /* ------------------------------------------------------------- autotuner */
 /* Each FFT pass of the operator exists in three tile variants (row passes:
  * 2048 / 4096 / 8192 points per workgroup; strided passes: 8 columns x 256
- * threads, 16 x 256, 16 x 512 per workgroup). fwi_autotune times every
+ * threads, 16 x 256, 16 x 512 per workgroup, columns halved while a tile needs
+ * more than 80 KiB of LDS). fwi_autotune times every
  * variant of every pass on the device for this problem's grid with B
  * right-hand sides (reps launches each, HIP events) and stores the fastest per
  * (pass, precision, padded length) in the context; a variant replaces the

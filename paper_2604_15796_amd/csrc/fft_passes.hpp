@@ -26,7 +26,8 @@ __host__ __device__ constexpr int row_nl() {
   return nl0 * (L + L / 8) * (int)sizeof(cplx<T>) <= kLdsMax - 4096 ? nl0 : (nl0 / 2 > 0 ? nl0 / 2 : 1);
 }
 // strided-pass variants: (columns, threads) = (8, 256), (16, 256), (16, 512);
-// columns are halved while the tile is over the LDS budget
+// columns are halved while the tile is over half the LDS (two workgroups per CU)
+constexpr int kColLds = 80 * 1024;
 template <int V>
 __host__ __device__ constexpr int col_nt() {
   return V == 2 ? 512 : 256;
@@ -35,8 +36,8 @@ template <typename T, int L, int V>
 __host__ __device__ constexpr int col_nl() {
   constexpr int nl0 = V == 0 ? 8 : 16;
   constexpr int lp = L + L / 8;
-  return nl0 * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0
-       : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kLdsMax ? nl0 / 2 : nl0 / 4;
+  return nl0 * lp * (int)sizeof(cplx<T>) <= kColLds ? nl0
+       : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kColLds ? nl0 / 2 : nl0 / 4;
 }
 
 // true if any row of the workgroup is to be processed (uniform: LDS flags)
