@@ -124,6 +124,11 @@ int fwi_create(fwi_ctx** out, int device, void* hip_stream);
 void fwi_destroy(fwi_ctx* ctx);
 const char* fwi_last_error(const fwi_ctx* ctx);
 int fwi_set_stream(fwi_ctx* ctx, void* hip_stream);
+/* Strided FFT passes address each plane through 32-bit buffer views and fall
+ * back to 64-bit addressing for planes of 2 GiB or more. wide = 1 forces the
+ * 64-bit path for every later call (a testing aid for that path; results are
+ * the same), 0 restores the automatic choice. FWI_E_INVAL for other values. */
+int fwi_set_addressing(fwi_ctx* ctx, int wide);
 void fwi_default_opts(fwi_solve_opts* opts);
 
 /* Host-only argument check; returns FWI_OK or FWI_E_INVAL / FWI_E_UNSUPPORTED.

@@ -28,6 +28,7 @@ thread_local long tl_active = 0;
 thread_local int tl_nfreq = 0;
 thread_local const FftTuning* tl_tune = nullptr;
 thread_local int tl_force_variant = -1;
+thread_local int tl_force_wide = 0;
 
 int default_variant(int pass, bool dbl, int L) {
   (void)L;
@@ -195,6 +196,7 @@ double now_ms() {
 
 struct fwi_ctx {
   int device = 0;
+  int force_wide = 0;          // fwi_set_addressing
   hipStream_t stream = nullptr;
   std::string err;
   Twiddles tw;
@@ -753,6 +755,7 @@ int guarded(fwi_ctx* c, F&& body) {
       tl_prof = c->prof.mask ? &c->prof : nullptr;
       tl_tune = &c->tune;
       tl_force_variant = -1;
+      tl_force_wide = c->force_wide;
       tl_active = 0;
       tl_nfreq = 0;
     }
@@ -760,6 +763,7 @@ int guarded(fwi_ctx* c, F&& body) {
       tl_prof = nullptr;
       tl_tune = nullptr;
       tl_force_variant = -1;
+      tl_force_wide = 0;
     }
   } scope(c);
   try {
@@ -1359,6 +1363,12 @@ const char* fwi_last_error(const fwi_ctx* c) { return c ? c->err.c_str() : "NULL
 int fwi_set_stream(fwi_ctx* c, void* stream) {
   if (!c) return FWI_E_INVAL;
   c->stream = (hipStream_t)stream;
+  return FWI_OK;
+}
+
+int fwi_set_addressing(fwi_ctx* c, int wide) {
+  if (!c || (wide != 0 && wide != 1)) return FWI_E_INVAL;
+  c->force_wide = wide;
   return FWI_OK;
 }
 

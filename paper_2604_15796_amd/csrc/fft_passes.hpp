@@ -355,7 +355,7 @@ void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_
   // an out-of-plane line (offset kBufferOut + ...) cannot wrap into range
   const long es = sizeof(cplx<T>);
   const long span = (long)L * std::max(a.pstride, mode == 2 ? a.gpstride : 0L) * es + (long)a.nlines * es;
-  const bool wide = span > kNarrowMax;
+  const bool wide = span > kNarrowMax || tl_force_wide;
   const bool hin = 2 * a.lin <= L, hout = 2 * a.lout <= L;
   if (mode == 2) {
     if (!hin || !hout) throw Error(-6, "convolution lines must be zero-padded to twice their length");
@@ -364,12 +364,13 @@ void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_
     else launch_strided_k<T, L, V, 2, true, false>(args, grid, st);
   } else if (mode == 0) {
     if (wide) {
-      if constexpr (sizeof(T) == 8) {
-        const dim3 g0((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y);
-        if (hin) launch_strided_k<T, L, 0, 0, true, true>(args, g0, st);
-        else launch_strided_k<T, L, 0, 0, false, true>(args, g0, st);
+      const dim3 g0((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y);
+      if (hin) {
+        launch_strided_k<T, L, 0, 0, true, true>(args, g0, st);
+      } else if constexpr (sizeof(T) == 8) {
+        launch_strided_k<T, L, 0, 0, false, true>(args, g0, st);
       } else {
-        throw Error(-6, "complex64 strided pass over a plane of 2 GiB or more");
+        throw Error(-6, "complex64 strided transforms need zero-padded lines");
       }
     } else if (hin) {
       launch_strided_k<T, L, V, 0, true, false>(args, grid, st);

@@ -66,6 +66,7 @@ struct FftTuning {
 };
 extern thread_local const FftTuning* tl_tune;
 extern thread_local int tl_force_variant;  // >= 0: every pass uses this variant
+extern thread_local int tl_force_wide;     // 1: strided passes use 64-bit addressing
 int default_variant(int pass, bool dbl, int L);
 int tune_variant(int pass, bool dbl, int L);
 int padded_length(int n);         // smallest supported L >= 2n, 0 if none

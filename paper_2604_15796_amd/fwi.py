@@ -89,6 +89,7 @@ def lib():
         "fwi_destroy": (None, [vp]),
         "fwi_last_error": (C.c_char_p, [vp]),
         "fwi_set_stream": (ip, [vp, vp]),
+        "fwi_set_addressing": (ip, [vp, ip]),
         "fwi_default_opts": (None, [op]),
         "fwi_validate_problem": (ip, [pp]),
         "fwi_padded_length": (ip, [ip]),
@@ -132,7 +133,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
-            "fwi_forward_batch"]
+            "fwi_forward_batch", "fwi_set_addressing"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -373,6 +374,11 @@ class Context:
             if any(ms):
                 out[name] = {"ms": ms, "chosen": rep.variant[k], "default": rep.default_variant[k]}
         return out
+
+    def set_addressing(self, wide):
+        """wide=True forces the 64-bit addressing path of the strided FFT passes
+        (otherwise used only for planes of 2 GiB or more)."""
+        self._check(self.L.fwi_set_addressing(self.h, 1 if wide else 0))
 
     def get_tuning(self):
         buf = (C.c_byte * TUNING_BYTES)()

@@ -165,6 +165,33 @@ def test_operator_every_tile_variant_and_autotune(ctx, F, dim):
     ctx.set_tuning(None)
 
 
+def test_operator_and_solve_with_64bit_addressing(ctx, F):
+    """The 64-bit addressing path of the strided passes (automatic only for
+    planes of 2 GiB or more) forced on small grids: the 2D and 3D operators in
+    both precisions and an FP32-refined solve match the oracle."""
+    try:
+        ctx.set_addressing(True)
+        for p in (W.small2d(seed=61, nx=40, nz=36, nf=1), W.small3d(seed=62, nx=16, ny=12, nz=10)):
+            m = O.contrast(p.c, p.alpha, p.c0)
+            x = W.random_complex(11, (2,) + p.shape)
+            Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), p.dim, p.nx, p.ny, p.nz, p.dx)
+            ref = np.stack([O.vie_apply(Gh, m, x[b]).ravel() for b in range(2)])
+            for prec in (0, 1):
+                dt = torch.complex64 if prec else torch.complex128
+                y = host(ctx.apply_operator(p, dev(m), [0, 0], dev(x.reshape(2, -1), dt), precision=prec))
+                assert relerr(y, ref) < (2e-6 if prec else 1e-13), (p.dim, prec)
+        p = W.small2d(seed=63, nx=32, nz=28, ne=3, nf=1)
+        m = O.contrast(p.c, p.alpha, p.c0)
+        k = O.wavenumber(p.freqs[0], p.c0)
+        P0 = O.incident_fields(k, O.cell_centres(2, p.nx, 1, p.nz, p.dx), p.elems, 2)
+        ref = O.solve(k, m, P0, 2, p.nx, 1, p.nz, p.dx)
+        opts = F.SolveOptions(precision=F.FWI_FP32_REFINE, rtol=1e-10, restart=16)
+        xs, _ = ctx.solve(p, dev(m), [0] * p.ne, dev(P0), opts)
+        assert relerr(host(xs), ref) < 1e-8
+    finally:
+        ctx.set_addressing(False)
+
+
 # --------------------------------------------------------------- solves ---
 
 @pytest.mark.parametrize("prec", [0, 1])
