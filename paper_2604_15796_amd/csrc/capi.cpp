@@ -429,7 +429,7 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.sn = a.take<c128>((size_t)B * JM);
   k.gv = a.take<c128>((size_t)B * (JM + 1));
   k.y = a.take<c128>((size_t)B * JM);
-  k.dotp = a.take<c128>((size_t)B * k.nblk * (JM + 1));
+  k.dotp = a.take<c128>((size_t)B * std::max(k.nblk, kMaxDotParts) * (JM + 1));
   k.nrmp = a.take<double>((size_t)B * k.nblk);
   k.rnorm = a.take<double>(B);
   k.bnorm = a.take<double>(B);
@@ -474,6 +474,19 @@ struct SolveTotals {
 // Each cycle starts from the true FP64 residual r = b - A x, normalises it,
 // runs at most `restart` Arnoldi steps per RHS (stopping each RHS at its
 // target) and adds the correction to the FP64 solution x.
+// Inner products of Arnoldi step j, to be fused into the operator's last pass.
+template <typename T>
+VieDots arnoldi_dots(const KrylovState<T>& ks, int j) {
+  VieDots d;
+  d.basis = ks.V;
+  d.vs = ks.vstride();
+  d.nvec = j + 1;
+  d.vscale = ks.vscale;
+  d.dotp = ks.dotp;
+  d.dstride = ks.JM + 1;
+  return d;
+}
+
 // r = b - A x in FP64 for every RHS; the epilogue stores r into V_0 of the
 // basis (rounded to the basis precision) and one |r|^2 partial per grid row.
 template <typename T>
@@ -529,9 +542,10 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       break;
     }
     for (int j = 0; j < ks.JM; ++j) {
+      VieDots dots = arnoldi_dots(ks, j);
       launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, ghatT, rhs_freq,
-                    s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
-      krylov_arnoldi(ks, j, st);
+                    s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
+      krylov_arnoldi(ks, j, dots.nparts, st);
       ++total;
       if ((j + 1) % o.check_every == 0 || j + 1 == ks.JM || total >= o.max_iter) {
         FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1009,9 +1023,10 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   }
   krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
   for (int j = 0; j < ks.JM; ++j) {
+    VieDots dots = arnoldi_dots(ks, j);
     launch_vie<T>(I.g, c->tw, ks.B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, gT,
-                  pc.rhs_freq, s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st);
-    krylov_arnoldi(ks, j, st);
+                  pc.rhs_freq, s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
+    krylov_arnoldi(ks, j, dots.nparts, st);
   }
   krylov_finish_cycle(ks, x, cyc == 0, st);
 }

@@ -119,7 +119,17 @@ struct RowInvArgs {
   int rows_per_rhs, nout;  // nout <= L/2 (cropped output)
   c64* y32;              // EPI_RESID32 output [rows][nout]
   double* rowpart;       // EPI_RESID / EPI_RESID32: [rows] sum of |residual|^2
+  // EPI_VIE_DOT: Arnoldi inner products of y against the basis (see VieDots)
+  const cplx<T>* basis;
+  long vs;
+  int nvec;
+  const cplx<T>* vscale;
+  int B;
+  c128* dotp;
+  int nparts, dstride;
 };
+
+constexpr int kMaxDotVec = 33;  // basis vectors of the largest restart (32) + 1
 
 template <typename T, int L, int NLV, int EPI>
 __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
@@ -153,7 +163,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
     const int p = pb + ro;
     const bool st = s_ok[line] && p < a.nout;
     const long o = row(line) * a.nout + (p < a.nout ? p : a.nout - 1);
-    if constexpr (EPI == EPI_VIE) {
+    if constexpr (EPI == EPI_VIE || EPI == EPI_VIE_DOT) {
       const cplx<T> y = a.x[o] * s_s[line] - v;
       if (st) a.y[o] = y;
     } else if constexpr (RESID) {
@@ -174,6 +184,63 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
       double s = 0.0;
       for (int i = 0; i < NsL; ++i) s += s_part[threadIdx.x * NsL + i];
       a.rowpart[g0 + threadIdx.x] = s;
+    }
+  }
+  if constexpr (EPI == EPI_VIE_DOT) {
+    // The workgroup's rows (one RHS, contiguous in y and in every basis
+    // vector) were just stored; after the barrier each thread reads back EPD
+    // elements of them and streams the basis vectors over the same elements.
+    __syncthreads();
+    constexpr int EPD = (C::NL * (L / 2) + NT - 1) / NT;
+    const long b0 = g0 / a.rows_per_rhs;
+    const int part = (int)((g0 - b0 * a.rows_per_rhs) / C::NL);
+    const long base = g0 * a.nout;
+    const int cnt = C::NL * a.nout;
+    const int t = threadIdx.x;
+    double yx[EPD], yy[EPD];
+#pragma unroll
+    for (int q = 0; q < EPD; ++q) {
+      const int e = t + q * NT;
+      const cplx<T> y = a.y[base + (e < cnt ? e : cnt - 1)];
+      yx[q] = e < cnt ? (double)y.x : 0.0;
+      yy[q] = e < cnt ? (double)y.y : 0.0;
+    }
+    __shared__ double red[2][kMaxDotVec][NT / 64];
+    const int lane = t & 63, wv = t >> 6;
+    for (int i = 0; i < a.nvec; ++i) {
+      const cplx<T>* Vi = a.basis + i * a.vs + base;
+      cplx<T> vv[EPD];
+#pragma unroll
+      for (int q = 0; q < EPD; ++q) {
+        const int e = t + q * NT;
+        vv[q] = Vi[e < cnt ? e : cnt - 1];
+      }
+      double r = 0.0, m = 0.0;
+#pragma unroll
+      for (int q = 0; q < EPD; ++q) {
+        const double vx = vv[q].x, vy = vv[q].y;
+        r = fma(vx, yx[q], r);
+        r = fma(vy, yy[q], r);
+        m = fma(vx, yy[q], m);
+        m = fma(-vy, yx[q], m);
+      }
+      r = wave_sum(r);
+      m = wave_sum(m);
+      if (lane == 0) {
+        red[0][i][wv] = r;
+        red[1][i][wv] = m;
+      }
+    }
+    __syncthreads();
+    if (t < a.nvec) {
+      double r = 0.0, m = 0.0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) {
+        r += red[0][t][w];
+        m += red[1][t][w];
+      }
+      const double sc = (double)a.vscale[(long)t * a.B + b0].x;  // stored V_i = basis vector / sc
+      a.dotp[((long)b0 * a.nparts + part) * a.dstride + t] = mk(sc * r, sc * m);
     }
   }
 }
@@ -324,7 +391,14 @@ void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
   if (2 * a.nout > L) throw Error(-6, "inverse row transform must crop to half a padded row");
-  if (epi == EPI_VIE) {
+  if (epi == EPI_VIE_DOT) {
+    // only when every workgroup's rows belong to one RHS and the parts fit
+    if (a.rows_per_rhs % NL != 0 || a.rows_per_rhs / NL > kMaxDotParts || a.nvec > kMaxDotVec)
+      throw Error(-6, "fused inner products not applicable");
+    RowInvArgs<T> b = a;
+    b.nparts = a.rows_per_rhs / NL;
+    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE_DOT>), dim3(grid), dim3(NT), 0, st, b);
+  } else if (epi == EPI_VIE) {
     hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
   } else if (epi == EPI_COPY) {
     hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
@@ -425,11 +499,23 @@ void row_inv_call(int L, const RowInvArgs<T>& a, int epi, hipStream_t st) {
   const int v = tune_variant(PK_ROW_INV, sizeof(T) == 8, L);
   FWI_LENGTHS(launch_row_inv_v, L, v, a, epi, st);
 }
+// rows per workgroup of the inverse row pass that row_inv_call will launch
+template <typename T, int L, int V>
+void row_inv_nl_v(int& nl) {
+  nl = row_nl<T, L, V>();
+}
+template <typename T>
+int row_inv_nl(int L) {
+  const int v = tune_variant(PK_ROW_INV, sizeof(T) == 8, L);
+  int nl = 0;
+  FWI_LENGTHS(row_inv_nl_v, L, v, nl);
+  return nl;
+}
 
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart) {
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const double act = (double)(active && tl_active > 0 && tl_active < B ? tl_active : B);
@@ -536,11 +622,28 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   r.nout = g.nx;
   r.y32 = y32;
   r.rowpart = rowpart;
+  if (dots) {
+    dots->nparts = 0;
+    const int nl = row_inv_nl<T>(g.Lx);
+    if (epi == EPI_VIE && rows_per_rhs % nl == 0 && rows_per_rhs / nl <= kMaxDotParts &&
+        dots->nvec <= kMaxDotVec) {
+      epi = EPI_VIE_DOT;
+      r.basis = static_cast<const cplx<T>*>(dots->basis);
+      r.vs = dots->vs;
+      r.nvec = dots->nvec;
+      r.vscale = static_cast<const cplx<T>*>(dots->vscale);
+      r.B = B;
+      r.dotp = dots->dotp;
+      r.dstride = dots->dstride;
+      dots->nparts = (int)(rows_per_rhs / nl);
+    }
+  }
   // per RHS: the x-pass intermediate, then x and y (VIE), or x, rhs, the
   // residual (complex128 or complex64) and one norm partial per row
   const double rows = (double)g.nz * g.ny;
   const double epi_bytes = epi == EPI_RESID     ? 3.0 * n * es + 8.0 * rows
                            : epi == EPI_RESID32 ? (2.0 * es + 8.0) * n + 8.0 * rows
+                           : epi == EPI_VIE_DOT ? (2.0 + (dots ? dots->nvec : 0)) * n * es
                                                 : 2.0 * n * es;
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);

@@ -96,7 +96,23 @@ struct Geo {
   long u2() const { return dim == 3 ? (long)nz * Ly * Lx : 0; }
 };
 
-enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3 };
+enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3, EPI_VIE_DOT = 4 };
+
+// Arnoldi inner products fused into the last pass of an EPI_VIE operator:
+// dotp[b][part][i] = vscale_i,b * sum over the part's rows of conj(V_i) . y,
+// i < nvec, one part per workgroup of the inverse row pass. Done only when
+// every workgroup's rows belong to one RHS and there are at most kMaxDotParts
+// parts per RHS; launch_vie reports whether it did them (and `nparts`).
+constexpr int kMaxDotParts = 256;
+struct VieDots {
+  const void* basis = nullptr;   // V_0 [B][n] (cplx<T>), vector i at basis + i*vs
+  long vs = 0;
+  int nvec = 0;                  // j + 1
+  const void* vscale = nullptr;  // [JM+1][B] cplx<T>
+  c128* dotp = nullptr;          // [B][nparts][dstride]
+  int dstride = 0;               // JM + 1
+  int nparts = 0;                // out: parts per RHS
+};
 
 // y = A x for B right-hand sides (Eq. 5 discretised):
 //   EPI_VIE  : y_b = s_b x_b - conv(m * s_b x_b)
@@ -110,7 +126,8 @@ enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3 };
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr, double* rowpart = nullptr);
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr, double* rowpart = nullptr,
+                VieDots* dots = nullptr);  // returns through dots->nparts (0: not fused)
 
 // Forward FFT of a full padded grid [Lz][Ly][Lx] (no padding, no crop), in place
 // through `work` of the same size: out = FFT(in). Used for the Green spectrum.

@@ -86,25 +86,35 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
                                              const int* __restrict__ active, const cplx<T>* __restrict__ vscale,
-                                             int B, const c128* __restrict__ dotp, int nblk, c128* __restrict__ H,
-                                             double* __restrict__ nrmp) {
+                                             int B, const c128* __restrict__ dotp, int ndot, int nblk,
+                                             c128* __restrict__ H, double* __restrict__ nrmp) {
   const int b = blockIdx.y;
   if (!active[b]) return;
   __shared__ double hr[JM + 1], hi[JM + 1];
   __shared__ double red[KT / 64];
   const int t = threadIdx.x;
-  if (t <= j) {
-    double r = 0.0, m = 0.0;
-    for (int k = 0; k < nblk; ++k) {
-      const c128 d = dotp[((long)b * nblk + k) * (JM + 1) + t];
-      r += d.x;
-      m += d.y;
+  // h_i = sum of the ndot inner-product parts: wave w reduces vectors
+  // i = w, w + 4, ..., each lane a fixed subset of parts, then a fixed-order
+  // wave sum (the same in every block)
+  {
+    const int lane = t & 63, w = t >> 6;
+    for (int i = w; i <= j; i += KT / 64) {
+      double r = 0.0, m = 0.0;
+      for (int k = lane; k < ndot; k += 64) {
+        const c128 d = dotp[((long)b * ndot + k) * (JM + 1) + i];
+        r += d.x;
+        m += d.y;
+      }
+      r = wave_sum(r);
+      m = wave_sum(m);
+      if (lane == 0) {
+        if (blockIdx.x == 0) H[((long)b * (JM + 1) + i) * JM + j] = mk(r, m);
+        // the update uses the stored (unnormalised) vectors: fold their scale in
+        const double sc = (double)vscale[(long)i * B + b].x;
+        hr[i] = r * sc;
+        hi[i] = m * sc;
+      }
     }
-    if (blockIdx.x == 0) H[((long)b * (JM + 1) + t) * JM + j] = mk(r, m);
-    // the update uses the stored (unnormalised) vectors: fold their scale in
-    const double sc = (double)vscale[(long)t * B + b].x;
-    hr[t] = r * sc;
-    hi[t] = m * sc;
   }
   __syncthreads();
   const long off = (long)b * n;
@@ -413,19 +423,25 @@ void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double i
 }
 
 template <typename T>
-void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st) {
+void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st) {
   const long vs = s.vstride();
   const double act = (double)(tl_active > 0 && tl_active < s.B ? tl_active : s.B);
   const double vb = (double)s.n * sizeof(cplx<T>);
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;
-  prof_begin(KC_DOTS + po, st);
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                          s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
-  FWI_LAUNCH_CHECK();
-  prof_end(KC_DOTS + po, st, act * (j + 2) * vb);
+  // nparts > 0: the operator's last pass already wrote nparts inner-product
+  // partials per RHS; otherwise they come from the inner-product kernel
+  int ndot = nparts;
+  if (ndot == 0) {
+    prof_begin(KC_DOTS + po, st);
+    FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
+                                            s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
+    FWI_LAUNCH_CHECK();
+    prof_end(KC_DOTS + po, st, act * (j + 2) * vb);
+    ndot = s.nblk;
+  }
   prof_begin(KC_ORTH + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                          s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk, s.H, s.nrmp));
+                                          s.chunk, s.active, s.vscale, s.B, s.dotp, ndot, s.nblk, s.H, s.nrmp));
   FWI_LAUNCH_CHECK();
   prof_end(KC_ORTH + po, st, act * (j + 3) * vb);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
@@ -454,7 +470,7 @@ void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
   template void krylov_start_norm<T>(const KrylovState<T>&, const c128*, hipStream_t);         \
   template void krylov_rows_norm<T>(const KrylovState<T>&, const double*, int, hipStream_t);   \
   template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
-  template void krylov_arnoldi<T>(const KrylovState<T>&, int, hipStream_t);                    \
+  template void krylov_arnoldi<T>(const KrylovState<T>&, int, int, hipStream_t);               \
   template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, int, hipStream_t);        \
   template void krylov_reset_iters<T>(const KrylovState<T>&, hipStream_t);
 FWI_INST(float)

@@ -20,7 +20,7 @@ struct KrylovState {
   c128* sn = nullptr;          // [B][JM]
   c128* gv = nullptr;          // [B][JM+1]
   c128* y = nullptr;           // [B][JM]
-  c128* dotp = nullptr;        // [B][nblk][JM+1]
+  c128* dotp = nullptr;        // [B][parts][JM+1], parts <= max(nblk, kMaxDotParts)
   double* nrmp = nullptr;      // [B][nblk]
   double* rnorm = nullptr;     // [B] residual norm at cycle start
   double* bnorm = nullptr;     // [B]
@@ -47,8 +47,10 @@ void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, 
 // Norms, activity, stopping targets and the scale of V_0 (1 / |r|).
 template <typename T>
 void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st);
+// Arnoldi step j after the matvec into V_{j+1}: inner products (unless the
+// operator's last pass produced `nparts` partials per RHS), update, Givens.
 template <typename T>
-void krylov_arnoldi(const KrylovState<T>& s, int j, hipStream_t st);  // dots, orth, givens, normalise
+void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st);
 // Back-substitution and x update; first: x is written, not read (x_0 = 0).
 template <typename T>
 void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st);
