@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--restart", type=int, default=16)
     ap.add_argument("--check-every", type=int, default=1)
+    ap.add_argument("--max-rhs", type=int, default=0,
+                    help="cap on RHS per batched solve (0: all frequencies of the step at once)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile variants")
@@ -106,9 +108,9 @@ def main():
     tuned_table = ctx.get_tuning()
 
     mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
-                             inner_rtol=args.inner_rtol, check_every=args.check_every)
+                             inner_rtol=args.inner_rtol, check_every=args.check_every, max_rhs=args.max_rhs)
     plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=args.restart,
-                             check_every=args.check_every)
+                             check_every=args.check_every, max_rhs=args.max_rhs)
     solves_per_step = 2 * p.nf * p.ne
 
     def step(opts):

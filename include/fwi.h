@@ -82,7 +82,9 @@ typedef struct fwi_solve_opts {
   int max_refine;       /* FP32_REFINE: cap on refinement steps */
   double inner_rtol;    /* FP32_REFINE: relative target of each inner solve */
   int max_rhs;          /* cap on RHS per batched solve (0: all frequencies at once) */
-  int check_every;      /* iterations between host convergence checks (>= 1) */
+  int check_every;      /* iterations between host convergence checks (>= 1); a check
+                           is read after the next step is enqueued, so at most one
+                           fully masked step follows convergence */
   int reciprocity_adjoint; /* 1: adjoint fields as sum_j conj(r_ij) p_j (no adjoint solves) */
 } fwi_solve_opts;
 

@@ -135,7 +135,9 @@ struct EventProfiler : LaunchProfiler {
   struct Rec {
     int cls;
     hipEvent_t a, b;
-    double bytes;
+    double per_rhs, fixed;
+    bool masked;
+    long B, act;
   };
   std::vector<Rec> recs;
   hipEvent_t cur[2 * KC_COUNT] = {};
@@ -155,11 +157,17 @@ struct EventProfiler : LaunchProfiler {
     cur[cls] = get();
     FWI_HIP(hipEventRecord(cur[cls], st));
   }
-  void end(int cls, hipStream_t st, double bytes) override {
+  void end(int cls, hipStream_t st, double per_rhs, double fixed, bool masked, long B) override {
     if (!((mask >> cls) & 1u)) return;
     hipEvent_t b = get();
     FWI_HIP(hipEventRecord(b, st));
-    recs.push_back({cls, cur[cls], b, bytes});
+    const long act = masked && tl_active > 0 && tl_active < B ? tl_active : B;
+    recs.push_back({cls, cur[cls], b, per_rhs, fixed, masked, B, act});
+  }
+  size_t mark() const override { return recs.size(); }
+  void set_active(size_t from, long act) override {
+    for (size_t k = from; k < recs.size(); ++k)
+      if (recs[k].masked) recs[k].act = act < recs[k].B ? act : recs[k].B;
   }
   void flush() {
     for (const Rec& r : recs) {
@@ -168,7 +176,7 @@ struct EventProfiler : LaunchProfiler {
       FWI_HIP(hipEventElapsedTime(&ms, r.a, r.b));
       tot_ms[r.cls] += ms;
       cnt[r.cls] += 1;
-      byt[r.cls] += r.bytes;
+      byt[r.cls] += r.per_rhs * (double)r.act + r.fixed;
     }
     recs.clear();
     used = 0;
@@ -216,7 +224,9 @@ struct fwi_ctx {
   std::vector<hipStream_t> branch;             // one per instance of a wave (default priority)
   std::vector<hipEvent_t> branch_ev;
   hipEvent_t fork_ev = nullptr;
+  hipEvent_t count_ev = nullptr;               // active-count copy of the solver loop
   ~fwi_ctx() {
+    if (count_ev) (void)hipEventDestroy(count_ev);
     for (auto& kv : bcache) kv.second.release();
     for (hipStream_t st : branch) (void)hipStreamDestroy(st);
     for (hipEvent_t e : branch_ev) (void)hipEventDestroy(e);
@@ -541,19 +551,34 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       res.unconverged = nact;
       break;
     }
+    // The active count after step j-1 is copied asynchronously and read only
+    // once step j is enqueued, so the device does not wait for the host
+    // between steps; a step enqueued after every RHS stopped runs fully masked.
+    bool pending = false;
     for (int j = 0; j < ks.JM; ++j) {
+      const size_t mark = tl_prof ? tl_prof->mark() : 0;
       VieDots dots = arnoldi_dots(ks, j);
       launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, ghatT, rhs_freq,
                     s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
       krylov_arnoldi(ks, j, dots.nparts, st);
       ++total;
-      if ((j + 1) % o.check_every == 0 || j + 1 == ks.JM || total >= o.max_iter) {
-        FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
-        FWI_HIP(hipStreamSynchronize(st));
-        tl_active = c->h_int[0];
-        if (c->h_int[0] == 0) break;
+      if (pending) {
+        pending = false;
+        FWI_HIP(hipEventSynchronize(c->count_ev));
+        const int na = c->h_int[8];  // RHS that step j processed
+        tl_active = na;
+        if (tl_prof) tl_prof->set_active(mark, na);
+        if (na == 0) {
+          --total;
+          break;
+        }
       }
-      if (total >= o.max_iter) break;
+      if (j + 1 == ks.JM || total >= o.max_iter) break;
+      if ((j + 1) % o.check_every == 0) {
+        FWI_HIP(hipMemcpyAsync(c->h_int + 8, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
+        FWI_HIP(hipEventRecord(c->count_ev, st));
+        pending = true;
+      }
     }
     krylov_finish_cycle(ks, x64, cyc == 0, st);
     x_written = true;
@@ -1353,6 +1378,7 @@ int fwi_create(fwi_ctx** out, int device, void* stream) {
     FWI_HIP(hipHostMalloc((void**)&c->h_int, 64 * sizeof(int), hipHostMallocDefault));
     FWI_HIP(hipHostMalloc((void**)&c->h_dbl, 64 * sizeof(double), hipHostMallocDefault));
     FWI_HIP(hipMalloc((void**)&c->d_int, 64 * sizeof(int)));
+    FWI_HIP(hipEventCreateWithFlags(&c->count_ev, hipEventDisableTiming));
   } catch (const Error& e) {
     fwi_destroy(c);
     return e.code;

@@ -518,7 +518,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
-  const double act = (double)(active && tl_active > 0 && tl_active < B ? tl_active : B);
+  const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
   const double gbytes = (double)(tl_nfreq > 0 ? tl_nfreq : 1) * g.npad() * es;
   const double n = (double)g.n();
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;  // FP64 launches are separate classes
@@ -536,7 +536,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.in_stride = g.nx;
   prof_begin(KC_ROW_FWD + po, st);
   row_fwd_call<T>(g.Lx, f, st);
-  prof_end(KC_ROW_FWD + po, st, act * (n + g.u1()) * es + n * es);
+  prof_end(KC_ROW_FWD + po, st, (n + g.u1()) * es, n * es, masked, B);
   if (g.dim == 2) {
     // pass 2: columns along z, convolution, in place
     StridedArgs<T> s{};
@@ -555,7 +555,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.lin = s.lout = g.nz;
     prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, s, B, 2, st);
-    prof_end(KC_CONV + po, st, act * 2.0 * g.u1() * es + gbytes);
+    prof_end(KC_CONV + po, st, 2.0 * g.u1() * es, gbytes, masked, B);
   } else {
     // forward along y: U1 [b][z][ny][Lx] -> U2 [b][z][Ly][Lx]
     StridedArgs<T> s{};
@@ -572,7 +572,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     s.lout = g.Ly;
     prof_begin(KC_Y_FWD + po, st);
     strided_call<T>(g.Ly, s, (long)B * g.nz, 0, st);
-    prof_end(KC_Y_FWD + po, st, act * (double)(g.u1() + g.u2()) * es);
+    prof_end(KC_Y_FWD + po, st, (double)(g.u1() + g.u2()) * es, 0.0, masked, B);
     // convolution along z, in place on U2
     StridedArgs<T> c{};
     c.in = U2;
@@ -590,7 +590,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     c.lin = c.lout = g.nz;
     prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, c, B, 2, st);
-    prof_end(KC_CONV + po, st, act * 2.0 * g.u2() * es + gbytes);
+    prof_end(KC_CONV + po, st, 2.0 * g.u2() * es, gbytes, masked, B);
     // inverse along y with crop: U2 -> U1
     StridedArgs<T> v{};
     v.in = U2;
@@ -606,7 +606,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
     v.lout = g.ny;
     prof_begin(KC_Y_INV + po, st);
     strided_call<T>(g.Ly, v, (long)B * g.nz, 1, st);
-    prof_end(KC_Y_INV + po, st, act * (double)(g.u1() + g.u2()) * es);
+    prof_end(KC_Y_INV + po, st, (double)(g.u1() + g.u2()) * es, 0.0, masked, B);
   }
   // last pass: rows along x, inverse, crop, epilogue
   RowInvArgs<T> r{};
@@ -647,7 +647,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                                                 : 2.0 * n * es;
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
-  prof_end(KC_ROW_INV + po, st, act * ((double)g.u1() * es + epi_bytes));
+  prof_end(KC_ROW_INV + po, st, (double)g.u1() * es + epi_bytes, 0.0, masked, B);
 }
 
 #ifdef FWI_FFT_WITH_FULL

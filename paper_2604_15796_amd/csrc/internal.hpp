@@ -33,19 +33,25 @@ enum KernelClass { KC_ROW_FWD = 0, KC_CONV, KC_ROW_INV, KC_Y_FWD, KC_Y_INV, KC_D
 // Per-thread hooks set by the entry points: launch sites report each launch of
 // a class with its algorithmic HBM bytes; active-RHS and frequency-count hints
 // let them compute those bytes for masked batches.
+// A launch moves per_rhs bytes for each RHS it processes plus fixed bytes; a
+// masked launch processes the RHS still active (tl_active when it is enqueued,
+// corrected by set_active once the solver has read the true count), an
+// unmasked one all B.
 struct LaunchProfiler {
   virtual void begin(int cls, hipStream_t st) = 0;
-  virtual void end(int cls, hipStream_t st, double bytes) = 0;
+  virtual void end(int cls, hipStream_t st, double per_rhs, double fixed, bool masked, long B) = 0;
+  virtual size_t mark() const = 0;                  // index of the next record
+  virtual void set_active(size_t from, long act) = 0;  // masked records from `from` on
   virtual ~LaunchProfiler() = default;
 };
 extern thread_local LaunchProfiler* tl_prof;
-extern thread_local long tl_active;  // RHS that the next launches actually process
+extern thread_local long tl_active;  // RHS that the next launches actually process (0: all)
 extern thread_local int tl_nfreq;    // distinct frequencies in the batch (Ghat reads)
 inline void prof_begin(int cls, hipStream_t st) {
   if (tl_prof) tl_prof->begin(cls, st);
 }
-inline void prof_end(int cls, hipStream_t st, double bytes) {
-  if (tl_prof) tl_prof->end(cls, st, bytes);
+inline void prof_end(int cls, hipStream_t st, double per_rhs, double fixed, bool masked, long B) {
+  if (tl_prof) tl_prof->end(cls, st, per_rhs, fixed, masked, B);
 }
 
 // Supported FFT lengths (padded axis sizes): 2^a 3^b from 32 to 1024.

@@ -425,7 +425,6 @@ void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double i
 template <typename T>
 void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st) {
   const long vs = s.vstride();
-  const double act = (double)(tl_active > 0 && tl_active < s.B ? tl_active : s.B);
   const double vb = (double)s.n * sizeof(cplx<T>);
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;
   // nparts > 0: the operator's last pass already wrote nparts inner-product
@@ -436,14 +435,14 @@ void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st) 
     FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
                                             s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
     FWI_LAUNCH_CHECK();
-    prof_end(KC_DOTS + po, st, act * (j + 2) * vb);
+    prof_end(KC_DOTS + po, st, (j + 2) * vb, 0.0, true, s.B);
     ndot = s.nblk;
   }
   prof_begin(KC_ORTH + po, st);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
                                           s.chunk, s.active, s.vscale, s.B, s.dotp, ndot, s.nblk, s.H, s.nrmp));
   FWI_LAUNCH_CHECK();
-  prof_end(KC_ORTH + po, st, act * (j + 3) * vb);
+  prof_end(KC_ORTH + po, st, (j + 3) * vb, 0.0, true, s.B);
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
                                           s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters,
                                           s.vscale + (long)(j + 1) * s.B, s.counters));
