@@ -146,8 +146,10 @@ struct EventProfiler : LaunchProfiler {
   double byt[2 * KC_COUNT] = {};
   hipEvent_t get() {
     if (used == pool.size()) {
+      // timing-only events: no system-scope fence, so a recorded event does
+      // not hold back the next launch
       hipEvent_t e;
-      FWI_HIP(hipEventCreate(&e));
+      FWI_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       pool.push_back(e);
     }
     return pool[used++];
@@ -449,8 +451,8 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.active = a.take<int>(B);
   k.ncol = a.take<int>(B);
   k.iters = a.take<int>(B);
-  k.counters = a.take<int>(2);
-  k.maxrel = a.take<double>(1);
+  k.counters = a.take<int>(4);  // active counts, then the max relative residual: one copy reads both
+  k.maxrel = k.counters ? reinterpret_cast<double*>(k.counters + 2) : nullptr;
   s.rowpart = a.take<double>((size_t)B * g.nz * g.ny);
   s.U1 = a.take<cplx<T>>((size_t)B * g.u1());
   s.U2 = g.dim == 3 ? a.take<cplx<T>>((size_t)B * g.u2()) : nullptr;
@@ -539,10 +541,9 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       res.matvecs += B;
     }
     krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
-    FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
-    FWI_HIP(hipMemcpyAsync(c->h_dbl, ks.maxrel, sizeof(double), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
     FWI_HIP(hipStreamSynchronize(st));
-    res.maxrel = c->h_dbl[0];
+    std::memcpy(&res.maxrel, c->h_int + 2, sizeof(double));
     if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
     const int nact = c->h_int[0];
     tl_active = nact;
@@ -554,7 +555,11 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     // The active count after step j-1 is copied asynchronously and read only
     // once step j is enqueued, so the device does not wait for the host
     // between steps; a step enqueued after every RHS stopped runs fully masked.
+    // Once at most half the RHS are left, the host waits for each count
+    // before enqueueing the next step instead (a wait costs less than a
+    // masked step).
     bool pending = false;
+    int known = nact;  // latest active count read
     for (int j = 0; j < ks.JM; ++j) {
       const size_t mark = tl_prof ? tl_prof->mark() : 0;
       VieDots dots = arnoldi_dots(ks, j);
@@ -565,10 +570,10 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       if (pending) {
         pending = false;
         FWI_HIP(hipEventSynchronize(c->count_ev));
-        const int na = c->h_int[8];  // RHS that step j processed
-        tl_active = na;
-        if (tl_prof) tl_prof->set_active(mark, na);
-        if (na == 0) {
+        known = c->h_int[8];  // RHS that step j processed
+        tl_active = known;
+        if (tl_prof) tl_prof->set_active(mark, known);
+        if (known == 0) {
           --total;
           break;
         }
@@ -577,7 +582,14 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       if ((j + 1) % o.check_every == 0) {
         FWI_HIP(hipMemcpyAsync(c->h_int + 8, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
         FWI_HIP(hipEventRecord(c->count_ev, st));
-        pending = true;
+        if (2 * known <= B) {
+          FWI_HIP(hipEventSynchronize(c->count_ev));
+          known = c->h_int[8];
+          tl_active = known;
+          if (known == 0) break;
+        } else {
+          pending = true;
+        }
       }
     }
     krylov_finish_cycle(ks, x64, cyc == 0, st);
