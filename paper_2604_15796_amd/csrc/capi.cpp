@@ -504,13 +504,28 @@ VieDots arnoldi_dots(const KrylovState<T>& ks, int j) {
 template <typename T>
 void launch_residual_basis(const Geo& g, const Twiddles& tw, int B, const c128* x64, const c128* m64,
                            const c128* ghat64, const int* rhs_freq, SolveBufs<T>& s, const c128* b64,
-                           hipStream_t st) {
+                           hipStream_t st, const XUpdate* xu = nullptr) {
   if (std::is_same<T, float>::value)
     launch_vie<double>(g, tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64, nullptr, b64,
-                       EPI_RESID32, st, reinterpret_cast<c64*>(s.ks.V), s.rowpart);
+                       EPI_RESID32, st, reinterpret_cast<c64*>(s.ks.V), s.rowpart, nullptr, xu);
   else
     launch_vie<double>(g, tw, B, x64, nullptr, nullptr, m64, ghat64, rhs_freq, s.U1_64, s.U2_64,
-                       reinterpret_cast<c128*>(s.ks.V), b64, EPI_RESID, st, nullptr, s.rowpart);
+                       reinterpret_cast<c128*>(s.ks.V), b64, EPI_RESID, st, nullptr, s.rowpart, nullptr, xu);
+}
+
+// The correction of a finished cycle, applied by the next residual's first pass.
+template <typename T>
+XUpdate cycle_update(const KrylovState<T>& ks, int first, int steps) {
+  XUpdate u;
+  u.basis = ks.V;
+  u.fp32 = std::is_same<T, float>::value;
+  u.vs = ks.vstride();
+  u.ncol = ks.ncol;
+  u.coef = ks.y;
+  u.cstride = ks.JM;
+  u.first = first;
+  u.kmax = steps;
+  return u;
 }
 
 template <typename T>
@@ -530,13 +545,16 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   krylov_reset_iters(ks, st);
   int total = 0, cyc = 0;
   bool x_written = false;
+  XUpdate pending_x;  // correction of the last cycle, not yet added to x
   for (;; ++cyc) {
     if (cyc == 0) {
       krylov_start_norm(ks, b64, st);  // x_0 = 0: r = b
     } else {
-      // FP64 residual; its epilogue writes V_0 (unscaled) and per-row norms
+      // FP64 residual of x plus the last cycle's correction (added to x by
+      // its first pass); its epilogue writes V_0 (unscaled) and per-row norms
       tl_active = B;
-      launch_residual_basis(g, c->tw, B, x64, m64, ghat64, rhs_freq, s, b64, st);
+      launch_residual_basis(g, c->tw, B, x64, m64, ghat64, rhs_freq, s, b64, st, &pending_x);
+      x_written = true;
       krylov_rows_norm(ks, s.rowpart, g.nz * g.ny, st);
       res.matvecs += B;
     }
@@ -560,6 +578,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     // masked step).
     bool pending = false;
     int known = nact;  // latest active count read
+    int steps = 0;     // Arnoldi steps of this cycle
     for (int j = 0; j < ks.JM; ++j) {
       const size_t mark = tl_prof ? tl_prof->mark() : 0;
       VieDots dots = arnoldi_dots(ks, j);
@@ -567,6 +586,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
                     s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
       krylov_arnoldi(ks, j, dots.nparts, st);
       ++total;
+      ++steps;
       if (pending) {
         pending = false;
         FWI_HIP(hipEventSynchronize(c->count_ev));
@@ -575,6 +595,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
         if (tl_prof) tl_prof->set_active(mark, known);
         if (known == 0) {
           --total;
+          --steps;
           break;
         }
       }
@@ -592,8 +613,8 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
         }
       }
     }
-    krylov_finish_cycle(ks, x64, cyc == 0, st);
-    x_written = true;
+    krylov_backsolve(ks, st);
+    pending_x = cycle_update(ks, cyc == 0, steps);
   }
   if (!x_written) launch_fill_zero_c128((long)B * ks.n, x64, st);  // nothing to solve: x = 0
   res.cycles = cyc;

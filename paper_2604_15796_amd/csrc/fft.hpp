@@ -17,9 +17,20 @@
 // predicated-off loads, and the inverse plan is the reverse of the forward one.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace fwi {
+
+// A stage source is called as src(line, pb, ro), or, if it takes them, with
+// the butterfly slot t and leg r of the calling thread as well (sources that
+// hold values prepared per slot in registers).
+template <class Src>
+__device__ __forceinline__ auto stage_load(Src& src, int line, int pb, int ro, int t, int r) {
+  if constexpr (std::is_invocable_v<Src&, int, int, int, int, int>) return src(line, pb, ro, t, r);
+  else return src(line, pb, ro);
+}
 
 // ---------------------------------------------------------------- plans ---
 // Two plan families: radices 8/6/4/3 (any tile), and for tiles holding at
@@ -303,8 +314,9 @@ struct LineCfg {
   }
 };
 
-// One Stockham stage: loads R points per butterfly through src(line, pb, ro),
-// then (after an optional barrier) twiddles, transforms and stores through
+// One Stockham stage: loads R points per butterfly through src(line, pb, ro)
+// (see stage_load), then (after an optional barrier) twiddles, transforms and
+// stores through
 // snk(line, pb, ro, value); the point index is pb + ro with ro a compile-time
 // offset (see LineCfg::lds). Twiddle table tw[m] = exp(-2 pi i m / L).
 // HIN: legs R/2 .. R-1 are zero and not loaded (first stage over zero-padded
@@ -328,7 +340,7 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
       C::template split<R>(t, line, j);
 #pragma unroll
       for (int r = 0; r < RIN; ++r)
-        v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
+        v[t][r] = RD_SPLIT ? stage_load(src, line, j, r * (L / R), t, r) : stage_load(src, line, j + r * (L / R), 0, t, r);
       if constexpr (Ns > 1) {
         const int k = j % Ns;
         tw1[t] = tw[k * (L / (Ns * R))];
@@ -384,7 +396,7 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
       C::template split<R>(t, line, j);
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        v[t][r] = RD_SPLIT ? src(line, j, r * (L / R)) : src(line, j + r * (L / R), 0);
+        v[t][r] = RD_SPLIT ? stage_load(src, line, j, r * (L / R), t, r) : stage_load(src, line, j + r * (L / R), 0, t, r);
       tw1[t] = tw[j];  // k = j < Ns, step 1
       if constexpr (R > 8) tw8[t] = tw[8 * j];
     }

@@ -59,10 +59,24 @@ struct RowFwdArgs {
   long nrows;
   int rows_per_rhs, nin;
   long in_stride;
+  // fused solution update (XUpdate; FP64 residuals only)
+  const void* xu_basis;
+  long xu_vs;
+  const int* xu_ncol;
+  const c128* xu_coef;
+  int xu_cstride, xu_first;
+  cplx<T>* xu_x;         // = x, written
+  int xu_kind;           // 0: none, 1: complex64 basis, 2: complex128 basis
 };
 
-// HIN: nin <= L/2, so the upper half of every padded row is skipped
-template <typename T, int L, int NLV, bool HIN>
+template <int XU>
+using xu_basis_t = std::conditional_t<XU == 1, float, double>;
+
+// HIN: nin <= L/2, so the upper half of every padded row is skipped.
+// XU (1: complex64 basis, 2: complex128 basis): the input rows are first
+// replaced by x + sum_i coef_i V_i (see XUpdate), formed in registers for the
+// points of the first stage and stored back to x.
+template <typename T, int L, int NLV, bool HIN, int XU = 0>
 __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
@@ -70,6 +84,8 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   __shared__ int s_m[C::NL];
   __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
+  __shared__ int s_k[XU ? C::NL : 1];
+  __shared__ int s_b[XU ? C::NL : 1];
   const long g0 = (long)blockIdx.x * C::NL;
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
@@ -82,6 +98,10 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     s_x[l] = gc * a.in_stride;
     s_m[l] = (int)z * a.nin;
     s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
+    if constexpr (XU != 0) {
+      s_k[l] = a.xu_ncol[b];
+      s_b[l] = (int)b;
+    }
   }
   __syncthreads();
   if (!any_row(s_ok, C::NL)) return;  // converged right-hand sides: no traffic
@@ -90,19 +110,85 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   // stands in for m and the blend below makes the factor exactly 1
   const T km = a.m ? (T)1 : (T)0;
   const cplx<T>* mp = a.m ? a.m : a.x;
-  auto src = [&](int line, int pb, int ro) -> cplx<T> {
-    const int p = pb + ro;
-    const int pc = p < a.nin ? p : a.nin - 1;
-    const cplx<T> xv = a.x[s_x[line] + pc];
-    const cplx<T> mv = mp[s_m[line] + pc];
-    const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
-    const cplx<T> v = xv * mf * s_s[line];
-    return p < a.nin ? v : mk((T)0, (T)0);
-  };
   auto snk = [&](int line, int pb, int ro, cplx<T> v) {
     if (s_ok[line]) a.out[(g0 + line) * L + pb + ro] = v;
   };
-  fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
+  if constexpr (XU == 0) {
+    auto src = [&](int line, int pb, int ro) -> cplx<T> {
+      const int p = pb + ro;
+      const int pc = p < a.nin ? p : a.nin - 1;
+      const cplx<T> xv = a.x[s_x[line] + pc];
+      const cplx<T> mv = mp[s_m[line] + pc];
+      const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
+      const cplx<T> v = xv * mf * s_s[line];
+      return p < a.nin ? v : mk((T)0, (T)0);
+    };
+    fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
+  } else {
+    static_assert(sizeof(T) == 8 && HIN, "the fused update is for FP64 residuals of padded rows");
+    using TB = xu_basis_t<XU>;
+    // the points the first stage will ask this thread for: slot t, leg r
+    constexpr int R0 = stage_radix(L, 0, 0, C::BIG);
+    constexpr int NB0 = C::NL * (L / R0), TT0 = (NB0 + NT - 1) / NT, RIN0 = R0 / 2;
+    int kmax = 0;
+    for (int l = 0; l < C::NL; ++l) kmax = max(kmax, s_k[l]);
+    const cplx<TB>* V = static_cast<const cplx<TB>*>(a.xu_basis);
+    cplx<T> xin[TT0][RIN0];
+#pragma unroll
+    for (int t = 0; t < TT0; ++t) {
+      int line, j;
+      C::template split<R0>(t, line, j);
+      if (line >= C::NL) line = C::NL - 1;  // idle slot of a partial tile: any valid line
+#pragma unroll
+      for (int r = 0; r < RIN0; ++r) {
+        const int p = j + r * (L / R0);
+        const int pc = p < a.nin ? p : a.nin - 1;
+        xin[t][r] = a.xu_first ? mk(0.0, 0.0) : a.x[s_x[line] + pc];
+      }
+    }
+#pragma unroll 4
+    for (int i = 0; i < kmax; ++i) {
+#pragma unroll
+      for (int t = 0; t < TT0; ++t) {
+        int line, j;
+        C::template split<R0>(t, line, j);
+        if (line >= C::NL) line = C::NL - 1;
+        const bool use = i < s_k[line];
+        const c128 c = a.xu_coef[(long)s_b[line] * a.xu_cstride + i];
+#pragma unroll
+        for (int r = 0; r < RIN0; ++r) {
+          const int p = j + r * (L / R0);
+          const int pc = p < a.nin ? p : a.nin - 1;
+          const cplx<TB> v = V[(long)i * a.xu_vs + s_x[line] + pc];
+          const c128 u = cfma(c, mk((double)v.x, (double)v.y), xin[t][r]);
+          // select per component (unused vectors may hold anything)
+          xin[t][r].x = use ? u.x : xin[t][r].x;
+          xin[t][r].y = use ? u.y : xin[t][r].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TT0; ++t) {
+      if (NB0 % NT == 0 || (int)threadIdx.x + t * NT < NB0) {
+        int line, j;
+        C::template split<R0>(t, line, j);
+#pragma unroll
+        for (int r = 0; r < RIN0; ++r) {
+          const int p = j + r * (L / R0);
+          if (s_ok[line] && p < a.nin) a.xu_x[s_x[line] + p] = xin[t][r];
+        }
+      }
+    }
+    auto src = [&](int line, int pb, int ro, int t, int r) -> cplx<T> {
+      const int p = pb + ro;
+      const int pc = p < a.nin ? p : a.nin - 1;
+      const cplx<T> mv = mp[s_m[line] + pc];
+      const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
+      const cplx<T> v = xin[t][r] * mf * s_s[line];
+      return p < a.nin ? v : mk((T)0, (T)0);
+    };
+    fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
+  }
 }
 
 // ------------------------------------------------------------- row pass 3 ---
@@ -376,7 +462,15 @@ void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
   constexpr int NL = row_nl<T, L, V>();
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
-  if (2 * a.nin <= L) {
+  if (a.xu_kind != 0) {
+    if constexpr (sizeof(T) == 8) {
+      if (2 * a.nin > L) throw Error(-6, "the fused update needs zero-padded rows");
+      if (a.xu_kind == 1) hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, 1>), dim3(grid), dim3(NT), 0, st, a);
+      else hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, 2>), dim3(grid), dim3(NT), 0, st, a);
+    } else {
+      throw Error(-6, "the fused update is for complex128 residuals");
+    }
+  } else if (2 * a.nin <= L) {
     hipLaunchKernelGGL((k_row_fwd<T, L, NL, true>), dim3(grid), dim3(NT), 0, st, a);
   } else if constexpr (sizeof(T) == 8) {
     hipLaunchKernelGGL((k_row_fwd<T, L, NL, false>), dim3(grid), dim3(NT), 0, st, a);
@@ -515,7 +609,8 @@ int row_inv_nl(int L) {
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots) {
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
+                const XUpdate* xu) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
@@ -534,9 +629,23 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.rows_per_rhs = (int)rows_per_rhs;
   f.nin = g.nx;
   f.in_stride = g.nx;
+  double xu_bytes = 0.0;
+  if (xu) {
+    if (sizeof(T) != 8 || active) throw Error(-6, "the fused update is for complex128 residuals");
+    f.xu_kind = xu->fp32 ? 1 : 2;
+    f.xu_basis = xu->basis;
+    f.xu_vs = xu->vs;
+    f.xu_ncol = xu->ncol;
+    f.xu_coef = xu->coef;
+    f.xu_cstride = xu->cstride;
+    f.xu_first = xu->first;
+    f.xu_x = const_cast<cplx<T>*>(x);
+    // x read (unless first) and written, kmax basis vectors read, instead of the plain x read
+    xu_bytes = n * es * (xu->first ? 0.0 : 1.0) + (double)xu->kmax * n * (xu->fp32 ? 8.0 : 16.0);
+  }
   prof_begin(KC_ROW_FWD + po, st);
   row_fwd_call<T>(g.Lx, f, st);
-  prof_end(KC_ROW_FWD + po, st, (n + g.u1()) * es, n * es, masked, B);
+  prof_end(KC_ROW_FWD + po, st, (n + g.u1()) * es + xu_bytes, n * es, masked, B);
   if (g.dim == 2) {
     // pass 2: columns along z, convolution, in place
     StridedArgs<T> s{};

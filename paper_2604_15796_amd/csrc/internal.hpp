@@ -120,6 +120,21 @@ struct VieDots {
   int nparts = 0;                // out: parts per RHS
 };
 
+// Solution update of a refinement cycle fused into the first pass of the
+// next FP64 residual: before its row transform, every RHS forms
+// x_b = (first ? 0 : x_b) + sum_{i < ncol_b} coef[b][i] V_i,b (FP64), stores it
+// back into x and transforms it (the residual is then that of the new x).
+struct XUpdate {
+  const void* basis = nullptr;  // V_0 [B][n] of complex64 (fp32) or complex128, vector i at basis + i*vs
+  bool fp32 = true;
+  long vs = 0;
+  const int* ncol = nullptr;    // [B] vectors per RHS
+  const c128* coef = nullptr;   // [B][cstride]
+  int cstride = 0;
+  int first = 0;
+  int kmax = 0;                 // bound on ncol (profiled bytes only)
+};
+
 // y = A x for B right-hand sides (Eq. 5 discretised):
 //   EPI_VIE  : y_b = s_b x_b - conv(m * s_b x_b)
 //   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored), and
@@ -128,12 +143,14 @@ struct VieDots {
 // x, y, rhs: [B][n]; scale: [B] or null; active: [B] or null (inactive RHS are
 // skipped and their y left untouched); ghat: [nf][npad] spectra with k^2 and
 // 1/npad folded in; rhs_freq: [B] frequency index per RHS; U1 [B][u1],
-// U2 [B][u2] (3D) scratch.
+// U2 [B][u2] (3D) scratch. xu (FP64 residuals only): x is first updated in
+// place as described for XUpdate.
 template <typename T>
 void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr, double* rowpart = nullptr,
-                VieDots* dots = nullptr);  // returns through dots->nparts (0: not fused)
+                VieDots* dots = nullptr,  // returns through dots->nparts (0: not fused)
+                const XUpdate* xu = nullptr);
 
 // Forward FFT of a full padded grid [Lz][Ly][Lx] (no padding, no crop), in place
 // through `work` of the same size: out = FFT(in). Used for the Green spectrum.

@@ -306,9 +306,10 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
 }
 
 // Back-substitution R y = g for each RHS (k = ncol columns).
-template <int JM>
+template <typename T, int JM>
 __global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __restrict__ H,
-                            const c128* __restrict__ gv, c128* __restrict__ y) {
+                            const c128* __restrict__ gv, c128* __restrict__ y, const double* __restrict__ rnorm,
+                            const cplx<T>* __restrict__ vscale) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const int k = ncol[b];
@@ -321,15 +322,21 @@ __global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __r
     // acc / d
     y[(long)b * JM + i] = mk((acc.x * d.x + acc.y * d.y) / dn, (acc.y * d.x - acc.x * d.y) / dn);
   }
+  // the basis is normalised by |r| (cycle start) and stored with scales
+  for (int i = 0; i < k; ++i) {
+    const double sc = rnorm[b] * (double)vscale[(long)i * B + b].x;
+    const c128 v = y[(long)b * JM + i];
+    y[(long)b * JM + i] = mk(sc * v.x, sc * v.y);
+  }
 }
 
-// x_b += |r_b| sum_{i < ncol_b} y_i V_i  (FP64 accumulation); first: x_b is
-// not read (the first cycle starts from x = 0), and RHS that did no step get 0.
+// x_b += sum_{i < ncol_b} y_i V_i (FP64 accumulation, y from k_backsolve);
+// first: x_b is not read (the first cycle starts from x = 0), and RHS that
+// did no step get 0.
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, long vs, long n,
                                                 const int* __restrict__ ncol, const c128* __restrict__ y,
-                                                const double* __restrict__ rnorm, const cplx<T>* __restrict__ vscale,
-                                                int B, c128* __restrict__ x, int first) {
+                                                c128* __restrict__ x, int first) {
   const int b = blockIdx.y;
   const int k = ncol[b];
   if (k == 0) {
@@ -337,13 +344,8 @@ __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, l
       for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) x[(long)b * n + e] = mk(0.0, 0.0);
     return;
   }
-  __shared__ double yr[JM], yi[JM];
-  if (threadIdx.x < k) {
-    const c128 v = y[(long)b * JM + threadIdx.x];
-    const double sc = rnorm[b] * (double)vscale[(long)threadIdx.x * B + b].x;
-    yr[threadIdx.x] = sc * v.x;
-    yi[threadIdx.x] = sc * v.y;
-  }
+  __shared__ c128 yc[JM];
+  if (threadIdx.x < k) yc[threadIdx.x] = y[(long)b * JM + threadIdx.x];
   __syncthreads();
   const long off = (long)b * n;
   for (long e = (long)blockIdx.x * KT + threadIdx.x; e < n; e += (long)gridDim.x * KT) {
@@ -352,9 +354,7 @@ __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, l
     for (int i = 0; i < JM; ++i) {
       if (i < k) {
         const cplx<T> v = V[(long)i * vs + off + e];
-        const double vx = v.x, vy = v.y;
-        acc.x += yr[i] * vx - yi[i] * vy;
-        acc.y += yr[i] * vy + yi[i] * vx;
+        acc = cfma(yc[i], mk((double)v.x, (double)v.y), acc);
       }
     }
     x[off + e] = acc;
@@ -450,13 +450,23 @@ void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st) 
 }
 
 template <typename T>
-void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st) {
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_backsolve<JMC>), dim3((s.B + 63) / 64), dim3(64), 0, st, s.B, s.ncol,
-                                          s.H, s.gv, s.y));
+void krylov_backsolve(const KrylovState<T>& s, hipStream_t st) {
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_backsolve<T, JMC>), dim3((s.B + 63) / 64), dim3(64), 0, st, s.B,
+                                          s.ncol, s.H, s.gv, s.y, s.rnorm, s.vscale));
   FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_xupdate(const KrylovState<T>& s, c128* x, int first, hipStream_t st) {
   FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_xupdate<T, JMC>), dim3(vec_blocks(s.n), s.B), dim3(KT), 0, st, s.V,
-                                          s.vstride(), s.n, s.ncol, s.y, s.rnorm, s.vscale, s.B, x, first));
+                                          s.vstride(), s.n, s.ncol, s.y, x, first));
   FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st) {
+  krylov_backsolve(s, st);
+  krylov_xupdate(s, x, first, st);
 }
 
 template <typename T>
@@ -470,6 +480,8 @@ void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
   template void krylov_rows_norm<T>(const KrylovState<T>&, const double*, int, hipStream_t);   \
   template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
   template void krylov_arnoldi<T>(const KrylovState<T>&, int, int, hipStream_t);               \
+  template void krylov_backsolve<T>(const KrylovState<T>&, hipStream_t);                       \
+  template void krylov_xupdate<T>(const KrylovState<T>&, c128*, int, hipStream_t);             \
   template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, int, hipStream_t);        \
   template void krylov_reset_iters<T>(const KrylovState<T>&, hipStream_t);
 FWI_INST(float)

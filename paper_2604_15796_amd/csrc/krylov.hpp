@@ -19,7 +19,7 @@ struct KrylovState {
   double* cs = nullptr;        // [B][JM]
   c128* sn = nullptr;          // [B][JM]
   c128* gv = nullptr;          // [B][JM+1]
-  c128* y = nullptr;           // [B][JM]
+  c128* y = nullptr;           // [B][JM] correction x += sum_i y_i V_i (stored V_i; |r| and scales folded in)
   c128* dotp = nullptr;        // [B][parts][JM+1], parts <= max(nblk, kMaxDotParts)
   double* nrmp = nullptr;      // [B][nblk]
   double* rnorm = nullptr;     // [B] residual norm at cycle start
@@ -51,7 +51,14 @@ void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double i
 // operator's last pass produced `nparts` partials per RHS), update, Givens.
 template <typename T>
 void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st);
-// Back-substitution and x update; first: x is written, not read (x_0 = 0).
+// Back-substitution: y from the rotated Hessenberg system, scaled so that
+// the correction is sum_{i < ncol} y_i V_i over the stored basis vectors.
+template <typename T>
+void krylov_backsolve(const KrylovState<T>& s, hipStream_t st);
+// x += sum_{i < ncol} y_i V_i; first: x is written, not read (x_0 = 0).
+template <typename T>
+void krylov_xupdate(const KrylovState<T>& s, c128* x, int first, hipStream_t st);
+// Both of the above.
 template <typename T>
 void krylov_finish_cycle(const KrylovState<T>& s, c128* x, int first, hipStream_t st);
 template <typename T>
