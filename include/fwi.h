@@ -248,7 +248,10 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void
 /* Kernel classes: 0 row forward FFT pass, 1 Green convolution pass (forward
  * FFT, spectrum product, inverse FFT along the depth axis), 2 row inverse
  * pass with epilogue, 3 / 4 forward / inverse elevation passes (3D),
- * 5 Arnoldi inner products, 6 Arnoldi orthogonalisation. */
+ * 5 Arnoldi inner products (when not fused into the row inverse pass),
+ * 6 Arnoldi orthogonalisation alone (after the last step of a cycle),
+ * 7 Arnoldi orthogonalisation fused with the row forward pass of the next
+ * matvec. */
 #define FWI_KC_ROW_FWD 0
 #define FWI_KC_CONV 1
 #define FWI_KC_ROW_INV 2
@@ -256,7 +259,8 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void
 #define FWI_KC_Y_INV 4
 #define FWI_KC_DOTS 5
 #define FWI_KC_ORTH 6
-/* Class k + 7 is the complex128 launch of class k (k + 0: complex64).
+#define FWI_KC_ORTH_FWD 7
+/* Class k + 8 is the complex128 launch of class k (k + 0: complex64).
  * Time every launch of the classes in `mask` (bit k = class k) with HIP events
  * recorded on the context's stream; resets the accumulated figures. 0 turns it off. */
 int fwi_profile(fwi_ctx* ctx, unsigned mask);

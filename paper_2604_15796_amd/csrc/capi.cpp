@@ -442,6 +442,7 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.gv = a.take<c128>((size_t)B * (JM + 1));
   k.y = a.take<c128>((size_t)B * JM);
   k.dotp = a.take<c128>((size_t)B * std::max(k.nblk, kMaxDotParts) * (JM + 1));
+  k.hcoef = a.take<c128>((size_t)B * (JM + 1));
   k.nrmp = a.take<double>((size_t)B * k.nblk);
   k.rnorm = a.take<double>(B);
   k.bnorm = a.take<double>(B);
@@ -499,6 +500,65 @@ VieDots arnoldi_dots(const KrylovState<T>& ks, int j) {
   return d;
 }
 
+// Orthogonalisation of the matvec result of step j (stored in V_{j+1}),
+// fused into the first pass of step j + 1 (or done alone after the last step).
+template <typename T>
+OrthIn arnoldi_orth(const KrylovState<T>& ks, int j, double* rowpart, bool transform) {
+  OrthIn o;
+  o.basis = ks.V;
+  o.vs = ks.vstride();
+  o.nvec = j + 1;
+  o.coef = ks.hcoef;
+  o.cstride = ks.JM + 1;
+  o.rowpart = rowpart;
+  o.transform = transform;
+  return o;
+}
+
+// Arnoldi steps of one cycle, in launch order. Step j: the tail of the
+// matvec (convolution, last pass with the inner products of w = A v_j
+// against V_0..V_j) writes w into V_{j+1}; then column j of H is summed and
+// the first pass of the next matvec orthogonalises w into v_{j+1}, stores it,
+// sums |v_{j+1}|^2 per row and row-transforms it (only orthogonalises after
+// the last step); then the Givens kernel finishes column j and sets the scale
+// of v_{j+1}, so the next tail runs on the RHS still active.
+template <typename T>
+struct ArnoldiDriver {
+  const Geo& g;
+  const Twiddles& tw;
+  KrylovState<T>& ks;
+  SolveBufs<T>& s;
+  const cplx<T>* mT;
+  const cplx<T>* ghatT;
+  const int* rhs_freq;
+  hipStream_t st;
+  int B;
+  // first pass of step 0 on V_0 (scaled by vscale_0 in the last pass)
+  void first_rows() {
+    launch_vie_rows<T>(g, tw, B, ks.V, ks.active, mT, s.U1, st);
+  }
+  // rest of step j: w into V_{j+1}, inner products, column j of H
+  void tail(int j) {
+    const long vs = ks.vstride();
+    VieDots dots = arnoldi_dots(ks, j);
+    launch_vie_tail<T>(g, tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, ghatT, rhs_freq, s.U1,
+                       s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
+    int ndot = dots.nparts;
+    if (ndot == 0) {
+      krylov_dots(ks, j, st);
+      ndot = ks.nblk;
+    }
+    krylov_hsum(ks, j, ndot, st);
+  }
+  // orthogonalise w_{j+1} (and transform it unless this was the last step),
+  // then the rotations of column j
+  void orth_givens(int j, bool transform) {
+    const OrthIn o = arnoldi_orth(ks, j, s.rowpart, transform);
+    launch_vie_rows<T>(g, tw, B, ks.V + (long)(j + 1) * ks.vstride(), ks.active, mT, s.U1, st, nullptr, &o);
+    krylov_givens(ks, j, s.rowpart, g.nz * g.ny, st);
+  }
+};
+
 // r = b - A x in FP64 for every RHS; the epilogue stores r into V_0 of the
 // basis (rounded to the basis precision) and one |r|^2 partial per grid row.
 template <typename T>
@@ -538,7 +598,6 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   const bool fp32 = std::is_same<T, float>::value;
   const double inner = fp32 ? o.inner_rtol : 0.0;
   const int max_cycles = fp32 ? o.max_refine : (o.max_iter + o.restart - 1) / o.restart + 1;
-  const long vs = ks.vstride();
   const double t0 = now_ms();
   SolveTotals res;
   res.solves = B;
@@ -576,17 +635,18 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     // Once at most half the RHS are left, the host waits for each count
     // before enqueueing the next step instead (a wait costs less than a
     // masked step).
+    ArnoldiDriver<T> drv{g, c->tw, ks, s, mT, ghatT, rhs_freq, st, B};
     bool pending = false;
     int known = nact;  // latest active count read
     int steps = 0;     // Arnoldi steps of this cycle
-    for (int j = 0; j < ks.JM; ++j) {
+    drv.first_rows();
+    for (int j = 0;; ++j) {
       const size_t mark = tl_prof ? tl_prof->mark() : 0;
-      VieDots dots = arnoldi_dots(ks, j);
-      launch_vie<T>(g, c->tw, B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, ghatT, rhs_freq,
-                    s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
-      krylov_arnoldi(ks, j, dots.nparts, st);
+      drv.tail(j);
       ++total;
       ++steps;
+      const bool last = j + 1 == ks.JM || total >= o.max_iter;
+      drv.orth_givens(j, !last);
       if (pending) {
         pending = false;
         FWI_HIP(hipEventSynchronize(c->count_ev));
@@ -599,7 +659,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
           break;
         }
       }
-      if (j + 1 == ks.JM || total >= o.max_iter) break;
+      if (last) break;
       if ((j + 1) % o.check_every == 0) {
         FWI_HIP(hipMemcpyAsync(c->h_int + 8, ks.counters, sizeof(int), hipMemcpyDeviceToHost, st));
         FWI_HIP(hipEventRecord(c->count_ev, st));
@@ -1072,7 +1132,6 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   const ProblemCache& pc = *I.pc;
   const cplx<T>* mT = fp32 ? (const cplx<T>*)I.cb.m32 : (const cplx<T>*)I.cb.m64;
   const cplx<T>* gT = fp32 ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
-  const long vs = ks.vstride();
   if (cyc == 0) {
     krylov_start_norm(ks, rhs, st);
   } else {
@@ -1080,11 +1139,12 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
     krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
   }
   krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
+  // every step of the cycle, masked once an RHS has converged
+  ArnoldiDriver<T> drv{I.g, c->tw, ks, s, mT, gT, pc.rhs_freq, st, ks.B};
+  drv.first_rows();
   for (int j = 0; j < ks.JM; ++j) {
-    VieDots dots = arnoldi_dots(ks, j);
-    launch_vie<T>(I.g, c->tw, ks.B, ks.V + (long)j * vs, ks.vscale + (long)j * ks.B, ks.active, mT, gT,
-                  pc.rhs_freq, s.U1, s.U2, ks.V + (long)(j + 1) * vs, nullptr, EPI_VIE, st, nullptr, nullptr, &dots);
-    krylov_arnoldi(ks, j, dots.nparts, st);
+    drv.tail(j);
+    drv.orth_givens(j, j + 1 < ks.JM);
   }
   krylov_finish_cycle(ks, x, cyc == 0, st);
 }
@@ -1754,8 +1814,8 @@ int fwi_autotune(fwi_ctx* c, const fwi_problem* p, int precision, int B, int rep
     tl_prof = saved;
     tl_force_variant = -1;
     // class -> pass kind and length
-    const int kinds[KC_COUNT] = {PK_ROW_FWD, PK_CONV, PK_ROW_INV, PK_STRIDED, PK_STRIDED, -1, -1};
-    const int lens[KC_COUNT] = {g.Lx, g.Lz, g.Lx, g.Ly, g.Ly, 0, 0};
+    const int kinds[KC_COUNT] = {PK_ROW_FWD, PK_CONV, PK_ROW_INV, PK_STRIDED, PK_STRIDED, -1, -1, -1};
+    const int lens[KC_COUNT] = {g.Lx, g.Lz, g.Lx, g.Ly, g.Ly, 0, 0, 0};
     double strided_sum[kNumVariants] = {};
     for (int v = 0; v < kNumVariants; ++v) strided_sum[v] = t[KC_Y_FWD][v] + t[KC_Y_INV][v];
     for (int k = 0; k < KC_COUNT; ++k) {

@@ -40,6 +40,14 @@ __host__ __device__ constexpr int col_nl() {
        : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kColLds ? nl0 / 2 : nl0 / 4;
 }
 
+// A value that is the same in every lane, moved to scalar registers (values
+// read from LDS are otherwise treated as per-lane).
+__device__ __forceinline__ long uniform_long(long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(unsigned long)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long)v >> 32));
+  return (long)(((unsigned long)hi << 32) | lo);
+}
+
 // true if any row of the workgroup is to be processed (uniform: LDS flags)
 __device__ __forceinline__ bool any_row(const int* s_ok, int nl) {
   int any = 0;
@@ -48,44 +56,56 @@ __device__ __forceinline__ bool any_row(const int* s_ok, int nl) {
 }
 
 // ------------------------------------------------------------- row pass 1 ---
+// Input of the first pass: the rows of x as they are, or a combination with
+// basis vectors formed first (see k_row_fwd).
+enum RowInKind { RI_PLAIN = 0, RI_UPD32 = 1, RI_UPD64 = 2, RI_ORTH = 3, RI_ORTH_ONLY = 4 };
+
 template <typename T>
 struct RowFwdArgs {
   const cplx<T>* x;      // rows of length nin, row stride in_stride
   const cplx<T>* m;      // [rows_per_rhs][nin] or null
-  const cplx<T>* scale;  // [B] or null
   const int* active;     // [B] or null
   cplx<T>* out;          // rows of length L
   const cplx<T>* tw;
   long nrows;
   int rows_per_rhs, nin;
   long in_stride;
-  // fused solution update (XUpdate; FP64 residuals only)
-  const void* xu_basis;
-  long xu_vs;
-  const int* xu_ncol;
-  const c128* xu_coef;
-  int xu_cstride, xu_first;
-  cplx<T>* xu_x;         // = x, written
-  int xu_kind;           // 0: none, 1: complex64 basis, 2: complex128 basis
+  // combined input (kind != RI_PLAIN)
+  int kind;
+  const void* lc_basis;  // V_0; vector i at lc_basis + i * lc_vs elements
+  long lc_vs;
+  const int* lc_ncol;    // update: [B] vectors per RHS
+  int lc_nvec;           // orthogonalisation: vectors of every RHS
+  const c128* lc_coef;   // [B][lc_cstride]
+  int lc_cstride, lc_first;
+  cplx<T>* lc_out;       // = x, written
+  double* lc_rowpart;    // orthogonalisation: |v|^2 per row
 };
 
-template <int XU>
-using xu_basis_t = std::conditional_t<XU == 1, float, double>;
+template <typename T, int K>
+using lc_basis_t = std::conditional_t<K == RI_UPD32, float, std::conditional_t<K == RI_UPD64, double, T>>;
 
-// HIN: nin <= L/2, so the upper half of every padded row is skipped.
-// XU (1: complex64 basis, 2: complex128 basis): the input rows are first
-// replaced by x + sum_i coef_i V_i (see XUpdate), formed in registers for the
-// points of the first stage and stored back to x.
-template <typename T, int L, int NLV, bool HIN, int XU = 0>
+// Rows of x (times m) zero-padded to L and transformed. HIN: nin <= L/2, so
+// the upper half of every padded row is skipped.
+// K != RI_PLAIN: the input is first formed, in FP64 registers for the points
+// the first stage will ask this thread for, and stored back to x:
+//   RI_UPD32 / RI_UPD64 (complex128 x, complex64 / complex128 basis): the
+//     solution update x = (first ? 0 : x) + sum_{i < ncol_b} coef[b][i] V_i;
+//   RI_ORTH (x the new Arnoldi vector w, basis of type T): classical
+//     Gram-Schmidt v = w + sum_{i < nvec} coef[b][i] V_i (coef = -h_i times
+//     the vector's scale, accumulated in T like every vector update of the
+//     solver), stored, and |v|^2 summed per row in FP64 into rowpart;
+//     RI_ORTH_ONLY stops there (no transform).
+template <typename T, int L, int NLV, bool HIN, int K = RI_PLAIN>
 __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
+  constexpr bool ORTH = K == RI_ORTH || K == RI_ORTH_ONLY;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ long s_x[C::NL];
   __shared__ int s_m[C::NL];
-  __shared__ cplx<T> s_s[C::NL];
   __shared__ int s_ok[C::NL];
-  __shared__ int s_k[XU ? C::NL : 1];
-  __shared__ int s_b[XU ? C::NL : 1];
+  __shared__ int s_k[K != RI_PLAIN ? C::NL : 1];
+  __shared__ int s_b[K != RI_PLAIN ? C::NL : 1];
   const long g0 = (long)blockIdx.x * C::NL;
   for (int l = threadIdx.x; l < C::NL; l += NT) {
     const long g = g0 + l;
@@ -97,9 +117,8 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     s_ok[l] = ok;
     s_x[l] = gc * a.in_stride;
     s_m[l] = (int)z * a.nin;
-    s_s[l] = a.scale ? a.scale[b] : mk((T)1, (T)0);
-    if constexpr (XU != 0) {
-      s_k[l] = a.xu_ncol[b];
+    if constexpr (K != RI_PLAIN) {
+      s_k[l] = ORTH ? a.lc_nvec : a.lc_ncol[b];
       s_b[l] = (int)b;
     }
   }
@@ -113,27 +132,33 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   auto snk = [&](int line, int pb, int ro, cplx<T> v) {
     if (s_ok[line]) a.out[(g0 + line) * L + pb + ro] = v;
   };
-  if constexpr (XU == 0) {
+  if constexpr (K == RI_PLAIN) {
     auto src = [&](int line, int pb, int ro) -> cplx<T> {
       const int p = pb + ro;
       const int pc = p < a.nin ? p : a.nin - 1;
       const cplx<T> xv = a.x[s_x[line] + pc];
       const cplx<T> mv = mp[s_m[line] + pc];
       const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
-      const cplx<T> v = xv * mf * s_s[line];
+      const cplx<T> v = xv * mf;
       return p < a.nin ? v : mk((T)0, (T)0);
     };
     fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
   } else {
-    static_assert(sizeof(T) == 8 && HIN, "the fused update is for FP64 residuals of padded rows");
-    using TB = xu_basis_t<XU>;
+    static_assert(HIN, "combined inputs are rows of zero-padded operators");
+    static_assert(ORTH || sizeof(T) == 8, "the solution update is complex128");
+    using TB = lc_basis_t<T, K>;
+    using TA = std::conditional_t<ORTH, T, double>;  // accumulation type
     // the points the first stage will ask this thread for: slot t, leg r
     constexpr int R0 = stage_radix(L, 0, 0, C::BIG);
-    constexpr int NB0 = C::NL * (L / R0), TT0 = (NB0 + NT - 1) / NT, RIN0 = R0 / 2;
+    constexpr int NJ = L / R0, NB0 = C::NL * NJ, TT0 = (NB0 + NT - 1) / NT, RIN0 = R0 / 2;
     int kmax = 0;
     for (int l = 0; l < C::NL; ++l) kmax = max(kmax, s_k[l]);
-    const cplx<TB>* V = static_cast<const cplx<TB>*>(a.xu_basis);
-    cplx<T> xin[TT0][RIN0];
+    // addresses: a uniform base at the workgroup's first row (made scalar
+    // explicitly, it comes from LDS) plus small per-lane element offsets, the
+    // same for every basis vector
+    const long x0 = uniform_long(s_x[0]);
+    unsigned off[TT0][RIN0];
+    cplx<TA> acc[TT0][RIN0];
 #pragma unroll
     for (int t = 0; t < TT0; ++t) {
       int line, j;
@@ -141,53 +166,91 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
       if (line >= C::NL) line = C::NL - 1;  // idle slot of a partial tile: any valid line
 #pragma unroll
       for (int r = 0; r < RIN0; ++r) {
-        const int p = j + r * (L / R0);
+        const int p = j + r * NJ;
         const int pc = p < a.nin ? p : a.nin - 1;
-        xin[t][r] = a.xu_first ? mk(0.0, 0.0) : a.x[s_x[line] + pc];
+        off[t][r] = (unsigned)(s_x[line] - x0 + pc);
+        const cplx<T> w = a.x[x0 + off[t][r]];
+        acc[t][r] = (!ORTH && a.lc_first) ? mk((TA)0, (TA)0) : mk((TA)w.x, (TA)w.y);
       }
     }
+    const cplx<TB>* V0 = static_cast<const cplx<TB>*>(a.lc_basis) + x0;
 #pragma unroll 4
     for (int i = 0; i < kmax; ++i) {
+      const cplx<TB>* Vi = V0 + (long)i * a.lc_vs;  // uniform
 #pragma unroll
       for (int t = 0; t < TT0; ++t) {
         int line, j;
         C::template split<R0>(t, line, j);
         if (line >= C::NL) line = C::NL - 1;
-        const bool use = i < s_k[line];
-        const c128 c = a.xu_coef[(long)s_b[line] * a.xu_cstride + i];
+        const bool use = ORTH || i < s_k[line];  // every RHS of an orthogonalisation has nvec vectors
+        const c128 c64 = a.lc_coef[(long)s_b[line] * a.lc_cstride + i];
+        const cplx<TA> c = mk((TA)c64.x, (TA)c64.y);
 #pragma unroll
         for (int r = 0; r < RIN0; ++r) {
-          const int p = j + r * (L / R0);
-          const int pc = p < a.nin ? p : a.nin - 1;
-          const cplx<TB> v = V[(long)i * a.xu_vs + s_x[line] + pc];
-          const c128 u = cfma(c, mk((double)v.x, (double)v.y), xin[t][r]);
+          // 32-bit byte offset from a uniform base: a scalar-base load
+          const unsigned bo = off[t][r] * (unsigned)sizeof(cplx<TB>);
+          const cplx<TB> v = *reinterpret_cast<const cplx<TB>*>(reinterpret_cast<const char*>(Vi) + bo);
+          const cplx<TA> u = cfma(c, mk((TA)v.x, (TA)v.y), acc[t][r]);
           // select per component (unused vectors may hold anything)
-          xin[t][r].x = use ? u.x : xin[t][r].x;
-          xin[t][r].y = use ? u.y : xin[t][r].y;
+          acc[t][r].x = use ? u.x : acc[t][r].x;
+          acc[t][r].y = use ? u.y : acc[t][r].y;
         }
       }
     }
+    cplx<T> xin[TT0][RIN0];
+    double nrm[TT0];
 #pragma unroll
     for (int t = 0; t < TT0; ++t) {
-      if (NB0 % NT == 0 || (int)threadIdx.x + t * NT < NB0) {
-        int line, j;
-        C::template split<R0>(t, line, j);
+      nrm[t] = 0.0;
+      int line, j;
+      C::template split<R0>(t, line, j);
+      const bool slot = (NB0 % NT == 0 || (int)threadIdx.x + t * NT < NB0);
+      if (line >= C::NL) line = C::NL - 1;
 #pragma unroll
-        for (int r = 0; r < RIN0; ++r) {
-          const int p = j + r * (L / R0);
-          if (s_ok[line] && p < a.nin) a.xu_x[s_x[line] + p] = xin[t][r];
+      for (int r = 0; r < RIN0; ++r) {
+        const int p = j + r * NJ;
+        xin[t][r] = mk((T)acc[t][r].x, (T)acc[t][r].y);
+        if (slot && s_ok[line] && p < a.nin) {
+          a.lc_out[x0 + off[t][r]] = xin[t][r];
+          if constexpr (ORTH)
+            nrm[t] += (double)xin[t][r].x * (double)xin[t][r].x + (double)xin[t][r].y * (double)xin[t][r].y;
         }
       }
     }
-    auto src = [&](int line, int pb, int ro, int t, int r) -> cplx<T> {
-      const int p = pb + ro;
-      const int pc = p < a.nin ? p : a.nin - 1;
-      const cplx<T> mv = mp[s_m[line] + pc];
-      const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
-      const cplx<T> v = xin[t][r] * mf * s_s[line];
-      return p < a.nin ? v : mk((T)0, (T)0);
-    };
-    fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
+    if constexpr (K != RI_ORTH_ONLY) {
+      auto src = [&](int line, int pb, int ro, int t, int r) -> cplx<T> {
+        const int p = pb + ro;
+        const int pc = p < a.nin ? p : a.nin - 1;
+        const cplx<T> mv = mp[s_m[line] + pc];
+        const cplx<T> mf = mk(km * mv.x + ((T)1 - km), km * mv.y);
+        const cplx<T> v = xin[t][r] * mf;
+        return p < a.nin ? v : mk((T)0, (T)0);
+      };
+      fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
+    }
+    if constexpr (ORTH) {
+      // per-row sums in a fixed order: first-stage slot (line, j) belongs to
+      // one thread; the LDS tile is free once the transform is done
+      double* part = reinterpret_cast<double*>(sh);
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < TT0; ++t) {
+        if (NB0 % NT == 0 || (int)threadIdx.x + t * NT < NB0) {
+          int line, j;
+          C::template split<R0>(t, line, j);
+          part[line * NJ + j] = nrm[t];
+        }
+      }
+      __syncthreads();
+      // one wave per row: lanes over the slots, then a fixed-order wave sum
+      const int lane = threadIdx.x & 63;
+      for (int l = threadIdx.x >> 6; l < C::NL; l += NT / 64) {
+        double s = 0.0;
+        for (int q = lane; q < NJ; q += 64) s += part[l * NJ + q];
+        s = wave_sum(s);
+        if (lane == 0 && s_ok[l]) a.lc_rowpart[g0 + l] = s;
+      }
+    }
   }
 }
 
@@ -195,7 +258,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
 template <typename T>
 struct RowInvArgs {
   const cplx<T>* in;     // rows of length L
-  const cplx<T>* x;      // [rows][nout] operand (scaled by s_b) or null for EPI_COPY
+  const cplx<T>* x;      // [rows][nout] operand (its result is scaled by s_b) or null for EPI_COPY
   const cplx<T>* rhs;    // [rows][nout] (EPI_RESID)
   const cplx<T>* scale;
   const int* active;
@@ -250,7 +313,7 @@ __global__ void __launch_bounds__(NT) k_row_inv(RowInvArgs<T> a) {
     const bool st = s_ok[line] && p < a.nout;
     const long o = row(line) * a.nout + (p < a.nout ? p : a.nout - 1);
     if constexpr (EPI == EPI_VIE || EPI == EPI_VIE_DOT) {
-      const cplx<T> y = a.x[o] * s_s[line] - v;
+      const cplx<T> y = (a.x[o] - v) * s_s[line];  // the operator is linear: s (x - conv(m x))
       if (st) a.y[o] = y;
     } else if constexpr (RESID) {
       const cplx<T> r = a.rhs[o] - (a.x[o] - v);
@@ -462,13 +525,17 @@ void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
   constexpr int NL = row_nl<T, L, V>();
   const unsigned grid = (unsigned)((a.nrows + NL - 1) / NL);
   if (grid == 0) return;
-  if (a.xu_kind != 0) {
-    if constexpr (sizeof(T) == 8) {
-      if (2 * a.nin > L) throw Error(-6, "the fused update needs zero-padded rows");
-      if (a.xu_kind == 1) hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, 1>), dim3(grid), dim3(NT), 0, st, a);
-      else hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, 2>), dim3(grid), dim3(NT), 0, st, a);
+  if (a.kind != RI_PLAIN) {
+    if (2 * a.nin > L) throw Error(-6, "combined row inputs need zero-padded rows");
+    if (a.kind == RI_ORTH) {
+      hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_ORTH>), dim3(grid), dim3(NT), 0, st, a);
+    } else if (a.kind == RI_ORTH_ONLY) {
+      hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_ORTH_ONLY>), dim3(grid), dim3(NT), 0, st, a);
+    } else if constexpr (sizeof(T) == 8) {
+      if (a.kind == RI_UPD32) hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_UPD32>), dim3(grid), dim3(NT), 0, st, a);
+      else hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_UPD64>), dim3(grid), dim3(NT), 0, st, a);
     } else {
-      throw Error(-6, "the fused update is for complex128 residuals");
+      throw Error(-6, "the fused solution update is for complex128 residuals");
     }
   } else if (2 * a.nin <= L) {
     hipLaunchKernelGGL((k_row_fwd<T, L, NL, true>), dim3(grid), dim3(NT), 0, st, a);
@@ -607,21 +674,16 @@ int row_inv_nl(int L) {
 }
 
 template <typename T>
-void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
-                const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
-                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
-                const XUpdate* xu) {
+void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
-  const double gbytes = (double)(tl_nfreq > 0 ? tl_nfreq : 1) * g.npad() * es;
   const double n = (double)g.n();
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;  // FP64 launches are separate classes
-  // pass 1: rows along x
   RowFwdArgs<T> f{};
   f.x = x;
   f.m = m;
-  f.scale = epi == EPI_RESID ? nullptr : scale;
   f.active = active;
   f.out = U1;
   f.tw = tw.get<T>(g.Lx);
@@ -629,23 +691,51 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   f.rows_per_rhs = (int)rows_per_rhs;
   f.nin = g.nx;
   f.in_stride = g.nx;
-  double xu_bytes = 0.0;
+  // per RHS: x read, the x-pass intermediate written (m once)
+  double per_rhs = (n + g.u1()) * es;
+  if (xu && orth) throw Error(-6, "one combined input per pass");
   if (xu) {
-    if (sizeof(T) != 8 || active) throw Error(-6, "the fused update is for complex128 residuals");
-    f.xu_kind = xu->fp32 ? 1 : 2;
-    f.xu_basis = xu->basis;
-    f.xu_vs = xu->vs;
-    f.xu_ncol = xu->ncol;
-    f.xu_coef = xu->coef;
-    f.xu_cstride = xu->cstride;
-    f.xu_first = xu->first;
-    f.xu_x = const_cast<cplx<T>*>(x);
-    // x read (unless first) and written, kmax basis vectors read, instead of the plain x read
-    xu_bytes = n * es * (xu->first ? 0.0 : 1.0) + (double)xu->kmax * n * (xu->fp32 ? 8.0 : 16.0);
+    if (sizeof(T) != 8 || active) throw Error(-6, "the fused solution update is for complex128 residuals");
+    f.kind = xu->fp32 ? RI_UPD32 : RI_UPD64;
+    f.lc_basis = xu->basis;
+    f.lc_vs = xu->vs;
+    f.lc_ncol = xu->ncol;
+    f.lc_coef = xu->coef;
+    f.lc_cstride = xu->cstride;
+    f.lc_first = xu->first;
+    f.lc_out = const_cast<cplx<T>*>(x);
+    // x read (unless first) and written, up to kmax basis vectors read
+    per_rhs = g.u1() * es + n * es * (xu->first ? 1.0 : 2.0) + (double)xu->kmax * n * (xu->fp32 ? 8.0 : 16.0);
+  } else if (orth) {
+    f.kind = orth->transform ? RI_ORTH : RI_ORTH_ONLY;
+    f.lc_basis = orth->basis;
+    f.lc_vs = orth->vs;
+    f.lc_nvec = orth->nvec;
+    f.lc_coef = orth->coef;
+    f.lc_cstride = orth->cstride;
+    f.lc_out = const_cast<cplx<T>*>(x);
+    f.lc_rowpart = orth->rowpart;
+    // w read, nvec basis vectors read, v written, per-row norms (and the x-pass intermediate)
+    per_rhs = (2.0 + orth->nvec) * n * es + 8.0 * rows_per_rhs + (orth->transform ? g.u1() * es : 0.0);
   }
-  prof_begin(KC_ROW_FWD + po, st);
+  // the orthogonalising first pass and the orthogonalisation alone are classes of their own
+  const int cls = orth ? (orth->transform ? KC_ORTH_FWD : KC_ORTH) : KC_ROW_FWD;
+  prof_begin(cls + po, st);
   row_fwd_call<T>(g.Lx, f, st);
-  prof_end(KC_ROW_FWD + po, st, (n + g.u1()) * es + xu_bytes, n * es, masked, B);
+  prof_end(cls + po, st, per_rhs, n * es, masked, B);
+}
+
+template <typename T>
+void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale,
+                     const int* active, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2,
+                     cplx<T>* y, const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart,
+                     VieDots* dots) {
+  const long rows_per_rhs = (long)g.nz * g.ny;
+  const double es = sizeof(cplx<T>);
+  const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
+  const double gbytes = (double)(tl_nfreq > 0 ? tl_nfreq : 1) * g.npad() * es;
+  const double n = (double)g.n();
+  const int po = sizeof(T) == 8 ? KC_COUNT : 0;  // FP64 launches are separate classes
   if (g.dim == 2) {
     // pass 2: columns along z, convolution, in place
     StridedArgs<T> s{};
@@ -757,6 +847,15 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
   prof_begin(KC_ROW_INV + po, st);
   row_inv_call<T>(g.Lx, r, epi, st);
   prof_end(KC_ROW_INV + po, st, (double)g.u1() * es + epi_bytes, 0.0, masked, B);
+}
+
+template <typename T>
+void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale, const int* active,
+                const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
+                const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
+                const XUpdate* xu) {
+  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr);
+  launch_vie_tail<T>(g, tw, B, x, scale, active, ghat, rhs_freq, U1, U2, y, rhs, epi, st, y32, rowpart, dots);
 }
 
 #ifdef FWI_FFT_WITH_FULL

@@ -29,7 +29,7 @@ struct Error : std::runtime_error {
 #define FWI_LAUNCH_CHECK() FWI_HIP(hipGetLastError())
 
 // Kernel classes that can be timed with HIP events (fwi_profile).
-enum KernelClass { KC_ROW_FWD = 0, KC_CONV, KC_ROW_INV, KC_Y_FWD, KC_Y_INV, KC_DOTS, KC_ORTH, KC_COUNT };
+enum KernelClass { KC_ROW_FWD = 0, KC_CONV, KC_ROW_INV, KC_Y_FWD, KC_Y_INV, KC_DOTS, KC_ORTH, KC_ORTH_FWD, KC_COUNT };
 // Per-thread hooks set by the entry points: launch sites report each launch of
 // a class with its algorithmic HBM bytes; active-RHS and frequency-count hints
 // let them compute those bytes for masked batches.
@@ -135,8 +135,23 @@ struct XUpdate {
   int kmax = 0;                 // bound on ncol (profiled bytes only)
 };
 
+// Arnoldi orthogonalisation fused into the first pass of the next matvec:
+// the new vector w (stored in place of V_nvec) becomes
+// v = w + sum_{i < nvec} coef[b][i] V_i (FP64, coef = -h_i times the stored
+// vector's scale), is rounded and stored back, |v|^2 is summed per grid row
+// into rowpart, and v (unscaled) is row-transformed unless !transform.
+struct OrthIn {
+  const void* basis = nullptr;  // V_0 [B][n] (cplx<T>), vector i at basis + i*vs
+  long vs = 0;
+  int nvec = 0;
+  const c128* coef = nullptr;   // [B][cstride]
+  int cstride = 0;
+  double* rowpart = nullptr;    // [B * rows per RHS]
+  bool transform = true;
+};
+
 // y = A x for B right-hand sides (Eq. 5 discretised):
-//   EPI_VIE  : y_b = s_b x_b - conv(m * s_b x_b)
+//   EPI_VIE  : y_b = s_b (x_b - conv(m * x_b)) = s_b x_b - conv(m * s_b x_b)
 //   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored), and
 //              rowpart[row] = sum over the row of |y_b|^2 (rows of nx points)
 //   EPI_RESID32: the same residual rounded to complex64 into y32 (y unused)
@@ -151,6 +166,16 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr, double* rowpart = nullptr,
                 VieDots* dots = nullptr,  // returns through dots->nparts (0: not fused)
                 const XUpdate* xu = nullptr);
+// The same operator in two launches groups: the first pass (rows of x, or of
+// the combined input of xu / orth, transformed into U1) and the rest.
+template <typename T>
+void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu = nullptr, const OrthIn* orth = nullptr);
+template <typename T>
+void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale,
+                     const int* active, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2,
+                     cplx<T>* y, const cplx<T>* rhs, int epi, hipStream_t st, c64* y32 = nullptr,
+                     double* rowpart = nullptr, VieDots* dots = nullptr);
 
 // Forward FFT of a full padded grid [Lz][Ly][Lx] (no padding, no crop), in place
 // through `work` of the same size: out = FFT(in). Used for the Green spectrum.

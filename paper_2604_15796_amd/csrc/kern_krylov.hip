@@ -81,142 +81,93 @@ __global__ void __launch_bounds__(KT) k_dots(const cplx<T>* __restrict__ V, long
   }
 }
 
-// V_{j+1} -= sum_i h_i V_i with h_i reduced from dotp (same order in every block);
-// nrmp[b][blk] = |V_{j+1}|^2 over the chunk; block 0 stores the H column.
+// Column j of H: h_i = sum of the ndot inner-product parts of RHS b, wave w
+// reducing vectors i = w, w + 4, ..., each lane a fixed subset of parts, then
+// a fixed-order wave sum. The classical Gram-Schmidt coefficients
+// coef_i = -h_i * scale_i (the update uses the stored, unnormalised vectors)
+// go to hcoef for the first pass of the next matvec. Zeroes the active count
+// that k_givens accumulates.
 template <typename T, int JM>
-__global__ void __launch_bounds__(KT) k_orth(cplx<T>* __restrict__ V, long vs, int j, long n, int chunk,
-                                             const int* __restrict__ active, const cplx<T>* __restrict__ vscale,
-                                             int B, const c128* __restrict__ dotp, int ndot, int nblk,
-                                             c128* __restrict__ H, double* __restrict__ nrmp) {
-  const int b = blockIdx.y;
+__global__ void __launch_bounds__(KT) k_hsum(int j, int B, const int* __restrict__ active,
+                                             const cplx<T>* __restrict__ vscale, const c128* __restrict__ dotp,
+                                             int ndot, c128* __restrict__ H, c128* __restrict__ hcoef,
+                                             int* __restrict__ counters) {
+  const int b = blockIdx.x;
+  if (b == 0 && threadIdx.x == 0) counters[0] = 0;
   if (!active[b]) return;
-  __shared__ double hr[JM + 1], hi[JM + 1];
-  __shared__ double red[KT / 64];
-  const int t = threadIdx.x;
-  // h_i = sum of the ndot inner-product parts: wave w reduces vectors
-  // i = w, w + 4, ..., each lane a fixed subset of parts, then a fixed-order
-  // wave sum (the same in every block)
-  {
-    const int lane = t & 63, w = t >> 6;
-    for (int i = w; i <= j; i += KT / 64) {
-      double r = 0.0, m = 0.0;
-      for (int k = lane; k < ndot; k += 64) {
-        const c128 d = dotp[((long)b * ndot + k) * (JM + 1) + i];
-        r += d.x;
-        m += d.y;
-      }
-      r = wave_sum(r);
-      m = wave_sum(m);
-      if (lane == 0) {
-        if (blockIdx.x == 0) H[((long)b * (JM + 1) + i) * JM + j] = mk(r, m);
-        // the update uses the stored (unnormalised) vectors: fold their scale in
-        const double sc = (double)vscale[(long)i * B + b].x;
-        hr[i] = r * sc;
-        hi[i] = m * sc;
-      }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = w; i <= j; i += KT / 64) {
+    double r = 0.0, m = 0.0;
+    for (int k = lane; k < ndot; k += 64) {
+      const c128 d = dotp[((long)b * ndot + k) * (JM + 1) + i];
+      r += d.x;
+      m += d.y;
+    }
+    r = wave_sum(r);
+    m = wave_sum(m);
+    if (lane == 0) {
+      H[((long)b * (JM + 1) + i) * JM + j] = mk(r, m);
+      const double sc = (double)vscale[(long)i * B + b].x;
+      hcoef[(long)b * (JM + 1) + i] = mk(-(r * sc), -(m * sc));
     }
   }
-  __syncthreads();
-  const long off = (long)b * n;
-  const long e0 = (long)blockIdx.x * chunk;
-  const int cnt = (int)min((long)chunk, n - e0);
-  cplx<T>* W = V + (long)(j + 1) * vs + off + e0;
-  double ax[EPT], ay[EPT];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = t + q * KT;
-    const cplx<T> w = W[e < cnt ? e : cnt - 1];
-    ax[q] = w.x;
-    ay[q] = w.y;
-  }
-  for (int i = 0; i <= j; ++i) {
-    const cplx<T>* Vi = V + (long)i * vs + off + e0;
-    const double a = hr[i], bb = hi[i];
-    cplx<T> vv[EPT];  // all loads of the vector issued before any arithmetic
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = t + q * KT;
-      vv[q] = Vi[e < cnt ? e : cnt - 1];
-    }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const double vx = vv[q].x, vy = vv[q].y;
-      ax[q] = fma(-a, vx, ax[q]);
-      ax[q] = fma(bb, vy, ax[q]);
-      ay[q] = fma(-a, vy, ay[q]);
-      ay[q] = fma(-bb, vx, ay[q]);
-    }
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = t + q * KT;
-    if (e < cnt) {
-      const cplx<T> o = mk((T)ax[q], (T)ay[q]);
-      W[e] = o;
-      acc += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
-    }
-  }
-  const double s = block_sum<KT>(acc, red);
-  if (t == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
 }
 
-// One thread per RHS: finish column j (norm, previous rotations, new rotation),
-// update the residual estimate and the convergence mask; count active RHS.
+// One wave per RHS: finish column j (norm of the orthogonalised vector from
+// its per-row sums, previous rotations, new rotation), update the residual
+// estimate and the convergence mask, count the RHS still active.
 template <typename T, int JM>
-__global__ void __launch_bounds__(1024) k_givens(int j, int B, int nblk, int* __restrict__ active,
-                                                 const double* __restrict__ nrmp, c128* __restrict__ H,
-                                                 double* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ gv,
-                                                 const double* __restrict__ target, int* __restrict__ ncol,
-                                                 int* __restrict__ iters, cplx<T>* __restrict__ vscale_next,
-                                                 int* __restrict__ counters) {
-  __shared__ double red[1024 / 64];
-  double cnt = 0.0;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    if (!active[b]) continue;
-    double s2 = 0.0;
-    for (int k = 0; k < nblk; ++k) s2 += nrmp[(long)b * nblk + k];
-    const double hn = sqrt(s2);
-    c128* col = H + (long)b * (JM + 1) * JM + j;  // col[i*JM] = H[i][j]
-    for (int i = 0; i < j; ++i) {
-      const c128 a = col[i * JM], c2 = col[(i + 1) * JM];
-      const double c = cs[b * JM + i];
-      const c128 s = sn[b * JM + i];
-      col[i * JM] = c * a + s * c2;
-      col[(i + 1) * JM] = c * c2 - conj(s) * a;
-    }
-    const c128 a = col[j * JM];
-    const double aa = sqrt(norm2(a));
-    const double nu = sqrt(aa * aa + hn * hn);
-    double c;
-    c128 s;
-    if (aa == 0.0) {
-      c = 0.0;
-      s = mk(1.0, 0.0);
-    } else {
-      c = aa / nu;
-      s = (hn / (nu * aa)) * a;
-    }
-    cs[b * JM + j] = c;
-    sn[b * JM + j] = s;
-    col[j * JM] = c * a + hn * s;
-    col[(j + 1) * JM] = mk(0.0, 0.0);
-    const c128 g = gv[b * (JM + 1) + j];
-    gv[b * (JM + 1) + j] = c * g;
-    const c128 g1 = (-1.0) * (conj(s) * g);
-    gv[b * (JM + 1) + j + 1] = g1;
-    ncol[b] = j + 1;
-    iters[b] += 1;
-    const double res = sqrt(norm2(g1));
-    if (res <= target[b] || !(hn > 1e-300) || nu == 0.0) {
-      active[b] = 0;
-    } else {
-      vscale_next[b] = mk((T)(1.0 / hn), (T)0);
-      cnt += 1.0;
-    }
+__global__ void __launch_bounds__(KT) k_givens(int j, int B, int rows, const double* __restrict__ rowpart,
+                                               int* __restrict__ active, c128* __restrict__ H,
+                                               double* __restrict__ cs, c128* __restrict__ sn,
+                                               c128* __restrict__ gv, const double* __restrict__ target,
+                                               int* __restrict__ ncol, int* __restrict__ iters,
+                                               cplx<T>* __restrict__ vscale_next, int* __restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const int b = blockIdx.x * (KT / 64) + (threadIdx.x >> 6);
+  if (b >= B || !active[b]) return;  // uniform per wave
+  double s2 = 0.0;
+  for (int k = lane; k < rows; k += 64) s2 += rowpart[(long)b * rows + k];
+  s2 = wave_sum(s2);
+  if (lane != 0) return;
+  const double hn = sqrt(s2);
+  c128* col = H + (long)b * (JM + 1) * JM + j;  // col[i*JM] = H[i][j]
+  for (int i = 0; i < j; ++i) {
+    const c128 a = col[i * JM], c2 = col[(i + 1) * JM];
+    const double c = cs[b * JM + i];
+    const c128 s = sn[b * JM + i];
+    col[i * JM] = c * a + s * c2;
+    col[(i + 1) * JM] = c * c2 - conj(s) * a;
   }
-  const double tot = block_sum<1024>(cnt, red);
-  if (threadIdx.x == 0) counters[0] = (int)tot;
+  const c128 a = col[j * JM];
+  const double aa = sqrt(norm2(a));
+  const double nu = sqrt(aa * aa + hn * hn);
+  double c;
+  c128 s;
+  if (aa == 0.0) {
+    c = 0.0;
+    s = mk(1.0, 0.0);
+  } else {
+    c = aa / nu;
+    s = (hn / (nu * aa)) * a;
+  }
+  cs[b * JM + j] = c;
+  sn[b * JM + j] = s;
+  col[j * JM] = c * a + hn * s;
+  col[(j + 1) * JM] = mk(0.0, 0.0);
+  const c128 g = gv[b * (JM + 1) + j];
+  gv[b * (JM + 1) + j] = c * g;
+  const c128 g1 = (-1.0) * (conj(s) * g);
+  gv[b * (JM + 1) + j + 1] = g1;
+  ncol[b] = j + 1;
+  iters[b] += 1;
+  const double res = sqrt(norm2(g1));
+  if (res <= target[b] || !(hn > 1e-300) || nu == 0.0) {
+    active[b] = 0;
+  } else {
+    vscale_next[b] = mk((T)(1.0 / hn), (T)0);
+    atomicAdd(counters, 1);
+  }
 }
 
 // |x_b|^2 partial sums of an FP64 array [B][n]
@@ -423,29 +374,27 @@ void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double i
 }
 
 template <typename T>
-void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st) {
-  const long vs = s.vstride();
-  const double vb = (double)s.n * sizeof(cplx<T>);
+void krylov_dots(const KrylovState<T>& s, int j, hipStream_t st) {
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;
-  // nparts > 0: the operator's last pass already wrote nparts inner-product
-  // partials per RHS; otherwise they come from the inner-product kernel
-  int ndot = nparts;
-  if (ndot == 0) {
-    prof_begin(KC_DOTS + po, st);
-    FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                            s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
-    FWI_LAUNCH_CHECK();
-    prof_end(KC_DOTS + po, st, (j + 2) * vb, 0.0, true, s.B);
-    ndot = s.nblk;
-  }
-  prof_begin(KC_ORTH + po, st);
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_orth<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, vs, j, s.n,
-                                          s.chunk, s.active, s.vscale, s.B, s.dotp, ndot, s.nblk, s.H, s.nrmp));
+  prof_begin(KC_DOTS + po, st);
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, s.vstride(), j,
+                                          s.n, s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
   FWI_LAUNCH_CHECK();
-  prof_end(KC_ORTH + po, st, (j + 3) * vb, 0.0, true, s.B);
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(1), dim3(1024), 0, st, j, s.B, s.nblk, s.active,
-                                          s.nrmp, s.H, s.cs, s.sn, s.gv, s.target, s.ncol, s.iters,
-                                          s.vscale + (long)(j + 1) * s.B, s.counters));
+  prof_end(KC_DOTS + po, st, (j + 2) * (double)s.n * sizeof(cplx<T>), 0.0, true, s.B);
+}
+
+template <typename T>
+void krylov_hsum(const KrylovState<T>& s, int j, int ndot, hipStream_t st) {
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_hsum<T, JMC>), dim3(s.B), dim3(KT), 0, st, j, s.B, s.active, s.vscale,
+                                          s.dotp, ndot, s.H, s.hcoef, s.counters));
+  FWI_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_givens(const KrylovState<T>& s, int j, const double* rowpart, int rows, hipStream_t st) {
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3((s.B + KT / 64 - 1) / (KT / 64)), dim3(KT), 0, st,
+                                          j, s.B, rows, rowpart, s.active, s.H, s.cs, s.sn, s.gv, s.target, s.ncol,
+                                          s.iters, s.vscale + (long)(j + 1) * s.B, s.counters));
   FWI_LAUNCH_CHECK();
 }
 
@@ -479,7 +428,9 @@ void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
   template void krylov_start_norm<T>(const KrylovState<T>&, const c128*, hipStream_t);         \
   template void krylov_rows_norm<T>(const KrylovState<T>&, const double*, int, hipStream_t);   \
   template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
-  template void krylov_arnoldi<T>(const KrylovState<T>&, int, int, hipStream_t);               \
+  template void krylov_dots<T>(const KrylovState<T>&, int, hipStream_t);                        \
+  template void krylov_hsum<T>(const KrylovState<T>&, int, int, hipStream_t);                   \
+  template void krylov_givens<T>(const KrylovState<T>&, int, const double*, int, hipStream_t);  \
   template void krylov_backsolve<T>(const KrylovState<T>&, hipStream_t);                       \
   template void krylov_xupdate<T>(const KrylovState<T>&, c128*, int, hipStream_t);             \
   template void krylov_finish_cycle<T>(const KrylovState<T>&, c128*, int, hipStream_t);        \

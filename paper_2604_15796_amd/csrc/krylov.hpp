@@ -21,6 +21,7 @@ struct KrylovState {
   c128* gv = nullptr;          // [B][JM+1]
   c128* y = nullptr;           // [B][JM] correction x += sum_i y_i V_i (stored V_i; |r| and scales folded in)
   c128* dotp = nullptr;        // [B][parts][JM+1], parts <= max(nblk, kMaxDotParts)
+  c128* hcoef = nullptr;       // [B][JM+1] Gram-Schmidt coefficients of the current step
   double* nrmp = nullptr;      // [B][nblk]
   double* rnorm = nullptr;     // [B] residual norm at cycle start
   double* bnorm = nullptr;     // [B]
@@ -47,10 +48,20 @@ void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, 
 // Norms, activity, stopping targets and the scale of V_0 (1 / |r|).
 template <typename T>
 void krylov_cycle_init(const KrylovState<T>& s, int first, double rtol, double inner_rtol, hipStream_t st);
-// Arnoldi step j after the matvec into V_{j+1}: inner products (unless the
-// operator's last pass produced `nparts` partials per RHS), update, Givens.
+// Arnoldi step j after the matvec w = A v_j stored into V_{j+1}:
+// inner products of w with V_0..V_j in nblk parts per RHS (used when the
+// operator's last pass could not produce them);
 template <typename T>
-void krylov_arnoldi(const KrylovState<T>& s, int j, int nparts, hipStream_t st);
+void krylov_dots(const KrylovState<T>& s, int j, hipStream_t st);
+// column j of H from ndot parts per RHS and the Gram-Schmidt coefficients
+// (hcoef) that the first pass of the next matvec applies to w (see OrthIn);
+template <typename T>
+void krylov_hsum(const KrylovState<T>& s, int j, int ndot, hipStream_t st);
+// after that pass: the norm of the orthogonalised vector from its per-row
+// sums (rows per RHS), Givens rotations, convergence, scale of V_{j+1} and
+// the active count.
+template <typename T>
+void krylov_givens(const KrylovState<T>& s, int j, const double* rowpart, int rows, hipStream_t st);
 // Back-substitution: y from the rotated Hessenberg system, scaled so that
 // the correction is sum_{i < ncol} y_i V_i over the stored basis vectors.
 template <typename T>

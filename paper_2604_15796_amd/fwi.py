@@ -137,7 +137,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
-_BASE_CLASSES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv", "dots", "orth"]
+_BASE_CLASSES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv", "dots", "orth", "orth_fwd"]
 # class k: complex64 launches; class k + 7: complex128 launches
 KERNEL_CLASSES = [f"{c}_c64" for c in _BASE_CLASSES] + [f"{c}_c128" for c in _BASE_CLASSES]
 
