@@ -36,8 +36,24 @@ template <typename T, int L, int V>
 __host__ __device__ constexpr int col_nl() {
   constexpr int nl0 = V == 0 ? 8 : 16;
   constexpr int lp = L + L / 8;
-  return nl0 * lp * (int)sizeof(cplx<T>) <= kColLds ? nl0
-       : (nl0 / 2) * lp * (int)sizeof(cplx<T>) <= kColLds ? nl0 / 2 : nl0 / 4;
+  constexpr int es = (int)sizeof(cplx<T>);
+  return nl0 * lp * es <= kColLds ? nl0 : (nl0 / 2) * lp * es <= kColLds ? nl0 / 2 : nl0 / 4;
+}
+
+// Column tile of a strided-pass workgroup. Workgroups are dealt to the 8
+// XCDs in turn (linear id modulo 8); when a tile's row segment is narrower
+// than a 128-byte cache line, each XCD takes a contiguous range of tiles in
+// launch order, so neighbouring tiles (halves of one line) are fetched into
+// the same L2 at about the same time.
+template <int NL, int ES>
+__device__ __forceinline__ int col_tile() {
+  const int x = blockIdx.x, n = gridDim.x;
+  if constexpr (NL * ES >= 128) {
+    return x;
+  } else {
+    if (n % 8 != 0) return x;
+    return (x % 8) * (n / 8) + x / 8;
+  }
 }
 
 // A value that is the same in every lane, moved to scalar registers (values
@@ -425,7 +441,7 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
   using C = LineCfg<T, L, NLV, NTV, true>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   constexpr unsigned ES = sizeof(cplx<T>);
-  const int line0 = blockIdx.x * C::NL;
+  const int line0 = col_tile<C::NL, (int)ES>() * C::NL;
   const int nl = a.nlines - line0;
   // line-fastest mapping: the thread's line is fixed; a line past the plane
   // gets an offset past every view (its loads read zero, its stores drop)

@@ -132,5 +132,9 @@ int main() {
   all_modes<float, 512, 16, 256, false>("float");   // row pass, radix-16/32 plan
   all_modes<float, 128, 32, 256, false>("float");   // radix 16 x 8
   all_modes<float, 768, 8, 256, false>("float");    // radix 16/16/3, butterflies not a divisor of NT
+  all_modes<double, 512, 4, 256, true>("double");   // narrow strided tiles
+  all_modes<double, 1024, 4, 256, true>("double");
+  all_modes<float, 512, 4, 256, true>("float");
+  all_modes<float, 96, 4, 256, true>("float");
   return 0;
 }

@@ -27,7 +27,7 @@ def test_line_fft_plans_on_host(tmp_path):
                     "-o", str(exe), "-lpthread"], check=True, timeout=600)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=600).stdout
     lines = [l for l in out.splitlines() if l.strip()]
-    assert len(lines) == 36, out
+    assert len(lines) == 40, out
     bad = [l for l in lines if not l.endswith(" ok")]
     assert not bad, "\n".join(bad)
     assert sum(" BIG=1 " in l for l in lines) >= 8  # the radix-16/32 plans are exercised
