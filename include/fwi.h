@@ -80,7 +80,10 @@ typedef struct fwi_solve_opts {
   int max_iter;         /* cap on Krylov iterations per RHS (all cycles) */
   int restart;          /* GMRES basis length: 8, 16 or 32 */
   int max_refine;       /* FP32_REFINE: cap on refinement steps */
-  double inner_rtol;    /* FP32_REFINE: relative target of each inner solve */
+  double inner_rtol;    /* FP32_REFINE: floor of each inner cycle's relative target; a cycle
+                           stops at the larger of this and half the reduction that
+                           rtol still needs (the FP64 residual of the next cycle start
+                           decides convergence) */
   int max_rhs;          /* cap on RHS per batched solve (0: all frequencies at once) */
   int check_every;      /* iterations between host convergence checks (>= 1); a check
                            is read after the next step is enqueued, so at most one

@@ -1,13 +1,16 @@
 // Batched GMRES kernels: classical Gram-Schmidt Arnoldi with FP64 inner
 // products (two-stage, fixed-order reductions, no floating-point atomics),
-// device-side complex Givens rotations and per-RHS convergence masks.
+// device-side complex Givens rotations and per-RHS convergence masks. The
+// Gram-Schmidt update itself and the solution update run inside the first FFT
+// pass of the next matvec (fft_passes.hpp); the kernels here reduce, rotate,
+// test and, on the graph-replayed path, update the solution.
 #include "krylov.hpp"
 
 namespace fwi {
 
 constexpr int KT = 256;  // threads per block of the vector kernels
 
-// Blocks per RHS of the Arnoldi kernels: chunks of at most EPT * KT = 4096
+// Blocks per RHS of the vector kernels: chunks of at most EPT * KT = 4096
 // elements, EPT per thread held in registers.
 constexpr int EPT = 16;
 int krylov_nblk(long n) {
@@ -15,11 +18,12 @@ int krylov_nblk(long n) {
   return (int)(nb < 1 ? 1 : nb);
 }
 
-// Both Arnoldi kernels keep the block's EPT elements per thread of the new
-// vector in registers and stream the basis vectors one after another, each
-// with EPT independent coalesced loads per thread (indices clamped, values
-// masked, so the loads are not behind branches); per-vector sums are reduced
-// wave by wave in a fixed order.
+// The inner-product kernel (used when the operator's last pass cannot
+// produce them) keeps the block's EPT elements per thread of the new vector
+// in registers and streams the basis vectors one after another, each with EPT
+// independent coalesced loads per thread (indices clamped, values masked, so
+// the loads are not behind branches); per-vector sums are reduced wave by
+// wave in a fixed order.
 
 // ------------------------------------------------------------------ dots ---
 // dotp[b][blk][i] = sum over the block's chunk of conj(V_i) . V_{j+1}, i <= j
@@ -233,7 +237,12 @@ __global__ void __launch_bounds__(1024) k_cycle_init(int B, int nblk, int first,
     mx = fmax(mx, rel);
     if (act) {
       cnt += 1.0;
+      // relative reduction this cycle must reach for |r| <= rtol |b|; an inner
+      // (complex64) cycle aims at half of it, since its residual estimate
+      // is not the FP64 residual that the next cycle start checks, and stops
+      // no later than at inner_rtol
       double tg = rtol * bn / rn;
+      if (inner_rtol > 0.0) tg *= 0.5;
       if (inner_rtol > tg) tg = inner_rtol;
       target[b] = tg;
       rscale[b] = 1.0 / rn;
