@@ -39,7 +39,9 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # of known size, and the VALU busy fraction from SQ_ACTIVE_INST_VALU over
 # GRBM_GUI_ACTIVE. Reported only while the timed dominant class runs that
 # kernel (profiles/gradient256_hbm_traffic.md, profiles/gradient256_valu.md).
-MEASURED = {"k_strided<float, 512, 16, 512, 2, true, false>": {"traffic": 907.5e6, "valu_busy": 0.75}}
+MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1762.0e6},
+            "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.5e6},
+            "k_strided<float, 512, 8, 256, 2, true, false>": {"traffic": 898.5e6, "valu_busy": 0.779}}
 
 
 def parse():
@@ -259,9 +261,36 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof):
                       "flops_per_launch": flops / launches, "kernel_name": name,
                       "traffic": m.get("traffic"), "valu_busy": m.get("valu_busy"), "hbm": hbm})
     else:
+        name = hbm_kernel_name(ctx, prob, dominant)
+        m = MEASURED.get(name, {}) if name else {}
         entry.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "traffic": None})
+                      "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "kernel_name": name,
+                      "traffic": m.get("traffic")})
     return entry
+
+
+def row_tile(L, es, v):
+    """Rows per workgroup of row-pass variant v (2048 / 4096 / 8192 points),
+    halved while the tile would not fit the LDS, as in the library."""
+    pts = (2048, 4096, 8192)[v]
+    nl0 = max(pts // L, 1)
+    return nl0 if nl0 * (L + L // 8) * es <= 160 * 1024 - 4096 else max(nl0 // 2, 1)
+
+
+def hbm_kernel_name(ctx, prob, cls):
+    """Kernel that a streaming class of the complex64 Arnoldi steps launches
+    on the 2D workload (the inverse row pass with the fused inner products,
+    or the orthogonalising forward row pass), or None."""
+    Lz, Lx = ctx.padded_shape(prob)
+    table = ctx.get_tuning()
+    li = [32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024].index(Lx)
+    if cls == "row_inv_c64":
+        v = table[(1 * 2 + 0) * 11 + li]
+        return f"k_row_inv<float, {Lx}, {row_tile(Lx, 8, 0 if v in (255, -1) else v)}, 4>"
+    if cls == "orth_fwd_c64":
+        v = table[(0 * 2 + 0) * 11 + li]
+        return f"k_row_fwd<float, {Lx}, {row_tile(Lx, 8, 0 if v in (255, -1) else v)}, true, 3>"
+    return None
 
 
 def bench_uneven(args):
