@@ -227,6 +227,7 @@ struct fwi_ctx {
   std::vector<hipEvent_t> branch_ev;
   hipEvent_t fork_ev = nullptr;
   hipEvent_t count_ev = nullptr;               // active-count copy of the solver loop
+  unsigned long long* d_itstat = nullptr;      // iteration max / sum of the current call's solves
   ~fwi_ctx() {
     if (count_ev) (void)hipEventDestroy(count_ev);
     for (auto& kv : bcache) kv.second.release();
@@ -678,14 +679,9 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   }
   if (!x_written) launch_fill_zero_c128((long)B * ks.n, x64, st);  // nothing to solve: x = 0
   res.cycles = cyc;
-  std::vector<int> it(B);
-  FWI_HIP(hipMemcpyAsync(it.data(), ks.iters, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-  FWI_HIP(hipStreamSynchronize(st));
-  for (int b = 0; b < B; ++b) {
-    res.iters_max = std::max(res.iters_max, it[b]);
-    res.matvecs += it[b];
-  }
-  res.t_solve = now_ms() - t0;
+  // iteration counts stay on the device until the call collects them
+  launch_iter_stats(B, ks.iters, c->d_itstat, st);
+  res.t_solve = now_ms() - t0;  // the last cycle start was waited for: the solve's work is done
   return res;
 }
 
@@ -781,6 +777,7 @@ struct Runner {
     n = g.n();
     nfg = freqs_per_group(p, o);
     ngroups = (p->nf + nfg - 1) / nfg;
+    launch_zero_u64(2, c->d_itstat, c->stream);  // this call's iteration statistics
   }
 
   // Solve the forward problem for frequencies [l0, l0+nf) into `fields`.
@@ -851,6 +848,18 @@ struct Runner {
     return phi;
   }
 };
+
+// Adds the iteration statistics the call's solves left on the device (waits
+// for the stream).
+void collect_iters(fwi_ctx* c, SolveTotals& t) {
+  FWI_HIP(hipMemcpyAsync(c->h_dbl + 8, c->d_itstat, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         c->stream));
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  unsigned long long v[2];
+  std::memcpy(v, c->h_dbl + 8, sizeof(v));
+  t.iters_max = std::max(t.iters_max, (int)v[0]);
+  t.matvecs += (long long)v[1];
+}
 
 void fill_stats(fwi_stats* s, const SolveTotals& t, double t_setup, double t_total) {
   if (!s) return;
@@ -966,6 +975,7 @@ int forward_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doubl
   R.t_setup += now_ms() - ts;
   R.forward<T>(sb, (c128*)data_out, (c128*)fields_out);
   FWI_HIP(hipStreamSynchronize(c->stream));
+  collect_iters(c, R.tot);
   fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
   return finish_rc(R.tot);
 }
@@ -993,6 +1003,7 @@ int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doub
                                    (c128*)grad_m_out, gc, ga);
   FWI_HIP(hipStreamSynchronize(c->stream));
   if (misfit_out) *misfit_out = phi;
+  collect_iters(c, R.tot);
   fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
   return finish_rc(R.tot);
 }
@@ -1092,6 +1103,7 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
     rep->tv = c->h_dbl[0];
     rep->dm_norm = std::sqrt(c->h_dbl[1]);
   }
+  collect_iters(c, R.tot);
   fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
   return finish_rc(R.tot);
 }
@@ -1472,6 +1484,8 @@ int fwi_create(fwi_ctx** out, int device, void* stream) {
     FWI_HIP(hipHostMalloc((void**)&c->h_dbl, 64 * sizeof(double), hipHostMallocDefault));
     FWI_HIP(hipMalloc((void**)&c->d_int, 64 * sizeof(int)));
     FWI_HIP(hipEventCreateWithFlags(&c->count_ev, hipEventDisableTiming));
+    FWI_HIP(hipMalloc((void**)&c->d_itstat, 2 * sizeof(unsigned long long)));
+    launch_zero_u64(2, c->d_itstat, c->stream);
   } catch (const Error& e) {
     fwi_destroy(c);
     return e.code;
@@ -1489,6 +1503,7 @@ void fwi_destroy(fwi_ctx* c) {
   if (c->h_int) (void)hipHostFree(c->h_int);
   if (c->h_dbl) (void)hipHostFree(c->h_dbl);
   if (c->d_int) (void)hipFree(c->d_int);
+  if (c->d_itstat) (void)hipFree(c->d_itstat);
   delete c;
 }
 
@@ -1637,7 +1652,8 @@ int fwi_solve(fwi_ctx* c, const fwi_problem* p, const void* m, int B, const int*
     };
     if (o->precision == FWI_FP32_REFINE) run(float{});
     else run(double{});
-    fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+    collect_iters(c, R.tot);
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
     return finish_rc(R.tot);
   });
 }

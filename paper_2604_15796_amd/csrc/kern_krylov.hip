@@ -321,6 +321,48 @@ __global__ void __launch_bounds__(KT) k_xupdate(const cplx<T>* __restrict__ V, l
   }
 }
 
+// Largest and total iteration count of a solve, folded into st[0] (max) and
+// st[1] (sum) so the host reads them once per call.
+__global__ void __launch_bounds__(KT) k_iter_stats(int B, const int* __restrict__ iters,
+                                                   unsigned long long* __restrict__ st) {
+  __shared__ unsigned long long smax[KT], ssum[KT];
+  unsigned long long mx = 0, s = 0;
+  for (int b = threadIdx.x; b < B; b += KT) {
+    const unsigned long long v = (unsigned long long)iters[b];
+    mx = v > mx ? v : mx;
+    s += v;
+  }
+  smax[threadIdx.x] = mx;
+  ssum[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = KT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      smax[threadIdx.x] = smax[threadIdx.x] > smax[threadIdx.x + o] ? smax[threadIdx.x] : smax[threadIdx.x + o];
+      ssum[threadIdx.x] += ssum[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&st[0], smax[0]);
+    atomicAdd(&st[1], ssum[0]);
+  }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+void launch_iter_stats(int B, const int* iters, unsigned long long* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_iter_stats, dim3(1), dim3(KT), 0, s, B, iters, st);
+  FWI_LAUNCH_CHECK();
+}
+
+void launch_zero_u64(int count, unsigned long long* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
+  FWI_LAUNCH_CHECK();
+}
+
 __global__ void k_zero_int(int* p, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0;

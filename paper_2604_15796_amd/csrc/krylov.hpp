@@ -76,6 +76,9 @@ template <typename T>
 void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st);
 
 void launch_fill_zero_c128(long count, c128* p, hipStream_t st);
+// st[0] = max(st[0], max_b iters[b]), st[1] += sum_b iters[b]
+void launch_iter_stats(int B, const int* iters, unsigned long long* st, hipStream_t s);
+void launch_zero_u64(int count, unsigned long long* p, hipStream_t s);
 void launch_copy_c128(long count, const c128* in, c128* out, hipStream_t st);
 
 }  // namespace fwi
