@@ -14,11 +14,25 @@ namespace fwi {
 
 constexpr double PI = 3.14159265358979323846;
 
+// ------------------------------------------------- FP64 matrix-core tiles ---
+// v_mfma_f64_16x16x4f64: D (16 x 16) += A (16 x 4) B (4 x 16), one value per
+// lane and operand: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k, and
+// D[i][j] in lane j + 16 (i % 4), element i / 4 of the lane's four doubles.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Complex 16 x 16 tile (cr, ci) += A B from this lane's complex operands, as
+// four real products.
+__device__ __forceinline__ void cmfma(c128 a, c128 b, v4d& cr, v4d& ci) {
+  cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+  cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+  ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
+}
+
 // ------------------------------------------------------------- gemm (NT) ---
-// 64 x 64 output tile per block, 256 threads each holding a 4 x 4 complex
-// register block (rows ty + 16a, columns tx + 16b): every A and Bm element of a
-// split is read from HBM once per output tile, and each LDS value feeds four
-// complex FMAs.
+// 64 x 64 output tile per block of 4 waves: wave w owns rows 16w .. 16w+15 as
+// four 16 x 16 complex tiles on the FP64 matrix cores; every A and Bm element
+// of a split is read from HBM once per output tile and staged through LDS.
 constexpr int GT = 64;  // output tile
 constexpr int GK = 16;  // k step
 
@@ -33,14 +47,15 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, lon
   const int ti = blockIdx.y / tj_n, tj = blockIdx.y % tj_n;
   const int l = blockIdx.z;
   const int t = threadIdx.x;
-  const int ty = t / 16, tx = t % 16;
+  const int lane = t & 63, wv = t >> 6;
   const c128* Al = A + l * a_ls;
   const c128* Bl = Bm + l * b_ls;
-  c128 acc[4][4];
+  v4d cr[4], ci[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+  for (int b = 0; b < 4; ++b) {
+    cr[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    ci[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
   const long k0 = ks * kchunk;
   const long k1 = min(n, k0 + kchunk);
   // 64 x 16 tiles of A (rows ti*64 ..) and Bm (rows tj*64 ..), k in [kb, kb+16);
@@ -77,26 +92,21 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, lon
     }
     __syncthreads();
     if (kb + GK < k1) fetch(kb + GK);
-#pragma unroll 4
-    for (int c = 0; c < GK; ++c) {
-      c128 av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sa[ty + 16 * a][c];
+    for (int c = 0; c < GK; c += 4) {
+      // A[i][k] = sa[16 wv + i][c + k], B[k][j] = sb[16 b + j][c + k]
+      const c128 av = sa[16 * wv + (lane & 15)][c + (lane >> 4)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = sb[tx + 16 * b][c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = cfma(av[a], bv[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) cmfma(av, sb[16 * b + (lane & 15)][c + (lane >> 4)], cr[b], ci[b]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti * GT + ty + 16 * a, j = tj * GT + tx + 16 * b;
-      if (i < ni && j < nj) part[(((long)ks * nf + l) * ni + i) * nj + j] = acc[a][b];
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * GT + 16 * wv + (lane >> 4) + 4 * v, j = tj * GT + 16 * b + (lane & 15);
+      if (i < ni && j < nj) part[(((long)ks * nf + l) * ni + i) * nj + j] = mk(cr[b][v], ci[b][v]);
     }
 }
 
@@ -113,8 +123,9 @@ __global__ void k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, 
 
 // ------------------------------------------------------------- gemm (NN) ---
 // S[l][i][n] = sum_j conj(M[l][i][j]) P[l][j][n]: 64 (i) x 64 (n) output tile
-// per block, 4 x 4 complex register block per thread, j in steps of 16 through
-// LDS; each P element is read from HBM once per 64 rows of S.
+// per block (wave w: rows 16w .. 16w+15, four 16 x 16 complex matrix-core
+// tiles), j in steps of 16 through LDS; each P element is read from HBM once
+// per 64 rows of S.
 constexpr int CT = 64;  // output tile (rows of S, points n)
 constexpr int CK = 16;  // j step
 
@@ -127,14 +138,15 @@ __global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int
   const int i0 = blockIdx.y * CT;
   const long n0 = (long)blockIdx.x * CT;
   const int t = threadIdx.x;
-  const int ty = t / 16, tx = t % 16;
+  const int lane = t & 63, wv = t >> 6;
   const c128* Ml = M + (long)l * ni * nj;
   const c128* Pl = P + l * p_ls;
-  c128 acc[4][4];
+  v4d cr[4], ci[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+  for (int b = 0; b < 4; ++b) {
+    cr[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    ci[b] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
   // M tile (row-major [i][j]) and P tile (n fastest, coalesced); the next pair
   // is loaded into registers while the current one is used
   // (clamped loads, masked at the LDS store: nothing waits for them early)
@@ -170,28 +182,23 @@ __global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int
     }
     __syncthreads();
     if (jb + CK < nj) fetch(jb + CK);
-#pragma unroll 4
-    for (int c = 0; c < CK; ++c) {
-      c128 mv[4], pv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) mv[a] = sm[ty + 16 * a][c];
+    for (int c = 0; c < CK; c += 4) {
+      // A[i][k] = sm[16 wv + i][c + k], B[k][j] = sp[c + k][16 b + j]
+      const c128 mv = sm[16 * wv + (lane & 15)][c + (lane >> 4)];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) pv[b] = sp[c][tx + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = cfma(mv[a], pv[b], acc[a][b]);
+      for (int b = 0; b < 4; ++b) cmfma(mv, sp[c + (lane >> 4)][16 * b + (lane & 15)], cr[b], ci[b]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + ty + 16 * a;
+  for (int v = 0; v < 4; ++v) {
+    const int i = i0 + 16 * wv + (lane >> 4) + 4 * v;
     if (i >= ni) continue;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const long nn = n0 + tx + 16 * b;
-      if (nn < n) S[l * s_ls + (long)i * n + nn] = acc[a][b];
+      const long nn = n0 + 16 * b + (lane & 15);
+      if (nn < n) S[l * s_ls + (long)i * n + nn] = mk(cr[b][v], ci[b][v]);
     }
   }
 }
