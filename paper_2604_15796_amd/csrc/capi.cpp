@@ -303,14 +303,19 @@ Geo make_geo(const fwi_problem* p) {
   return g;
 }
 
+// Cache key of a problem: the raw bytes of everything the cached data depend
+// on (exact comparison, no formatting cost).
 std::string problem_key(const fwi_problem* p) {
-  std::ostringstream os;
-  os.precision(17);
-  os << p->dim << ' ' << p->nx << ' ' << p->ny << ' ' << p->nz << ' ' << p->dx << ' ' << p->c0 << ' ' << p->nf;
-  for (int l = 0; l < p->nf; ++l) os << ' ' << p->freq_hz[l];
-  os << ' ' << p->ne;
-  for (int e = 0; e < 3 * p->ne; ++e) os << ' ' << p->elem_xyz[e];
-  return os.str();
+  std::string k;
+  auto put = [&k](const void* src, size_t bytes) { k.append(static_cast<const char*>(src), bytes); };
+  const int ints[5] = {p->dim, p->nx, p->ny, p->nz, p->nf};
+  put(ints, sizeof(ints));
+  put(&p->dx, sizeof(double));
+  put(&p->c0, sizeof(double));
+  put(p->freq_hz, sizeof(double) * p->nf);
+  put(&p->ne, sizeof(int));
+  put(p->elem_xyz, sizeof(double) * 3 * p->ne);
+  return k;
 }
 
 // ------------------------------------------------------------ twiddles ---
@@ -606,6 +611,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   int total = 0, cyc = 0;
   bool x_written = false;
   XUpdate pending_x;  // correction of the last cycle, not yet added to x
+  ArnoldiDriver<T> drv{g, c->tw, ks, s, mT, ghatT, rhs_freq, st, B};
   for (;; ++cyc) {
     if (cyc == 0) {
       krylov_start_norm(ks, b64, st);  // x_0 = 0: r = b
@@ -620,6 +626,9 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     }
     krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
     FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
+    // the first cycle almost never starts with nothing to do: its first pass
+    // is queued before the host reads the count (masked if it does)
+    if (cyc == 0) drv.first_rows();
     FWI_HIP(hipStreamSynchronize(st));
     std::memcpy(&res.maxrel, c->h_int + 2, sizeof(double));
     if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
@@ -636,11 +645,10 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     // Once at most half the RHS are left, the host waits for each count
     // before enqueueing the next step instead (a wait costs less than a
     // masked step).
-    ArnoldiDriver<T> drv{g, c->tw, ks, s, mT, ghatT, rhs_freq, st, B};
     bool pending = false;
     int known = nact;  // latest active count read
     int steps = 0;     // Arnoldi steps of this cycle
-    drv.first_rows();
+    if (cyc > 0) drv.first_rows();
     for (int j = 0;; ++j) {
       const size_t mark = tl_prof ? tl_prof->mark() : 0;
       drv.tail(j);
