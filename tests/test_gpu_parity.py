@@ -225,6 +225,28 @@ def test_forward_vs_oracle(ctx, F, prec):
     assert st["solves"] == p.nf * p.ne
 
 
+@pytest.mark.parametrize("prec,restart,check_every,inner,rtol,tol", [
+    (1, 8, 1, 1e-6, 1e-7, 1e-6),    # several complex64 cycles, full ones ended by the orthogonalisation alone
+    (1, 8, 3, 1e-3, 1e-8, 1e-6),    # host checks every third step, refinement in several stages
+    (1, 16, 1, 1e-6, 1e-6, 1e-5),   # one cycle down to the outer tolerance (the bench setting)
+    (0, 8, 2, 1e-3, 1e-12, 1e-10),  # plain FP64 with restarts every 8 steps
+])
+def test_solver_control_paths_vs_oracle(ctx, F, prec, restart, check_every, inner, rtol, tol):
+    """Restart lengths, host check intervals and inner tolerances that take
+    the solver through its different step orders (orthogonalisation fused into
+    the next matvec or alone at a cycle end, waits for every count or a step
+    ahead) give the oracle's fields to the tolerance the settings promise."""
+    p = W.small2d(seed=27, nx=34, nz=30, ne=4, nf=2)
+    opts = F.SolveOptions(precision=prec, rtol=rtol, restart=restart, check_every=check_every, inner_rtol=inner,
+                          max_iter=400)
+    data, fields, st = ctx.forward(p, dev(p.c, torch.float64), dev(p.alpha, torch.float64), opts, fields=True)
+    rd, rf, _ = O.forward(p.c, p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert st["unconverged"] == 0 and st["solves"] == p.nf * p.ne
+    assert st["max_rel_residual"] <= rtol
+    assert relerr(host(fields), rf) < tol
+    assert relerr(host(data), rd) < tol
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("recip", [0, 1])
 def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
