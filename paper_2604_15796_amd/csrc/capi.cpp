@@ -626,10 +626,12 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     }
     krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
     FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipEventRecord(c->count_ev, st));
     // the first cycle almost never starts with nothing to do: its first pass
-    // is queued before the host reads the count (masked if it does)
+    // is queued before the host reads the count (masked if it does) and runs
+    // while the host waits for the copy only
     if (cyc == 0) drv.first_rows();
-    FWI_HIP(hipStreamSynchronize(st));
+    FWI_HIP(hipEventSynchronize(c->count_ev));
     std::memcpy(&res.maxrel, c->h_int + 2, sizeof(double));
     if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
     const int nact = c->h_int[0];
