@@ -25,6 +25,8 @@ namespace fwi {
 
 thread_local LaunchProfiler* tl_prof = nullptr;
 thread_local long tl_active = 0;
+thread_local hipEvent_t tl_ev_start = nullptr, tl_ev_stop = nullptr;
+thread_local bool tl_ev_used = false;
 thread_local int tl_nfreq = 0;
 thread_local const FftTuning* tl_tune = nullptr;
 thread_local int tl_force_variant = -1;
@@ -140,7 +142,6 @@ struct EventProfiler : LaunchProfiler {
     long B, act;
   };
   std::vector<Rec> recs;
-  hipEvent_t cur[2 * KC_COUNT] = {};
   double tot_ms[2 * KC_COUNT] = {};
   long long cnt[2 * KC_COUNT] = {};
   double byt[2 * KC_COUNT] = {};
@@ -154,17 +155,19 @@ struct EventProfiler : LaunchProfiler {
     }
     return pool[used++];
   }
-  void begin(int cls, hipStream_t st) override {
+  // the region's single kernel launch records the two events
+  void begin(int cls, hipStream_t) override {
     if (!((mask >> cls) & 1u)) return;
-    cur[cls] = get();
-    FWI_HIP(hipEventRecord(cur[cls], st));
+    tl_ev_start = get();
+    tl_ev_stop = get();
+    tl_ev_used = false;
   }
-  void end(int cls, hipStream_t st, double per_rhs, double fixed, bool masked, long B) override {
+  void end(int cls, hipStream_t, double per_rhs, double fixed, bool masked, long B) override {
     if (!((mask >> cls) & 1u)) return;
-    hipEvent_t b = get();
-    FWI_HIP(hipEventRecord(b, st));
     const long act = masked && tl_active > 0 && tl_active < B ? tl_active : B;
-    recs.push_back({cls, cur[cls], b, per_rhs, fixed, masked, B, act});
+    if (tl_ev_used) recs.push_back({cls, tl_ev_start, tl_ev_stop, per_rhs, fixed, masked, B, act});
+    tl_ev_start = tl_ev_stop = nullptr;
+    tl_ev_used = false;
   }
   size_t mark() const override { return recs.size(); }
   void set_active(size_t from, long act) override {
@@ -912,6 +915,8 @@ int guarded(fwi_ctx* c, F&& body) {
     }
     ~Scope() {
       tl_prof = nullptr;
+      tl_ev_start = tl_ev_stop = nullptr;
+      tl_ev_used = false;
       tl_tune = nullptr;
       tl_force_variant = -1;
       tl_force_wide = 0;

@@ -544,19 +544,19 @@ void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
   if (a.kind != RI_PLAIN) {
     if (2 * a.nin > L) throw Error(-6, "combined row inputs need zero-padded rows");
     if (a.kind == RI_ORTH) {
-      hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_ORTH>), dim3(grid), dim3(NT), 0, st, a);
+      FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_ORTH>), dim3(grid), dim3(NT), 0, st, a);
     } else if (a.kind == RI_ORTH_ONLY) {
-      hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_ORTH_ONLY>), dim3(grid), dim3(NT), 0, st, a);
+      FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_ORTH_ONLY>), dim3(grid), dim3(NT), 0, st, a);
     } else if constexpr (sizeof(T) == 8) {
-      if (a.kind == RI_UPD32) hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_UPD32>), dim3(grid), dim3(NT), 0, st, a);
-      else hipLaunchKernelGGL((k_row_fwd<T, L, NL, true, RI_UPD64>), dim3(grid), dim3(NT), 0, st, a);
+      if (a.kind == RI_UPD32) FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_UPD32>), dim3(grid), dim3(NT), 0, st, a);
+      else FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_UPD64>), dim3(grid), dim3(NT), 0, st, a);
     } else {
       throw Error(-6, "the fused solution update is for complex128 residuals");
     }
   } else if (2 * a.nin <= L) {
-    hipLaunchKernelGGL((k_row_fwd<T, L, NL, true>), dim3(grid), dim3(NT), 0, st, a);
+    FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true>), dim3(grid), dim3(NT), 0, st, a);
   } else if constexpr (sizeof(T) == 8) {
-    hipLaunchKernelGGL((k_row_fwd<T, L, NL, false>), dim3(grid), dim3(NT), 0, st, a);
+    FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, false>), dim3(grid), dim3(NT), 0, st, a);
   } else {
     throw Error(-6, "complex64 row transforms need zero-padded rows");
   }
@@ -574,14 +574,14 @@ void launch_row_inv_v(const RowInvArgs<T>& a, int epi, hipStream_t st) {
       throw Error(-6, "fused inner products not applicable");
     RowInvArgs<T> b = a;
     b.nparts = a.rows_per_rhs / NL;
-    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE_DOT>), dim3(grid), dim3(NT), 0, st, b);
+    FWI_TIMED_LAUNCH((k_row_inv<T, L, NL, EPI_VIE_DOT>), dim3(grid), dim3(NT), 0, st, b);
   } else if (epi == EPI_VIE) {
-    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
+    FWI_TIMED_LAUNCH((k_row_inv<T, L, NL, EPI_VIE>), dim3(grid), dim3(NT), 0, st, a);
   } else if (epi == EPI_COPY) {
-    hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
+    FWI_TIMED_LAUNCH((k_row_inv<T, L, NL, EPI_COPY>), dim3(grid), dim3(NT), 0, st, a);
   } else if constexpr (sizeof(T) == 8) {
-    if (epi == EPI_RESID) hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
-    else hipLaunchKernelGGL((k_row_inv<T, L, NL, EPI_RESID32>), dim3(grid), dim3(NT), 0, st, a);
+    if (epi == EPI_RESID) FWI_TIMED_LAUNCH((k_row_inv<T, L, NL, EPI_RESID>), dim3(grid), dim3(NT), 0, st, a);
+    else FWI_TIMED_LAUNCH((k_row_inv<T, L, NL, EPI_RESID32>), dim3(grid), dim3(NT), 0, st, a);
   } else {
     throw Error(-6, "residual epilogue needs the complex128 operator");
   }
@@ -591,7 +591,7 @@ template <typename T, int L, int V, int MODE, bool HALF, bool WIDE>
 void launch_strided_k(const StridedArgs<T>& a, dim3 grid, hipStream_t st) {
   constexpr int NL = col_nl<T, L, V>();
   constexpr int NTV = col_nt<V>();
-  hipLaunchKernelGGL((k_strided<T, L, NL, NTV, MODE, HALF, WIDE>), grid, dim3(NTV), 0, st, a);
+  FWI_TIMED_LAUNCH((k_strided<T, L, NL, NTV, MODE, HALF, WIDE>), grid, dim3(NTV), 0, st, a);
 }
 template <typename T, int L, int V>
 void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_t st) {

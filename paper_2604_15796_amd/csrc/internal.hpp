@@ -2,6 +2,7 @@
 // kernel launchers. Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
@@ -45,6 +46,21 @@ struct LaunchProfiler {
   virtual ~LaunchProfiler() = default;
 };
 extern thread_local LaunchProfiler* tl_prof;
+// Events of the launch being profiled (null otherwise): the kernel launch
+// itself records them (hipExtLaunchKernel), so timing adds no packets to the
+// stream; every profiled region launches exactly one kernel.
+extern thread_local hipEvent_t tl_ev_start, tl_ev_stop;
+extern thread_local bool tl_ev_used;  // the events were handed to a launch
+#define FWI_TIMED_LAUNCH(kernel, grid, block, shmem, st, ...)                                          \
+  do {                                                                                                 \
+    if (::fwi::tl_ev_start) {                                                                          \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, ::fwi::tl_ev_start, ::fwi::tl_ev_stop, 0, \
+                            __VA_ARGS__);                                                              \
+      ::fwi::tl_ev_used = true;                                                                        \
+    } else {                                                                                           \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);                                 \
+    }                                                                                                  \
+  } while (0)
 extern thread_local long tl_active;  // RHS that the next launches actually process (0: all)
 extern thread_local int tl_nfreq;    // distinct frequencies in the batch (Ghat reads)
 inline void prof_begin(int cls, hipStream_t st) {

@@ -428,7 +428,7 @@ template <typename T>
 void krylov_dots(const KrylovState<T>& s, int j, hipStream_t st) {
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;
   prof_begin(KC_DOTS + po, st);
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, s.vstride(), j,
+  FWI_JM_SWITCH(s.JM, FWI_TIMED_LAUNCH((k_dots<T, JMC>), dim3(s.nblk, s.B), dim3(KT), 0, st, s.V, s.vstride(), j,
                                           s.n, s.chunk, s.active, s.vscale, s.B, s.dotp, s.nblk));
   FWI_LAUNCH_CHECK();
   prof_end(KC_DOTS + po, st, (j + 2) * (double)s.n * sizeof(cplx<T>), 0.0, true, s.B);
