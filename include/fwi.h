@@ -265,7 +265,8 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void
 #define FWI_KC_ORTH_FWD 7
 /* Class k + 8 is the complex128 launch of class k (k + 0: complex64).
  * Time every launch of the classes in `mask` (bit k = class k) with HIP events
- * recorded on the context's stream; resets the accumulated figures. 0 turns it off. */
+ * that the kernel launch itself records on the context's stream (no extra
+ * stream packets); resets the accumulated figures. 0 turns it off. */
 int fwi_profile(fwi_ctx* ctx, unsigned mask);
 /* Accumulated event time [ms], launch count and algorithmic HBM bytes (the
  * bytes each launch must read and write for the RHS it processes) of a class. */
