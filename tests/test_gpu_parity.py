@@ -247,6 +247,21 @@ def test_solver_control_paths_vs_oracle(ctx, F, prec, restart, check_every, inne
     assert relerr(host(data), rd) < tol
 
 
+@pytest.mark.parametrize("prec,check_every", [(1, 1), (1, 2), (0, 1)])
+def test_solver_control_paths_3d_vs_oracle(ctx, F, prec, check_every):
+    """The fused orthogonalisation and solution update on a ragged 3D grid
+    (rows of several RHS per workgroup, inner products in their own kernel)."""
+    p = W.small3d(seed=29, nx=13, ny=9, nz=11, ne=3, nf=1)
+    rtol, tol = (1e-7, 1e-6) if prec == 1 else (1e-12, 1e-10)
+    opts = F.SolveOptions(precision=prec, rtol=rtol, restart=8, check_every=check_every, inner_rtol=1e-6,
+                          max_iter=400)
+    data, fields, st = ctx.forward(p, dev(p.c, torch.float64), dev(p.alpha, torch.float64), opts, fields=True)
+    rd, rf, _ = O.forward(p.c, p.alpha, 3, p.nx, p.ny, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert st["unconverged"] == 0 and st["max_rel_residual"] <= rtol
+    assert relerr(host(fields), rf) < tol
+    assert relerr(host(data), rd) < tol
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("recip", [0, 1])
 def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
