@@ -617,7 +617,11 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   ArnoldiDriver<T> drv{g, c->tw, ks, s, mT, ghatT, rhs_freq, st, B};
   for (;; ++cyc) {
     if (cyc == 0) {
-      krylov_start_norm(ks, b64, st);  // x_0 = 0: r = b
+      // x_0 = 0, r = b: the first pass casts b into V_0, sums |b|^2 per row
+      // and transforms V_0 (every RHS; masks come with the cycle start)
+      const StartIn si{b64, s.rowpart};
+      launch_vie_rows<T>(g, c->tw, B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
+      krylov_rows_norm(ks, s.rowpart, g.nz * g.ny, st);
     } else {
       // FP64 residual of x plus the last cycle's correction (added to x by
       // its first pass); its epilogue writes V_0 (unscaled) and per-row norms
@@ -630,10 +634,6 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
     krylov_cycle_init(ks, cyc == 0, o.rtol, inner, st);
     FWI_HIP(hipMemcpyAsync(c->h_int, ks.counters, 2 * sizeof(int) + sizeof(double), hipMemcpyDeviceToHost, st));
     FWI_HIP(hipEventRecord(c->count_ev, st));
-    // the first cycle almost never starts with nothing to do: its first pass
-    // is queued before the host reads the count (masked if it does) and runs
-    // while the host waits for the copy only
-    if (cyc == 0) drv.first_rows();
     FWI_HIP(hipEventSynchronize(c->count_ev));
     std::memcpy(&res.maxrel, c->h_int + 2, sizeof(double));
     if (!std::isfinite(res.maxrel)) throw Error(FWI_E_NONFINITE, "non-finite residual in the Krylov solve");
@@ -1160,7 +1160,9 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   const cplx<T>* mT = fp32 ? (const cplx<T>*)I.cb.m32 : (const cplx<T>*)I.cb.m64;
   const cplx<T>* gT = fp32 ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
   if (cyc == 0) {
-    krylov_start_norm(ks, rhs, st);
+    const StartIn si{rhs, s.rowpart};  // first pass of the first step included
+    launch_vie_rows<T>(I.g, c->tw, ks.B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
+    krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
   } else {
     launch_residual_basis(I.g, c->tw, ks.B, x, I.cb.m64, pc.ghat64, pc.rhs_freq, s, rhs, st);
     krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
@@ -1168,7 +1170,7 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
   // every step of the cycle, masked once an RHS has converged
   ArnoldiDriver<T> drv{I.g, c->tw, ks, s, mT, gT, pc.rhs_freq, st, ks.B};
-  drv.first_rows();
+  if (cyc > 0) drv.first_rows();
   for (int j = 0; j < ks.JM; ++j) {
     drv.tail(j);
     drv.orth_givens(j, j + 1 < ks.JM);

@@ -74,7 +74,7 @@ __device__ __forceinline__ bool any_row(const int* s_ok, int nl) {
 // ------------------------------------------------------------- row pass 1 ---
 // Input of the first pass: the rows of x as they are, or a combination with
 // basis vectors formed first (see k_row_fwd).
-enum RowInKind { RI_PLAIN = 0, RI_UPD32 = 1, RI_UPD64 = 2, RI_ORTH = 3, RI_ORTH_ONLY = 4 };
+enum RowInKind { RI_PLAIN = 0, RI_UPD32 = 1, RI_UPD64 = 2, RI_ORTH = 3, RI_ORTH_ONLY = 4, RI_START = 5 };
 
 template <typename T>
 struct RowFwdArgs {
@@ -95,7 +95,8 @@ struct RowFwdArgs {
   const c128* lc_coef;   // [B][lc_cstride]
   int lc_cstride, lc_first;
   cplx<T>* lc_out;       // = x, written
-  double* lc_rowpart;    // orthogonalisation: |v|^2 per row
+  double* lc_rowpart;    // orthogonalisation / start: |v|^2 per row
+  const c128* lc_src;    // start: the right-hand sides
 };
 
 template <typename T, int K>
@@ -111,11 +112,15 @@ using lc_basis_t = std::conditional_t<K == RI_UPD32, float, std::conditional_t<K
 //     Gram-Schmidt v = w + sum_{i < nvec} coef[b][i] V_i (coef = -h_i times
 //     the vector's scale, accumulated in T like every vector update of the
 //     solver), stored, and |v|^2 summed per row in FP64 into rowpart;
-//     RI_ORTH_ONLY stops there (no transform).
+//     RI_ORTH_ONLY stops there (no transform);
+//   RI_START (first cycle, x_0 = 0): x = src rounded to T (src complex128),
+//     with |src|^2 summed per row in FP64 into rowpart.
 template <typename T, int L, int NLV, bool HIN, int K = RI_PLAIN>
 __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
   using C = LineCfg<T, L, NLV, NT, false>;
   constexpr bool ORTH = K == RI_ORTH || K == RI_ORTH_ONLY;
+  constexpr bool START = K == RI_START;
+  constexpr bool NORM = ORTH || START;  // per-row sums of |v|^2
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   __shared__ long s_x[C::NL];
   __shared__ int s_m[C::NL];
@@ -134,7 +139,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     s_x[l] = gc * a.in_stride;
     s_m[l] = (int)z * a.nin;
     if constexpr (K != RI_PLAIN) {
-      s_k[l] = ORTH ? a.lc_nvec : a.lc_ncol[b];
+      s_k[l] = ORTH ? a.lc_nvec : START ? 0 : a.lc_ncol[b];
       s_b[l] = (int)b;
     }
   }
@@ -161,7 +166,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
     fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
   } else {
     static_assert(HIN, "combined inputs are rows of zero-padded operators");
-    static_assert(ORTH || sizeof(T) == 8, "the solution update is complex128");
+    static_assert(ORTH || START || sizeof(T) == 8, "the solution update is complex128");
     using TB = lc_basis_t<T, K>;
     using TA = std::conditional_t<ORTH, T, double>;  // accumulation type
     // the points the first stage will ask this thread for: slot t, leg r
@@ -185,11 +190,15 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
         const int p = j + r * NJ;
         const int pc = p < a.nin ? p : a.nin - 1;
         off[t][r] = (unsigned)(s_x[line] - x0 + pc);
-        const cplx<T> w = a.x[x0 + off[t][r]];
-        acc[t][r] = (!ORTH && a.lc_first) ? mk((TA)0, (TA)0) : mk((TA)w.x, (TA)w.y);
+        if constexpr (START) {
+          acc[t][r] = a.lc_src[x0 + off[t][r]];
+        } else {
+          const cplx<T> w = a.x[x0 + off[t][r]];
+          acc[t][r] = (!ORTH && a.lc_first) ? mk((TA)0, (TA)0) : mk((TA)w.x, (TA)w.y);
+        }
       }
     }
-    const cplx<TB>* V0 = static_cast<const cplx<TB>*>(a.lc_basis) + x0;
+    const cplx<TB>* V0 = START ? nullptr : static_cast<const cplx<TB>*>(a.lc_basis) + x0;
 #pragma unroll 4
     for (int i = 0; i < kmax; ++i) {
       const cplx<TB>* Vi = V0 + (long)i * a.lc_vs;  // uniform
@@ -230,6 +239,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
           a.lc_out[x0 + off[t][r]] = xin[t][r];
           if constexpr (ORTH)
             nrm[t] += (double)xin[t][r].x * (double)xin[t][r].x + (double)xin[t][r].y * (double)xin[t][r].y;
+          if constexpr (START) nrm[t] += norm2(acc[t][r]);  // of the complex128 value
         }
       }
     }
@@ -244,7 +254,7 @@ __global__ void __launch_bounds__(NT) k_row_fwd(RowFwdArgs<T> a) {
       };
       fft_line_transform<C, 0, HIN, false>(a.tw, sh, src, snk);
     }
-    if constexpr (ORTH) {
+    if constexpr (NORM) {
       // per-row sums in a fixed order: first-stage slot (line, j) belongs to
       // one thread; the LDS tile is free once the transform is done
       double* part = reinterpret_cast<double*>(sh);
@@ -547,6 +557,8 @@ void launch_row_fwd_v(const RowFwdArgs<T>& a, hipStream_t st) {
       FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_ORTH>), dim3(grid), dim3(NT), 0, st, a);
     } else if (a.kind == RI_ORTH_ONLY) {
       FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_ORTH_ONLY>), dim3(grid), dim3(NT), 0, st, a);
+    } else if (a.kind == RI_START) {
+      FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_START>), dim3(grid), dim3(NT), 0, st, a);
     } else if constexpr (sizeof(T) == 8) {
       if (a.kind == RI_UPD32) FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_UPD32>), dim3(grid), dim3(NT), 0, st, a);
       else FWI_TIMED_LAUNCH((k_row_fwd<T, L, NL, true, RI_UPD64>), dim3(grid), dim3(NT), 0, st, a);
@@ -691,7 +703,7 @@ int row_inv_nl(int L) {
 
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
-                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth) {
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth, const StartIn* start) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
@@ -709,7 +721,7 @@ void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
   f.in_stride = g.nx;
   // per RHS: x read, the x-pass intermediate written (m once)
   double per_rhs = (n + g.u1()) * es;
-  if (xu && orth) throw Error(-6, "one combined input per pass");
+  if ((xu != nullptr) + (orth != nullptr) + (start != nullptr) > 1) throw Error(-6, "one combined input per pass");
   if (xu) {
     if (sizeof(T) != 8 || active) throw Error(-6, "the fused solution update is for complex128 residuals");
     f.kind = xu->fp32 ? RI_UPD32 : RI_UPD64;
@@ -733,6 +745,14 @@ void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
     f.lc_rowpart = orth->rowpart;
     // w read, nvec basis vectors read, v written, per-row norms (and the x-pass intermediate)
     per_rhs = (2.0 + orth->nvec) * n * es + 8.0 * rows_per_rhs + (orth->transform ? g.u1() * es : 0.0);
+  } else if (start) {
+    if (!m || active) throw Error(-6, "the start pass needs the contrast and every RHS");
+    f.kind = RI_START;
+    f.lc_src = start->b;
+    f.lc_out = const_cast<cplx<T>*>(x);
+    f.lc_rowpart = start->rowpart;
+    // b read (complex128), V_0 written, per-row norms, the x-pass intermediate
+    per_rhs = n * (16.0 + es) + 8.0 * rows_per_rhs + g.u1() * es;
   }
   // the orthogonalising first pass and the orthogonalisation alone are classes of their own
   const int cls = orth ? (orth->transform ? KC_ORTH_FWD : KC_ORTH) : KC_ROW_FWD;
@@ -870,7 +890,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
                 const XUpdate* xu) {
-  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr);
+  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr, nullptr);
   launch_vie_tail<T>(g, tw, B, x, scale, active, ghat, rhs_freq, U1, U2, y, rhs, epi, st, y32, rowpart, dots);
 }
 

@@ -166,6 +166,14 @@ struct OrthIn {
   bool transform = true;
 };
 
+// First cycle (x_0 = 0, r = b) fused into the first pass: V_0 = b rounded to
+// the basis precision, |b|^2 summed per grid row into rowpart (FP64), V_0
+// (unscaled) row-transformed, for every RHS.
+struct StartIn {
+  const c128* b = nullptr;      // [B][n]
+  double* rowpart = nullptr;    // [B * rows per RHS]
+};
+
 // y = A x for B right-hand sides (Eq. 5 discretised):
 //   EPI_VIE  : y_b = s_b (x_b - conv(m * x_b)) = s_b x_b - conv(m * s_b x_b)
 //   EPI_RESID: y_b = rhs_b - (x_b - conv(m * x_b))        (scale ignored), and
@@ -186,7 +194,8 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
 // the combined input of xu / orth, transformed into U1) and the rest.
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
-                     cplx<T>* U1, hipStream_t st, const XUpdate* xu = nullptr, const OrthIn* orth = nullptr);
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu = nullptr, const OrthIn* orth = nullptr,
+                     const StartIn* start = nullptr);
 template <typename T>
 void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale,
                      const int* active, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2,

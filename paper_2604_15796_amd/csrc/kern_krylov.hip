@@ -174,28 +174,6 @@ __global__ void __launch_bounds__(KT) k_givens(int j, int B, int rows, const dou
   }
 }
 
-// |x_b|^2 partial sums of an FP64 array [B][n]
-// First cycle (x_0 = 0, r = b): V_0 = (T) b, unscaled, and nrmp[b][blk] =
-// |b|^2 over the block's chunk (FP64, fixed order).
-template <typename T>
-__global__ void __launch_bounds__(KT) k_start_norm(const c128* __restrict__ x, cplx<T>* __restrict__ V0, long n,
-                                                   int chunk, double* __restrict__ nrmp, int nblk) {
-  __shared__ double red[KT / 64];
-  const int b = blockIdx.y;
-  const long e0 = (long)blockIdx.x * chunk;
-  const long e1 = min(n, e0 + chunk);
-  const c128* xb = x + (long)b * n;
-  cplx<T>* vb = V0 + (long)b * n;
-  double acc = 0.0;
-  for (long e = e0 + threadIdx.x; e < e1; e += KT) {
-    const c128 v = xb[e];
-    vb[e] = mk((T)v.x, (T)v.y);
-    acc += norm2(v);
-  }
-  const double s = block_sum<KT>(acc, red);
-  if (threadIdx.x == 0) nrmp[(long)b * nblk + blockIdx.x] = s;
-}
-
 // nrmp[b][blk] = sum of the block's share of the per-row partials of RHS b.
 __global__ void __launch_bounds__(KT) k_rows_norm(const double* __restrict__ rowpart, int rows, int per,
                                                   double* __restrict__ nrmp, int nblk) {
@@ -404,12 +382,6 @@ static unsigned vec_blocks(long n) {
   }
 
 template <typename T>
-void krylov_start_norm(const KrylovState<T>& s, const c128* b, hipStream_t st) {
-  hipLaunchKernelGGL((k_start_norm<T>), dim3(s.nblk, s.B), dim3(KT), 0, st, b, s.V, s.n, s.chunk, s.nrmp, s.nblk);
-  FWI_LAUNCH_CHECK();
-}
-
-template <typename T>
 void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, hipStream_t st) {
   const int per = (rows + s.nblk - 1) / s.nblk;
   hipLaunchKernelGGL(k_rows_norm, dim3(s.nblk, s.B), dim3(KT), 0, st, rowpart, rows, per, s.nrmp, s.nblk);
@@ -476,7 +448,6 @@ void krylov_reset_iters(const KrylovState<T>& s, hipStream_t st) {
 }
 
 #define FWI_INST(T)                                                                            \
-  template void krylov_start_norm<T>(const KrylovState<T>&, const c128*, hipStream_t);         \
   template void krylov_rows_norm<T>(const KrylovState<T>&, const double*, int, hipStream_t);   \
   template void krylov_cycle_init<T>(const KrylovState<T>&, int, double, double, hipStream_t); \
   template void krylov_dots<T>(const KrylovState<T>&, int, hipStream_t);                        \

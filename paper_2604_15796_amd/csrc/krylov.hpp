@@ -38,11 +38,9 @@ struct KrylovState {
 
 int krylov_nblk(long n);
 
-// First cycle: V_0 = (T) b (stored unscaled) and the norm partials of b.
-template <typename T>
-void krylov_start_norm(const KrylovState<T>& s, const c128* b, hipStream_t st);  // -> V_0, nrmp
-// Later cycles: V_0 was written by the residual epilogue of the operator
-// together with one |r|^2 partial per grid row; fold those into nrmp.
+// V_0 was written by the first pass of the first cycle (b) or by the residual
+// epilogue of the operator (later cycles) together with one |r|^2 partial per
+// grid row; fold those into nrmp.
 template <typename T>
 void krylov_rows_norm(const KrylovState<T>& s, const double* rowpart, int rows, hipStream_t st);
 // Norms, activity, stopping targets and the scale of V_0 (1 / |r|).
