@@ -10,8 +10,8 @@ timed beside it for the speedup, and the field / gradient errors of the timed
 form against the plain FP64 solve are reported (bar: 1e-5 fields, 1e-4
 gradient).
 
-Prints one JSON line (rank 0, N = 1). `--gpus N` with N > 1 is refused: this
-build runs on one GPU.
+Prints one JSON line (rank 0, N = 1). `--gpus N` with N > 1 is refused: the
+library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "forward+adjoint solves/s at 1e-5 rel err vs FP64 plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
 # MI355X FP32 vector peak (published, counts packed dual-FP32 FMAs) and the
-# peak without packed FP32, which this build does not use: 256 CUs x 4 SIMD x
+# peak without packed FP32, which the library does not use: 256 CUs x 4 SIMD x
 # 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP32_UNPACKED_PEAK_TFLOPS = 78.6
@@ -83,7 +83,7 @@ def main():
     if args.inner_rtol is None:
         args.inner_rtol = 1e-3 if args.workload == "uneven-batch" else 1e-6
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU frequency-sharded layout is design-only.", file=sys.stderr)
         sys.exit(2)
     import torch
