@@ -1150,8 +1150,16 @@ struct BatchInst {
   c128* data_out = nullptr;
 };
 
+// Parts of a cycle, captured as separate graphs so that the host can skip
+// the second half of the steps once every RHS of the wave has stopped.
+enum CyclePart { CP_HEAD = 0, CP_REST = 1, CP_FINISH = 2 };
+inline int head_steps(int JM) { return JM / 2; }
+
+// CP_HEAD: cycle start (first-cycle start pass, or FP64 residual), norms,
+// cycle init and the first JM/2 Arnoldi steps; CP_REST: the remaining steps
+// and the solution update; CP_FINISH: the solution update only.
 template <typename T>
-void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cyc, const fwi_solve_opts& o,
+void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cyc, int part, const fwi_solve_opts& o,
                    hipStream_t st) {
   const bool fp32 = std::is_same<T, float>::value;
   KrylovState<T>& ks = I.sb.ks;
@@ -1159,35 +1167,39 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   const ProblemCache& pc = *I.pc;
   const cplx<T>* mT = fp32 ? (const cplx<T>*)I.cb.m32 : (const cplx<T>*)I.cb.m64;
   const cplx<T>* gT = fp32 ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
-  if (cyc == 0) {
-    const StartIn si{rhs, s.rowpart};  // first pass of the first step included
-    launch_vie_rows<T>(I.g, c->tw, ks.B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
-    krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
-  } else {
-    launch_residual_basis(I.g, c->tw, ks.B, x, I.cb.m64, pc.ghat64, pc.rhs_freq, s, rhs, st);
-    krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
-  }
-  krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
-  // every step of the cycle, masked once an RHS has converged
   ArnoldiDriver<T> drv{I.g, c->tw, ks, s, mT, gT, pc.rhs_freq, st, ks.B};
-  if (cyc > 0) drv.first_rows();
-  for (int j = 0; j < ks.JM; ++j) {
+  const int s1 = head_steps(ks.JM);
+  if (part == CP_HEAD) {
+    if (cyc == 0) {
+      const StartIn si{rhs, s.rowpart};  // first pass of the first step included
+      launch_vie_rows<T>(I.g, c->tw, ks.B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
+      krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
+    } else {
+      launch_residual_basis(I.g, c->tw, ks.B, x, I.cb.m64, pc.ghat64, pc.rhs_freq, s, rhs, st);
+      krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
+    }
+    krylov_cycle_init(ks, cyc == 0, o.rtol, fp32 ? o.inner_rtol : 0.0, st);
+    if (cyc > 0) drv.first_rows();
+  }
+  // the steps of this part, masked once an RHS has converged
+  const int j0 = part == CP_HEAD ? 0 : s1, j1 = part == CP_HEAD ? s1 : part == CP_REST ? ks.JM : s1;
+  for (int j = j0; j < j1; ++j) {
     drv.tail(j);
     drv.orth_givens(j, j + 1 < ks.JM);
   }
-  krylov_finish_cycle(ks, x, cyc == 0, st);
+  if (part != CP_HEAD) krylov_finish_cycle(ks, x, cyc == 0, st);
 }
 
 template <typename T, class RhsOf, class XOf>
-hipGraphExec_t capture_cycle(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int cyc, const fwi_solve_opts& o,
-                             RhsOf&& rhs_of, XOf&& x_of) {
+hipGraphExec_t capture_cycle(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int cyc, int part,
+                             const fwi_solve_opts& o, RhsOf&& rhs_of, XOf&& x_of) {
   hipStream_t main = c->cap_stream;
   FWI_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
   try {
     FWI_HIP(hipEventRecord(c->fork_ev, main));
     for (BatchInst<T>* I : wave) {
       FWI_HIP(hipStreamWaitEvent(I->st, c->fork_ev, 0));
-      enqueue_cycle<T>(c, *I, rhs_of(*I), x_of(*I), cyc, o, I->st);
+      enqueue_cycle<T>(c, *I, rhs_of(*I), x_of(*I), cyc, part, o, I->st);
       FWI_HIP(hipEventRecord(I->join, I->st));
       FWI_HIP(hipStreamWaitEvent(main, I->join, 0));
     }
@@ -1221,32 +1233,51 @@ void batch_solve(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int* ctr_dev, con
   const int max_cycles = fp32 ? o.max_refine : (o.max_iter + o.restart - 1) / o.restart + 1;
   const double t0 = now_ms();
   for (BatchInst<T>* I : wave) krylov_reset_iters(I->sb.ks, main);  // x is written by the first cycle
-  hipGraphExec_t g0 = capture_cycle<T>(c, wave, 0, o, rhs_of, x_of);
-  hipGraphExec_t gN = nullptr;
+  // graphs per (first cycle or later, part), captured when first needed
+  hipGraphExec_t gx[2][3] = {};
+  auto graph = [&](int cyc, int part) {
+    hipGraphExec_t& e = gx[cyc == 0 ? 0 : 1][part];
+    if (!e) e = capture_cycle<T>(c, wave, cyc == 0 ? 0 : 1, part, o, rhs_of, x_of);
+    return e;
+  };
+  auto destroy = [&]() {
+    for (auto& row : gx)
+      for (hipGraphExec_t& e : row)
+        if (e) {
+          (void)hipGraphExecDestroy(e);
+          e = nullptr;
+        }
+  };
   try {
-    gN = capture_cycle<T>(c, wave, 1, o, rhs_of, x_of);
     const int W = (int)wave.size();
     std::vector<int> ctr(2 * W);
     for (int cyc = 0;; ++cyc) {
-      FWI_HIP(hipGraphLaunch(cyc == 0 ? g0 : gN, main));
+      // cycle start and the first half of the steps, then the host reads the
+      // counts at the cycle start and after those steps
+      FWI_HIP(hipGraphLaunch(graph(cyc, CP_HEAD), main));
       tot.graph_launches += 1;
       FWI_HIP(hipMemcpyAsync(ctr.data(), ctr_dev, sizeof(int) * 2 * W, hipMemcpyDeviceToHost, main));
       FWI_HIP(hipStreamSynchronize(main));
-      int active = 0;
-      for (int i = 0; i < W; ++i) active += ctr[2 * i + 1];  // RHS active at the start of this cycle
+      int active = 0, still = 0;
+      for (int i = 0; i < W; ++i) {
+        active += ctr[2 * i + 1];  // RHS active at the start of this cycle
+        still += ctr[2 * i];       // RHS active after the first half of the steps
+      }
       if (active == 0) break;
+      // the rest of the steps only while some RHS is still active
+      FWI_HIP(hipGraphLaunch(graph(cyc, still > 0 ? CP_REST : CP_FINISH), main));
+      tot.graph_launches += 1;
       if (cyc >= max_cycles) {
         tot.unconverged += active;
         break;
       }
     }
   } catch (...) {
-    if (g0) (void)hipGraphExecDestroy(g0);
-    if (gN) (void)hipGraphExecDestroy(gN);
+    destroy();
     throw;
   }
-  FWI_HIP(hipGraphExecDestroy(g0));
-  FWI_HIP(hipGraphExecDestroy(gN));
+  FWI_HIP(hipStreamSynchronize(main));
+  destroy();
   for (BatchInst<T>* I : wave) {
     std::vector<int> it(I->B);
     double mr = 0.0;
