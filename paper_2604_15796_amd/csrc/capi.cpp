@@ -1273,6 +1273,7 @@ void batch_solve(fwi_ctx* c, std::vector<BatchInst<T>*>& wave, int* ctr_dev, con
       }
     }
   } catch (...) {
+    (void)hipStreamSynchronize(main);  // no graph is destroyed while it may still run
     destroy();
     throw;
   }
