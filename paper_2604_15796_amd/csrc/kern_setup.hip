@@ -15,7 +15,9 @@ __global__ void k_contrast(long n, double c0, const double* __restrict__ c, cons
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double cc = c[i], a = alpha ? alpha[i] : 0.0;
-  const double re = c0 * c0 * (1.0 / (cc * cc) - a * a / (4.0 * PI * PI)) - 1.0;
+  // c0^2/c^2 - 1 as (c0 - c)(c0 + c)/c^2: no cancellation near the
+  // background, and exactly zero where c = c0
+  const double re = (c0 - cc) * (c0 + cc) / (cc * cc) - c0 * c0 * (a * a / (4.0 * PI * PI));
   const double im = c0 * c0 * a / (PI * cc);
   m64[i] = mk(re, im);
   if (m32) m32[i] = mk((float)re, (float)im);

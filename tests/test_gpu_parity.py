@@ -279,6 +279,43 @@ def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
     assert st["solves"] == (1 if recip else 2) * p.nf * p.ne
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("case", ["homogeneous", "single_rhs"])
+def test_degenerate_problems_vs_oracle(ctx, F, prec, case):
+    """Degenerate inputs of the method. A homogeneous medium (c = c0, no
+    attenuation) has zero contrast: the operator is the identity, the fields
+    are the incident fields and the scattered data vanish exactly (every term
+    of the data sum carries a factor m = 0). One element at one frequency is
+    a batch of one RHS for the forward and for the adjoint solve."""
+    if case == "homogeneous":
+        q = W.small2d(seed=57, nx=26, nz=22, ne=4, nf=2)
+        p = W.Problem("homogeneous_26x22", 2, q.nx, 1, q.nz, q.dx, q.c0, q.freqs, q.elems,
+                      np.full(q.shape, q.c0), np.zeros(q.shape))
+        d_obs = W.random_data(3, p.nf, p.ne, 1e-4)
+    else:
+        p = W.small2d(seed=58, nx=30, nz=25, ne=1, nf=1)
+        d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=8)
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    data, fields, st = ctx.forward(p, c, a, opts, fields=True)
+    assert st["unconverged"] == 0 and st["solves"] == p.nf * p.ne
+    rd, rf, _ = O.forward(p.c, p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert relerr(host(fields), rf) < 1e-10
+    if case == "homogeneous":
+        assert not bool(torch.any(data != 0)) and not np.any(rd)
+        cen = O.cell_centres(2, p.nx, 1, p.nz, p.dx)
+        for l, f in enumerate(p.freqs):
+            P0 = O.incident_fields(O.wavenumber(f, p.c0), cen, p.elems, 2)
+            assert relerr(host(fields[l]), P0) < 1e-12
+    else:
+        assert relerr(host(data), rd) < 1e-10
+    phi, gm, _, _, st = ctx.adjoint_gradient(p, c, a, dev(d_obs), opts)
+    rphi, rg, _, _, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert st["unconverged"] == 0
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert relerr(host(gm), rg) < 1e-9
+
+
 def test_jacobian_products_vs_oracle(ctx):
     p = W.small2d(seed=24, nx=20, nz=18, ne=4, nf=2)
     m = O.contrast(p.c, p.alpha, p.c0)
