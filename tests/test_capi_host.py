@@ -49,6 +49,13 @@ def test_validation_codes():
     assert fwi.validate_problem(_prob()) == fwi.FWI_OK
     assert fwi.validate_problem(_prob(dim=4)) == fwi.FWI_E_UNSUPPORTED
     assert fwi.validate_problem(_prob(nx=600)) == fwi.FWI_E_UNSUPPORTED
+    # largest grid extent the FFT lengths cover (2 x 512 = 1024), and one past it
+    assert fwi.validate_problem(_prob(nx=512, c=np.full((20, 512), 1540.0), alpha=np.zeros((20, 512)))) == fwi.FWI_OK
+    assert fwi.validate_problem(_prob(nz=513)) == fwi.FWI_E_UNSUPPORTED
+    # empty inputs: no frequency, no element, no cell
+    assert fwi.validate_problem(_prob(freqs=np.array([]))) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(elems=np.zeros((0, 3)))) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(nx=0)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(dx=-1.0)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(c0=float("nan"))) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(freqs=np.array([1e6, -1.0]))) == fwi.FWI_E_INVAL
