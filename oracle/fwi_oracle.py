@@ -339,6 +339,85 @@ def adjoint_gradient(c, alpha, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems):
 
 
 # --------------------------------------------------------------------------
+# Transmits other than the single elements (Sec. IV-B, Sec. V)
+# --------------------------------------------------------------------------
+
+def forward_tx_m(m, dim, nx, ny, nz, dx, c0, freqs, elems, weights):
+    """Fields and data of transmits synthesised from the elements (Sec. V fires
+    steered plane waves from the array; every element receives). Transmit t
+    at frequency l drives element e with the complex weight weights[l, t, e],
+    so its incident field is sum_e weights[l, t, e] P0_l[e] and its total field
+    p_{l,t} solves A_l p = that incident field (Eq. 5). Data [nf, nt, ne] by the
+    point-receiver rule of Eq. 4 (receivers are the elements)."""
+    cen = cell_centres(dim, nx, ny, nz, dx)
+    mf = m.reshape(-1)
+    data, fields, P0s = [], [], []
+    for l, f in enumerate(freqs):
+        k = wavenumber(f, c0)
+        P0 = incident_fields(k, cen, elems, dim)
+        p = solve(k, m, weights[l] @ P0, dim, nx, ny, nz, dx)
+        data.append(scattered_data(k, mf, P0, p, dx, dim))
+        fields.append(p)
+        P0s.append(P0)
+    return np.array(data), np.array(fields), np.array(P0s)
+
+
+def receiver_fields(m, dim, nx, ny, nz, dx, c0, freqs, elems):
+    """Fields p~_{l,j} of sources placed at the receivers (Sec. IV-B, the
+    adjoint fields of the Jacobian): with receivers = elements these are the
+    element fields, A_l^{-1} P0_l[j]."""
+    return forward_m(m, dim, nx, ny, nz, dx, c0, freqs, elems)[1]
+
+
+def jacobian_apply_tx(tx_fields, rx_fields, a_flat, freqs, c0, dx, dim):
+    """(J a)_{l,t,j} = k_l^2 dV sum_n p_{l,t}(x_n) p~_{l,j}(x_n) a_n: the
+    sensitivity of Sec. IV-B with transmit fields p and receiver fields p~
+    (midpoint rule over each cell)."""
+    dV = cell_volume(dim, dx)
+    out = []
+    for l, f in enumerate(freqs):
+        k = wavenumber(f, c0)
+        out.append(k**2 * dV * (tx_fields[l] * a_flat[None, :]) @ rx_fields[l].T)
+    return np.array(out)
+
+
+def jacobian_adjoint_apply_tx(tx_fields, rx_fields, b, freqs, c0, dx, dim):
+    """(J^H b)_n = sum_{l,t,j} conj(k_l^2 dV p_{l,t}(x_n) p~_{l,j}(x_n)) b_{l,t,j}."""
+    dV = cell_volume(dim, dx)
+    out = np.zeros(tx_fields.shape[-1], dtype=np.complex128)
+    for l, f in enumerate(freqs):
+        k = wavenumber(f, c0)
+        out += np.conj(k**2 * dV) * np.einsum("tn,jn,tj->n", np.conj(tx_fields[l]), np.conj(rx_fields[l]), b[l])
+    return out
+
+
+def adjoint_gradient_tx_m(m, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, weights, upstream=None):
+    """Misfit and gradient J^H r for synthesised transmits by adjoint solves:
+    adjoint sources s_{l,t} = sum_j conj(r_{l,t,j}) P0_l[j], adjoint fields
+    lam = A_l^{-1} s, g_n = dV sum_l conj(k_l^2) sum_t conj(p_{l,t}(x_n) lam_{l,t}(x_n))
+    (as for element transmits; only the transmit fields change)."""
+    mf = m.reshape(-1)
+    dV = cell_volume(dim, dx)
+    data, fields, P0s = forward_tx_m(m, dim, nx, ny, nz, dx, c0, freqs, elems, weights)
+    r = data - d_obs if upstream is None else upstream
+    phi = misfit(data, d_obs) if d_obs is not None else None
+    g = np.zeros(mf.shape, dtype=np.complex128)
+    for l, f in enumerate(freqs):
+        k = wavenumber(f, c0)
+        lam = solve(k, m, np.conj(r[l]) @ P0s[l], dim, nx, ny, nz, dx)
+        g += dV * np.conj(k**2) * np.sum(np.conj(fields[l] * lam), axis=0)
+    return phi, g, data, fields
+
+
+def adjoint_gradient_tx(c, alpha, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, weights):
+    """adjoint_gradient_tx_m at m(c, alpha) with the chain rule to c and alpha."""
+    m = contrast(c, alpha, c0)
+    phi, g, data, fields = adjoint_gradient_tx_m(m, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, weights)
+    dm_dc, dm_da = contrast_derivs(np.asarray(c).reshape(-1), np.asarray(alpha).reshape(-1), c0)
+    return phi, g, np.real(np.conj(g) * dm_dc), np.real(np.conj(g) * dm_da), data
+
+
+# --------------------------------------------------------------------------
 # TV operators and the ADMM step (Eq. 7-14, Algorithm 1)
 # --------------------------------------------------------------------------
 

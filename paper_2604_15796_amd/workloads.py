@@ -286,6 +286,20 @@ def small3d(seed=11, nx=12, ny=10, nz=9, ne=4, nf=1, dx=0.2e-3, f_lo=0.8e6, f_hi
     return p
 
 
+def plane_wave_weights(freqs, elems, angles_deg, c0=C0):
+    """Transmit weights [nf, nt, ne] of plane waves steered to the given angles
+    (from the depth axis) by the element array (Sec. V synthesises its
+    transmissions this way; the paper gives no formula). Reading: element e
+    fires with delay (x_e - x_mid) sin(theta) / c0, which under the
+    exp(-i omega t) convention is the complex weight exp(i k (x_e - x_mid) sin(theta)),
+    k = 2 pi f / c0; unit amplitudes."""
+    x = np.asarray(elems, dtype=np.float64)[:, 0]
+    x = x - 0.5 * (x.min() + x.max())
+    th = np.deg2rad(np.asarray(angles_deg, dtype=np.float64))
+    k = 2.0 * math.pi * np.asarray(freqs, dtype=np.float64) / c0
+    return np.exp(1j * k[:, None, None] * np.sin(th)[None, :, None] * x[None, None, :])
+
+
 def random_data(seed, nf, ne, scale=1.0):
     """Seeded complex data array [nf][ne][ne] (stand-in for measured data)."""
     rng = np.random.default_rng(seed)
