@@ -193,6 +193,29 @@ int fwi_tv_admm_step(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_param
                      void* g_inout, void* u_inout, const void* m_ref, const void* d_obs,
                      const fwi_solve_opts* opts, fwi_admm_report* report, fwi_stats* stats);
 
+/* ------------------------------------------------ synthesised transmits */
+/* Transmits other than single elements (Sec. V fires steered plane waves from
+ * the array; every element still receives). Transmit t at frequency l drives
+ * element e with the complex weight w[l][t][e], so its incident field is
+ * sum_e w[l][t][e] p0_le and its total field solves A_l p = that field
+ * (Eq. 5). tx_weights: device [nf][nt][ne] complex128, 1 <= nt <= ne (else
+ * FWI_E_INVAL; non-finite weights give FWI_E_NONFINITE). data_out
+ * [nf][nt][ne] complex128 (Eq. 4, receivers = elements); fields_out NULL or
+ * [nf][nt][n] complex128. Workspace as for fwi_adjoint_gradient. */
+int fwi_forward_tx(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha, int nt,
+                   const void* tx_weights, const fwi_solve_opts* opts, void* data_out, void* fields_out,
+                   fwi_stats* stats);
+
+/* Misfit and gradient for synthesised transmits by adjoint solves: adjoint
+ * sources sum_j conj(r_ltj) p0_lj with r = F - d_obs [nf][nt][ne], adjoint
+ * fields by the same operator, g as in fwi_adjoint_gradient with the
+ * transmit fields. opts->reciprocity_adjoint must be 0 (the transmit fields
+ * are not the receiver fields): else FWI_E_UNSUPPORTED. */
+int fwi_adjoint_gradient_tx(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha, int nt,
+                            const void* tx_weights, const void* d_obs, const fwi_solve_opts* opts,
+                            double* misfit_out, void* grad_m_out, double* grad_c_out, double* grad_alpha_out,
+                            fwi_stats* stats);
+
 /* ---------------------------------------------------------- uneven batches */
 /* Many independent problems (grids, element counts and frequency counts may
  * all differ) solved together. One refinement cycle of every instance of a
@@ -246,6 +269,17 @@ int fwi_fft_padded(fwi_ctx* ctx, const fwi_problem* prob, int precision, const v
 int fwi_jacobian_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields, const void* a, void* out_data);
 int fwi_jacobian_adjoint_apply(fwi_ctx* ctx, const fwi_problem* prob, const void* fields, const void* b,
                                void* out_m);
+/* The same products with separate transmit fields and receiver fields (the
+ * sensitivity of Sec. IV-B): (J a)_{l,t,j} = k_l^2 dV sum_n p_lt(x_n)
+ * p~_lj(x_n) a_n, and its adjoint. tx_fields [nf][nt][n] (e.g. fields_out of
+ * fwi_forward_tx), rx_fields [nf][ne][n] (sources at the receivers: fields_out
+ * of fwi_forward, which a caller may keep over several model updates, the
+ * Born reuse of Sec. IV-B), a [n], out_data [nf][nt][ne], b [nf][nt][ne],
+ * out [n]: complex128; 1 <= nt <= ne. */
+int fwi_jacobian_apply_tx(fwi_ctx* ctx, const fwi_problem* prob, int nt, const void* tx_fields,
+                          const void* rx_fields, const void* a, void* out_data);
+int fwi_jacobian_adjoint_apply_tx(fwi_ctx* ctx, const fwi_problem* prob, int nt, const void* tx_fields,
+                                  const void* rx_fields, const void* b, void* out);
 
 /* ----------------------------------------------------------- measurement */
 /* Kernel classes: 0 row forward FFT pass, 1 Green convolution pass (forward

@@ -718,6 +718,7 @@ struct CallBufs {
   c128* gacc = nullptr;     // [n]
   double* misfits = nullptr;  // [ngroups]
   int* rfreq = nullptr;     // [B]
+  c128* wtx = nullptr;      // [nf][nt][ne] conjugated transmit weights (nt <= ne; gradient plans)
   // ADMM
   c128 *cg_x = nullptr, *cg_r = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *vec = nullptr;
   c128 *gm = nullptr, *tmpd = nullptr, *Jp = nullptr;
@@ -758,6 +759,7 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
     cb.S = a.take<c128>((size_t)B * n);
     cb.lam = a.take<c128>((size_t)B * n);
   }
+  if (entry == FWI_ENTRY_GRADIENT) cb.wtx = a.take<c128>(ndata);
   if (entry == FWI_ENTRY_ADMM) {
     cb.cg_x = a.take<c128>(n);
     cb.cg_r = a.take<c128>(n);
@@ -793,19 +795,76 @@ struct Runner {
     launch_zero_u64(2, c->d_itstat, c->stream);  // this call's iteration statistics
   }
 
-  // Solve the forward problem for frequencies [l0, l0+nf) into `fields`.
+  // Solve the forward problem for frequencies [l0, l0+nf) into `fields`:
+  // `per` RHS per frequency (the elements, or nt synthesised transmits).
   template <typename T>
-  void solve_rhs(SolveBufs<T>& sb, int l0, int nf, const c128* rhs, c128* out) {
+  void solve_rhs(SolveBufs<T>& sb, int l0, int nf, const c128* rhs, c128* out, int per = 0) {
     const ProblemCache& pc = c->pc;
-    const int B = nf * p->ne;
+    const int B = nf * (per > 0 ? per : p->ne);
     const cplx<T>* mT = std::is_same<T, float>::value ? (const cplx<T>*)cb.m32 : (const cplx<T>*)cb.m64;
     const cplx<T>* gT = std::is_same<T, float>::value ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
+    const int* rf = pc.rhs_freq + (long)l0 * p->ne;
+    if (per > 0) {
+      launch_fill_rfreq(B, per, l0, cb.rfreq, c->stream);
+      rf = cb.rfreq;
+    }
     // a short batch reuses the planned buffers with a smaller B
     SolveBufs<T> s = sb;
     s.ks.B = B;
-    SolveTotals r =
-        run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, pc.rhs_freq + (long)l0 * p->ne, out, o, s, nf);
+    SolveTotals r = run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, rf, out, o, s, nf);
     tot.merge(r);
+  }
+
+  // Transmits synthesised from the elements (Sec. V: steered plane waves;
+  // every element receives): transmit t of frequency l drives element e with
+  // weight w[l][t][e], so its incident field is sum_e w P0_l[e] and, the
+  // problem being linear, its total field solves A_l p = that field. cb.wtx
+  // holds conj(w) (the NN product conjugates its left operand). Data
+  // [nf][nt][ne] by the point-receiver rule of Eq. 4.
+  template <typename T>
+  void forward_tx(SolveBufs<T>& sb, int nt, c128* data_out, c128* fields_out) {
+    const ProblemCache& pc = c->pc;
+    hipStream_t st = c->stream;
+    const long nd = (long)nt * p->ne;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
+      const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
+      c128* F = fields_out ? fields_out + (long)l0 * nt * n : cb.fields;
+      launch_gemm_cn(nf, cb.wtx + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
+      solve_rhs<T>(sb, l0, nf, cb.S, F, nt);
+      launch_gemm_nt(nf, F, (long)nt * n, nt, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0, cb.gpart,
+                     gemm_splits(n), data_out + l0 * nd, st);
+    }
+  }
+
+  // misfit and J^H r for synthesised transmits by adjoint solves: adjoint
+  // sources sum_j conj(r_tj) P0_j (the receivers are the elements), adjoint
+  // fields by the same operator, g as for element transmits.
+  template <typename T>
+  double gradient_tx(SolveBufs<T>& sb, int nt, const c128* dobs, c128* data_out, const double* cc,
+                     const double* alpha, c128* gm_out, double* gc, double* ga) {
+    const ProblemCache& pc = c->pc;
+    hipStream_t st = c->stream;
+    const long nd = (long)nt * p->ne;
+    for (int gi = 0; gi < ngroups; ++gi) {
+      const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
+      const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
+      launch_gemm_cn(nf, cb.wtx + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
+      solve_rhs<T>(sb, l0, nf, cb.S, cb.fields, nt);
+      launch_gemm_nt(nf, cb.fields, (long)nt * n, nt, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0,
+                     cb.gpart, gemm_splits(n), data_out + l0 * nd, st);
+      launch_residual(nf * nd, data_out + l0 * nd, dobs + l0 * nd, cb.r + l0 * nd, cb.misfits + gi, st);
+      launch_gemm_cn(nf, cb.r + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
+      solve_rhs<T>(sb, l0, nf, cb.S, cb.lam, nt);
+      launch_gradient_accum(n, nf, nt, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
+    }
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, cc, alpha, gm_out, gc, ga, st);
+    std::vector<double> mf(ngroups);
+    FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * ngroups, hipMemcpyDeviceToHost, st));
+    FWI_HIP(hipStreamSynchronize(st));
+    double phi = 0.0;
+    for (double v : mf) phi += v;
+    return phi;
   }
 
   template <typename T>
@@ -1017,6 +1076,57 @@ int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doub
   const double phi = R.gradient<T>(sb, (const c128*)dobs, (const c128*)upstream, R.cb.data, cc, alpha,
                                    (c128*)grad_m_out, gc, ga);
   FWI_HIP(hipStreamSynchronize(c->stream));
+  if (misfit_out) *misfit_out = phi;
+  collect_iters(c, R.tot);
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+  return finish_rc(R.tot);
+}
+
+// Synthesised transmits: nt in [1, ne] transmits per frequency with weights
+// w [nf][nt][ne] (device); planned as the gradient entry (adjoint-source
+// buffer for the synthesised incident fields, room for the weights).
+template <typename T>
+void prepare_tx(fwi_ctx* c, Runner& R, SolveBufs<T>& sb, int nt, const void* w, const double* cc,
+                const double* alpha) {
+  if (!cc || !w) throw Error(FWI_E_INVAL, "NULL array argument");
+  if (nt < 1 || nt > R.p->ne) throw Error(FWI_E_INVAL, "need 1 <= nt <= ne synthesised transmits");
+  prepare<T>(c, R, sb, FWI_ENTRY_GRADIENT);
+  const long nw = (long)R.p->nf * nt * R.p->ne;
+  check_complex(c, nw, (const c128*)w, "transmit weights");
+  launch_conj_c128(nw, (const c128*)w, R.cb.wtx, c->stream);
+  const double ts = now_ms();
+  check_sos(c, R.n, cc, alpha);
+  launch_contrast(R.n, R.p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+  R.t_setup += now_ms() - ts;
+}
+
+template <typename T>
+int forward_tx_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, int nt, const void* w,
+                    const fwi_solve_opts* opts, void* data_out, void* fields_out, fwi_stats* stats) {
+  const double t0 = now_ms();
+  if (!data_out) throw Error(FWI_E_INVAL, "NULL array argument");
+  Runner R(c, p, *opts);
+  SolveBufs<T> sb;
+  prepare_tx<T>(c, R, sb, nt, w, cc, alpha);
+  R.forward_tx<T>(sb, nt, (c128*)data_out, (c128*)fields_out);
+  FWI_HIP(hipStreamSynchronize(c->stream));
+  collect_iters(c, R.tot);
+  fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
+  return finish_rc(R.tot);
+}
+
+template <typename T>
+int gradient_tx_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, int nt, const void* w,
+                     const void* dobs, const fwi_solve_opts* opts, double* misfit_out, void* grad_m_out, double* gc,
+                     double* ga, fwi_stats* stats) {
+  const double t0 = now_ms();
+  if (!dobs) throw Error(FWI_E_INVAL, "NULL array argument");
+  if (opts->reciprocity_adjoint)
+    throw Error(FWI_E_UNSUPPORTED, "reciprocity adjoint needs transmit set = receive set");
+  Runner R(c, p, *opts);
+  SolveBufs<T> sb;
+  prepare_tx<T>(c, R, sb, nt, w, cc, alpha);
+  const double phi = R.gradient_tx<T>(sb, nt, (const c128*)dobs, R.cb.data, cc, alpha, (c128*)grad_m_out, gc, ga);
   if (misfit_out) *misfit_out = phi;
   collect_iters(c, R.tot);
   fill_stats(stats, R.tot, R.t_setup, now_ms() - t0);
@@ -1610,6 +1720,29 @@ int fwi_adjoint_gradient(fwi_ctx* c, const fwi_problem* p, const double* cc, con
   });
 }
 
+int fwi_forward_tx(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, int nt,
+                   const void* tx_weights, const fwi_solve_opts* o, void* data_out, void* fields_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? forward_tx_impl<float>(c, p, cc, alpha, nt, tx_weights, o, data_out, fields_out, stats)
+               : forward_tx_impl<double>(c, p, cc, alpha, nt, tx_weights, o, data_out, fields_out, stats);
+  });
+}
+
+int fwi_adjoint_gradient_tx(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, int nt,
+                            const void* tx_weights, const void* dobs, const fwi_solve_opts* o, double* misfit_out,
+                            void* grad_m_out, double* gc, double* ga, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? gradient_tx_impl<float>(c, p, cc, alpha, nt, tx_weights, dobs, o, misfit_out, grad_m_out, gc, ga,
+                                         stats)
+               : gradient_tx_impl<double>(c, p, cc, alpha, nt, tx_weights, dobs, o, misfit_out, grad_m_out, gc, ga,
+                                          stats);
+  });
+}
+
 int fwi_vjp(fwi_ctx* c, const fwi_problem* p, const void* m, const void* grad_data, const fwi_solve_opts* o,
             void* grad_m_out, fwi_stats* stats) {
   return guarded(c, [&] {
@@ -1801,6 +1934,69 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* c, const fwi_problem* p, const void* fie
     plan(ar, cb);
     jh_apply(c, p, g, cb, p->nf, (const c128*)fields, (const c128*)b, (c128*)out);
     FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+// Jacobian products with separate transmit fields [nf][nt][n] and receiver
+// fields [nf][ne][n] (Sec. IV-B): (J a)_{l,t,j} = k_l^2 dV sum_n p_t p~_j a_n,
+// J^H b = dV sum_l conj(k_l^2) sum_t conj(p_t) conj(sum_j conj(b_tj) p~_j).
+static void check_tx_fields(const fwi_problem* p, int nt, const void* tx, const void* rx, const void* v,
+                            const void* out) {
+  if (!tx || !rx || !v || !out) throw Error(FWI_E_INVAL, "bad arguments");
+  if (nt < 1 || nt > p->ne) throw Error(FWI_E_INVAL, "need 1 <= nt <= ne transmits");
+}
+
+int fwi_jacobian_apply_tx(fwi_ctx* c, const fwi_problem* p, int nt, const void* tx_fields, const void* rx_fields,
+                          const void* a, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    check_tx_fields(p, nt, tx_fields, rx_fields, a, out);
+    ensure_cache(c, p);
+    const long n = make_geo(p).n();
+    const size_t part = (size_t)gemm_splits(n) * p->nf * nt * p->ne;
+    Arena dry;
+    dry.take<c128>(part);
+    Arena ar;
+    bind_workspace(c, ar, dry.used);
+    c128* gpart = ar.take<c128>(part);
+    launch_gemm_nt(p->nf, (const c128*)tx_fields, (long)nt * n, nt, (const c128*)a, (const c128*)rx_fields,
+                   (long)p->ne * n, p->ne, n, c->pc.coef, gpart, gemm_splits(n), (c128*)out, c->stream);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
+  });
+}
+
+int fwi_jacobian_adjoint_apply_tx(fwi_ctx* c, const fwi_problem* p, int nt, const void* tx_fields,
+                                  const void* rx_fields, const void* b, void* out) {
+  return guarded(c, [&] {
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    check_tx_fields(p, nt, tx_fields, rx_fields, b, out);
+    ensure_cache(c, p);
+    const Geo g = make_geo(p);
+    const long n = g.n();
+    auto plan = [&](Arena& ar, CallBufs& cb) {
+      cb.lam = ar.take<c128>((size_t)p->nf * nt * n);
+      cb.gpart = ar.take<c128>((size_t)kGradSeg * n);
+      cb.gacc = ar.take<c128>(n);
+    };
+    Arena dry;
+    CallBufs d;
+    plan(dry, d);
+    Arena ar;
+    bind_workspace(c, ar, dry.used);
+    CallBufs cb;
+    plan(ar, cb);
+    hipStream_t st = c->stream;
+    launch_gemm_cn(p->nf, (const c128*)b, nt, p->ne, (const c128*)rx_fields, (long)p->ne * n, n, cb.lam,
+                   (long)nt * n, st);
+    launch_gradient_accum(n, p->nf, nt, (const c128*)tx_fields, cb.lam, c->pc.k2, cb.gpart, kGradSeg, 1, cb.gacc, st);
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, nullptr, nullptr, (c128*)out, nullptr, nullptr, st);
+    FWI_HIP(hipStreamSynchronize(st));
     return FWI_OK;
   });
 }

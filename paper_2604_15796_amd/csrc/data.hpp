@@ -31,5 +31,7 @@ void launch_sum(int nb, const double* part, double* out, hipStream_t st);
 void launch_cg_step1(long n, const double* sc, c128* x, c128* r, const c128* p, const c128* Ap, hipStream_t st);
 void launch_cg_step2(long n, const double* sc, const c128* r, c128* p, hipStream_t st);
 void launch_copy_scalar(const double* in, double* out, hipStream_t st);
+void launch_conj_c128(long count, const c128* in, c128* out, hipStream_t st);
+void launch_fill_rfreq(int B, int per, int l0, int* rf, hipStream_t st);
 
 }  // namespace fwi

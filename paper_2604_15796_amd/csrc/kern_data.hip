@@ -506,4 +506,27 @@ void launch_copy_scalar(const double* in, double* out, hipStream_t st) {
   FWI_LAUNCH_CHECK();
 }
 
+// out[i] = conj(in[i]) (transmit weights into the form the NN product takes)
+__global__ void k_conj_c128(long count, const c128* __restrict__ in, c128* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = conj(in[i]);
+}
+void launch_conj_c128(long count, const c128* in, c128* out, hipStream_t st) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_conj_c128, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, in, out);
+  FWI_LAUNCH_CHECK();
+}
+
+// rf[b] = l0 + b / per: frequency index of RHS b of a batch that holds `per`
+// RHS per frequency, frequency-major
+__global__ void k_fill_rfreq(int B, int per, int l0, int* __restrict__ rf) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) rf[b] = l0 + b / per;
+}
+void launch_fill_rfreq(int B, int per, int l0, int* rf, hipStream_t st) {
+  if (B == 0) return;
+  hipLaunchKernelGGL(k_fill_rfreq, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, B, per, l0, rf);
+  FWI_LAUNCH_CHECK();
+}
+
 }  // namespace fwi

@@ -108,6 +108,10 @@ def lib():
         "fwi_fft_padded": (ip, [vp, pp, ip, vp, vp]),
         "fwi_jacobian_apply": (ip, [vp, pp, vp, vp, vp]),
         "fwi_jacobian_adjoint_apply": (ip, [vp, pp, vp, vp, vp]),
+        "fwi_forward_tx": (ip, [vp, pp, vp, vp, ip, vp, op, vp, vp, sp]),
+        "fwi_adjoint_gradient_tx": (ip, [vp, pp, vp, vp, ip, vp, vp, op, dp, vp, vp, vp, sp]),
+        "fwi_jacobian_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
+        "fwi_jacobian_adjoint_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
         "fwi_host_bessel01": (None, [C.c_double, dp]),
         "fwi_profile": (ip, [vp, C.c_uint]),
         "fwi_profile_read": (ip, [vp, ip, dp, C.POINTER(C.c_longlong), dp]),
@@ -133,7 +137,8 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
-            "fwi_forward_batch", "fwi_set_addressing"]
+            "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
+            "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -312,6 +317,77 @@ class Context:
                                          C.byref(phi), _ptr(gm), _ptr(gc), _ptr(ga), C.byref(st))
         self._check(rc, allow_noconv)
         return phi.value, gm, gc, ga, st.as_dict()
+
+    # ------------------------------------------- synthesised transmits ---
+    def _tx_weights(self, prob, w):
+        if w.dtype != torch.complex128 or w.dim() != 3 or w.shape[0] != prob.nf or w.shape[2] != prob.ne:
+            raise ValueError(f"tx_weights: expected complex128 [nf={prob.nf}, nt, ne={prob.ne}], "
+                             f"got {w.dtype} {tuple(w.shape)}")
+        if not w.is_contiguous():
+            raise ValueError("tx_weights must be contiguous")
+        return int(w.shape[1])
+
+    def forward_tx(self, prob, c, alpha, w, opts=None, fields=False, allow_noconv=False):
+        """Data [nf, nt, ne] (and fields [nf, nt, n]) of transmits with element
+        weights w [nf, nt, ne] (complex128, device)."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(c, torch.float64, prob.shape, "c")
+        nt = self._tx_weights(prob, w)
+        data = torch.empty((prob.nf, nt, prob.ne), dtype=torch.complex128, device=self.device)
+        F = torch.empty((prob.nf, nt, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_GRADIENT)
+        rc = self.L.fwi_forward_tx(self.h, prob.ref(), _ptr(c), _ptr(alpha), nt, _ptr(w), C.byref(o), _ptr(data),
+                                   _ptr(F), C.byref(st))
+        self._check(rc, allow_noconv)
+        return (data, F, st.as_dict()) if fields else (data, st.as_dict())
+
+    def adjoint_gradient_tx(self, prob, c, alpha, w, d_obs, opts=None, allow_noconv=False):
+        """(misfit, grad_m [n] complex, grad_c [n], grad_alpha [n], stats) for
+        transmits with element weights w [nf, nt, ne]; d_obs [nf, nt, ne]."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(c, torch.float64, prob.shape, "c")
+        nt = self._tx_weights(prob, w)
+        _check_dtype(d_obs, torch.complex128, (prob.nf, nt, prob.ne), "d_obs")
+        gm = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        gc = torch.empty(prob.n, dtype=torch.float64, device=self.device)
+        ga = torch.empty(prob.n, dtype=torch.float64, device=self.device)
+        phi = C.c_double()
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_GRADIENT)
+        rc = self.L.fwi_adjoint_gradient_tx(self.h, prob.ref(), _ptr(c), _ptr(alpha), nt, _ptr(w), _ptr(d_obs),
+                                            C.byref(o), C.byref(phi), _ptr(gm), _ptr(gc), _ptr(ga), C.byref(st))
+        self._check(rc, allow_noconv)
+        return phi.value, gm, gc, ga, st.as_dict()
+
+    def jacobian_apply_tx(self, prob, tx_fields, rx_fields, a):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        nt = int(tx_fields.shape[1])
+        _check_dtype(tx_fields, torch.complex128, (prob.nf, nt, prob.n), "tx_fields")
+        _check_dtype(rx_fields, torch.complex128, (prob.nf, prob.ne, prob.n), "rx_fields")
+        out = torch.empty((prob.nf, nt, prob.ne), dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_jacobian_apply_tx(self.h, prob.ref(), nt, _ptr(tx_fields), _ptr(rx_fields), _ptr(a),
+                                                 _ptr(out)))
+        return out
+
+    def jacobian_adjoint_apply_tx(self, prob, tx_fields, rx_fields, b):
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        nt = int(tx_fields.shape[1])
+        _check_dtype(tx_fields, torch.complex128, (prob.nf, nt, prob.n), "tx_fields")
+        _check_dtype(rx_fields, torch.complex128, (prob.nf, prob.ne, prob.n), "rx_fields")
+        _check_dtype(b, torch.complex128, (prob.nf, nt, prob.ne), "b")
+        out = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_jacobian_adjoint_apply_tx(self.h, prob.ref(), nt, _ptr(tx_fields), _ptr(rx_fields),
+                                                         _ptr(b), _ptr(out)))
+        return out
 
     def vjp(self, prob, m, grad_data, opts=None, allow_noconv=False):
         prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)

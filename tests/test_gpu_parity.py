@@ -316,6 +316,63 @@ def test_degenerate_problems_vs_oracle(ctx, F, prec, case):
     assert relerr(host(gm), rg) < 1e-9
 
 
+@pytest.mark.parametrize("prec,angles,max_rhs", [
+    (0, [-25.0, 0.0, 15.0, 40.0], 0),
+    (1, [-25.0, 0.0, 15.0, 40.0], 0),
+    (1, [10.0], 0),                                        # one transmit
+    (0, [-50.0, -30.0, -10.0, 10.0, 30.0, 50.0], 6),       # as many transmits as elements, one frequency per solve
+])
+def test_synthesised_transmits_vs_oracle(ctx, F, prec, angles, max_rhs):
+    """Plane-wave transmits synthesised from the elements (weights
+    [nf, nt, ne]): fields, data, misfit and gradient by adjoint solves, and
+    the Jacobian products with separate receiver fields, against the oracle."""
+    p = W.small2d(seed=59, nx=30, nz=26, ne=6, nf=2)
+    nt = len(angles)
+    w = W.plane_wave_weights(p.freqs, p.elems, angles, p.c0)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16, max_rhs=max_rhs)
+    c, a, wd = dev(p.c, torch.float64), dev(p.alpha, torch.float64), dev(w)
+    data, fields, st = ctx.forward_tx(p, c, a, wd, opts, fields=True)
+    rd, rf, _ = O.forward_tx_m(m, *args, w)
+    assert st["unconverged"] == 0 and st["solves"] == p.nf * nt
+    assert relerr(host(fields), rf) < 1e-10
+    assert relerr(host(data), rd) < 1e-10
+    d_obs = O.forward_tx_m(O.contrast(p.extra["c_obs"], p.alpha, p.c0), *args, w)[0]
+    phi, gm, gc, ga, st = ctx.adjoint_gradient_tx(p, c, a, wd, dev(d_obs), opts)
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient_tx(p.c, p.alpha, d_obs, *args, w)
+    assert st["unconverged"] == 0 and st["solves"] == 2 * p.nf * nt
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert relerr(host(gm), rg) < 1e-9
+    assert relerr(host(gc), rgc) < 1e-9 and relerr(host(ga), rga) < 1e-9
+    _, rx, _ = ctx.forward(p, c, a, opts, fields=True)
+    rx_or = O.receiver_fields(m, *args)
+    av = W.random_complex(9, p.n)
+    b = W.random_complex(10, (p.nf, nt, p.ne))
+    Ja = ctx.jacobian_apply_tx(p, fields, rx, dev(av))
+    assert relerr(host(Ja), O.jacobian_apply_tx(rf, rx_or, av, p.freqs, p.c0, p.dx, 2)) < 1e-9
+    JHb = ctx.jacobian_adjoint_apply_tx(p, fields, rx, dev(b))
+    assert relerr(host(JHb), O.jacobian_adjoint_apply_tx(rf, rx_or, b, p.freqs, p.c0, p.dx, 2)) < 1e-9
+
+
+def test_synthesised_transmit_argument_errors(ctx, F):
+    p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    too_many = dev(W.plane_wave_weights(p.freqs, p.elems, [-20.0, -10.0, 0.0, 10.0], p.c0))
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward_tx(p, c, a, too_many)
+    assert e.value.code == F.FWI_E_INVAL
+    w = W.plane_wave_weights(p.freqs, p.elems, [0.0, 10.0], p.c0)
+    d_obs = dev(np.zeros((1, 2, 3), complex))
+    with pytest.raises(F.FWIError) as e:
+        ctx.adjoint_gradient_tx(p, c, a, dev(w), d_obs, F.SolveOptions(reciprocity_adjoint=1))
+    assert e.value.code == F.FWI_E_UNSUPPORTED
+    w[0, 1, 2] = np.nan
+    with pytest.raises(F.FWIError) as e:
+        ctx.forward_tx(p, c, a, dev(w))
+    assert e.value.code == F.FWI_E_NONFINITE
+
+
 def test_jacobian_products_vs_oracle(ctx):
     p = W.small2d(seed=24, nx=20, nz=18, ne=4, nf=2)
     m = O.contrast(p.c, p.alpha, p.c0)
