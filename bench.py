@@ -63,9 +63,11 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile variants")
     ap.add_argument("--cpu-solves", type=int, default=8,
                     help="oracle forward (and adjoint) solves per frequency in the CPU sample")
-    ap.add_argument("--workload", default="gradient-256", choices=["gradient-256", "uneven-batch"],
-                    help="gradient-256: the headline workload; uneven-batch: 32 instances of different grids, "
-                         "element and frequency counts through the graph-replayed batched path")
+    ap.add_argument("--workload", default="gradient-256", choices=["gradient-256", "planewave-256", "uneven-batch"],
+                    help="gradient-256: the headline workload; planewave-256: the same grid, frequencies and "
+                         "array firing 60 steered plane waves (-60..60 degrees) instead of single elements; "
+                         "uneven-batch: 32 instances of different grids, element and frequency counts through "
+                         "the graph-replayed batched path")
     ap.add_argument("--tuning", default=None,
                     help="hex tuning table (as printed in tuning_hex) to use instead of autotuning")
     ap.add_argument("--counter-sample", action="store_true",
@@ -99,8 +101,15 @@ def main():
     a = torch.as_tensor(p.alpha).to(dev)
     c_obs = torch.as_tensor(p.extra["c_obs"]).to(dev)
     ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32)
+    planewave = args.workload == "planewave-256"
+    # plane-wave transmits: unit-amplitude steering weights [nf, nt, ne]
+    w_tx = torch.as_tensor(W.plane_wave_weights(p.freqs, p.elems, np.linspace(-60.0, 60.0, 60), p.c0)).to(dev) \
+        if planewave else None
     log("setup: observed data from the perturbed model (FP64, untimed)")
-    d_obs, st0 = ctx.forward(prob, c_obs, a, ref_opts)
+    if planewave:
+        d_obs, st0 = ctx.forward_tx(prob, c_obs, a, w_tx, ref_opts)
+    else:
+        d_obs, st0 = ctx.forward(prob, c_obs, a, ref_opts)
     log(f"setup done: cache {st0['t_setup_ms']:.1f} ms, {st0['iterations']} its")
 
     # autotune the FFT-pass tiles for this grid (untimed set-up), then time one
@@ -118,10 +127,18 @@ def main():
                              inner_rtol=args.inner_rtol, check_every=args.check_every, max_rhs=args.max_rhs)
     plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=args.restart,
                              check_every=args.check_every, max_rhs=args.max_rhs)
-    solves_per_step = 2 * p.nf * p.ne
+    nt = w_tx.shape[1] if planewave else p.ne
+    solves_per_step = 2 * p.nf * nt
 
     def step(opts):
+        if planewave:
+            return ctx.adjoint_gradient_tx(prob, c, a, w_tx, d_obs, opts)
         return ctx.adjoint_gradient(prob, c, a, d_obs, opts)
+
+    def fields_of(opts):
+        if planewave:
+            return ctx.forward_tx(prob, c, a, w_tx, opts, fields=True)[1]
+        return ctx.forward(prob, c, a, opts, fields=True)[1]
 
     if args.counter_sample:
         step(mixed)
@@ -169,13 +186,17 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = solves_per_step / (ms_step * 1e-3)
     log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
-    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof)
+    # counter figures were taken on the element-transmit workload only
+    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not planewave)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
-           "config": {"workload": "2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
-                                  "forward+adjoint gradient (512+512 solves)",
+           "config": {"workload": ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements firing 60 plane "
+                                   "waves -60..60 deg: forward+adjoint gradient (480+480 solves)") if planewave else
+                                  ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
+                                   "forward+adjoint gradient (512+512 solves)"),
+                      "transmits_per_freq": int(nt),
                       "grid": [p.nz, p.nx], "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
                       "precision": "complex64 GMRES in FP64-residual refinement",
                       "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
@@ -188,13 +209,13 @@ def main():
 
     # accuracy of the timed form against the plain FP64 solve (full size)
     if not args.no_fp64:
-        _, F32, _ = ctx.forward(prob, c, a, mixed, fields=True)
-        _, F64, _ = ctx.forward(prob, c, a, ref_opts, fields=True)
+        F32 = fields_of(mixed)
+        F64 = fields_of(ref_opts)
         ferr = torch.linalg.vector_norm(F32 - F64, dim=2) / torch.linalg.vector_norm(F64, dim=2)
         field_err = float(ferr.max())
         del F32, F64
         _, g32, _, _, _ = step(mixed)
-        _, g64, _, _, _ = ctx.adjoint_gradient(prob, c, a, d_obs, ref_opts)
+        _, g64, _, _, _ = step(ref_opts)
         grad_err = float(torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64))
         torch.cuda.synchronize()
         tp0 = time.perf_counter()
@@ -211,6 +232,8 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
+        if planewave:
+            out["cpu_baseline"]["sample"] += " (element sources: same operators and per-solve cost)"
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -225,7 +248,7 @@ def strided_tile(L, es, v):
     return nl, (512 if v == 2 else 256)
 
 
-def roofline_entry(fwi, ctx, prob, p, dominant, prof):
+def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True):
     """Roofline of the dominant kernel class over the timed launches.
 
     The 2D convolution pass (forward FFT, spectrum product, inverse FFT along
@@ -256,7 +279,7 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof):
         rhs = (prof["bytes"] - launches * gbytes) / per_rhs_bytes
         flops = rhs * per_rhs_flops
         tf = flops / sec / 1e12
-        m = MEASURED.get(name, {})
+        m = MEASURED.get(name, {}) if measured else {}
         entry.update({"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
                       "peak_unpacked_fp32": FP32_UNPACKED_PEAK_TFLOPS,
@@ -265,7 +288,7 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof):
                       "traffic": m.get("traffic"), "valu_busy": m.get("valu_busy"), "hbm": hbm})
     else:
         name = hbm_kernel_name(ctx, prob, dominant)
-        m = MEASURED.get(name, {}) if name else {}
+        m = MEASURED.get(name, {}) if name and measured else {}
         entry.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "kernel_name": name,
                       "traffic": m.get("traffic")})
