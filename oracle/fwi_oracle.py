@@ -533,3 +533,43 @@ def admm_step(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems,
     report = dict(misfit=misfit(data, d_obs), tv=tv_norm(gm_new),
                   dm_norm=float(np.linalg.norm(dm)))
     return m_new, g_new, u_new, report
+
+
+def admm_step_tx(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, weights,
+                 lam, rho, gamma, n_cg, rx_fields=None, data_scale=1.0, dual_step=None):
+    """admm_step for synthesised transmits (weights [nf, nt, ne], d_obs
+    [nf, nt, ne]): the Jacobian of Sec. IV-B from the transmit fields at m_k
+    and the receiver fields p~. rx_fields None: p~ recomputed at m_k (the
+    distorted-Born Jacobian); given: used as they are (the paper's Born reuse
+    of receiver fields from an earlier iterate). Returns (m, g, u, report,
+    receiver fields used)."""
+    if dual_step is None:
+        dual_step = rho
+    shape = grid_shape(dim, nx, ny, nz)
+    m = m.reshape(shape)
+    data, fields, _ = forward_tx_m(m, dim, nx, ny, nz, dx, c0, freqs, elems, weights)
+    rx = receiver_fields(m, dim, nx, ny, nz, dx, c0, freqs, elems) if rx_fields is None else rx_fields
+    r = d_obs - data
+    gm = tv_grad(m)
+    b = data_scale * jacobian_adjoint_apply_tx(fields, rx, r, freqs, c0, dx, dim).reshape(shape)
+    b = b + rho * tv_grad_T(g + u - gm)
+    use_ref = m_ref is not None and gamma != 0.0
+    if use_ref:
+        b = b + gamma * (m_ref.reshape(shape) - m)
+
+    def apply_A(a):
+        a = a.reshape(shape)
+        Ja = jacobian_apply_tx(fields, rx, a.reshape(-1), freqs, c0, dx, dim)
+        out = data_scale * jacobian_adjoint_apply_tx(fields, rx, Ja, freqs, c0, dx, dim).reshape(shape)
+        out = out + rho * tv_grad_T(tv_grad(a))
+        if use_ref:
+            out = out + gamma * a
+        return out
+
+    dm = conjugate_gradient(apply_A, b, n_cg)
+    m_new = m + dm
+    gm_new = tv_grad(m_new)
+    g_new = shrink(gm_new - u, lam / rho)
+    u_new = u + dual_step * (g_new - gm_new)
+    report = dict(misfit=misfit(data, d_obs), tv=tv_norm(gm_new), dm_norm=float(np.linalg.norm(dm)))
+    return m_new, g_new, u_new, report, rx

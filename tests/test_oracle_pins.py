@@ -511,3 +511,46 @@ def test_plane_wave_weights_steer():
     k = 2 * math.pi * p.freqs / p.c0
     dphi = np.angle(w[:, 1, 1:] / w[:, 1, :-1])
     np.testing.assert_allclose(dphi, (k * 0.5 * np.diff(p.elems[:, 0])[0])[:, None] * np.ones(5), rtol=1e-12)
+
+
+def test_admm_step_tx_vs_dense_normal_equations_and_born_reuse():
+    """ADMM step with synthesised transmits: with n_cg >= n the CG update is
+    the dense solve of Eq. 11-12 whose Jacobian rows are k^2 dV p_t p~_j
+    (transmit fields, receiver fields); receiver fields passed in (Born reuse)
+    replace p~ and nothing else; identity weights give the element step."""
+    p = W.small2d(seed=19, nx=6, nz=5, ne=3, nf=2)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    w = W.plane_wave_weights(p.freqs, p.elems, [-15.0, 20.0], p.c0)
+    m_obs = O.contrast(p.extra["c_obs"], p.alpha, p.c0)
+    d_obs = O.forward_tx_m(m_obs, *args, w)[0]
+    rng = np.random.default_rng(5)
+    g = 0.01 * (rng.standard_normal((2,) + m.shape) + 1j * rng.standard_normal((2,) + m.shape))
+    u = 0.01 * (rng.standard_normal((2,) + m.shape) + 1j * rng.standard_normal((2,) + m.shape))
+    m_ref = np.zeros_like(m)
+    lam, rho, gam, s = 1e-3, 1e-2, 1e-5, 1.0 / np.sum(np.abs(d_obs) ** 2)
+    D = _dense_grad_matrix(p.nz, p.nx)
+    data, f_tx, _ = O.forward_tx_m(m, *args, w)
+    # receiver fields of an earlier iterate (the homogeneous start): Born reuse
+    for rx_in in (None, O.receiver_fields(np.zeros_like(m), *args)):
+        m1, g1, u1, rep, rx = O.admm_step_tx(m, g, u, m_ref, d_obs, *args, w, lam, rho, gam, n_cg=200,
+                                             rx_fields=rx_in, data_scale=s)
+        if rx_in is None:
+            np.testing.assert_allclose(rx, O.forward_m(m, *args)[1], rtol=0, atol=1e-14)
+        J = np.concatenate([np.stack([p.dx**2 * O.wavenumber(f, p.c0) ** 2 * f_tx[l][t] * rx[l][j]
+                                      for t in range(2) for j in range(p.ne)])
+                            for l, f in enumerate(p.freqs)])
+        A = s * J.conj().T @ J + rho * D.T @ D + gam * np.eye(p.n)
+        b = (s * J.conj().T @ (d_obs - data).ravel() + rho * D.T @ (g + u).reshape(-1)
+             - rho * D.T @ D @ m.ravel() + gam * (m_ref - m).ravel())
+        dm = np.linalg.solve(A, b)
+        np.testing.assert_allclose(m1.ravel(), m.ravel() + dm, rtol=0, atol=1e-9 * np.abs(dm).max())
+        gm = (D @ m1.ravel()).reshape(2, *m.shape)
+        np.testing.assert_allclose(g1, O.shrink(gm - u, lam / rho), atol=1e-14)
+        np.testing.assert_allclose(u1, u + rho * (g1 - gm), atol=1e-14)
+    eye = np.broadcast_to(np.eye(p.ne), (p.nf, p.ne, p.ne))
+    d_el = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    a1 = O.admm_step(m, g, u, m_ref, d_el, *args, lam, rho, gam, n_cg=12, data_scale=s)
+    a2 = O.admm_step_tx(m, g, u, m_ref, d_el, *args, eye, lam, rho, gam, n_cg=12, data_scale=s)
+    for x, y in zip(a1[:3], a2[:3]):
+        np.testing.assert_allclose(x, y, rtol=0, atol=1e-12 * np.abs(x).max())
