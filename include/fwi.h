@@ -216,6 +216,17 @@ int fwi_adjoint_gradient_tx(fwi_ctx* ctx, const fwi_problem* prob, const double*
                             double* misfit_out, void* grad_m_out, double* grad_c_out, double* grad_alpha_out,
                             fwi_stats* stats);
 
+/* fwi_tv_admm_step for synthesised transmits: the Jacobian of Sec. IV-B from
+ * the transmit fields at m_k and the receiver fields rx_fields [nf][ne][n]
+ * complex128 (device). refresh_rx != 0: rx_fields are recomputed at m_k (ne
+ * element solves per frequency, written back); 0: used as given, e.g. kept
+ * from an earlier iterate (the paper's Born reuse of the receiver fields).
+ * tx_weights as in fwi_forward_tx, d_obs [nf][nt][ne]. */
+int fwi_tv_admm_step_tx(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_params* params, int nt,
+                        const void* tx_weights, void* rx_fields, int refresh_rx, void* m_inout, void* g_inout,
+                        void* u_inout, const void* m_ref, const void* d_obs, const fwi_solve_opts* opts,
+                        fwi_admm_report* report, fwi_stats* stats);
+
 /* ---------------------------------------------------------- uneven batches */
 /* Many independent problems (grids, element counts and frequency counts may
  * all differ) solved together. One refinement cycle of every instance of a

@@ -759,7 +759,7 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
     cb.S = a.take<c128>((size_t)B * n);
     cb.lam = a.take<c128>((size_t)B * n);
   }
-  if (entry == FWI_ENTRY_GRADIENT) cb.wtx = a.take<c128>(ndata);
+  if (entry != FWI_ENTRY_FORWARD) cb.wtx = a.take<c128>(ndata);
   if (entry == FWI_ENTRY_ADMM) {
     cb.cg_x = a.take<c128>(n);
     cb.cg_r = a.take<c128>(n);
@@ -1133,42 +1133,53 @@ int gradient_tx_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const d
   return finish_rc(R.tot);
 }
 
-// J^H b over all frequency groups from stored fields [nf][ne][n] -> out [n] (times dV)
-void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int nfg, const c128* fields, const c128* b,
-              c128* out) {
+// J^H b over all frequency groups from stored transmit fields tx [nf][nt][n]
+// and receiver fields rx [nf][ne][n] (the same array for element transmits,
+// nt = ne), b [nf][nt][ne] -> out [n] (times dV)
+void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int nfg, int nt, const c128* tx,
+              const c128* rx, const c128* b, c128* out) {
   const ProblemCache& pc = c->pc;
-  const long n = g.n(), ne2 = (long)p->ne * p->ne;
+  const long n = g.n(), nd = (long)nt * p->ne;
   const int ngroups = (p->nf + nfg - 1) / nfg;
   for (int gi = 0; gi < ngroups; ++gi) {
     const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
-    const c128* Fg = fields + (long)l0 * p->ne * n;
-    launch_gemm_cn(nf, b + l0 * ne2, p->ne, p->ne, Fg, (long)p->ne * n, n, cb.lam, (long)p->ne * n, c->stream);
-    launch_gradient_accum(n, nf, p->ne, Fg, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, c->stream);
+    launch_gemm_cn(nf, b + l0 * nd, nt, p->ne, rx + (long)l0 * p->ne * n, (long)p->ne * n, n, cb.lam, (long)nt * n,
+                   c->stream);
+    launch_gradient_accum(n, nf, nt, tx + (long)l0 * nt * n, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc,
+                          c->stream);
   }
   launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, nullptr, nullptr, out, nullptr, nullptr, c->stream);
 }
 
-// J a from stored fields -> out [nf][ne][ne]
-void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, const c128* fields, const c128* a,
-             c128* out) {
+// J a from stored transmit and receiver fields -> out [nf][nt][ne]
+void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int nt, const c128* tx, const c128* rx,
+             const c128* a, c128* out) {
   const long n = g.n();
-  launch_gemm_nt(p->nf, fields, (long)p->ne * n, p->ne, a, fields, (long)p->ne * n, p->ne, n, c->pc.coef, cb.gpart,
-                 gemm_splits(n), out, c->stream);
+  launch_gemm_nt(p->nf, tx, (long)nt * n, nt, a, rx, (long)p->ne * n, p->ne, n, c->pc.coef, cb.gpart, gemm_splits(n),
+                 out, c->stream);
 }
 
+// One ADMM iteration. nt = 0: element transmits (the Jacobian from the
+// forward fields alone). nt > 0: synthesised transmits with weights w
+// [nf][nt][ne] and receiver fields rx [nf][ne][n], recomputed at m_k when
+// refresh_rx is set and used as given otherwise (Born reuse, Sec. IV-B).
 template <typename T>
 int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void* m_io, void* g_io, void* u_io,
               const void* m_ref, const void* dobs_v, const fwi_solve_opts* opts, fwi_admm_report* rep,
-              fwi_stats* stats) {
+              fwi_stats* stats, int nt = 0, const void* w = nullptr, c128* rx = nullptr, int refresh_rx = 1) {
   const double t0 = now_ms();
   if (!prm || !m_io || !g_io || !u_io || !dobs_v) throw Error(FWI_E_INVAL, "NULL argument");
   if (!(prm->rho > 0.0) || prm->lambda < 0.0 || prm->gamma < 0.0 || prm->n_cg < 0)
     throw Error(FWI_E_INVAL, "ADMM parameters: need rho > 0, lambda >= 0, gamma >= 0, n_cg >= 0");
+  const bool tx = nt > 0;
+  if (tx && (!w || !rx)) throw Error(FWI_E_INVAL, "NULL transmit weights or receiver fields");
+  if (tx && nt > p->ne) throw Error(FWI_E_INVAL, "need 1 <= nt <= ne synthesised transmits");
   Runner R(c, p, *opts);
   SolveBufs<T> sb;
   prepare<T>(c, R, sb, FWI_ENTRY_ADMM);
   hipStream_t st = c->stream;
-  const long n = R.n, ne2 = (long)p->ne * p->ne, ndata = (long)p->nf * ne2;
+  const int ntx = tx ? nt : p->ne;
+  const long n = R.n, ndata = (long)p->nf * ntx * p->ne;
   const Geo& g = R.g;
   CallBufs& cb = R.cb;
   c128* m = (c128*)m_io;
@@ -1181,7 +1192,17 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   launch_copy_c128(n, m, cb.m64, st);
   launch_cast_64_32(n, cb.m64, cb.m32, st);
   // 1. forward solves at m_k, all fields kept for the Jacobian products
-  R.forward<T>(sb, cb.data, cb.fields);
+  const c128* rxf = cb.fields;
+  if (tx) {
+    const long nw = (long)p->nf * nt * p->ne;
+    check_complex(c, nw, (const c128*)w, "transmit weights");
+    launch_conj_c128(nw, (const c128*)w, cb.wtx, st);
+    R.forward_tx<T>(sb, nt, cb.data, cb.fields);
+    if (refresh_rx) R.forward<T>(sb, cb.Jp, rx);  // receiver fields at m_k (data not used)
+    rxf = rx;
+  } else {
+    R.forward<T>(sb, cb.data, cb.fields);
+  }
   // 2. residual d_obs - F and data scale
   launch_residual(ndata, cb.data, dobs, cb.r, cb.sc + 4, st);   // r = F - d_obs, sc[4] = misfit
   launch_residual(ndata, dobs, nullptr, cb.Jp, cb.sc + 5, st);  // sc[5] = |d_obs|^2 / 2
@@ -1193,7 +1214,7 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   const double rho = prm->rho, gam = use_ref ? prm->gamma : 0.0;
   const double dual = prm->dual_step;
   // 3. b = -s J^H(F - d) + rho grad^T(g + u - grad m) + gamma (m_ref - m)
-  jh_apply(c, p, g, cb, R.nfg, cb.fields, cb.r, cb.vec);
+  jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf, cb.r, cb.vec);
   launch_tv_grad(g, m, cb.gm, st);
   launch_lincomb((long)g.dim * n, 1.0, gg, 1.0, uu, -1.0, cb.gm, cb.tmpd, st);
   launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_r, st);
@@ -1204,8 +1225,8 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   launch_copy_c128(n, cb.cg_r, cb.cg_p, st);
   launch_dot_re(n, cb.cg_r, cb.cg_r, cb.dpart, cb.sc + 0, st);
   for (int it = 0; it < prm->n_cg; ++it) {
-    j_apply(c, p, g, cb, cb.fields, cb.cg_p, cb.Jp);
-    jh_apply(c, p, g, cb, R.nfg, cb.fields, cb.Jp, cb.vec);
+    j_apply(c, p, g, cb, ntx, cb.fields, rxf, cb.cg_p, cb.Jp);
+    jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf, cb.Jp, cb.vec);
     launch_tv_grad(g, cb.cg_p, cb.tmpd, st);
     launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_Ap, st);
     launch_lincomb(n, 1.0, cb.cg_Ap, s, cb.vec, gam, use_ref ? cb.cg_p : nullptr, cb.cg_Ap, st);
@@ -1766,6 +1787,20 @@ int fwi_tv_admm_step(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* pr
   });
 }
 
+int fwi_tv_admm_step_tx(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, int nt, const void* tx_weights,
+                        void* rx_fields, int refresh_rx, void* m_io, void* g_io, void* u_io, const void* m_ref,
+                        const void* dobs, const fwi_solve_opts* o, fwi_admm_report* rep, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    if (nt < 1) throw Error(FWI_E_INVAL, "need 1 <= nt <= ne synthesised transmits");
+    return o->precision == FWI_FP32_REFINE
+               ? admm_impl<float>(c, p, prm, m_io, g_io, u_io, m_ref, dobs, o, rep, stats, nt, tx_weights,
+                                  (c128*)rx_fields, refresh_rx)
+               : admm_impl<double>(c, p, prm, m_io, g_io, u_io, m_ref, dobs, o, rep, stats, nt, tx_weights,
+                                   (c128*)rx_fields, refresh_rx);
+  });
+}
+
 int fwi_apply_operator(fwi_ctx* c, const fwi_problem* p, int precision, const void* m, int B, const int* freq_index,
                        const void* x, void* y) {
   return guarded(c, [&] {
@@ -1905,7 +1940,7 @@ int fwi_jacobian_apply(fwi_ctx* c, const fwi_problem* p, const void* fields, con
     bind_workspace(c, ar, dry.used);
     CallBufs cb;
     cb.gpart = ar.take<c128>((size_t)gemm_splits(n) * p->nf * p->ne * p->ne);
-    j_apply(c, p, g, cb, (const c128*)fields, (const c128*)a, (c128*)out);
+    j_apply(c, p, g, cb, p->ne, (const c128*)fields, (const c128*)fields, (const c128*)a, (c128*)out);
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
   });
@@ -1932,7 +1967,7 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* c, const fwi_problem* p, const void* fie
     bind_workspace(c, ar, dry.used);
     CallBufs cb;
     plan(ar, cb);
-    jh_apply(c, p, g, cb, p->nf, (const c128*)fields, (const c128*)b, (c128*)out);
+    jh_apply(c, p, g, cb, p->nf, p->ne, (const c128*)fields, (const c128*)fields, (const c128*)b, (c128*)out);
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
   });

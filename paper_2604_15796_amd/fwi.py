@@ -111,6 +111,8 @@ def lib():
         "fwi_forward_tx": (ip, [vp, pp, vp, vp, ip, vp, op, vp, vp, sp]),
         "fwi_adjoint_gradient_tx": (ip, [vp, pp, vp, vp, ip, vp, vp, op, dp, vp, vp, vp, sp]),
         "fwi_jacobian_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
+        "fwi_tv_admm_step_tx": (ip, [vp, pp, C.POINTER(CAdmmParams), ip, vp, vp, ip, vp, vp, vp, vp, vp, op,
+                                     C.POINTER(CAdmmReport), sp]),
         "fwi_jacobian_adjoint_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
         "fwi_host_bessel01": (None, [C.c_double, dp]),
         "fwi_profile": (ip, [vp, C.c_uint]),
@@ -138,7 +140,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
-            "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx"]
+            "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -417,6 +419,30 @@ class Context:
         self._workspace(prob, o, ENTRY_ADMM)
         rc = self.L.fwi_tv_admm_step(self.h, prob.ref(), C.byref(prm), _ptr(m), _ptr(g), _ptr(u), _ptr(m_ref),
                                      _ptr(d_obs), C.byref(o), C.byref(rep), C.byref(st))
+        self._check(rc, allow_noconv)
+        return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
+
+    def tv_admm_step_tx(self, prob, w, rx_fields, m, g, u, d_obs, lam, rho, gamma=0.0, n_cg=10, m_ref=None,
+                        data_scale=0.0, dual_step=None, refresh_rx=True, opts=None, allow_noconv=False):
+        """One ADMM iteration with synthesised transmits (weights w [nf, nt, ne]);
+        rx_fields [nf, ne, n] complex128 are recomputed at m (refresh_rx) or used
+        as given (Born reuse). m, g, u, rx_fields are updated in place."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        nt = self._tx_weights(prob, w)
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        _check_dtype(g, torch.complex128, (prob.dim,) + prob.shape, "g")
+        _check_dtype(u, torch.complex128, (prob.dim,) + prob.shape, "u")
+        _check_dtype(rx_fields, torch.complex128, (prob.nf, prob.ne, prob.n), "rx_fields")
+        _check_dtype(d_obs, torch.complex128, (prob.nf, nt, prob.ne), "d_obs")
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        rep = CAdmmReport()
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_ADMM)
+        rc = self.L.fwi_tv_admm_step_tx(self.h, prob.ref(), C.byref(prm), nt, _ptr(w), _ptr(rx_fields),
+                                        1 if refresh_rx else 0, _ptr(m), _ptr(g), _ptr(u), _ptr(m_ref), _ptr(d_obs),
+                                        C.byref(o), C.byref(rep), C.byref(st))
         self._check(rc, allow_noconv)
         return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
 

@@ -355,6 +355,42 @@ def test_synthesised_transmits_vs_oracle(ctx, F, prec, angles, max_rhs):
     assert relerr(host(JHb), O.jacobian_adjoint_apply_tx(rf, rx_or, b, p.freqs, p.c0, p.dx, 2)) < 1e-9
 
 
+@pytest.mark.parametrize("refresh", [True, False])
+def test_admm_step_synthesised_transmits_vs_oracle(ctx, F, refresh):
+    """ADMM step with plane-wave transmits: receiver fields recomputed at m_k
+    (and written back), or kept from the homogeneous start (Born reuse)."""
+    p = W.small2d(seed=61, nx=22, nz=20, ne=4, nf=2)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    w = W.plane_wave_weights(p.freqs, p.elems, [-20.0, 5.0, 30.0], p.c0)
+    m0 = O.contrast(p.c, p.alpha, p.c0) * 0.5
+    d_obs = O.forward_tx_m(O.contrast(p.extra["c_obs"], p.alpha, p.c0), *args, w)[0]
+    g = O.tv_grad(m0)
+    u = W.random_complex(4, g.shape, 1e-3)
+    m_ref = np.zeros_like(m0)
+    lam, rho, gam, ncg = 1e-3, 1e-2, 1e-5, 6
+    s = 1.0 / float(np.sum(np.abs(d_obs) ** 2))
+    opts = F.SolveOptions(rtol=1e-13, restart=16)
+    zero = np.zeros_like(m0)
+    rx_start = O.receiver_fields(zero, *args)
+    rm, rgv, ru, rep, rrx = O.admm_step_tx(m0, g, u, m_ref, d_obs, *args, w, lam, rho, gam, ncg,
+                                           rx_fields=None if refresh else rx_start, data_scale=s)
+    _, rx, _ = ctx.forward_m(p, dev(zero), opts, fields=True)
+    assert relerr(host(rx), rx_start) < 1e-10
+    rx_before = rx.clone()
+    mt, gt, ut = dev(m0), dev(g), dev(u)
+    grep, _ = ctx.tv_admm_step_tx(p, dev(w), rx, mt, gt, ut, dev(d_obs), lam, rho, gam, ncg, m_ref=dev(m_ref),
+                                  data_scale=s, refresh_rx=refresh, opts=opts)
+    assert relerr(host(mt), rm) < 1e-8
+    assert relerr(host(gt), rgv) < 1e-8
+    assert relerr(host(ut), ru) < 1e-8
+    assert abs(grep["misfit"] - rep["misfit"]) < 1e-9 * rep["misfit"]
+    assert abs(grep["dm_norm"] - rep["dm_norm"]) < 1e-8 * rep["dm_norm"]
+    if refresh:
+        assert relerr(host(rx), rrx) < 1e-10
+    else:
+        assert torch.equal(rx, rx_before)
+
+
 def test_synthesised_transmit_argument_errors(ctx, F):
     p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
     c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
