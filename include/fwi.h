@@ -193,6 +193,26 @@ int fwi_tv_admm_step(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_param
                      void* g_inout, void* u_inout, const void* m_ref, const void* d_obs,
                      const fwi_solve_opts* opts, fwi_admm_report* report, fwi_stats* stats);
 
+/* Algorithm 1 (Sec. III): g_0 = grad m_0, u_0 = 0, then ADMM iterations as in
+ * fwi_tv_admm_step (fwi_tv_admm_step_tx when nt > 0: receiver fields
+ * recomputed at the first iteration and every born_every-th after it, reused
+ * in between; born_every <= 0: first iteration only) until the misfit at the
+ * iterate is <= tol * 1/2 ||d_obs||^2 (that iteration's update is kept) or
+ * max_iter iterations have run. m_inout [n]: m_0 in, final model out;
+ * g_out, u_out [dim][n] (final ADMM variables); rx_fields [nf][ne][n] when
+ * nt > 0; all complex128 device arrays. misfit_hist: host double[max_iter]
+ * or NULL (misfit at each iterate); iters_done: host int or NULL. stats sum
+ * the solves of all iterations. */
+int fwi_invert(fwi_ctx* ctx, const fwi_problem* prob, const fwi_admm_params* params, int max_iter, double tol,
+               int nt, const void* tx_weights, void* rx_fields, int born_every, void* m_inout, void* g_out,
+               void* u_out, const void* m_ref, const void* d_obs, const fwi_solve_opts* opts, double* misfit_hist,
+               int* iters_done, fwi_stats* stats);
+
+/* Speed of sound c [n] and attenuation alpha [n] (double, device; either may
+ * be NULL) of a contrast m [n] complex128: the inverse of Eq. 1-3 (the
+ * positive root of its quadratic in c^2; NaN where none exists). */
+int fwi_sos_from_contrast(fwi_ctx* ctx, const fwi_problem* prob, const void* m, double* c_out, double* alpha_out);
+
 /* ------------------------------------------------ synthesised transmits */
 /* Transmits other than single elements (Sec. V fires steered plane waves from
  * the array; every element still receives). Transmit t at frequency l drives

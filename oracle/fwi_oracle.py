@@ -573,3 +573,45 @@ def admm_step_tx(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, w
     u_new = u + dual_step * (g_new - gm_new)
     report = dict(misfit=misfit(data, d_obs), tv=tv_norm(gm_new), dm_norm=float(np.linalg.norm(dm)))
     return m_new, g_new, u_new, report, rx
+
+
+def sos_from_contrast(m, c0):
+    """Speed of sound and attenuation of a contrast (inverse of Eq. 1-3): with
+    R = Re m + 1 and I = Im m, Eq. 3 gives R = c0^2/c^2 - c0^2 alpha^2/(4 pi^2)
+    and I = c0^2 alpha/(pi c); eliminating alpha = pi c I / c0^2 leaves the
+    quadratic (I^2/(4 c0^2)) x^2 + R x - c0^2 = 0 in x = c^2, of which c^2 is
+    the positive root, (-R + sqrt(R^2 + I^2)) 2 c0^2 / I^2, taken in the
+    equivalent form 2 c0^2 / (R + sqrt(R^2 + I^2)) (no cancellation for small
+    I; c0^2 / R at I = 0)."""
+    m = np.asarray(m, dtype=np.complex128)
+    R, I = m.real + 1.0, m.imag
+    c = np.sqrt(2.0 * c0**2 / (R + np.sqrt(R**2 + I**2)))
+    return c, math.pi * c * I / c0**2
+
+
+def invert(m0, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, lam, rho, gamma, n_cg, max_iter, tol=0.0,
+           m_ref=None, data_scale=1.0, dual_step=None, weights=None, born_every=0):
+    """Algorithm 1: g_0 = nabla m_0, u_0 = 0, then ADMM iterations (admm_step,
+    or admm_step_tx with receiver fields recomputed at the first iteration and
+    every born_every-th one, reused in between) until the misfit at an iterate
+    is <= tol * 1/2 ||d_obs||^2 (that iteration's update kept) or max_iter
+    iterations have run. Returns (m, g, u, misfits per iteration)."""
+    shape = grid_shape(dim, nx, ny, nz)
+    m = np.asarray(m0, dtype=np.complex128).reshape(shape)
+    g = tv_grad(m)
+    u = np.zeros_like(g)
+    half = 0.5 * float(np.sum(np.abs(d_obs) ** 2))
+    args = (dim, nx, ny, nz, dx, c0, freqs, elems)
+    hist, rx = [], None
+    for k in range(max_iter):
+        if weights is None:
+            m, g, u, rep = admm_step(m, g, u, m_ref, d_obs, *args, lam, rho, gamma, n_cg, data_scale, dual_step)
+        else:
+            refresh = k == 0 or (born_every > 0 and k % born_every == 0)
+            m, g, u, rep, rx = admm_step_tx(m, g, u, m_ref, d_obs, *args, weights, lam, rho, gamma, n_cg,
+                                            rx_fields=None if refresh else rx, data_scale=data_scale,
+                                            dual_step=dual_step)
+        hist.append(rep["misfit"])
+        if rep["misfit"] <= tol * half:
+            break
+    return m, g, u, hist

@@ -1166,7 +1166,8 @@ void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int n
 template <typename T>
 int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void* m_io, void* g_io, void* u_io,
               const void* m_ref, const void* dobs_v, const fwi_solve_opts* opts, fwi_admm_report* rep,
-              fwi_stats* stats, int nt = 0, const void* w = nullptr, c128* rx = nullptr, int refresh_rx = 1) {
+              fwi_stats* stats, int nt = 0, const void* w = nullptr, c128* rx = nullptr, int refresh_rx = 1,
+              double* half_dobs2 = nullptr) {
   const double t0 = now_ms();
   if (!prm || !m_io || !g_io || !u_io || !dobs_v) throw Error(FWI_E_INVAL, "NULL argument");
   if (!(prm->rho > 0.0) || prm->lambda < 0.0 || prm->gamma < 0.0 || prm->n_cg < 0)
@@ -1209,6 +1210,7 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   FWI_HIP(hipMemcpyAsync(c->h_dbl, cb.sc + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   FWI_HIP(hipStreamSynchronize(st));
   const double misfit = c->h_dbl[0];
+  if (half_dobs2) *half_dobs2 = c->h_dbl[1];
   double s = prm->data_scale;
   if (!(s > 0.0)) s = c->h_dbl[1] > 0.0 ? 1.0 / (2.0 * c->h_dbl[1]) : 1.0;
   const double rho = prm->rho, gam = use_ref ? prm->gamma : 0.0;
@@ -1596,6 +1598,50 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
   }
   return tot.unconverged ? FWI_E_NOCONV : FWI_OK;
 }
+// Algorithm 1: g_0 = grad m_0, u_0 = 0, then ADMM iterations until the misfit
+// at the iterate falls to tol * 1/2 ||d_obs||^2 (that iteration's update is
+// kept) or max_iter iterations have run.
+template <typename T>
+int invert_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, int max_iter, double tol, int nt,
+                const void* w, void* rx, int born_every, void* m_io, void* g_out, void* u_out, const void* m_ref,
+                const void* dobs, const fwi_solve_opts* o, double* hist, int* done, fwi_stats* stats) {
+  if (!m_io || !g_out || !u_out || !dobs) throw Error(FWI_E_INVAL, "NULL argument");
+  if (max_iter < 0 || !(tol >= 0.0)) throw Error(FWI_E_INVAL, "need max_iter >= 0 and tol >= 0");
+  if (nt > 0 && (!w || !rx)) throw Error(FWI_E_INVAL, "NULL transmit weights or receiver fields");
+  std::string msg;
+  int rc = validate_problem(p, msg);
+  if (rc) throw Error(rc, msg);
+  const Geo g = make_geo(p);
+  launch_tv_grad(g, (const c128*)m_io, (c128*)g_out, c->stream);
+  launch_fill_zero_c128((long)g.dim * g.n(), (c128*)u_out, c->stream);
+  if (done) *done = 0;
+  fwi_stats tot{};
+  int ret = FWI_OK;
+  for (int k = 0; k < max_iter; ++k) {
+    fwi_admm_report r{};
+    fwi_stats s{};
+    double half = 0.0;
+    const int refresh = nt > 0 && (k == 0 || (born_every > 0 && k % born_every == 0));
+    const int rk = admm_impl<T>(c, p, prm, m_io, g_out, u_out, m_ref, dobs, o, &r, &s, nt, w, (c128*)rx, refresh,
+                                &half);
+    if (rk != FWI_OK) ret = rk;
+    if (hist) hist[k] = r.misfit;
+    if (done) *done = k + 1;
+    tot.iterations = std::max(tot.iterations, s.iterations);
+    tot.cycles = std::max(tot.cycles, s.cycles);
+    tot.unconverged += s.unconverged;
+    tot.max_rel_residual = std::max(tot.max_rel_residual, s.max_rel_residual);
+    tot.solves += s.solves;
+    tot.matvecs += s.matvecs;
+    tot.t_setup_ms += s.t_setup_ms;
+    tot.t_solve_ms += s.t_solve_ms;
+    tot.t_total_ms += s.t_total_ms;
+    if (r.misfit <= tol * half) break;
+  }
+  if (stats) *stats = tot;
+  return ret;
+}
+
 }  // namespace
 
 // ===================================================================== ABI ===
@@ -1798,6 +1844,32 @@ int fwi_tv_admm_step_tx(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params*
                                   (c128*)rx_fields, refresh_rx)
                : admm_impl<double>(c, p, prm, m_io, g_io, u_io, m_ref, dobs, o, rep, stats, nt, tx_weights,
                                    (c128*)rx_fields, refresh_rx);
+  });
+}
+
+int fwi_invert(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, int max_iter, double tol, int nt,
+               const void* tx_weights, void* rx_fields, int born_every, void* m_inout, void* g_out, void* u_out,
+               const void* m_ref, const void* d_obs, const fwi_solve_opts* o, double* misfit_hist, int* iters_done,
+               fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!o || !prm) throw Error(FWI_E_INVAL, "NULL argument");
+    return o->precision == FWI_FP32_REFINE
+               ? invert_impl<float>(c, p, prm, max_iter, tol, nt, tx_weights, rx_fields, born_every, m_inout, g_out,
+                                    u_out, m_ref, d_obs, o, misfit_hist, iters_done, stats)
+               : invert_impl<double>(c, p, prm, max_iter, tol, nt, tx_weights, rx_fields, born_every, m_inout, g_out,
+                                     u_out, m_ref, d_obs, o, misfit_hist, iters_done, stats);
+  });
+}
+
+int fwi_sos_from_contrast(fwi_ctx* c, const fwi_problem* p, const void* m, double* c_out, double* alpha_out) {
+  return guarded(c, [&] {
+    if (!p || !m || (!c_out && !alpha_out)) throw Error(FWI_E_INVAL, "bad arguments");
+    std::string msg;
+    int rc = validate_problem(p, msg);
+    if (rc) throw Error(rc, msg);
+    launch_sos_from_contrast(make_geo(p).n(), p->c0, (const c128*)m, c_out, alpha_out, c->stream);
+    FWI_HIP(hipStreamSynchronize(c->stream));
+    return FWI_OK;
   });
 }
 

@@ -29,6 +29,27 @@ void launch_contrast(long n, double c0, const double* c, const double* alpha, c1
   FWI_LAUNCH_CHECK();
 }
 
+// Inverse of the contrast formula: with R = Re m + 1 and I = Im m, c^2 is the
+// positive root of (I^2 / (4 c0^2)) x^2 + R x - c0^2 = 0, written without
+// cancellation as x = 2 c0^2 / (R + sqrt(R^2 + I^2)); then alpha = pi c I / c0^2.
+// No positive root (R <= 0 and I = 0): NaN.
+__global__ void k_sos_from_contrast(long n, double c0, const c128* __restrict__ m, double* __restrict__ c,
+                                    double* __restrict__ alpha) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double R = m[i].x + 1.0, I = m[i].y;
+  const double den = R + sqrt(R * R + I * I);
+  const double cc = den > 0.0 ? sqrt(2.0 * c0 * c0 / den) : nan("");
+  if (c) c[i] = cc;
+  if (alpha) alpha[i] = PI * cc * I / (c0 * c0);
+}
+
+void launch_sos_from_contrast(long n, double c0, const c128* m, double* c, double* alpha, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_sos_from_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c0, m, c, alpha);
+  FWI_LAUNCH_CHECK();
+}
+
 // Cell weight constants (Richmond: equal-area disk / equal-volume ball of radius a).
 //  2D: W(r>0) = (i/4)(2 pi a/k) J1(ka) H0(kr),  W(0) = (i pi a/(2k)) H1(ka) - 1/k^2
 //  3D: W(r>0) = (4 pi/k^3)(sin ka - ka cos ka) e^{ikr}/(4 pi r),

@@ -111,6 +111,9 @@ def lib():
         "fwi_forward_tx": (ip, [vp, pp, vp, vp, ip, vp, op, vp, vp, sp]),
         "fwi_adjoint_gradient_tx": (ip, [vp, pp, vp, vp, ip, vp, vp, op, dp, vp, vp, vp, sp]),
         "fwi_jacobian_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
+        "fwi_invert": (ip, [vp, pp, C.POINTER(CAdmmParams), ip, C.c_double, ip, vp, vp, ip, vp, vp, vp, vp, vp, op,
+                            dp, C.POINTER(C.c_int), sp]),
+        "fwi_sos_from_contrast": (ip, [vp, pp, vp, vp, vp]),
         "fwi_tv_admm_step_tx": (ip, [vp, pp, C.POINTER(CAdmmParams), ip, vp, vp, ip, vp, vp, vp, vp, vp, op,
                                      C.POINTER(CAdmmReport), sp]),
         "fwi_jacobian_adjoint_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
@@ -140,7 +143,8 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
-            "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx"]
+            "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx", "fwi_invert",
+            "fwi_sos_from_contrast"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -445,6 +449,43 @@ class Context:
                                         C.byref(o), C.byref(rep), C.byref(st))
         self._check(rc, allow_noconv)
         return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
+
+    def invert(self, prob, m, d_obs, lam, rho, gamma=0.0, n_cg=10, max_iter=20, tol=0.0, m_ref=None,
+               data_scale=0.0, dual_step=None, w=None, born_every=0, opts=None, allow_noconv=False):
+        """Algorithm 1 from m (complex128 device tensor, updated in place): up to
+        max_iter ADMM iterations, stopping once the misfit at an iterate is
+        <= tol * 1/2 ||d_obs||^2. w [nf, nt, ne]: synthesised transmits with
+        receiver fields refreshed every born_every iterations. Returns
+        (misfit per iteration, g, u, stats)."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        nt = self._tx_weights(prob, w) if w is not None else 0
+        _check_dtype(d_obs, torch.complex128, (prob.nf, nt or prob.ne, prob.ne), "d_obs")
+        g = torch.empty((prob.dim,) + prob.shape, dtype=torch.complex128, device=self.device)
+        u = torch.empty_like(g)
+        rx = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if nt else None
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        hist = (C.c_double * max(max_iter, 1))()
+        done = C.c_int()
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_ADMM)
+        rc = self.L.fwi_invert(self.h, prob.ref(), C.byref(prm), max_iter, tol, nt, _ptr(w), _ptr(rx), born_every,
+                               _ptr(m), _ptr(g), _ptr(u), _ptr(m_ref), _ptr(d_obs), C.byref(o), hist, C.byref(done),
+                               C.byref(st))
+        self._check(rc, allow_noconv)
+        return list(hist)[:done.value], g, u, st.as_dict()
+
+    def sos_from_contrast(self, prob, m):
+        """(c [n], alpha [n]) float64 device tensors: the inverse of Eq. 1-3."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        c = torch.empty(prob.shape, dtype=torch.float64, device=self.device)
+        a = torch.empty_like(c)
+        self._stream()
+        self._check(self.L.fwi_sos_from_contrast(self.h, prob.ref(), _ptr(m), _ptr(c), _ptr(a)))
+        return c, a
 
     def profile(self, classes):
         """Start HIP-event timing of the named kernel classes (empty: stop)."""

@@ -391,6 +391,45 @@ def test_admm_step_synthesised_transmits_vs_oracle(ctx, F, refresh):
         assert torch.equal(rx, rx_before)
 
 
+@pytest.mark.parametrize("tx", [False, True])
+def test_invert_algorithm1_vs_oracle(ctx, F, tx):
+    """Algorithm 1 from the homogeneous model (three ADMM iterations; with
+    plane-wave transmits the receiver fields are refreshed every second
+    iteration): iterates, ADMM variables and misfit history against the
+    oracle; the misfit falls and the speed-of-sound error shrinks."""
+    p = W.small2d(seed=62, nx=20, nz=18, ne=4, nf=2)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    w = W.plane_wave_weights(p.freqs, p.elems, [-20.0, 0.0, 20.0], p.c0) if tx else None
+    m_true = O.contrast(p.c, p.alpha, p.c0)
+    d_obs = O.forward_tx_m(m_true, *args, w)[0] if tx else O.forward_m(m_true, *args)[0]
+    m0 = np.zeros_like(m_true)
+    lam, rho, gam, ncg = 1e-4, 1e-3, 1e-5, 8
+    s = 1.0 / float(np.sum(np.abs(d_obs) ** 2))
+    rm, rg, ru, rhist = O.invert(m0, d_obs, *args, lam, rho, gam, ncg, max_iter=3, m_ref=m0, data_scale=s,
+                                 weights=w, born_every=2)
+    mt = dev(m0)
+    hist, g, u, st = ctx.invert(p, mt, dev(d_obs), lam, rho, gam, ncg, max_iter=3, m_ref=dev(m0), data_scale=s,
+                                w=dev(w) if tx else None, born_every=2, opts=F.SolveOptions(rtol=1e-13, restart=16))
+    assert len(hist) == 3 and st["unconverged"] == 0
+    # misfits of nearly fitted iterates are differences of nearly equal data:
+    # their rounding is relative to the data scale (the first misfit)
+    np.testing.assert_allclose(hist, rhist, rtol=1e-9, atol=1e-9 * rhist[0])
+    assert relerr(host(mt), rm) < 1e-8
+    assert relerr(host(g), rg) < 1e-8 and relerr(host(u), ru) < 1e-8
+    assert hist[-1] < hist[0]
+    c_est, a_est = ctx.sos_from_contrast(p, mt)
+    rc_est, ra_est = O.sos_from_contrast(rm, p.c0)
+    assert relerr(host(c_est), rc_est) < 1e-12 and relerr(host(a_est), ra_est) < 1e-9
+    rmse = lambda c: float(np.sqrt(np.mean((c - p.c) ** 2)))
+    assert rmse(host(c_est)) < rmse(np.full_like(p.c, p.c0))
+    # the stopping rule: a threshold just above the second iterate's misfit
+    half = 0.5 * float(np.sum(np.abs(d_obs) ** 2))
+    h2, _, _, _ = ctx.invert(p, dev(m0), dev(d_obs), lam, rho, gam, ncg, max_iter=3, tol=1.0001 * rhist[1] / half,
+                             m_ref=dev(m0), data_scale=s, w=dev(w) if tx else None, born_every=2,
+                             opts=F.SolveOptions(rtol=1e-13, restart=16))
+    assert len(h2) == 2
+
+
 def test_synthesised_transmit_argument_errors(ctx, F):
     p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
     c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)

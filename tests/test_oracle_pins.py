@@ -554,3 +554,36 @@ def test_admm_step_tx_vs_dense_normal_equations_and_born_reuse():
     a2 = O.admm_step_tx(m, g, u, m_ref, d_el, *args, eye, lam, rho, gam, n_cg=12, data_scale=s)
     for x, y in zip(a1[:3], a2[:3]):
         np.testing.assert_allclose(x, y, rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_sos_from_contrast_inverts_the_contrast():
+    """c and alpha back from m = contrast(c, alpha) (Eq. 1-3), and the lossless
+    special case c = c0 / sqrt(1 + m)."""
+    p = W.small2d(seed=3)
+    alpha = p.alpha + W.db_cm_mhz_to_np_m_hz(0.4)
+    c, a = O.sos_from_contrast(O.contrast(p.c, alpha, p.c0), p.c0)
+    np.testing.assert_allclose(c, p.c, rtol=1e-14)
+    np.testing.assert_allclose(a, alpha, rtol=1e-12)
+    m = O.contrast(p.c, np.zeros_like(p.c), p.c0)
+    np.testing.assert_allclose(O.sos_from_contrast(m, p.c0)[0], p.c0 / np.sqrt(1.0 + m.real), rtol=1e-15)
+
+
+def test_invert_is_repeated_admm_steps_with_stopping():
+    """Algorithm 1: g_0 = grad m_0, u_0 = 0, then the ADMM steps in sequence;
+    the loop stops after the first iterate whose misfit is under the threshold."""
+    p = W.small2d(seed=20, nx=8, nz=7, ne=3, nf=1)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    d_obs = O.forward(p.c, p.alpha, *args)[0]
+    m0 = np.zeros((p.nz, p.nx), complex)
+    s = 1.0 / np.sum(np.abs(d_obs) ** 2)
+    m, g, u, hist = O.invert(m0, d_obs, *args, 1e-4, 1e-3, 0.0, 8, max_iter=3, data_scale=s)
+    mm, gg, uu = m0, O.tv_grad(m0), np.zeros((2,) + m0.shape, complex)
+    for k in range(3):
+        mm, gg, uu, rep = O.admm_step(mm, gg, uu, None, d_obs, *args, 1e-4, 1e-3, 0.0, 8, data_scale=s)
+        assert rep["misfit"] == hist[k]
+    np.testing.assert_array_equal(m, mm)
+    assert hist[2] < hist[0]
+    half = 0.5 * np.sum(np.abs(d_obs) ** 2)
+    _, _, _, h2 = O.invert(m0, d_obs, *args, 1e-4, 1e-3, 0.0, 8, max_iter=3, tol=1.01 * hist[1] / half,
+                           data_scale=s)
+    assert len(h2) == 2
