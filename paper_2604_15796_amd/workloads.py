@@ -300,6 +300,19 @@ def plane_wave_weights(freqs, elems, angles_deg, c0=C0):
     return np.exp(1j * k[:, None, None] * np.sin(th)[None, :, None] * x[None, None, :])
 
 
+def add_noise(d, rel, seed):
+    """d plus circular complex Gaussian noise of total norm about rel ||d||
+    (per-entry standard deviation rel ||d|| / sqrt(N)): the reading of the
+    paper's "2% Gaussian noise" on simulated data (Sec. V). Draw order: real
+    parts, then imaginary parts."""
+    d = np.asarray(d)
+    rng = np.random.default_rng(seed)
+    sigma = rel * np.linalg.norm(d) / math.sqrt(d.size)
+    re = rng.standard_normal(d.shape)
+    im = rng.standard_normal(d.shape)
+    return d + sigma * (re + 1j * im) / math.sqrt(2.0)
+
+
 def random_data(seed, nf, ne, scale=1.0):
     """Seeded complex data array [nf][ne][ne] (stand-in for measured data)."""
     rng = np.random.default_rng(seed)
