@@ -134,9 +134,40 @@ def cell_weight(k, r, dx, dim):
     return out
 
 
+class FiniteElements:
+    """Elements with an aperture on the top face (Sec. V models a finite-length
+    array; Eq. 4 integrates over the receiver region): a width x height
+    rectangle centred at each position (height only in 3D). Reading: each
+    element transmits and receives as the average of the point-source field
+    over its aperture, so a vanishing aperture is the point element; the
+    average is taken with a quad-point Gauss-Legendre rule per direction."""
+
+    def __init__(self, xyz, width=0.0, height=0.0, quad=1):
+        self.xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+        self.width, self.height, self.quad = float(width), float(height), int(quad)
+
+    def __len__(self):
+        return len(self.xyz)
+
+
 def incident_fields(k, centres, elems, dim):
     """P0[e, n] = G(|x_n - x_e|): field of a unit point source at element e in the
-    homogeneous background (Sec. II, the incident field p_{i,0})."""
+    homogeneous background (Sec. II, the incident field p_{i,0}); for
+    FiniteElements the aperture average of that field."""
+    if isinstance(elems, FiniteElements):
+        def rule(extent):
+            if extent <= 0.0:
+                return np.zeros(1), np.ones(1)
+            x, w = np.polynomial.legendre.leggauss(elems.quad)
+            return 0.5 * extent * x, 0.5 * w
+        xa, wa = rule(elems.width)
+        xb, wb = rule(elems.height)
+        out = 0.0
+        for a in range(len(xa)):
+            for b in range(len(xb)):
+                sub = elems.xyz + np.array([xa[a], xb[b], 0.0])
+                out = out + wa[a] * wb[b] * incident_fields(k, centres, sub, dim)
+        return out
     d = np.linalg.norm(centres[None, :, :] - elems[:, None, :], axis=2)
     return green(k, d, dim)
 

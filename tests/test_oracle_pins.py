@@ -587,3 +587,39 @@ def test_invert_is_repeated_admm_steps_with_stopping():
     _, _, _, h2 = O.invert(m0, d_obs, *args, 1e-4, 1e-3, 0.0, 8, max_iter=3, tol=1.01 * hist[1] / half,
                            data_scale=s)
     assert len(h2) == 2
+
+
+def test_finite_elements_aperture_average():
+    """The Gauss-Legendre aperture average converges to the integral of the
+    point-source field over the element (adaptive quadrature), tends to the
+    point element as the aperture vanishes, and keeps reciprocity of the data
+    (transmit and receive with the same aperture)."""
+    import scipy.integrate as si
+    p = W.small2d(seed=21, nx=10, nz=8, ne=3, nf=1)
+    k = O.wavenumber(p.freqs[0], p.c0)
+    cen = O.cell_centres(2, p.nx, 1, p.nz, p.dx)
+    width = 0.25e-3
+    P = O.incident_fields(k, cen, O.FiniteElements(p.elems, width, 0.0, 12), 2)
+    for e, n in ((0, 0), (1, 37), (2, 79)):
+        f = lambda s, part: part(O.green(k, np.array([np.hypot(cen[n, 0] - p.elems[e, 0] - s, cen[n, 2])]), 2)[0])
+        ref = (si.quad(f, -width / 2, width / 2, args=(np.real,), epsabs=0, epsrel=1e-13)[0]
+               + 1j * si.quad(f, -width / 2, width / 2, args=(np.imag,), epsabs=0, epsrel=1e-13)[0]) / width
+        assert abs(P[e, n] - ref) < 1e-11 * abs(ref)
+    P_pt = O.incident_fields(k, cen, p.elems, 2)
+    P_small = O.incident_fields(k, cen, O.FiniteElements(p.elems, 1e-7, 0.0, 4), 2)
+    assert np.abs(P_small - P_pt).max() < 1e-6 * np.abs(P_pt).max()
+    m = O.contrast(p.c, p.alpha, p.c0)
+    d, _, _ = O.forward_m(m, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, O.FiniteElements(p.elems, width, 0.0, 6))
+    np.testing.assert_allclose(d[0], d[0].T, rtol=0, atol=1e-12 * np.abs(d).max())
+    # 3D: width and elevation height
+    p3 = W.small3d(seed=22, nx=8, ny=7, nz=6, ne=2)
+    c3 = O.cell_centres(3, p3.nx, p3.ny, p3.nz, p3.dx)
+    k3 = O.wavenumber(p3.freqs[0], p3.c0)
+    fe = O.FiniteElements(p3.elems, 0.3e-3, 0.5e-3, 10)
+    P3 = O.incident_fields(k3, c3, fe, 3)
+    n = 100
+    g = lambda y, x, part: part(O.green(k3, np.array([np.linalg.norm(c3[n] - p3.elems[0] - [x, y, 0.0])]), 3)[0])
+    ref = (si.dblquad(g, -0.15e-3, 0.15e-3, -0.25e-3, 0.25e-3, args=(np.real,), epsabs=0, epsrel=1e-12)[0]
+           + 1j * si.dblquad(g, -0.15e-3, 0.15e-3, -0.25e-3, 0.25e-3, args=(np.imag,), epsabs=0,
+                             epsrel=1e-12)[0]) / (0.3e-3 * 0.5e-3)
+    assert abs(P3[0, n] - ref) < 1e-10 * abs(ref)
