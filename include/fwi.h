@@ -71,6 +71,15 @@ typedef struct fwi_problem {
   const double* freq_hz;   /* host [nf], > 0 */
   int ne;                  /* number of elements (transmit set = receive set) */
   const double* elem_xyz;  /* host [ne][3] positions [m]; z must be 0 */
+  /* Element aperture (Sec. V: finite elements; Eq. 4 integrates over the
+   * receiver region): a rectangle on the top face centred at elem_xyz, width
+   * along x, height along y (3D only). Each element transmits and receives as
+   * the average of the point-source field over its aperture, by an
+   * elem_quad-point Gauss-Legendre rule per direction (1..16). Zero width and
+   * height: point elements (elem_quad ignored). */
+  double elem_width;       /* [m], >= 0 */
+  double elem_height;      /* [m], >= 0, 0 in 2D */
+  int elem_quad;
 } fwi_problem;
 
 /* Solver options (Sec. IV-A: Krylov solve of the discretised Eq. 5). */
@@ -311,6 +320,11 @@ int fwi_jacobian_apply_tx(fwi_ctx* ctx, const fwi_problem* prob, int nt, const v
                           const void* rx_fields, const void* a, void* out_data);
 int fwi_jacobian_adjoint_apply_tx(fwi_ctx* ctx, const fwi_problem* prob, int nt, const void* tx_fields,
                                   const void* rx_fields, const void* b, void* out);
+
+/* Gauss-Legendre nodes x[q] and weights w[q] on [-1, 1] (1 <= q <= 16) of the
+ * element-aperture rule, computed on the host as the kernels receive them;
+ * returns 0, or FWI_E_INVAL for q out of range. */
+int fwi_host_gauss_legendre(int q, double* x, double* w);
 
 /* ----------------------------------------------------------- measurement */
 /* Kernel classes: 0 row forward FFT pass, 1 Green convolution pass (forward

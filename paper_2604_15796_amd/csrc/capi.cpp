@@ -274,6 +274,12 @@ int validate_problem(const fwi_problem* p, std::string& msg) {
     if (p->dim == 2 && y != 0.0) return msg = "2D elements must have y = 0", FWI_E_INVAL;
     if (!seen.insert({x, y}).second) return msg = "duplicate element position", FWI_E_INVAL;
   }
+  if (!(p->elem_width >= 0.0) || !std::isfinite(p->elem_width) || !(p->elem_height >= 0.0) ||
+      !std::isfinite(p->elem_height))
+    return msg = "element aperture must be finite and >= 0", FWI_E_INVAL;
+  if (p->dim == 2 && p->elem_height != 0.0) return msg = "2D elements have no height", FWI_E_INVAL;
+  if ((p->elem_width > 0.0 || p->elem_height > 0.0) && (p->elem_quad < 1 || p->elem_quad > kMaxGaussPoints))
+    return msg = "elem_quad must be in 1..16", FWI_E_INVAL;
   return FWI_OK;
 }
 
@@ -318,6 +324,12 @@ std::string problem_key(const fwi_problem* p) {
   put(p->freq_hz, sizeof(double) * p->nf);
   put(&p->ne, sizeof(int));
   put(p->elem_xyz, sizeof(double) * 3 * p->ne);
+  const bool ap = p->elem_width > 0.0 || p->elem_height > 0.0;
+  const double aw = p->elem_width, ah = p->elem_height;
+  const int q = ap ? p->elem_quad : 0;
+  put(&aw, sizeof(double));
+  put(&ah, sizeof(double));
+  put(&q, sizeof(int));
   return k;
 }
 
@@ -371,6 +383,10 @@ double build_cache(fwi_ctx* c, const fwi_problem* p, ProblemCache& pc, const std
   c128 *table = nullptr, *work = nullptr;
   FWI_HIP(hipMalloc((void**)&table, sizeof(c128) * np));
   FWI_HIP(hipMalloc((void**)&work, sizeof(c128) * np));
+  Aperture ap{};
+  ap.hw = 0.5 * p->elem_width;
+  ap.hh = 0.5 * p->elem_height;
+  ap.rule = gauss_legendre(ap.hw > 0.0 || ap.hh > 0.0 ? p->elem_quad : 1);
   for (int l = 0; l < pc.nf; ++l) {
     const double k = 2.0 * 3.14159265358979323846 * p->freq_hz[l] / p->c0;
     pc.k[l] = k;
@@ -380,7 +396,7 @@ double build_cache(fwi_ctx* c, const fwi_problem* p, ProblemCache& pc, const std
     launch_green_table(g, k, table, st);
     launch_fft_full(g, c->tw, table, work, pc.ghat64 + (long)l * np, st);
     launch_cast_64_32(np, pc.ghat64 + (long)l * np, pc.ghat32 + (long)l * np, st);
-    launch_incident(g, k, pc.ne, pc.elems, pc.P0 + (long)l * pc.ne * n, st);
+    launch_incident(g, k, pc.ne, pc.elems, ap, pc.P0 + (long)l * pc.ne * n, st);
   }
   FWI_HIP(hipMemcpyAsync(pc.k2, hk2.data(), sizeof(c128) * pc.nf, hipMemcpyHostToDevice, st));
   FWI_HIP(hipMemcpyAsync(pc.coef, hcoef.data(), sizeof(c128) * pc.nf, hipMemcpyHostToDevice, st));

@@ -215,7 +215,21 @@ void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx
 void launch_contrast(long n, double c0, const double* c, const double* alpha, c128* m64, c64* m32, hipStream_t st);
 void launch_sos_from_contrast(long n, double c0, const c128* m, double* c, double* alpha, hipStream_t st);
 void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st);
-void launch_incident(const Geo& g, double k, int ne, const double* elem_xyz_dev, c128* P0, hipStream_t st);
+// Gauss-Legendre rule on [-1, 1] for the element apertures.
+constexpr int kMaxGaussPoints = 16;
+struct GaussRule {
+  int q;
+  double x[kMaxGaussPoints], w[kMaxGaussPoints];
+};
+GaussRule gauss_legendre(int q);
+// Element aperture: half width (x) and half height (y) [m] and the rule used
+// in each direction with a nonzero extent.
+struct Aperture {
+  double hw, hh;
+  GaussRule rule;
+};
+void launch_incident(const Geo& g, double k, int ne, const double* elem_xyz_dev, const Aperture& ap, c128* P0,
+                     hipStream_t st);
 void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st);
 void launch_scale_c128(long count, double s, c128* x, hipStream_t st);
 

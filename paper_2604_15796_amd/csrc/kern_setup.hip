@@ -129,9 +129,12 @@ void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st) {
   FWI_LAUNCH_CHECK();
 }
 
-// P0[e][n] = G(k |x_n - x_e|): 2D (i/4) H0^(1), 3D e^{ikr}/(4 pi r).
+// P0[e][n] = G(k |x_n - x_e|): 2D (i/4) H0^(1), 3D e^{ikr}/(4 pi r); with an
+// aperture, the average of G over the element's rectangle on the top face
+// (product Gauss-Legendre rule: sub-point x_e + (hw xi_a, hh xi_b, 0) with
+// weight w_a w_b / 4, one point in a direction of zero extent).
 __global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k, int ne,
-                           const double* __restrict__ exyz, c128* __restrict__ P0) {
+                           const double* __restrict__ exyz, Aperture ap, c128* __restrict__ P0) {
   const long n = (long)nx * ny * nz;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int e = blockIdx.y;
@@ -139,30 +142,75 @@ __global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k,
   const int ix = (int)(i % nx);
   const int iy = (int)((i / nx) % ny);
   const int iz = (int)(i / ((long)nx * ny));
-  const double px = (ix + 0.5) * dx - exyz[3 * e + 0];
-  const double py = (dim == 3 ? (iy + 0.5) * dx : 0.0) - exyz[3 * e + 1];
-  const double pz = (iz + 0.5) * dx - exyz[3 * e + 2];
-  const double r = sqrt(px * px + py * py + pz * pz);
-  c128 v;
-  if (dim == 2) {
-    double j0, j1, y0, y1;
-    bessel01(k * r, &j0, &j1, &y0, &y1);
-    v = mk(-0.25 * y0, 0.25 * j0);
-  } else {
-    double s, c;
-    sincos(k * r, &s, &c);
-    const double g = 1.0 / (4.0 * PI * r);
-    v = mk(g * c, g * s);
+  const int qa = ap.hw > 0.0 ? ap.rule.q : 1, qb = ap.hh > 0.0 ? ap.rule.q : 1;
+  c128 v = mk(0.0, 0.0);
+  for (int a = 0; a < qa; ++a) {
+    const double sx = ap.hw > 0.0 ? ap.hw * ap.rule.x[a] : 0.0;
+    const double wa = ap.hw > 0.0 ? 0.5 * ap.rule.w[a] : 1.0;
+    for (int b = 0; b < qb; ++b) {
+      const double sy = ap.hh > 0.0 ? ap.hh * ap.rule.x[b] : 0.0;
+      const double wb = ap.hh > 0.0 ? 0.5 * ap.rule.w[b] : 1.0;
+      const double px = (ix + 0.5) * dx - (exyz[3 * e + 0] + sx);
+      const double py = (dim == 3 ? (iy + 0.5) * dx : 0.0) - (exyz[3 * e + 1] + sy);
+      const double pz = (iz + 0.5) * dx - exyz[3 * e + 2];
+      const double r = sqrt(px * px + py * py + pz * pz);
+      c128 gv;
+      if (dim == 2) {
+        double j0, j1, y0, y1;
+        bessel01(k * r, &j0, &j1, &y0, &y1);
+        gv = mk(-0.25 * y0, 0.25 * j0);
+      } else {
+        double s, c;
+        sincos(k * r, &s, &c);
+        const double g = 1.0 / (4.0 * PI * r);
+        gv = mk(g * c, g * s);
+      }
+      v = v + (wa * wb) * gv;
+    }
   }
   P0[(long)e * n + i] = v;
 }
 
-void launch_incident(const Geo& g, double k, int ne, const double* exyz, c128* P0, hipStream_t st) {
+void launch_incident(const Geo& g, double k, int ne, const double* exyz, const Aperture& ap, c128* P0,
+                     hipStream_t st) {
   const long n = g.n();
   if (n == 0 || ne == 0) return;
   hipLaunchKernelGGL(k_incident, dim3((unsigned)((n + 255) / 256), ne), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz, g.dx,
-                     k, ne, exyz, P0);
+                     k, ne, exyz, ap, P0);
   FWI_LAUNCH_CHECK();
+}
+
+// Gauss-Legendre nodes (roots of P_q) by Newton's method from the classical
+// starting values cos(pi (i + 3/4) / (q + 1/2)), P_q and P_q' by the
+// three-term recurrence; weights 2 / ((1 - x^2) P_q'(x)^2).
+GaussRule gauss_legendre(int q) {
+  GaussRule r{};
+  r.q = q;
+  for (int i = 0; i < q; ++i) {
+    double x = std::cos(PI * (i + 0.75) / (q + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= q; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (x * p1 - p0) / (x * x - 1.0);
+      const double step = p1 / dp;
+      x -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int j = 2; j <= q; ++j) {
+      const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = q * (x * p1 - p0) / (x * x - 1.0);
+    r.x[i] = x;
+    r.w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return r;
 }
 
 __global__ void k_cast_64_32(long count, const c128* __restrict__ in, c64* __restrict__ out) {
@@ -190,6 +238,17 @@ void launch_scale_c128(long count, double s, c128* x, hipStream_t st) {
 // Host evaluation of the same Bessel routine the kernels use (for CPU checks).
 extern "C" void fwi_host_bessel01(double x, double* out4) {
   fwi::bessel01(x, &out4[0], &out4[1], &out4[2], &out4[3]);
+}
+
+// The aperture rule the kernels receive (for CPU checks).
+extern "C" int fwi_host_gauss_legendre(int q, double* x, double* w) {
+  if (q < 1 || q > fwi::kMaxGaussPoints || !x || !w) return -1;
+  const fwi::GaussRule r = fwi::gauss_legendre(q);
+  for (int i = 0; i < q; ++i) {
+    x[i] = r.x[i];
+    w[i] = r.w[i];
+  }
+  return 0;
 }
 
 namespace fwi {

@@ -42,7 +42,8 @@ class FWIError(RuntimeError):
 class CProblem(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
                 ("c0", C.c_double), ("nf", C.c_int), ("freq_hz", C.POINTER(C.c_double)), ("ne", C.c_int),
-                ("elem_xyz", C.POINTER(C.c_double))]
+                ("elem_xyz", C.POINTER(C.c_double)), ("elem_width", C.c_double), ("elem_height", C.c_double),
+                ("elem_quad", C.c_int)]
 
 
 class CSolveOpts(C.Structure):
@@ -118,6 +119,7 @@ def lib():
                                      C.POINTER(CAdmmReport), sp]),
         "fwi_jacobian_adjoint_apply_tx": (ip, [vp, pp, ip, vp, vp, vp, vp]),
         "fwi_host_bessel01": (None, [C.c_double, dp]),
+        "fwi_host_gauss_legendre": (ip, [ip, dp, dp]),
         "fwi_profile": (ip, [vp, C.c_uint]),
         "fwi_profile_read": (ip, [vp, ip, dp, C.POINTER(C.c_longlong), dp]),
         "fwi_autotune": (ip, [vp, pp, ip, ip, ip, C.POINTER(CTuneReport)]),
@@ -144,7 +146,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
             "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx", "fwi_invert",
-            "fwi_sos_from_contrast"]
+            "fwi_sos_from_contrast", "fwi_host_gauss_legendre"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -178,9 +180,14 @@ class ProblemArgs:
         self.elems = np.ascontiguousarray(np.asarray(p.elems, dtype=np.float64).reshape(-1, 3))
         self.nf, self.ne = len(self.freqs), self.elems.shape[0]
         self.n = self.nx * self.ny * self.nz
+        # element aperture (point elements when absent)
+        self.elem_width = float(getattr(p, "elem_width", 0.0))
+        self.elem_height = float(getattr(p, "elem_height", 0.0))
+        self.elem_quad = int(getattr(p, "elem_quad", 1))
         self.c = CProblem(self.dim, self.nx, self.ny, self.nz, self.dx, self.c0, self.nf,
                           self.freqs.ctypes.data_as(C.POINTER(C.c_double)), self.ne,
-                          self.elems.ctypes.data_as(C.POINTER(C.c_double)))
+                          self.elems.ctypes.data_as(C.POINTER(C.c_double)), self.elem_width, self.elem_height,
+                          self.elem_quad)
 
     @property
     def shape(self):
@@ -648,6 +655,14 @@ class Context:
         self._internal_workspace()
         self._check(self.L.fwi_jacobian_adjoint_apply(self.h, prob.ref(), _ptr(fields), _ptr(b), _ptr(out)))
         return out
+
+
+def host_gauss_legendre(q):
+    """(nodes, weights) of the library's q-point element-aperture rule."""
+    x, w = (C.c_double * q)(), (C.c_double * q)()
+    if lib().fwi_host_gauss_legendre(q, x, w) != 0:
+        raise ValueError("q must be in 1..16")
+    return np.array(x[:]), np.array(w[:])
 
 
 def host_bessel01(x):

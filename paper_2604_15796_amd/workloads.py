@@ -54,6 +54,11 @@ class Problem:
     c: np.ndarray
     alpha: np.ndarray
     extra: dict = field(default_factory=dict)
+    # element aperture on the top face [m] (0: point elements) and the
+    # Gauss-Legendre points per aperture direction
+    elem_width: float = 0.0
+    elem_height: float = 0.0
+    elem_quad: int = 1
 
     @property
     def shape(self):

@@ -93,3 +93,20 @@ def test_workspace_size_arithmetic():
         fwi.workspace_size(p, fwi.SolveOptions(restart=12))
     with pytest.raises(fwi.FWIError):
         fwi.workspace_size(p, fwi.SolveOptions(rtol=2.0))
+
+
+def test_aperture_rule_and_validation():
+    """The library's Gauss-Legendre rule (host) against numpy's, and the
+    aperture fields of the problem checked like the others."""
+    for q in (1, 3, 8, 16):
+        x, w = fwi.host_gauss_legendre(q)
+        X, Wt = np.polynomial.legendre.leggauss(q)
+        o = np.argsort(x)
+        np.testing.assert_allclose(x[o], X, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(w[o], Wt, rtol=0, atol=1e-14)
+    with pytest.raises(ValueError):
+        fwi.host_gauss_legendre(17)
+    assert fwi.validate_problem(_prob(elem_width=0.2e-3, elem_quad=4)) == fwi.FWI_OK
+    assert fwi.validate_problem(_prob(elem_width=0.2e-3, elem_quad=0)) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(elem_width=-1e-3, elem_quad=4)) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(elem_height=1e-3, elem_quad=4)) == fwi.FWI_E_INVAL  # 2D: no height
