@@ -430,6 +430,34 @@ def test_invert_algorithm1_vs_oracle(ctx, F, tx):
     assert len(h2) == 2
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_finite_elements_vs_oracle(ctx, F, dim):
+    """Elements with an aperture (width, and elevation height in 3D): incident
+    fields, forward data and the adjoint gradient against the oracle."""
+    if dim == 2:
+        p = W.small2d(seed=63, nx=26, nz=22, ne=4, nf=2)
+        p.elem_width, p.elem_quad = 0.25e-3, 4
+    else:
+        p = W.small3d(seed=64, nx=12, ny=10, nz=9, ne=3, nf=1)
+        p.elem_width, p.elem_height, p.elem_quad = 0.3e-3, 0.6e-3, 3
+    fe = O.FiniteElements(p.elems, p.elem_width, p.elem_height, p.elem_quad)
+    args = (dim, p.nx, p.ny, p.nz, p.dx, p.c0, p.freqs, fe)
+    cen = O.cell_centres(dim, p.nx, p.ny, p.nz, p.dx)
+    for l, f in enumerate(p.freqs):
+        ref = O.incident_fields(O.wavenumber(f, p.c0), cen, fe, dim)
+        assert relerr(host(ctx.incident(p, l)), ref) < 1e-13
+    opts = F.SolveOptions(rtol=1e-12, restart=16)
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    data, _ = ctx.forward(p, c, a, opts)
+    rd, _, _ = O.forward(p.c, p.alpha, *args)
+    assert relerr(host(data), rd) < 1e-10
+    d_obs = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    phi, gm, _, _, _ = ctx.adjoint_gradient(p, c, a, dev(d_obs), opts)
+    rphi, rg, _, _, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, *args)
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert relerr(host(gm), rg) < 1e-9
+
+
 def test_synthesised_transmit_argument_errors(ctx, F):
     p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
     c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
