@@ -521,8 +521,34 @@ def conjugate_gradient(apply_A, b, n_iter):
     return x
 
 
+def coarse_shape(dim, nx, ny, nz, r):
+    """Inversion-mesh shape for an integer coarsening r of the forward mesh
+    (ceil per axis; the last cell of an axis may cover fewer forward cells)."""
+    cz, cx = -(-nz // r), -(-nx // r)
+    return (cz, cx) if dim == 2 else (cz, -(-ny // r), cx)
+
+
+def prolong(mc, dim, nx, ny, nz, r):
+    """Forward-mesh values of an inversion-mesh field (Sec. IV: the contrast is
+    represented on a coarser grid than the forward mesh). Reading: piecewise
+    constant, forward cell (i, j, k) takes inversion cell (i // r, j // r, k // r)."""
+    mc = np.asarray(mc).reshape(coarse_shape(dim, nx, ny, nz, r))
+    out = mc
+    for ax, nfine in enumerate(grid_shape(dim, nx, ny, nz)):
+        out = np.repeat(out, r, axis=ax).take(np.arange(nfine), axis=ax)
+    return out
+
+
+def restrict(gf, dim, nx, ny, nz, r):
+    """Adjoint of prolong: each inversion cell sums its forward cells."""
+    out = np.asarray(gf).reshape(grid_shape(dim, nx, ny, nz))
+    for ax, nfine in enumerate(grid_shape(dim, nx, ny, nz)):
+        out = np.add.reduceat(out, np.arange(0, nfine, r), axis=ax)
+    return out
+
+
 def admm_step(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems,
-              lam, rho, gamma, n_cg, data_scale=1.0, dual_step=None):
+              lam, rho, gamma, n_cg, data_scale=1.0, dual_step=None, inv_factor=1):
     """One iteration of Algorithm 1 (forward, model update, g update, u update).
 
     Model update: Gauss-Newton normal equations (Eq. 11-12) with the data term
@@ -533,15 +559,21 @@ def admm_step(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems,
     solved by exactly n_cg CG iterations from zero (the gamma terms are dropped
     when m_ref is None). Then g = shrink_{lam/rho}(nabla m_{k+1} - u_k) (Eq. 13-14)
     and u += dual_step (g - nabla m_{k+1}) with dual_step = rho as printed.
+    inv_factor r > 1: m, g, u, m_ref live on the inversion mesh (coarse_shape),
+    the forward model is prolong(m), the Jacobian is J P (its adjoint
+    P^T J^H) and nabla acts on the inversion mesh.
     Returns (m, g, u, report)."""
     if dual_step is None:
         dual_step = rho
-    shape = grid_shape(dim, nx, ny, nz)
+    r_ = int(inv_factor)
+    shape = grid_shape(dim, nx, ny, nz) if r_ <= 1 else coarse_shape(dim, nx, ny, nz, r_)
+    P = (lambda a: a) if r_ <= 1 else (lambda a: prolong(a, dim, nx, ny, nz, r_))
+    PT = (lambda a: a) if r_ <= 1 else (lambda a: restrict(a, dim, nx, ny, nz, r_))
     m = m.reshape(shape)
-    data, fields, _ = forward_m(m, dim, nx, ny, nz, dx, c0, freqs, elems)
+    data, fields, _ = forward_m(P(m), dim, nx, ny, nz, dx, c0, freqs, elems)
     r = d_obs - data
     gm = tv_grad(m)
-    b = data_scale * jacobian_adjoint_apply(fields, r, freqs, c0, dx, dim).reshape(shape)
+    b = data_scale * PT(jacobian_adjoint_apply(fields, r, freqs, c0, dx, dim)).reshape(shape)
     b = b + rho * tv_grad_T(g + u - gm)
     use_ref = m_ref is not None and gamma != 0.0
     if use_ref:
@@ -549,8 +581,8 @@ def admm_step(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems,
 
     def apply_A(a):
         a = a.reshape(shape)
-        Ja = jacobian_apply(fields, a.reshape(-1), freqs, c0, dx, dim)
-        out = data_scale * jacobian_adjoint_apply(fields, Ja, freqs, c0, dx, dim).reshape(shape)
+        Ja = jacobian_apply(fields, P(a).reshape(-1), freqs, c0, dx, dim)
+        out = data_scale * PT(jacobian_adjoint_apply(fields, Ja, freqs, c0, dx, dim)).reshape(shape)
         out = out + rho * tv_grad_T(tv_grad(a))
         if use_ref:
             out = out + gamma * a
@@ -621,13 +653,13 @@ def sos_from_contrast(m, c0):
 
 
 def invert(m0, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, lam, rho, gamma, n_cg, max_iter, tol=0.0,
-           m_ref=None, data_scale=1.0, dual_step=None, weights=None, born_every=0):
+           m_ref=None, data_scale=1.0, dual_step=None, weights=None, born_every=0, inv_factor=1):
     """Algorithm 1: g_0 = nabla m_0, u_0 = 0, then ADMM iterations (admm_step,
     or admm_step_tx with receiver fields recomputed at the first iteration and
     every born_every-th one, reused in between) until the misfit at an iterate
     is <= tol * 1/2 ||d_obs||^2 (that iteration's update kept) or max_iter
     iterations have run. Returns (m, g, u, misfits per iteration)."""
-    shape = grid_shape(dim, nx, ny, nz)
+    shape = grid_shape(dim, nx, ny, nz) if inv_factor <= 1 else coarse_shape(dim, nx, ny, nz, inv_factor)
     m = np.asarray(m0, dtype=np.complex128).reshape(shape)
     g = tv_grad(m)
     u = np.zeros_like(g)
@@ -636,7 +668,8 @@ def invert(m0, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, lam, rho, gamma, n_
     hist, rx = [], None
     for k in range(max_iter):
         if weights is None:
-            m, g, u, rep = admm_step(m, g, u, m_ref, d_obs, *args, lam, rho, gamma, n_cg, data_scale, dual_step)
+            m, g, u, rep = admm_step(m, g, u, m_ref, d_obs, *args, lam, rho, gamma, n_cg, data_scale, dual_step,
+                                     inv_factor=inv_factor)
         else:
             refresh = k == 0 or (born_every > 0 and k % born_every == 0)
             m, g, u, rep, rx = admm_step_tx(m, g, u, m_ref, d_obs, *args, weights, lam, rho, gamma, n_cg,

@@ -623,3 +623,46 @@ def test_finite_elements_aperture_average():
            + 1j * si.dblquad(g, -0.15e-3, 0.15e-3, -0.25e-3, 0.25e-3, args=(np.imag,), epsabs=0,
                              epsrel=1e-12)[0]) / (0.3e-3 * 0.5e-3)
     assert abs(P3[0, n] - ref) < 1e-10 * abs(ref)
+
+
+def test_coarse_inversion_mesh():
+    """Inversion mesh r times coarser (ragged extents): restrict is the adjoint
+    of prolong, r = 1 is the forward-mesh step, and the ADMM step solves the
+    dense normal equations with the Jacobian J P and nabla on the coarse mesh."""
+    rng = np.random.default_rng(6)
+    for dim, (nx, ny, nz) in ((2, (7, 1, 5)), (3, (5, 4, 3))):
+        cs = O.coarse_shape(dim, nx, ny, nz, 2)
+        a = rng.standard_normal(cs) + 1j * rng.standard_normal(cs)
+        b = rng.standard_normal(O.grid_shape(dim, nx, ny, nz)) + 1j * rng.standard_normal(O.grid_shape(dim, nx, ny, nz))
+        lhs = np.vdot(O.prolong(a, dim, nx, ny, nz, 2), b)
+        rhs = np.vdot(a, O.restrict(b, dim, nx, ny, nz, 2))
+        assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    p = W.small2d(seed=24, nx=7, nz=5, ne=3, nf=2)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    d_obs = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    s = 1.0 / np.sum(np.abs(d_obs) ** 2)
+    cs = O.coarse_shape(2, p.nx, 1, p.nz, 2)
+    mc = 0.02 * (rng.standard_normal(cs) + 1j * rng.standard_normal(cs))
+    g = O.tv_grad(mc)
+    u = 0.01 * (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape))
+    lam, rho, gam = 1e-3, 1e-2, 1e-5
+    ref = np.zeros_like(mc)
+    m1, g1, u1, rep = O.admm_step(mc, g, u, ref, d_obs, *args, lam, rho, gam, 200, data_scale=s, inv_factor=2)
+    mf = O.prolong(mc, 2, p.nx, 1, p.nz, 2)
+    data, fields, _ = O.forward_m(mf, *args)
+    J = np.concatenate([np.stack([p.dx**2 * O.wavenumber(f, p.c0) ** 2 * fields[l][i] * fields[l][j]
+                                  for i in range(p.ne) for j in range(p.ne)]) for l, f in enumerate(p.freqs)])
+    nc = mc.size
+    Pm = np.stack([O.prolong(np.eye(nc)[k].reshape(cs), 2, p.nx, 1, p.nz, 2).ravel() for k in range(nc)], axis=1)
+    Jc = J @ Pm
+    D = _dense_grad_matrix(*cs)
+    A = s * Jc.conj().T @ Jc + rho * D.T @ D + gam * np.eye(nc)
+    b = (s * Jc.conj().T @ (d_obs - data).ravel() + rho * D.T @ (g + u).reshape(-1) - rho * D.T @ D @ mc.ravel()
+         + gam * (ref - mc).ravel())
+    np.testing.assert_allclose(m1.ravel(), mc.ravel() + np.linalg.solve(A, b), rtol=0, atol=1e-9 * np.abs(m1 - mc).max())
+    m0 = O.contrast(p.c, p.alpha, p.c0)
+    a1 = O.admm_step(m0, O.tv_grad(m0), np.zeros((2,) + m0.shape, complex), None, d_obs, *args, lam, rho, 0.0, 5,
+                     data_scale=s)
+    a2 = O.admm_step(m0, O.tv_grad(m0), np.zeros((2,) + m0.shape, complex), None, d_obs, *args, lam, rho, 0.0, 5,
+                     data_scale=s, inv_factor=1)
+    np.testing.assert_array_equal(a1[0], a2[0])
