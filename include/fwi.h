@@ -121,6 +121,10 @@ typedef struct fwi_admm_params {
   int n_cg;           /* CG iterations on the normal equations (Eq. 11-12) */
   double data_scale;  /* s multiplying the data term; <= 0 selects 1/||d_obs||^2 */
   double dual_step;   /* u += dual_step (g - grad m); the paper prints rho */
+  int inv_factor;     /* inversion mesh (Sec. IV: coarser than the forward mesh): <= 1 the forward
+                         mesh; r > 1 cells of r x r (x r) forward cells (ceil per axis, ragged last
+                         cells), piecewise-constant model, Jacobian J P. m, g, u, m_ref then live on
+                         the inversion mesh ([ceil(nz/r)][ceil(ny/r)][ceil(nx/r)]) */
 } fwi_admm_params;
 
 typedef struct fwi_admm_report {

@@ -738,6 +738,7 @@ struct CallBufs {
   // ADMM
   c128 *cg_x = nullptr, *cg_r = nullptr, *cg_p = nullptr, *cg_Ap = nullptr, *vec = nullptr;
   c128 *gm = nullptr, *tmpd = nullptr, *Jp = nullptr;
+  c128* fine = nullptr;     // [n] forward-mesh vector of a coarse inversion mesh
   double *dpart = nullptr, *sc = nullptr;
 };
 
@@ -785,6 +786,7 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
     cb.gm = a.take<c128>((size_t)g.dim * n);
     cb.tmpd = a.take<c128>((size_t)g.dim * n);
     cb.Jp = a.take<c128>(ndata);
+    cb.fine = a.take<c128>(n);
     cb.dpart = a.take<double>(std::max(dot_blocks(n), (int)((n + 255) / 256)) + 8);
     cb.sc = a.take<double>(8);
   }
@@ -1175,6 +1177,19 @@ void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int n
                  out, c->stream);
 }
 
+// Inversion mesh r times coarser than the forward mesh (ceil per axis).
+Geo coarse_geo(const Geo& g, int r) {
+  Geo c = g;
+  if (r > 1) {
+    c.nx = (g.nx + r - 1) / r;
+    c.ny = g.dim == 3 ? (g.ny + r - 1) / r : 1;
+    c.nz = (g.nz + r - 1) / r;
+  }
+  return c;
+}
+// Receiver fields of the Jacobian: the forward fields for element transmits.
+inline const c128* rxf_of(const CallBufs& cb, const c128* rx, bool tx) { return tx ? rx : cb.fields; }
+
 // One ADMM iteration. nt = 0: element transmits (the Jacobian from the
 // forward fields alone). nt > 0: synthesised transmits with weights w
 // [nf][nt][ne] and receiver fields rx [nf][ne][n], recomputed at m_k when
@@ -1196,8 +1211,13 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   prepare<T>(c, R, sb, FWI_ENTRY_ADMM);
   hipStream_t st = c->stream;
   const int ntx = tx ? nt : p->ne;
-  const long n = R.n, ndata = (long)p->nf * ntx * p->ne;
+  const long ndata = (long)p->nf * ntx * p->ne;
   const Geo& g = R.g;
+  // inversion mesh: the forward mesh, or r times coarser (piecewise-constant
+  // model, Jacobian J P, TV on the coarse cells)
+  const int rf = prm->inv_factor > 1 ? prm->inv_factor : 1;
+  const Geo gc = coarse_geo(g, rf);
+  const long n = gc.n();
   CallBufs& cb = R.cb;
   c128* m = (c128*)m_io;
   c128* gg = (c128*)g_io;
@@ -1206,17 +1226,32 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   const c128* mref = (const c128*)m_ref;
   const bool use_ref = mref && prm->gamma != 0.0;
   check_complex(c, n, m, "m");
-  launch_copy_c128(n, m, cb.m64, st);
-  launch_cast_64_32(n, cb.m64, cb.m32, st);
+  if (rf > 1) launch_prolong(g, rf, m, cb.m64, st);
+  else launch_copy_c128(n, m, cb.m64, st);
+  launch_cast_64_32(R.n, cb.m64, cb.m32, st);
+  // J^H b and J a on the inversion mesh
+  auto jh = [&](const c128* b, c128* out) {
+    if (rf > 1) {
+      jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf_of(cb, rx, tx), b, cb.fine);
+      launch_restrict(g, rf, cb.fine, out, st);
+    } else {
+      jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf_of(cb, rx, tx), b, out);
+    }
+  };
+  auto jv = [&](const c128* a, c128* out) {
+    if (rf > 1) {
+      launch_prolong(g, rf, a, cb.fine, st);
+      a = cb.fine;
+    }
+    j_apply(c, p, g, cb, ntx, cb.fields, rxf_of(cb, rx, tx), a, out);
+  };
   // 1. forward solves at m_k, all fields kept for the Jacobian products
-  const c128* rxf = cb.fields;
   if (tx) {
     const long nw = (long)p->nf * nt * p->ne;
     check_complex(c, nw, (const c128*)w, "transmit weights");
     launch_conj_c128(nw, (const c128*)w, cb.wtx, st);
     R.forward_tx<T>(sb, nt, cb.data, cb.fields);
     if (refresh_rx) R.forward<T>(sb, cb.Jp, rx);  // receiver fields at m_k (data not used)
-    rxf = rx;
   } else {
     R.forward<T>(sb, cb.data, cb.fields);
   }
@@ -1232,10 +1267,10 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   const double rho = prm->rho, gam = use_ref ? prm->gamma : 0.0;
   const double dual = prm->dual_step;
   // 3. b = -s J^H(F - d) + rho grad^T(g + u - grad m) + gamma (m_ref - m)
-  jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf, cb.r, cb.vec);
-  launch_tv_grad(g, m, cb.gm, st);
-  launch_lincomb((long)g.dim * n, 1.0, gg, 1.0, uu, -1.0, cb.gm, cb.tmpd, st);
-  launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_r, st);
+  jh(cb.r, cb.vec);
+  launch_tv_grad(gc, m, cb.gm, st);
+  launch_lincomb((long)gc.dim * n, 1.0, gg, 1.0, uu, -1.0, cb.gm, cb.tmpd, st);
+  launch_tv_gradT(gc, cb.tmpd, rho, 0.0, cb.cg_r, st);
   launch_lincomb(n, 1.0, cb.cg_r, -s, cb.vec, 0.0, nullptr, cb.cg_r, st);
   if (use_ref) launch_lincomb(n, 1.0, cb.cg_r, gam, mref, -gam, m, cb.cg_r, st);
   // 4. CG on (s J^H J + rho grad^T grad + gamma I) dm = b from dm = 0
@@ -1243,10 +1278,10 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   launch_copy_c128(n, cb.cg_r, cb.cg_p, st);
   launch_dot_re(n, cb.cg_r, cb.cg_r, cb.dpart, cb.sc + 0, st);
   for (int it = 0; it < prm->n_cg; ++it) {
-    j_apply(c, p, g, cb, ntx, cb.fields, rxf, cb.cg_p, cb.Jp);
-    jh_apply(c, p, g, cb, R.nfg, ntx, cb.fields, rxf, cb.Jp, cb.vec);
-    launch_tv_grad(g, cb.cg_p, cb.tmpd, st);
-    launch_tv_gradT(g, cb.tmpd, rho, 0.0, cb.cg_Ap, st);
+    jv(cb.cg_p, cb.Jp);
+    jh(cb.Jp, cb.vec);
+    launch_tv_grad(gc, cb.cg_p, cb.tmpd, st);
+    launch_tv_gradT(gc, cb.tmpd, rho, 0.0, cb.cg_Ap, st);
     launch_lincomb(n, 1.0, cb.cg_Ap, s, cb.vec, gam, use_ref ? cb.cg_p : nullptr, cb.cg_Ap, st);
     launch_dot_re(n, cb.cg_p, cb.cg_Ap, cb.dpart, cb.sc + 1, st);
     launch_cg_step1(n, cb.sc, cb.cg_x, cb.cg_r, cb.cg_p, cb.cg_Ap, st);
@@ -1256,8 +1291,8 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   }
   // 5. m += dm; g = shrink(grad m - u); u += dual (g - grad m)
   launch_lincomb(n, 1.0, m, 1.0, cb.cg_x, 0.0, nullptr, m, st);
-  launch_tv_grad(g, m, cb.gm, st);
-  const int nb = launch_tv_shrink_dual(g, cb.gm, prm->lambda / rho, dual, gg, uu, cb.dpart, st);
+  launch_tv_grad(gc, m, cb.gm, st);
+  const int nb = launch_tv_shrink_dual(gc, cb.gm, prm->lambda / rho, dual, gg, uu, cb.dpart, st);
   launch_sum(nb, cb.dpart, cb.sc + 6, st);
   launch_dot_re(n, cb.cg_x, cb.cg_x, cb.dpart, cb.sc + 7, st);
   FWI_HIP(hipMemcpyAsync(c->h_dbl, cb.sc + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1627,7 +1662,7 @@ int invert_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, in
   std::string msg;
   int rc = validate_problem(p, msg);
   if (rc) throw Error(rc, msg);
-  const Geo g = make_geo(p);
+  const Geo g = coarse_geo(make_geo(p), prm->inv_factor);
   launch_tv_grad(g, (const c128*)m_io, (c128*)g_out, c->stream);
   launch_fill_zero_c128((long)g.dim * g.n(), (c128*)u_out, c->stream);
   if (done) *done = 0;

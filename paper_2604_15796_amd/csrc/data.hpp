@@ -32,6 +32,10 @@ void launch_cg_step1(long n, const double* sc, c128* x, c128* r, const c128* p, 
 void launch_cg_step2(long n, const double* sc, const c128* r, c128* p, hipStream_t st);
 void launch_copy_scalar(const double* in, double* out, hipStream_t st);
 void launch_conj_c128(long count, const c128* in, c128* out, hipStream_t st);
+// coarse inversion mesh (factor r) <-> forward mesh g: piecewise-constant
+// prolongation and its adjoint
+void launch_prolong(const Geo& g, int r, const c128* mc, c128* mf, hipStream_t st);
+void launch_restrict(const Geo& g, int r, const c128* gf, c128* gcv, hipStream_t st);
 void launch_fill_rfreq(int B, int per, int l0, int* rf, hipStream_t st);
 
 }  // namespace fwi

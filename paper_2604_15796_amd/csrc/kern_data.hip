@@ -506,6 +506,52 @@ void launch_copy_scalar(const double* in, double* out, hipStream_t st) {
   FWI_LAUNCH_CHECK();
 }
 
+// Coarse inversion mesh (factor r): forward cell (ix, iy, iz) takes coarse
+// cell (ix / r, iy / r, iz / r); the restriction sums each coarse cell's
+// forward cells in a fixed order (the adjoint of the prolongation).
+__global__ void k_prolong(TvGeo g, int r, const c128* __restrict__ mc, c128* __restrict__ mf) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int ix = (int)(i % g.nx), iy = (int)((i / g.nx) % g.ny), iz = (int)(i / ((long)g.nx * g.ny));
+  const int cx = (g.nx + r - 1) / r, cy = g.dim == 3 ? (g.ny + r - 1) / r : 1;
+  const int jy = g.dim == 3 ? iy / r : 0;
+  mf[i] = mc[((long)(iz / r) * cy + jy) * cx + ix / r];
+}
+__global__ void k_restrict(TvGeo g, int r, const c128* __restrict__ gf, c128* __restrict__ gcv) {
+  const int cx = (g.nx + r - 1) / r, cy = g.dim == 3 ? (g.ny + r - 1) / r : 1, cz = (g.nz + r - 1) / r;
+  const long nc = (long)cx * cy * cz;
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  const int jx = (int)(j % cx), jy = (int)((j / cx) % cy), jz = (int)(j / ((long)cx * cy));
+  const int ry = g.dim == 3 ? r : 1;
+  c128 s = mk(0.0, 0.0);
+  for (int a = 0; a < r; ++a) {
+    const int iz = jz * r + a;
+    if (iz >= g.nz) break;
+    for (int b = 0; b < ry; ++b) {
+      const int iy = g.dim == 3 ? jy * r + b : 0;
+      if (iy >= g.ny) break;
+      for (int e = 0; e < r; ++e) {
+        const int ix = jx * r + e;
+        if (ix >= g.nx) break;
+        s = s + gf[((long)iz * g.ny + iy) * g.nx + ix];
+      }
+    }
+  }
+  gcv[j] = s;
+}
+void launch_prolong(const Geo& g, int r, const c128* mc, c128* mf, hipStream_t st) {
+  const long n = g.n();
+  hipLaunchKernelGGL(k_prolong, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, tvgeo(g), r, mc, mf);
+  FWI_LAUNCH_CHECK();
+}
+void launch_restrict(const Geo& g, int r, const c128* gf, c128* gcv, hipStream_t st) {
+  const long nc = (long)((g.nx + r - 1) / r) * (g.dim == 3 ? (g.ny + r - 1) / r : 1) * ((g.nz + r - 1) / r);
+  hipLaunchKernelGGL(k_restrict, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, tvgeo(g), r, gf, gcv);
+  FWI_LAUNCH_CHECK();
+}
+
 // out[i] = conj(in[i]) (transmit weights into the form the NN product takes)
 __global__ void k_conj_c128(long count, const c128* __restrict__ in, c128* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;

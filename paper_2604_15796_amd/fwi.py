@@ -63,7 +63,7 @@ class CStats(C.Structure):
 
 class CAdmmParams(C.Structure):
     _fields_ = [("lam", C.c_double), ("rho", C.c_double), ("gamma", C.c_double), ("n_cg", C.c_int),
-                ("data_scale", C.c_double), ("dual_step", C.c_double)]
+                ("data_scale", C.c_double), ("dual_step", C.c_double), ("inv_factor", C.c_int)]
 
 
 class CAdmmReport(C.Structure):
@@ -222,6 +222,14 @@ def _ptr(t):
     if not t.is_contiguous():
         raise ValueError("contiguous tensor expected")
     return C.c_void_p(t.data_ptr())
+
+
+def inversion_shape(prob, r):
+    """Shape of the inversion mesh r times coarser than the forward mesh."""
+    if r <= 1:
+        return prob.shape
+    cz, cx = -(-prob.nz // r), -(-prob.nx // r)
+    return (cz, cx) if prob.dim == 2 else (cz, -(-prob.ny // r), cx)
 
 
 def _check_dtype(t, dtype, shape, what):
@@ -416,14 +424,16 @@ class Context:
         return gm, st.as_dict()
 
     def tv_admm_step(self, prob, m, g, u, d_obs, lam, rho, gamma=0.0, n_cg=10, m_ref=None, data_scale=0.0,
-                     dual_step=None, opts=None, allow_noconv=False):
-        """One ADMM iteration; m, g, u (complex128 device tensors) are updated in place."""
+                     dual_step=None, opts=None, allow_noconv=False, inv_factor=1):
+        """One ADMM iteration; m, g, u (complex128 device tensors, on the
+        inversion mesh when inv_factor > 1) are updated in place."""
         prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
         o = (opts or SolveOptions()).c()
-        _check_dtype(m, torch.complex128, prob.shape, "m")
-        _check_dtype(g, torch.complex128, (prob.dim,) + prob.shape, "g")
-        _check_dtype(u, torch.complex128, (prob.dim,) + prob.shape, "u")
-        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        shp = inversion_shape(prob, inv_factor)
+        _check_dtype(m, torch.complex128, shp, "m")
+        _check_dtype(g, torch.complex128, (prob.dim,) + shp, "g")
+        _check_dtype(u, torch.complex128, (prob.dim,) + shp, "u")
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step, inv_factor)
         rep = CAdmmReport()
         st = CStats()
         self._stream()
@@ -446,7 +456,7 @@ class Context:
         _check_dtype(u, torch.complex128, (prob.dim,) + prob.shape, "u")
         _check_dtype(rx_fields, torch.complex128, (prob.nf, prob.ne, prob.n), "rx_fields")
         _check_dtype(d_obs, torch.complex128, (prob.nf, nt, prob.ne), "d_obs")
-        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step, 1)
         rep = CAdmmReport()
         st = CStats()
         self._stream()
@@ -458,7 +468,7 @@ class Context:
         return {"misfit": rep.misfit, "tv": rep.tv, "dm_norm": rep.dm_norm}, st.as_dict()
 
     def invert(self, prob, m, d_obs, lam, rho, gamma=0.0, n_cg=10, max_iter=20, tol=0.0, m_ref=None,
-               data_scale=0.0, dual_step=None, w=None, born_every=0, opts=None, allow_noconv=False):
+               data_scale=0.0, dual_step=None, w=None, born_every=0, opts=None, allow_noconv=False, inv_factor=1):
         """Algorithm 1 from m (complex128 device tensor, updated in place): up to
         max_iter ADMM iterations, stopping once the misfit at an iterate is
         <= tol * 1/2 ||d_obs||^2. w [nf, nt, ne]: synthesised transmits with
@@ -466,13 +476,14 @@ class Context:
         (misfit per iteration, g, u, stats)."""
         prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
         o = (opts or SolveOptions()).c()
-        _check_dtype(m, torch.complex128, prob.shape, "m")
+        shp = inversion_shape(prob, inv_factor)
+        _check_dtype(m, torch.complex128, shp, "m")
         nt = self._tx_weights(prob, w) if w is not None else 0
         _check_dtype(d_obs, torch.complex128, (prob.nf, nt or prob.ne, prob.ne), "d_obs")
-        g = torch.empty((prob.dim,) + prob.shape, dtype=torch.complex128, device=self.device)
+        g = torch.empty((prob.dim,) + shp, dtype=torch.complex128, device=self.device)
         u = torch.empty_like(g)
         rx = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if nt else None
-        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step)
+        prm = CAdmmParams(lam, rho, gamma, n_cg, data_scale, rho if dual_step is None else dual_step, inv_factor)
         hist = (C.c_double * max(max_iter, 1))()
         done = C.c_int()
         st = CStats()

@@ -458,6 +458,37 @@ def test_finite_elements_vs_oracle(ctx, F, dim):
     assert relerr(host(gm), rg) < 1e-9
 
 
+@pytest.mark.parametrize("r", [2, 3])
+def test_admm_and_invert_on_coarse_inversion_mesh_vs_oracle(ctx, F, r):
+    """Inversion mesh r times coarser than the forward mesh (ragged extents):
+    one ADMM step and two iterations of Algorithm 1 against the oracle."""
+    p = W.small2d(seed=65, nx=21, nz=19, ne=4, nf=2)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    d_obs = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    cs = O.coarse_shape(2, p.nx, 1, p.nz, r)
+    rng = np.random.default_rng(66)
+    m0 = 0.02 * (rng.standard_normal(cs) + 1j * rng.standard_normal(cs))
+    g0 = O.tv_grad(m0)
+    u0 = W.random_complex(5, g0.shape, 1e-3)
+    lam, rho, gam, ncg = 1e-3, 1e-2, 1e-5, 6
+    s = 1.0 / float(np.sum(np.abs(d_obs) ** 2))
+    opts = F.SolveOptions(rtol=1e-13, restart=16)
+    rm, rg, ru, rep = O.admm_step(m0, g0, u0, np.zeros_like(m0), d_obs, *args, lam, rho, gam, ncg, data_scale=s,
+                                  inv_factor=r)
+    mt, gt, ut = dev(m0), dev(g0), dev(u0)
+    grep, _ = ctx.tv_admm_step(p, mt, gt, ut, dev(d_obs), lam, rho, gam, ncg, m_ref=dev(np.zeros_like(m0)),
+                               data_scale=s, opts=opts, inv_factor=r)
+    assert relerr(host(mt), rm) < 1e-8 and relerr(host(gt), rg) < 1e-8 and relerr(host(ut), ru) < 1e-8
+    assert abs(grep["misfit"] - rep["misfit"]) < 1e-9 * rep["misfit"]
+    rm2, rg2, ru2, rhist = O.invert(np.zeros(cs, complex), d_obs, *args, lam, rho, gam, ncg, max_iter=2,
+                                    m_ref=np.zeros(cs, complex), data_scale=s, inv_factor=r)
+    mi = torch.zeros(cs, dtype=torch.complex128, device=DEV)
+    hist, gi, ui, _ = ctx.invert(p, mi, dev(d_obs), lam, rho, gam, ncg, max_iter=2, m_ref=torch.zeros_like(mi),
+                                 data_scale=s, opts=opts, inv_factor=r)
+    np.testing.assert_allclose(hist, rhist, rtol=1e-9, atol=1e-9 * rhist[0])
+    assert relerr(host(mi), rm2) < 1e-8 and relerr(host(gi), rg2) < 1e-8 and relerr(host(ui), ru2) < 1e-8
+
+
 def test_synthesised_transmit_argument_errors(ctx, F):
     p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
     c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
