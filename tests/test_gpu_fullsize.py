@@ -115,6 +115,34 @@ def test_cfg1_gradient_mixed_vs_fp64_and_properties(ctx, F, cfg1):
     assert rel(data, data.transpose(1, 2)) < 1e-9
 
 
+def test_cfg1_plane_wave_transmits(ctx, F, cfg1):
+    """The 256^2 workload firing 60 plane waves (the plane-wave bench line):
+    sampled transmit fields against the oracle, the mixed gradient against
+    the plain FP64 one, and the adjoint-solve gradient against J^H r built
+    from the transmit fields and the receiver (element) fields."""
+    p, c, a, _ = cfg1
+    w = W.plane_wave_weights(p.freqs, p.elems, np.linspace(-60.0, 60.0, 60), p.c0)
+    wd = t(w)
+    d_obs, _ = ctx.forward_tx(p, t(p.extra["c_obs"]), a, wd, plain(F))
+    _, fields, st = ctx.forward_tx(p, c, a, wd, mixed(F, inner_rtol=1e-6), fields=True)
+    assert st["unconverged"] == 0 and st["solves"] == p.nf * 60
+    m = O.contrast(p.c, p.alpha, p.c0)
+    cen = O.cell_centres(2, p.nx, 1, p.nz, p.dx)
+    for l, tx in [(0, 0), (5, 29), (7, 59)]:
+        k = O.wavenumber(p.freqs[l], p.c0)
+        rhs = w[l, tx] @ O.incident_fields(k, cen, p.elems, 2)
+        ref = O.solve(k, m, rhs[None], 2, p.nx, 1, p.nz, p.dx)[0]
+        assert rel(fields[l, tx], ref) < 1e-5, (l, tx)
+    del fields
+    phi32, g32, _, _, _ = ctx.adjoint_gradient_tx(p, c, a, wd, d_obs, mixed(F, inner_rtol=1e-6))
+    phi64, g64, _, _, _ = ctx.adjoint_gradient_tx(p, c, a, wd, d_obs, plain(F))
+    assert rel(g32, g64) < 1e-4 and abs(phi32 - phi64) < 1e-4 * phi64
+    data, ftx, _ = ctx.forward_tx(p, c, a, wd, plain(F), fields=True)
+    _, frx, _ = ctx.forward(p, c, a, plain(F), fields=True)
+    jhr = ctx.jacobian_adjoint_apply_tx(p, ftx, frx, data - d_obs)
+    assert rel(g64, jhr) < 1e-8
+
+
 def test_cfg1_directional_derivative(ctx, F, cfg1):
     """(phi(m + h dm) - phi(m - h dm)) / 2h = Re <g, dm> (FP64, full size)."""
     p, c, a, d_obs = cfg1
