@@ -64,12 +64,14 @@ def parse():
     ap.add_argument("--cpu-solves", type=int, default=8,
                     help="oracle forward (and adjoint) solves per frequency in the CPU sample")
     ap.add_argument("--workload", default="gradient-256",
-                    choices=["gradient-256", "planewave-256", "uneven-batch", "invert-384"],
+                    choices=["gradient-256", "planewave-256", "uneven-batch", "invert-384", "gradient-3d"],
                     help="gradient-256: the headline workload; planewave-256: the same grid, frequencies and "
                          "array firing 60 steered plane waves (-60..60 degrees) instead of single elements; "
                          "uneven-batch: 32 instances of different grids, element and frequency counts through "
                          "the graph-replayed batched path; invert-384: Algorithm 1 on the 384^2 thyroid-like "
-                         "phantom from noisy data, FWI-TV against basic FWI (speed-of-sound RMSE and SSIM)")
+                         "phantom from noisy data, FWI-TV against basic FWI (speed-of-sound RMSE and SSIM); "
+                         "gradient-3d: 128x128x96, 4 frequencies, 64 elements, one frequency per batched solve "
+                         "(fields recomputed per frequency)")
     ap.add_argument("--iters", type=int, default=20, help="ADMM iterations of the invert-384 workload")
     ap.add_argument("--tuning", default=None,
                     help="hex tuning table (as printed in tuning_hex) to use instead of autotuning")
@@ -99,13 +101,16 @@ def main():
     if args.workload == "invert-384":
         return bench_invert(args)
     dev = torch.device("cuda", 0)
-    p = W.config1()
+    three_d = args.workload == "gradient-3d"
+    p = W.config4() if three_d else W.config1()
+    if three_d and args.max_rhs == 0:
+        args.max_rhs = p.ne  # one frequency per batched solve: fields recomputed, never all stored
     prob = fwi.ProblemArgs(p)
     ctx = fwi.Context(0)
     c = torch.as_tensor(p.c).to(dev)
     a = torch.as_tensor(p.alpha).to(dev)
     c_obs = torch.as_tensor(p.extra["c_obs"]).to(dev)
-    ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32)
+    ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32, max_rhs=args.max_rhs)
     planewave = args.workload == "planewave-256"
     # plane-wave transmits: unit-amplitude steering weights [nf, nt, ne]
     w_tx = torch.as_tensor(W.plane_wave_weights(p.freqs, p.elems, np.linspace(-60.0, 60.0, 60), p.c0)).to(dev) \
@@ -123,8 +128,9 @@ def main():
     if args.tuning:
         ctx.set_tuning(bytes.fromhex(args.tuning))
     elif not args.no_tune:
-        tune["c64"] = ctx.autotune(prob, fwi.FWI_FP32_REFINE, B=p.nf * p.ne, reps=3)
-        tune["c128"] = ctx.autotune(prob, fwi.FWI_FP64, B=p.nf * p.ne, reps=2)
+        tb = min(p.nf * p.ne, args.max_rhs) if args.max_rhs else p.nf * p.ne
+        tune["c64"] = ctx.autotune(prob, fwi.FWI_FP32_REFINE, B=tb, reps=3)
+        tune["c128"] = ctx.autotune(prob, fwi.FWI_FP64, B=tb, reps=2)
         log(f"autotune: {tune}")
     tuned_table = ctx.get_tuning()
 
@@ -191,18 +197,23 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = solves_per_step / (ms_step * 1e-3)
     log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
-    # counter figures were taken on the element-transmit workload only
-    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not planewave)
+    # counter figures were taken on the 2D element-transmit workload only
+    nf_launch = max(1, min(p.nf, args.max_rhs // p.ne)) if args.max_rhs else p.nf
+    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not (planewave or three_d),
+                              nf_launch=nf_launch)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
            "config": {"workload": ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements firing 60 plane "
                                    "waves -60..60 deg: forward+adjoint gradient (480+480 solves)") if planewave else
+                                  ("3D 128x128x96 dx=0.2mm, 4 freqs 0.4-0.8 MHz, 64 elements: forward+adjoint "
+                                   "gradient (256+256 solves), one frequency per batched solve") if three_d else
                                   ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
                                    "forward+adjoint gradient (512+512 solves)"),
+                      "max_rhs": args.max_rhs,
                       "transmits_per_freq": int(nt),
-                      "grid": [p.nz, p.nx], "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
+                      "grid": list(p.shape), "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
                       "precision": "complex64 GMRES in FP64-residual refinement",
                       "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
            "roofline": roofline,
@@ -235,7 +246,7 @@ def main():
         out["speedup_vs_fp64_plain"] = round(ms_plain / ms_step, 3)
         log(f"accuracy: field {field_err:.2e}, grad {grad_err:.2e}; fp64 plain {ms_plain:.1f} ms")
 
-    if not args.no_cpu:
+    if not args.no_cpu and not three_d:
         out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
         if planewave:
             out["cpu_baseline"]["sample"] += " (element sources: same operators and per-solve cost)"
@@ -253,7 +264,7 @@ def strided_tile(L, es, v):
     return nl, (512 if v == 2 else 256)
 
 
-def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True):
+def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True, nf_launch=None):
     """Roofline of the dominant kernel class over the timed launches.
 
     The 2D convolution pass (forward FFT, spectrum product, inverse FFT along
@@ -270,17 +281,19 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True):
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": prof["bytes"] / launches}
     table = ctx.get_tuning()
     entry = {"kernel": dominant, "avg_launch_us": round(prof["ms"] * 1e3 / launches, 2), "launches": launches}
-    if dominant == "conv_c64" and p.dim == 2:
-        Lz, Lx = ctx.padded_shape(prob)
+    if dominant == "conv_c64":
+        shp = ctx.padded_shape(prob)
+        Lz, Lx = shp[0], shp[-1]
+        cols = Lx * (shp[1] if p.dim == 3 else 1)       # lines of the depth-axis convolution per RHS
         es = 8
         li = [32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024].index(Lz)
         v = table[(2 * 2 + 0) * 11 + li]  # pass PK_CONV, complex64, length index
         v = 2 if v in (255, -1) else v     # unset: built-in default of the complex64 convolution pass
         nl, nt = strided_tile(Lz, es, v)
         name = f"k_strided<float, {Lz}, {nl}, {nt}, 2, true, false>"
-        gbytes = p.nf * Lz * Lx * es                     # spectra read once per launch
-        per_rhs_bytes = 2.0 * p.nz * Lx * es             # half-padded plane in and out
-        per_rhs_flops = Lx * (2 * 5 * Lz * np.log2(Lz) + 6 * Lz)
+        gbytes = (nf_launch or p.nf) * Lz * cols * es    # spectra of the launch's frequencies, read once
+        per_rhs_bytes = 2.0 * p.nz * cols * es           # half-padded volume in and out
+        per_rhs_flops = cols * (2 * 5 * Lz * np.log2(Lz) + 6 * Lz)
         rhs = (prof["bytes"] - launches * gbytes) / per_rhs_bytes
         flops = rhs * per_rhs_flops
         tf = flops / sec / 1e12
@@ -292,7 +305,7 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True):
                       "flops_per_launch": flops / launches, "kernel_name": name,
                       "traffic": m.get("traffic"), "valu_busy": m.get("valu_busy"), "hbm": hbm})
     else:
-        name = hbm_kernel_name(ctx, prob, dominant)
+        name = hbm_kernel_name(ctx, prob, dominant) if p.dim == 2 else None
         m = MEASURED.get(name, {}) if name and measured else {}
         entry.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "kernel_name": name,
