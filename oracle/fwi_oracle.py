@@ -37,6 +37,24 @@ FFT_WORKERS = -1          # scipy.fft worker count (-1: all host cores)
 # Medium (Sec. II, Eq. 1-3)
 # --------------------------------------------------------------------------
 
+class Background:
+    """A lossy background (Sec. II: background compressibility kappa_0 from the
+    background SoS c0 and attenuation alpha0 [Np/m/Hz]); wherever the oracle
+    takes c0 it also takes a Background. A plain number is the lossless
+    background alpha0 = 0."""
+
+    def __init__(self, c0, alpha0=0.0):
+        self.c0, self.alpha0 = float(c0), float(alpha0)
+
+
+def kappa0_rho(c0):
+    """kappa_0 rho_0 of the background (Eq. 2 at the background values)."""
+    if isinstance(c0, Background):
+        a0 = c0.alpha0
+        return 1.0 / c0.c0**2 - a0**2 / (2.0 * math.pi) ** 2 + 1j * a0 / (math.pi * c0.c0)
+    return 1.0 / c0**2
+
+
 def contrast(c, alpha, c0):
     """Contrast m = kappa/kappa0 - 1 (Eq. 3) from speed of sound and attenuation.
 
@@ -47,19 +65,23 @@ def contrast(c, alpha, c0):
     c = np.asarray(c, dtype=np.float64)
     alpha = np.asarray(alpha, dtype=np.float64)
     kappa_rho = 1.0 / c**2 - alpha**2 / (2.0 * math.pi) ** 2 + 1j * alpha / (math.pi * c)
-    kappa0_rho = 1.0 / c0**2
-    return kappa_rho / kappa0_rho - 1.0
+    return kappa_rho / kappa0_rho(c0) - 1.0
 
 
 def contrast_derivs(c, alpha, c0):
     """dm/dc and dm/dalpha of the contrast above (for the chain rule)."""
-    dm_dc = c0**2 * (-2.0 / c**3 - 1j * alpha / (math.pi * c**2))
-    dm_da = c0**2 * (-2.0 * alpha / (2.0 * math.pi) ** 2 + 1j / (math.pi * c))
+    k0r = kappa0_rho(c0)
+    dm_dc = (-2.0 / c**3 - 1j * alpha / (math.pi * c**2)) / k0r
+    dm_da = (-2.0 * alpha / (2.0 * math.pi) ** 2 + 1j / (math.pi * c)) / k0r
     return dm_dc, dm_da
 
 
 def wavenumber(freq, c0):
-    """Background wavenumber k_{l,0} = omega_l sqrt(kappa0 rho0) = 2 pi f / c0 (Sec. II)."""
+    """Background wavenumber k_{l,0} = omega_l sqrt(kappa0 rho0) (Sec. II):
+    2 pi f / c0 for a lossless background, the root with Im k > 0 (outgoing,
+    decaying under exp(-i omega t)) for a lossy one."""
+    if isinstance(c0, Background):
+        return 2.0 * math.pi * float(freq) * np.sqrt(complex(kappa0_rho(c0)))
     return 2.0 * math.pi * float(freq) / c0
 
 
@@ -128,7 +150,7 @@ def cell_weight(k, r, dx, dim):
         out[off] = 0.25j * (2.0 * math.pi * a / k) * sp.jv(1, ka) * sp.hankel1(0, k * r[off])
         out[~off] = 1j * math.pi * a / (2.0 * k) * sp.hankel1(1, ka) - 1.0 / k**2
     else:
-        fac = 4.0 * math.pi / k**3 * (math.sin(ka) - ka * math.cos(ka))
+        fac = 4.0 * math.pi / k**3 * (np.sin(ka) - ka * np.cos(ka))
         out[off] = fac * np.exp(1j * k * r[off]) / (4.0 * math.pi * r[off])
         out[~off] = ((1.0 - 1j * ka) * np.exp(1j * ka) - 1.0) / k**2
     return out
@@ -639,6 +661,17 @@ def admm_step_tx(m, g, u, m_ref, d_obs, dim, nx, ny, nz, dx, c0, freqs, elems, w
 
 
 def sos_from_contrast(m, c0):
+    if isinstance(c0, Background):
+        # kappa rho = (m + 1) kappa_0 rho_0 = A + i B; 1/c^2 - alpha^2/(4 pi^2) = A,
+        # alpha/(pi c) = B: x = c^2 solves (B^2/4) x^2 + A x - 1 = 0
+        kr = (np.asarray(m, dtype=np.complex128) + 1.0) * kappa0_rho(c0)
+        A, B = kr.real, kr.imag
+        c = np.sqrt(2.0 / (A + np.sqrt(A**2 + B**2)))
+        return c, math.pi * c * B
+    return _sos_from_contrast_lossless(m, c0)
+
+
+def _sos_from_contrast_lossless(m, c0):
     """Speed of sound and attenuation of a contrast (inverse of Eq. 1-3): with
     R = Re m + 1 and I = Im m, Eq. 3 gives R = c0^2/c^2 - c0^2 alpha^2/(4 pi^2)
     and I = c0^2 alpha/(pi c); eliminating alpha = pi c I / c0^2 leaves the
