@@ -4,6 +4,7 @@
 #include "../../include/fwi.h"
 
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -107,7 +108,7 @@ struct ProblemCache {
   std::string key;
   Geo g;
   int nf = 0, ne = 0;
-  std::vector<double> k;
+  std::vector<c128> k;  // background wavenumbers (complex for a lossy background)
   c128* ghat64 = nullptr;   // [nf][npad]
   c64* ghat32 = nullptr;    // [nf][npad]
   c128* P0 = nullptr;       // [nf][ne][n]
@@ -280,6 +281,9 @@ int validate_problem(const fwi_problem* p, std::string& msg) {
   if (p->dim == 2 && p->elem_height != 0.0) return msg = "2D elements have no height", FWI_E_INVAL;
   if ((p->elem_width > 0.0 || p->elem_height > 0.0) && (p->elem_quad < 1 || p->elem_quad > kMaxGaussPoints))
     return msg = "elem_quad must be in 1..16", FWI_E_INVAL;
+  if (!(p->alpha0 >= 0.0) || !std::isfinite(p->alpha0)) return msg = "alpha0 must be finite and >= 0", FWI_E_INVAL;
+  if (p->dim == 2 && p->alpha0 > 0.0)
+    return msg = "a lossy background needs complex-argument Hankel functions: 3D only", FWI_E_UNSUPPORTED;
   return FWI_OK;
 }
 
@@ -309,7 +313,16 @@ Geo make_geo(const fwi_problem* p) {
   g.Lz = padded_length(g.nz);
   g.dx = p->dx;
   g.c0 = p->c0;
+  g.alpha0 = p->alpha0;
   return g;
+}
+
+// 1 / (kappa0 rho0) of a problem's background (c0^2 when lossless)
+c128 inv_kappa0(const Geo& g) {
+  if (g.alpha0 == 0.0) return mk(g.c0 * g.c0, 0.0);
+  const c128 k = kappa0_rho(g.c0, g.alpha0);
+  const double d = k.x * k.x + k.y * k.y;
+  return mk(k.x / d, -k.y / d);
 }
 
 // Cache key of a problem: the raw bytes of everything the cached data depend
@@ -330,6 +343,7 @@ std::string problem_key(const fwi_problem* p) {
   put(&aw, sizeof(double));
   put(&ah, sizeof(double));
   put(&q, sizeof(int));
+  put(&p->alpha0, sizeof(double));
   return k;
 }
 
@@ -388,10 +402,17 @@ double build_cache(fwi_ctx* c, const fwi_problem* p, ProblemCache& pc, const std
   ap.hh = 0.5 * p->elem_height;
   ap.rule = gauss_legendre(ap.hw > 0.0 || ap.hh > 0.0 ? p->elem_quad : 1);
   for (int l = 0; l < pc.nf; ++l) {
-    const double k = 2.0 * 3.14159265358979323846 * p->freq_hz[l] / p->c0;
+    // k = omega sqrt(kappa0 rho0), the root with Im k >= 0 (decaying)
+    const double w = 2.0 * 3.14159265358979323846 * p->freq_hz[l];
+    c128 k = mk(w / p->c0, 0.0);
+    if (p->alpha0 > 0.0) {
+      const c128 k0r = kappa0_rho(p->c0, p->alpha0);
+      const std::complex<double> s = std::sqrt(std::complex<double>(k0r.x, k0r.y));
+      k = mk(w * s.real(), w * s.imag());
+    }
     pc.k[l] = k;
-    hk2[l] = mk(k * k, 0.0);
-    hcoef[l] = mk(k * k * dV, 0.0);
+    hk2[l] = k * k;
+    hcoef[l] = dV * (k * k);
     for (int e = 0; e < pc.ne; ++e) hrf[(size_t)l * pc.ne + e] = l;
     launch_green_table(g, k, table, st);
     launch_fft_full(g, c->tw, table, work, pc.ghat64 + (long)l * np, st);
@@ -876,7 +897,7 @@ struct Runner {
       solve_rhs<T>(sb, l0, nf, cb.S, cb.lam, nt);
       launch_gradient_accum(n, nf, nt, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
     }
-    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, cc, alpha, gm_out, gc, ga, st);
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), cc, alpha, gm_out, gc, ga, st);
     std::vector<double> mf(ngroups);
     FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * ngroups, hipMemcpyDeviceToHost, st));
     FWI_HIP(hipStreamSynchronize(st));
@@ -927,7 +948,7 @@ struct Runner {
       }
       launch_gradient_accum(n, nf, p->ne, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
     }
-    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, cc, alpha, gm_out, gc, ga, st);
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), cc, alpha, gm_out, gc, ga, st);
     double phi = 0.0;
     if (!upstream) {
       std::vector<double> mf(ngroups);
@@ -1062,7 +1083,7 @@ int forward_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doubl
     launch_cast_64_32(R.n, R.cb.m64, R.cb.m32, c->stream);
   } else {
     check_sos(c, R.n, cc, alpha);
-    launch_contrast(R.n, p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+    launch_contrast(R.n, p->c0, p->alpha0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
   }
   R.t_setup += now_ms() - ts;
   R.forward<T>(sb, (c128*)data_out, (c128*)fields_out);
@@ -1088,7 +1109,7 @@ int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doub
     launch_cast_64_32(R.n, R.cb.m64, R.cb.m32, c->stream);
   } else {
     check_sos(c, R.n, cc, alpha);
-    launch_contrast(R.n, p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+    launch_contrast(R.n, p->c0, p->alpha0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
   }
   R.t_setup += now_ms() - ts;
   const double phi = R.gradient<T>(sb, (const c128*)dobs, (const c128*)upstream, R.cb.data, cc, alpha,
@@ -1114,7 +1135,7 @@ void prepare_tx(fwi_ctx* c, Runner& R, SolveBufs<T>& sb, int nt, const void* w, 
   launch_conj_c128(nw, (const c128*)w, R.cb.wtx, c->stream);
   const double ts = now_ms();
   check_sos(c, R.n, cc, alpha);
-  launch_contrast(R.n, R.p->c0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
+  launch_contrast(R.n, R.p->c0, R.p->alpha0, cc, alpha, R.cb.m64, R.cb.m32, c->stream);
   R.t_setup += now_ms() - ts;
 }
 
@@ -1166,7 +1187,7 @@ void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int 
     launch_gradient_accum(n, nf, nt, tx + (long)l0 * nt * n, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc,
                           c->stream);
   }
-  launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, nullptr, nullptr, out, nullptr, nullptr, c->stream);
+  launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), nullptr, nullptr, out, nullptr, nullptr, c->stream);
 }
 
 // J a from stored transmit and receiver fields -> out [nf][nt][ne]
@@ -1601,7 +1622,7 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
       FWI_HIP(hipMemcpyAsync(c->h_int, c->d_int, 2 * sizeof(int), hipMemcpyDeviceToHost, main));
       FWI_HIP(hipStreamSynchronize(main));
       if (c->h_int[0] || c->h_int[1]) throw Error(FWI_E_NONFINITE, "invalid speed of sound / attenuation");
-      launch_contrast(I->n, I->p->c0, I->c, I->alpha, I->cb.m64, I->cb.m32, main);
+      launch_contrast(I->n, I->p->c0, I->p->alpha0, I->c, I->alpha, I->cb.m64, I->cb.m32, main);
     }
     // forward solves
     batch_solve<T>(c, wave, ctr, o, [](BatchInst<T>& I) -> const c128* { return I.pc->P0; },
@@ -1623,7 +1644,7 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
         BatchInst<T>* I = wave[k];
         launch_gradient_accum(I->n, I->p->nf, I->p->ne, I->cb.fields, I->cb.lam, I->pc->k2, I->cb.gpart, kGradSeg,
                               1, I->cb.gacc, main);
-        launch_grad_chain(I->n, I->cb.gacc, std::pow(I->g.dx, I->g.dim), I->g.c0, nullptr, nullptr, I->grad,
+        launch_grad_chain(I->n, I->cb.gacc, std::pow(I->g.dx, I->g.dim), inv_kappa0(I->g), nullptr, nullptr, I->grad,
                           nullptr, nullptr, main);
         FWI_HIP(hipMemcpyAsync(&misfits[w[k]], I->cb.misfits, sizeof(double), hipMemcpyDeviceToHost, main));
       }
@@ -1918,7 +1939,8 @@ int fwi_sos_from_contrast(fwi_ctx* c, const fwi_problem* p, const void* m, doubl
     std::string msg;
     int rc = validate_problem(p, msg);
     if (rc) throw Error(rc, msg);
-    launch_sos_from_contrast(make_geo(p).n(), p->c0, (const c128*)m, c_out, alpha_out, c->stream);
+    launch_sos_from_contrast(make_geo(p).n(), kappa0_rho(p->c0, p->alpha0), (const c128*)m, c_out, alpha_out,
+                             c->stream);
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
   });
@@ -2153,7 +2175,7 @@ int fwi_jacobian_adjoint_apply_tx(fwi_ctx* c, const fwi_problem* p, int nt, cons
     launch_gemm_cn(p->nf, (const c128*)b, nt, p->ne, (const c128*)rx_fields, (long)p->ne * n, n, cb.lam,
                    (long)nt * n, st);
     launch_gradient_accum(n, p->nf, nt, (const c128*)tx_fields, cb.lam, c->pc.k2, cb.gpart, kGradSeg, 1, cb.gacc, st);
-    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), g.c0, nullptr, nullptr, (c128*)out, nullptr, nullptr, st);
+    launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), nullptr, nullptr, (c128*)out, nullptr, nullptr, st);
     FWI_HIP(hipStreamSynchronize(st));
     return FWI_OK;
   });

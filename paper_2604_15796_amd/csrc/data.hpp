@@ -17,7 +17,7 @@ void launch_residual(long count, const c128* data, const c128* dobs, c128* r, do
 void launch_gradient_accum(long n, int nf, int ni, const c128* p, const c128* lam, const c128* k2, c128* part,
                            int nseg, int first, c128* acc, hipStream_t st);
 // g = dV acc and the chain rule to c, alpha (each output may be null)
-void launch_grad_chain(long n, const c128* acc, double dV, double c0, const double* c, const double* alpha, c128* g,
+void launch_grad_chain(long n, const c128* acc, double dV, c128 ik0r, const double* c, const double* alpha, c128* g,
                        double* gc, double* ga, hipStream_t st);
 void launch_tv_grad(const Geo& g, const c128* m, c128* out, hipStream_t st);
 void launch_tv_gradT(const Geo& g, const c128* a, double alpha, double beta, c128* out, hipStream_t st);

@@ -111,6 +111,7 @@ struct Geo {
   int dim = 2, nx = 0, ny = 1, nz = 0;
   int Lx = 0, Ly = 1, Lz = 0;
   double dx = 0, c0 = 0;
+  double alpha0 = 0;  // background attenuation [Np/m/Hz] (3D only)
   long n() const { return (long)nx * ny * nz; }
   long npad() const { return (long)Lx * Ly * Lz; }
   // per-RHS intermediate sizes (elements): after the x pass / after the y pass
@@ -212,9 +213,15 @@ void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx
                        hipStream_t st);
 
 // ---------------------------------------------------------- setup kernels ---
-void launch_contrast(long n, double c0, const double* c, const double* alpha, c128* m64, c64* m32, hipStream_t st);
-void launch_sos_from_contrast(long n, double c0, const c128* m, double* c, double* alpha, hipStream_t st);
-void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st);
+// kappa_0 rho_0 of the background: 1/c0^2 - alpha0^2/(4 pi^2) + i alpha0/(pi c0)
+inline c128 kappa0_rho(double c0, double alpha0) {
+  const double pi = 3.14159265358979323846;
+  return mk(1.0 / (c0 * c0) - alpha0 * alpha0 / (4.0 * pi * pi), alpha0 / (pi * c0));
+}
+void launch_contrast(long n, double c0, double alpha0, const double* c, const double* alpha, c128* m64, c64* m32,
+                     hipStream_t st);
+void launch_sos_from_contrast(long n, c128 k0r, const c128* m, double* c, double* alpha, hipStream_t st);
+void launch_green_table(const Geo& g, c128 k, c128* table, hipStream_t st);
 // Gauss-Legendre rule on [-1, 1] for the element apertures.
 constexpr int kMaxGaussPoints = 16;
 struct GaussRule {
@@ -228,7 +235,7 @@ struct Aperture {
   double hw, hh;
   GaussRule rule;
 };
-void launch_incident(const Geo& g, double k, int ne, const double* elem_xyz_dev, const Aperture& ap, c128* P0,
+void launch_incident(const Geo& g, c128 k, int ne, const double* elem_xyz_dev, const Aperture& ap, c128* P0,
                      hipStream_t st);
 void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st);
 void launch_scale_c128(long count, double s, c128* x, hipStream_t st);

@@ -248,7 +248,7 @@ __global__ void k_grad_accum(const c128* __restrict__ part, int nseg, long n, in
 }
 
 // g = dV acc; optional chain rule d phi/dc = Re(conj(g) dm/dc), d phi/dalpha = Re(conj(g) dm/dalpha)
-__global__ void k_grad_chain(const c128* __restrict__ acc, long n, double dV, double c0,
+__global__ void k_grad_chain(const c128* __restrict__ acc, long n, double dV, c128 ik0r,
                              const double* __restrict__ c, const double* __restrict__ alpha,
                              c128* __restrict__ g, double* __restrict__ gc, double* __restrict__ ga) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -257,9 +257,10 @@ __global__ void k_grad_chain(const c128* __restrict__ acc, long n, double dV, do
   if (g) g[e] = s;
   if (gc || ga) {
     const double cc = c[e], a = alpha ? alpha[e] : 0.0;
-    // dm/dc = c0^2 (-2/c^3 - i alpha/(pi c^2)), dm/dalpha = c0^2 (-2 alpha/(2 pi)^2 + i/(pi c))
-    const c128 dmc = mk(c0 * c0 * (-2.0 / (cc * cc * cc)), -c0 * c0 * a / (PI * cc * cc));
-    const c128 dma = mk(-c0 * c0 * 2.0 * a / (4.0 * PI * PI), c0 * c0 / (PI * cc));
+    // m = kappa rho / (kappa_0 rho_0) - 1 (ik0r = 1 / (kappa_0 rho_0)):
+    // dm/dc = (-2/c^3 - i alpha/(pi c^2)) ik0r, dm/dalpha = (-2 alpha/(2 pi)^2 + i/(pi c)) ik0r
+    const c128 dmc = mk(-2.0 / (cc * cc * cc), -a / (PI * cc * cc)) * ik0r;
+    const c128 dma = mk(-2.0 * a / (4.0 * PI * PI), 1.0 / (PI * cc)) * ik0r;
     if (gc) gc[e] = s.x * dmc.x + s.y * dmc.y;
     if (ga) ga[e] = s.x * dma.x + s.y * dma.y;
   }
@@ -446,10 +447,10 @@ void launch_gradient_accum(long n, int nf, int ni, const c128* p, const c128* la
   FWI_LAUNCH_CHECK();
 }
 
-void launch_grad_chain(long n, const c128* acc, double dV, double c0, const double* c, const double* alpha, c128* g,
+void launch_grad_chain(long n, const c128* acc, double dV, c128 ik0r, const double* c, const double* alpha, c128* g,
                        double* gc, double* ga, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_chain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, n, dV, c0, c, alpha, g,
-                     gc, ga);
+  hipLaunchKernelGGL(k_grad_chain, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc, n, dV, ik0r, c, alpha,
+                     g, gc, ga);
   FWI_LAUNCH_CHECK();
 }
 

@@ -1,6 +1,8 @@
 // Set-up kernels: contrast (Eq. 1-3), the circulant Green table of the
 // discrete volume integral operator (Eq. 5, Sec. IV-A) and the incident fields
 // of point elements (Sec. II). All evaluated in FP64.
+#include <complex>
+
 #include "bessel.hpp"
 #include "internal.hpp"
 
@@ -9,44 +11,59 @@ namespace fwi {
 constexpr double PI = 3.14159265358979323846;
 
 // m = kappa/kappa0 - 1 with kappa rho0 = 1/c^2 - alpha^2/(2 pi)^2 + i alpha/(pi c)
-// (e^{-i omega t}) and a lossless background kappa0 rho0 = 1/c0^2.
-__global__ void k_contrast(long n, double c0, const double* __restrict__ c, const double* __restrict__ alpha,
-                           c128* __restrict__ m64, c64* __restrict__ m32) {
+// (e^{-i omega t}) and the background kappa0 rho0 from (c0, alpha0).
+__global__ void k_contrast(long n, double c0, double a0, const double* __restrict__ c,
+                           const double* __restrict__ alpha, c128* __restrict__ m64, c64* __restrict__ m32) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double cc = c[i], a = alpha ? alpha[i] : 0.0;
-  // c0^2/c^2 - 1 as (c0 - c)(c0 + c)/c^2: no cancellation near the
-  // background, and exactly zero where c = c0
-  const double re = (c0 - cc) * (c0 + cc) / (cc * cc) - c0 * c0 * (a * a / (4.0 * PI * PI));
-  const double im = c0 * c0 * a / (PI * cc);
+  double re, im;
+  if (a0 == 0.0) {
+    // c0^2/c^2 - 1 as (c0 - c)(c0 + c)/c^2: no cancellation near the
+    // background, and exactly zero where c = c0
+    re = (c0 - cc) * (c0 + cc) / (cc * cc) - c0 * c0 * (a * a / (4.0 * PI * PI));
+    im = c0 * c0 * a / (PI * cc);
+  } else {
+    // (kappa rho - kappa0 rho0) / (kappa0 rho0), the difference formed term by
+    // term (exactly zero on the background)
+    const double nr = (c0 - cc) * (c0 + cc) / (cc * cc * c0 * c0) - (a - a0) * (a + a0) / (4.0 * PI * PI);
+    const double ni = a / (PI * cc) - a0 / (PI * c0);
+    const double dr = 1.0 / (c0 * c0) - a0 * a0 / (4.0 * PI * PI), di = a0 / (PI * c0);
+    const double d2 = dr * dr + di * di;
+    re = (nr * dr + ni * di) / d2;
+    im = (ni * dr - nr * di) / d2;
+  }
   m64[i] = mk(re, im);
   if (m32) m32[i] = mk((float)re, (float)im);
 }
 
-void launch_contrast(long n, double c0, const double* c, const double* alpha, c128* m64, c64* m32, hipStream_t st) {
+void launch_contrast(long n, double c0, double alpha0, const double* c, const double* alpha, c128* m64, c64* m32,
+                     hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c0, c, alpha, m64, m32);
+  hipLaunchKernelGGL(k_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c0, alpha0, c, alpha, m64,
+                     m32);
   FWI_LAUNCH_CHECK();
 }
 
-// Inverse of the contrast formula: with R = Re m + 1 and I = Im m, c^2 is the
-// positive root of (I^2 / (4 c0^2)) x^2 + R x - c0^2 = 0, written without
-// cancellation as x = 2 c0^2 / (R + sqrt(R^2 + I^2)); then alpha = pi c I / c0^2.
-// No positive root (R <= 0 and I = 0): NaN.
-__global__ void k_sos_from_contrast(long n, double c0, const c128* __restrict__ m, double* __restrict__ c,
+// Inverse of the contrast formula: kappa rho = (m + 1) kappa0 rho0 = A + i B
+// with A = 1/c^2 - alpha^2/(4 pi^2) and B = alpha/(pi c), so c^2 is the
+// positive root of (B^2/4) x^2 + A x - 1 = 0, written without cancellation as
+// x = 2 / (A + sqrt(A^2 + B^2)); then alpha = pi c B. No positive root: NaN.
+__global__ void k_sos_from_contrast(long n, c128 k0r, const c128* __restrict__ m, double* __restrict__ c,
                                     double* __restrict__ alpha) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double R = m[i].x + 1.0, I = m[i].y;
-  const double den = R + sqrt(R * R + I * I);
-  const double cc = den > 0.0 ? sqrt(2.0 * c0 * c0 / den) : nan("");
+  const c128 kr = mk(m[i].x + 1.0, m[i].y) * k0r;
+  const double A = kr.x, B = kr.y;
+  const double den = A + sqrt(A * A + B * B);
+  const double cc = den > 0.0 ? sqrt(2.0 / den) : nan("");
   if (c) c[i] = cc;
-  if (alpha) alpha[i] = PI * cc * I / (c0 * c0);
+  if (alpha) alpha[i] = PI * cc * B;
 }
 
-void launch_sos_from_contrast(long n, double c0, const c128* m, double* c, double* alpha, hipStream_t st) {
+void launch_sos_from_contrast(long n, c128 k0r, const c128* m, double* c, double* alpha, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_sos_from_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, c0, m, c, alpha);
+  hipLaunchKernelGGL(k_sos_from_contrast, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, k0r, m, c, alpha);
   FWI_LAUNCH_CHECK();
 }
 
@@ -54,36 +71,49 @@ void launch_sos_from_contrast(long n, double c0, const c128* m, double* c, doubl
 //  2D: W(r>0) = (i/4)(2 pi a/k) J1(ka) H0(kr),  W(0) = (i pi a/(2k)) H1(ka) - 1/k^2
 //  3D: W(r>0) = (4 pi/k^3)(sin ka - ka cos ka) e^{ikr}/(4 pi r),
 //      W(0)  = ((1 - i ka) e^{ika} - 1)/k^2
+// k is complex for a lossy background (3D only; 2D takes its real part).
 struct WeightConsts {
-  double fac;        // real factor multiplying G(r) for r > 0 (2D: (2 pi a/k) J1(ka); 3D: (4 pi/k^3)(...))
+  c128 fac;          // factor multiplying G(r) for r > 0 (2D: (2 pi a/k) J1(ka); 3D: (4 pi/k^3)(...))
   c128 self;         // W(0)
 };
 
-static WeightConsts weight_consts(int dim, double k, double dx) {
+static WeightConsts weight_consts(int dim, c128 kc, double dx) {
   WeightConsts w{};
   if (dim == 2) {
+    const double k = kc.x;
     const double a = dx / std::sqrt(PI), ka = k * a;
     double j0, j1, y0, y1;
     bessel01(ka, &j0, &j1, &y0, &y1);
-    w.fac = (2.0 * PI * a / k) * j1;
+    w.fac = mk((2.0 * PI * a / k) * j1, 0.0);
     // (i pi a/(2k)) (J1 + i Y1) - 1/k^2
     const double s = PI * a / (2.0 * k);
     w.self = mk(-s * y1 - 1.0 / (k * k), s * j1);
   } else {
-    const double a = dx * std::cbrt(3.0 / (4.0 * PI)), ka = k * a;
-    w.fac = 4.0 * PI / (k * k * k) * (std::sin(ka) - ka * std::cos(ka));
-    // ((1 - i ka)(cos ka + i sin ka) - 1)/k^2
-    const double cs = std::cos(ka), sn = std::sin(ka);
-    w.self = mk((cs + ka * sn - 1.0) / (k * k), (sn - ka * cs) / (k * k));
+    using cd = std::complex<double>;
+    const cd k(kc.x, kc.y), I(0.0, 1.0);
+    const double a = dx * std::cbrt(3.0 / (4.0 * PI));
+    const cd ka = k * a;
+    const cd fac = 4.0 * PI / (k * k * k) * (std::sin(ka) - ka * std::cos(ka));
+    const cd self = ((1.0 - I * ka) * std::exp(I * ka) - 1.0) / (k * k);
+    w.fac = mk(fac.real(), fac.imag());
+    w.self = mk(self.real(), self.imag());
   }
   return w;
+}
+
+// e^{i k r} for complex k (Im k >= 0: decaying)
+__device__ __forceinline__ c128 expikr(c128 k, double r) {
+  double s, c;
+  sincos(k.x * r, &s, &c);
+  const double d = k.y != 0.0 ? exp(-k.y * r) : 1.0;
+  return mk(d * c, d * s);
 }
 
 // T[iz][iy][ix] = k^2 W(dx |Delta|) / (Lz Ly Lx) on the circulant grid: offset
 // i for i < n, i - L for i > L - n, and zero elsewhere (never reached by the
 // linear convolution of an n-point axis).
-__global__ void k_green_table(int dim, int nx, int ny, int nz, int Lx, int Ly, int Lz, double dx, double k,
-                              double fac, c128 self, double scale, c128* __restrict__ T) {
+__global__ void k_green_table(int dim, int nx, int ny, int nz, int Lx, int Ly, int Lz, double dx, c128 k,
+                              c128 fac, c128 self, double scale, c128* __restrict__ T) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long total = (long)Lx * Ly * Lz;
   if (i >= total) return;
@@ -107,21 +137,18 @@ __global__ void k_green_table(int dim, int nx, int ny, int nz, int Lx, int Ly, i
       v = self;
     } else if (dim == 2) {
       double j0, j1, y0, y1;
-      bessel01(k * r, &j0, &j1, &y0, &y1);
+      bessel01(k.x * r, &j0, &j1, &y0, &y1);
       // (i/4) H0 = (i/4)(J0 + i Y0) = (-Y0/4, J0/4)
-      v = mk(-0.25 * fac * y0, 0.25 * fac * j0);
+      v = mk(-0.25 * fac.x * y0, 0.25 * fac.x * j0);
     } else {
-      double s, c;
-      sincos(k * r, &s, &c);
-      const double g = fac / (4.0 * PI * r);
-      v = mk(g * c, g * s);
+      v = (1.0 / (4.0 * PI * r)) * (fac * expikr(k, r));
     }
-    v = (k * k * scale) * v;
+    v = (scale * (k * k)) * v;
   }
   T[i] = v;
 }
 
-void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st) {
+void launch_green_table(const Geo& g, c128 k, c128* table, hipStream_t st) {
   const WeightConsts w = weight_consts(g.dim, k, g.dx);
   const long total = g.npad();
   hipLaunchKernelGGL(k_green_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g.dim, g.nx, g.ny, g.nz,
@@ -133,7 +160,7 @@ void launch_green_table(const Geo& g, double k, c128* table, hipStream_t st) {
 // aperture, the average of G over the element's rectangle on the top face
 // (product Gauss-Legendre rule: sub-point x_e + (hw xi_a, hh xi_b, 0) with
 // weight w_a w_b / 4, one point in a direction of zero extent).
-__global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k, int ne,
+__global__ void k_incident(int dim, int nx, int ny, int nz, double dx, c128 k, int ne,
                            const double* __restrict__ exyz, Aperture ap, c128* __restrict__ P0) {
   const long n = (long)nx * ny * nz;
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,13 +184,10 @@ __global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k,
       c128 gv;
       if (dim == 2) {
         double j0, j1, y0, y1;
-        bessel01(k * r, &j0, &j1, &y0, &y1);
+        bessel01(k.x * r, &j0, &j1, &y0, &y1);
         gv = mk(-0.25 * y0, 0.25 * j0);
       } else {
-        double s, c;
-        sincos(k * r, &s, &c);
-        const double g = 1.0 / (4.0 * PI * r);
-        gv = mk(g * c, g * s);
+        gv = (1.0 / (4.0 * PI * r)) * expikr(k, r);
       }
       v = v + (wa * wb) * gv;
     }
@@ -171,7 +195,7 @@ __global__ void k_incident(int dim, int nx, int ny, int nz, double dx, double k,
   P0[(long)e * n + i] = v;
 }
 
-void launch_incident(const Geo& g, double k, int ne, const double* exyz, const Aperture& ap, c128* P0,
+void launch_incident(const Geo& g, c128 k, int ne, const double* exyz, const Aperture& ap, c128* P0,
                      hipStream_t st) {
   const long n = g.n();
   if (n == 0 || ne == 0) return;

@@ -43,7 +43,7 @@ class CProblem(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
                 ("c0", C.c_double), ("nf", C.c_int), ("freq_hz", C.POINTER(C.c_double)), ("ne", C.c_int),
                 ("elem_xyz", C.POINTER(C.c_double)), ("elem_width", C.c_double), ("elem_height", C.c_double),
-                ("elem_quad", C.c_int)]
+                ("elem_quad", C.c_int), ("alpha0", C.c_double)]
 
 
 class CSolveOpts(C.Structure):
@@ -184,10 +184,11 @@ class ProblemArgs:
         self.elem_width = float(getattr(p, "elem_width", 0.0))
         self.elem_height = float(getattr(p, "elem_height", 0.0))
         self.elem_quad = int(getattr(p, "elem_quad", 1))
+        self.alpha0 = float(getattr(p, "alpha0", 0.0))  # background attenuation [Np/m/Hz]
         self.c = CProblem(self.dim, self.nx, self.ny, self.nz, self.dx, self.c0, self.nf,
                           self.freqs.ctypes.data_as(C.POINTER(C.c_double)), self.ne,
                           self.elems.ctypes.data_as(C.POINTER(C.c_double)), self.elem_width, self.elem_height,
-                          self.elem_quad)
+                          self.elem_quad, self.alpha0)
 
     @property
     def shape(self):

@@ -59,6 +59,8 @@ class Problem:
     elem_width: float = 0.0
     elem_height: float = 0.0
     elem_quad: int = 1
+    # background attenuation [Np/m/Hz] (0: lossless background)
+    alpha0: float = 0.0
 
     @property
     def shape(self):

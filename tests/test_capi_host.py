@@ -110,3 +110,9 @@ def test_aperture_rule_and_validation():
     assert fwi.validate_problem(_prob(elem_width=0.2e-3, elem_quad=0)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(elem_width=-1e-3, elem_quad=4)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(elem_height=1e-3, elem_quad=4)) == fwi.FWI_E_INVAL  # 2D: no height
+    # lossy background: 3D only
+    assert fwi.validate_problem(_prob(alpha0=-1e-6)) == fwi.FWI_E_INVAL
+    assert fwi.validate_problem(_prob(alpha0=1e-6)) == fwi.FWI_E_UNSUPPORTED
+    p3 = W.small3d()
+    p3.alpha0 = 1e-6
+    assert fwi.validate_problem(p3) == fwi.FWI_OK

@@ -489,6 +489,48 @@ def test_admm_and_invert_on_coarse_inversion_mesh_vs_oracle(ctx, F, r):
     assert relerr(host(mi), rm2) < 1e-8 and relerr(host(gi), rg2) < 1e-8 and relerr(host(ui), ru2) < 1e-8
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lossy_background_3d_vs_oracle(ctx, F, prec):
+    """A lossy background in 3D (complex, decaying background wavenumber):
+    Green spectrum, incident fields, fields, data, the gradient and its chain
+    rule, and the speed of sound back from the contrast, against the oracle."""
+    p = W.small3d(seed=67, nx=12, ny=10, nz=9, ne=3, nf=2, f_lo=0.6e6, f_hi=0.9e6)
+    p.alpha0 = W.db_cm_mhz_to_np_m_hz(0.5)
+    p.alpha = p.alpha + p.alpha0
+    bg = O.Background(p.c0, p.alpha0)
+    args = (3, p.nx, p.ny, p.nz, p.dx, bg, p.freqs, p.elems)
+    cen = O.cell_centres(3, p.nx, p.ny, p.nz, p.dx)
+    for l, f in enumerate(p.freqs):
+        k = O.wavenumber(f, bg)
+        assert k.imag > 0
+        # the library's spectrum (padding 2^a 3^b >= 2n, 1/npad folded in) applied to an impulse
+        g = host(ctx.green_spectrum(p, l))
+        imp = np.zeros(p.shape, complex)
+        imp.flat[37] = 1.0
+        ref_col = O.convolve(O.green_spectrum(k, 3, p.nx, p.ny, p.nz, p.dx), imp)
+        pad = np.zeros(g.shape, complex)
+        pad[tuple(slice(0, s) for s in p.shape)] = imp
+        got_col = np.fft.ifftn(g * np.fft.fftn(pad))[tuple(slice(0, s) for s in p.shape)] * g.size
+        assert relerr(got_col, ref_col) < 1e-12
+        assert relerr(host(ctx.incident(p, l)), O.incident_fields(k, cen, p.elems, 3)) < 1e-13
+    tol = 1e-10 if prec == 0 else 1e-9
+    opts = F.SolveOptions(precision=prec, rtol=1e-12, restart=16)
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    data, fields, st = ctx.forward(p, c, a, opts, fields=True)
+    rd, rf, _ = O.forward(p.c, p.alpha, *args)
+    assert st["unconverged"] == 0
+    assert relerr(host(fields), rf) < tol and relerr(host(data), rd) < tol
+    d_obs = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    phi, gm, gc, ga, _ = ctx.adjoint_gradient(p, c, a, dev(d_obs), opts)
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, *args)
+    assert abs(phi - rphi) < 1e-9 * rphi
+    assert relerr(host(gm), rg) < 1e-8 and relerr(host(gc), rgc) < 1e-8 and relerr(host(ga), rga) < 1e-8
+    m = O.contrast(p.c, p.alpha, bg)
+    cs, al = ctx.sos_from_contrast(p, dev(m))
+    rc_, ra_ = O.sos_from_contrast(m, bg)
+    assert relerr(host(cs), rc_) < 1e-13 and relerr(host(al), ra_) < 1e-10
+
+
 def test_synthesised_transmit_argument_errors(ctx, F):
     p = W.small2d(seed=60, nx=24, nz=20, ne=3, nf=1)
     c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
