@@ -39,9 +39,9 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # of known size, and the VALU busy fraction from SQ_ACTIVE_INST_VALU over
 # GRBM_GUI_ACTIVE. Reported only while the timed dominant class runs that
 # kernel (profiles/gradient256_hbm_traffic.md, profiles/gradient256_valu.md).
-MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1762.0e6},
+MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.9e6},
             "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.7e6},
-            "k_strided<float, 512, 16, 512, 2, true, false>": {"traffic": 897.9e6, "valu_busy": 0.776}}
+            "k_strided<float, 512, 8, 256, 2, true, false>": {"traffic": 898.5e6, "valu_busy": 0.776}}
 
 
 def parse():
