@@ -81,9 +81,9 @@ typedef struct fwi_problem {
   double elem_height;      /* [m], >= 0, 0 in 2D */
   int elem_quad;
   /* Background attenuation alpha0 [Np/m/Hz] >= 0 (Sec. II: kappa_0 from c0 and
-   * alpha0; the background wavenumber is then complex and decaying). 0: the
-   * lossless background. > 0 is supported in 3D only (FWI_E_UNSUPPORTED in
-   * 2D, which would need Hankel functions of complex argument). */
+   * alpha0; the background wavenumber is then complex and decaying, and the
+   * 2D Green's function takes Hankel functions of complex argument). 0: the
+   * lossless background. */
   double alpha0;
 } fwi_problem;
 

@@ -282,8 +282,6 @@ int validate_problem(const fwi_problem* p, std::string& msg) {
   if ((p->elem_width > 0.0 || p->elem_height > 0.0) && (p->elem_quad < 1 || p->elem_quad > kMaxGaussPoints))
     return msg = "elem_quad must be in 1..16", FWI_E_INVAL;
   if (!(p->alpha0 >= 0.0) || !std::isfinite(p->alpha0)) return msg = "alpha0 must be finite and >= 0", FWI_E_INVAL;
-  if (p->dim == 2 && p->alpha0 > 0.0)
-    return msg = "a lossy background needs complex-argument Hankel functions: 3D only", FWI_E_UNSUPPORTED;
   return FWI_OK;
 }
 

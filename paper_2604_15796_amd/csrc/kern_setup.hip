@@ -71,7 +71,7 @@ void launch_sos_from_contrast(long n, c128 k0r, const c128* m, double* c, double
 //  2D: W(r>0) = (i/4)(2 pi a/k) J1(ka) H0(kr),  W(0) = (i pi a/(2k)) H1(ka) - 1/k^2
 //  3D: W(r>0) = (4 pi/k^3)(sin ka - ka cos ka) e^{ikr}/(4 pi r),
 //      W(0)  = ((1 - i ka) e^{ika} - 1)/k^2
-// k is complex for a lossy background (3D only; 2D takes its real part).
+// k is complex for a lossy background.
 struct WeightConsts {
   c128 fac;          // factor multiplying G(r) for r > 0 (2D: (2 pi a/k) J1(ka); 3D: (4 pi/k^3)(...))
   c128 self;         // W(0)
@@ -79,7 +79,7 @@ struct WeightConsts {
 
 static WeightConsts weight_consts(int dim, c128 kc, double dx) {
   WeightConsts w{};
-  if (dim == 2) {
+  if (dim == 2 && kc.y == 0.0) {
     const double k = kc.x;
     const double a = dx / std::sqrt(PI), ka = k * a;
     double j0, j1, y0, y1;
@@ -88,6 +88,18 @@ static WeightConsts weight_consts(int dim, c128 kc, double dx) {
     // (i pi a/(2k)) (J1 + i Y1) - 1/k^2
     const double s = PI * a / (2.0 * k);
     w.self = mk(-s * y1 - 1.0 / (k * k), s * j1);
+  } else if (dim == 2) {
+    using cd = std::complex<double>;
+    const cd k(kc.x, kc.y), I(0.0, 1.0);
+    const double a = dx / std::sqrt(PI);
+    const cd ka = k * a;
+    cz j0, j1, y0, y1;
+    cbessel01(cz{ka.real(), ka.imag()}, &j0, &j1, &y0, &y1);
+    const cd J1(j1.re, j1.im), H1(j1.re - y1.im, j1.im + y1.re);
+    const cd fac = (2.0 * PI * a / k) * J1;
+    const cd self = (I * PI * a / (2.0 * k)) * H1 - 1.0 / (k * k);
+    w.fac = mk(fac.real(), fac.imag());
+    w.self = mk(self.real(), self.imag());
   } else {
     using cd = std::complex<double>;
     const cd k(kc.x, kc.y), I(0.0, 1.0);
@@ -135,11 +147,14 @@ __global__ void k_green_table(int dim, int nx, int ny, int nz, int Lx, int Ly, i
     const double r = dx * sqrt((double)dxi * dxi + (double)dyi * dyi + (double)dzi * dzi);
     if (r == 0.0) {
       v = self;
-    } else if (dim == 2) {
+    } else if (dim == 2 && k.y == 0.0) {
       double j0, j1, y0, y1;
       bessel01(k.x * r, &j0, &j1, &y0, &y1);
       // (i/4) H0 = (i/4)(J0 + i Y0) = (-Y0/4, J0/4)
       v = mk(-0.25 * fac.x * y0, 0.25 * fac.x * j0);
+    } else if (dim == 2) {
+      const cz h = chankel0(cz{k.x * r, k.y * r});
+      v = fac * mk(-0.25 * h.im, 0.25 * h.re);  // (i/4) H0 times the weight factor
     } else {
       v = (1.0 / (4.0 * PI * r)) * (fac * expikr(k, r));
     }
@@ -182,10 +197,13 @@ __global__ void k_incident(int dim, int nx, int ny, int nz, double dx, c128 k, i
       const double pz = (iz + 0.5) * dx - exyz[3 * e + 2];
       const double r = sqrt(px * px + py * py + pz * pz);
       c128 gv;
-      if (dim == 2) {
+      if (dim == 2 && k.y == 0.0) {
         double j0, j1, y0, y1;
         bessel01(k.x * r, &j0, &j1, &y0, &y1);
         gv = mk(-0.25 * y0, 0.25 * j0);
+      } else if (dim == 2) {
+        const cz h = chankel0(cz{k.x * r, k.y * r});
+        gv = mk(-0.25 * h.im, 0.25 * h.re);
       } else {
         gv = (1.0 / (4.0 * PI * r)) * expikr(k, r);
       }
@@ -262,6 +280,24 @@ void launch_scale_c128(long count, double s, c128* x, hipStream_t st) {
 // Host evaluation of the same Bessel routine the kernels use (for CPU checks).
 extern "C" void fwi_host_bessel01(double x, double* out4) {
   fwi::bessel01(x, &out4[0], &out4[1], &out4[2], &out4[3]);
+}
+
+// Host evaluation of the complex-argument routine (for CPU checks):
+// out = J0, J1, Y0, Y1 as (re, im) pairs.
+extern "C" void fwi_host_cbessel01(double re, double im, double* out8) {
+  fwi::cz j0, j1, y0, y1;
+  fwi::cbessel01(fwi::cz{re, im}, &j0, &j1, &y0, &y1);
+  const fwi::cz v[4] = {j0, j1, y0, y1};
+  for (int i = 0; i < 4; ++i) {
+    out8[2 * i] = v[i].re;
+    out8[2 * i + 1] = v[i].im;
+  }
+}
+
+extern "C" void fwi_host_chankel0(double re, double im, double* out2) {
+  const fwi::cz h = fwi::chankel0(fwi::cz{re, im});
+  out2[0] = h.re;
+  out2[1] = h.im;
 }
 
 // The aperture rule the kernels receive (for CPU checks).

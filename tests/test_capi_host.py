@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI (no GPU): exports, validation, workspace
 arithmetic and the FP64 Bessel routine the kernels evaluate."""
+import ctypes as C
 import math
 import os
 import re
@@ -110,9 +111,35 @@ def test_aperture_rule_and_validation():
     assert fwi.validate_problem(_prob(elem_width=0.2e-3, elem_quad=0)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(elem_width=-1e-3, elem_quad=4)) == fwi.FWI_E_INVAL
     assert fwi.validate_problem(_prob(elem_height=1e-3, elem_quad=4)) == fwi.FWI_E_INVAL  # 2D: no height
-    # lossy background: 3D only
+    # lossy background
     assert fwi.validate_problem(_prob(alpha0=-1e-6)) == fwi.FWI_E_INVAL
-    assert fwi.validate_problem(_prob(alpha0=1e-6)) == fwi.FWI_E_UNSUPPORTED
+    assert fwi.validate_problem(_prob(alpha0=1e-6)) == fwi.FWI_OK
     p3 = W.small3d()
     p3.alpha0 = 1e-6
     assert fwi.validate_problem(p3) == fwi.FWI_OK
+
+
+def test_host_complex_bessel_and_hankel_match_scipy():
+    """The complex-argument J0, J1, Y0, Y1 and H0^(1) of the lossy 2D
+    background (the same code the kernels run) against scipy, from small
+    arguments to the largest k r of the workloads, just above the real axis and
+    further out."""
+    L = fwi.lib()
+    fb = L.fwi_host_cbessel01
+    fb.restype, fb.argtypes = None, [C.c_double, C.c_double, C.POINTER(C.c_double)]
+    fh = L.fwi_host_chankel0
+    fh.restype, fh.argtypes = None, [C.c_double, C.c_double, C.POINTER(C.c_double)]
+    o8, o2 = (C.c_double * 8)(), (C.c_double * 2)()
+    for mag in np.geomspace(1e-3, 600, 120):
+        for arg in (0.0, 1e-3, 0.01, 0.05) + ((0.3,) if mag < 40 else ()):
+            z = mag * np.exp(1j * arg)
+            fh(z.real, z.imag, o2)
+            ref = sp.hankel1(0, z)
+            tol = 1e-12 if arg <= 0.05 else 1e-9
+            assert abs(o2[0] + 1j * o2[1] - ref) <= tol * abs(ref), z
+            if mag < 25:
+                fb(z.real, z.imag, o8)
+                got = np.array(o8[:]).reshape(4, 2) @ np.array([1, 1j])
+                want = np.array([sp.jv(0, z), sp.jv(1, z), sp.yv(0, z), sp.yv(1, z)])
+                scale = np.maximum(np.abs(want), abs(sp.hankel1(0, z)))
+                assert np.all(np.abs(got - want) <= 1e-11 * scale), z
