@@ -750,6 +750,7 @@ struct CallBufs {
   c128* data = nullptr;     // [nf][ne][ne]
   c128* r = nullptr;        // [nf][ne][ne]
   c128* gpart = nullptr;    // [nks][nfg][ne][ne] or [nseg][n]
+  long gpart_len = 0;       // elements of gpart
   c128* gacc = nullptr;     // [n]
   double* misfits = nullptr;  // [ngroups]
   int* rfreq = nullptr;     // [B]
@@ -785,7 +786,8 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
   cb.r = a.take<c128>(ndata);
   cb.misfits = a.take<double>(ngroups + 2);
   const long gp = std::max((long)gemm_splits(n) * nfg * p->ne * p->ne, (long)kGradSeg * n);
-  cb.gpart = a.take<c128>(std::max(gp, (long)gemm_splits(n) * p->nf * p->ne * p->ne));
+  cb.gpart_len = std::max(gp, (long)gemm_splits(n) * p->nf * p->ne * p->ne);
+  cb.gpart = a.take<c128>(cb.gpart_len);
   cb.gacc = a.take<c128>(n);
   if (entry == FWI_ENTRY_ADMM)
     cb.fields = a.take<c128>((size_t)p->nf * p->ne * n);
@@ -1180,10 +1182,18 @@ void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int 
   const int ngroups = (p->nf + nfg - 1) / nfg;
   for (int gi = 0; gi < ngroups; ++gi) {
     const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
-    launch_gemm_cn(nf, b + l0 * nd, nt, p->ne, rx + (long)l0 * p->ne * n, (long)p->ne * n, n, cb.lam, (long)nt * n,
-                   c->stream);
-    launch_gradient_accum(n, nf, nt, tx + (long)l0 * nt * n, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc,
-                          c->stream);
+    const int nseg = gemm_cn_grad_segments(nf, nt);
+    if ((long)nseg * n <= cb.gpart_len) {
+      // the products with the transmit fields formed in the GEMM's epilogue
+      launch_gemm_cn_grad(nf, b + l0 * nd, nt, p->ne, rx + (long)l0 * p->ne * n, (long)p->ne * n, n,
+                          tx + (long)l0 * nt * n, (long)nt * n, pc.k2 + l0, cb.gpart, c->stream);
+      launch_grad_sum(n, cb.gpart, nseg, gi == 0, cb.gacc, c->stream);
+    } else {
+      launch_gemm_cn(nf, b + l0 * nd, nt, p->ne, rx + (long)l0 * p->ne * n, (long)p->ne * n, n, cb.lam, (long)nt * n,
+                     c->stream);
+      launch_gradient_accum(n, nf, nt, tx + (long)l0 * nt * n, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0,
+                            cb.gacc, c->stream);
+    }
   }
   launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), nullptr, nullptr, out, nullptr, nullptr, c->stream);
 }
@@ -2100,7 +2110,8 @@ int fwi_jacobian_adjoint_apply(fwi_ctx* c, const fwi_problem* p, const void* fie
     const long n = g.n();
     auto plan = [&](Arena& a, CallBufs& cb) {
       cb.lam = a.take<c128>((size_t)p->nf * p->ne * n);
-      cb.gpart = a.take<c128>((size_t)kGradSeg * n);
+      cb.gpart_len = (long)kGradSeg * n;
+      cb.gpart = a.take<c128>(cb.gpart_len);
       cb.gacc = a.take<c128>(n);
     };
     Arena dry;
@@ -2159,7 +2170,8 @@ int fwi_jacobian_adjoint_apply_tx(fwi_ctx* c, const fwi_problem* p, int nt, cons
     const long n = g.n();
     auto plan = [&](Arena& ar, CallBufs& cb) {
       cb.lam = ar.take<c128>((size_t)p->nf * nt * n);
-      cb.gpart = ar.take<c128>((size_t)kGradSeg * n);
+      cb.gpart_len = (long)kGradSeg * n;
+      cb.gpart = ar.take<c128>(cb.gpart_len);
       cb.gacc = ar.take<c128>(n);
     };
     Arena dry;

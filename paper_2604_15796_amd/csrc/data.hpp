@@ -32,6 +32,14 @@ void launch_cg_step1(long n, const double* sc, c128* x, c128* r, const c128* p, 
 void launch_cg_step2(long n, const double* sc, const c128* r, c128* p, hipStream_t st);
 void launch_copy_scalar(const double* in, double* out, hipStream_t st);
 void launch_conj_c128(long count, const c128* in, c128* out, hipStream_t st);
+// J^H b in one pass over the receiver fields: S = conj(M) P as in
+// launch_gemm_cn, reduced on the fly with the transmit fields T into
+// conj(k2) conj(T S) partials part [nf * ceil(ni / 64)][n]; launch_grad_sum
+// adds such partials (or those of launch_gradient_accum) in a fixed order.
+int gemm_cn_grad_segments(int nf, int ni);
+void launch_gemm_cn_grad(int nf, const c128* M, int ni, int nj, const c128* P, long p_ls, long n, const c128* T,
+                         long t_ls, const c128* k2, c128* part, hipStream_t st);
+void launch_grad_sum(long n, const c128* part, int nseg, int first, c128* acc, hipStream_t st);
 // coarse inversion mesh (factor r) <-> forward mesh g: piecewise-constant
 // prolongation and its adjoint
 void launch_prolong(const Geo& g, int r, const c128* mc, c128* mf, hipStream_t st);

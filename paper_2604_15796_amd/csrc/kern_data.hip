@@ -129,9 +129,16 @@ __global__ void k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, 
 constexpr int CT = 64;  // output tile (rows of S, points n)
 constexpr int CK = 16;  // j step
 
+// GRAD: instead of storing S, the epilogue forms conj(k2[l]) conj(T[l][i][n] S[l][i][n])
+// and sums it over the tile's 64 rows i in a fixed order (lane, then lanes
+// 16 and 32 apart, then the four waves), one partial per (l, row tile, n) in
+// part [nf][row tiles][n]: J^H b without storing the adjoint-like fields.
+template <bool GRAD>
 __global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int ni, int nj,
                                                  const c128* __restrict__ P, long p_ls, long n,
-                                                 c128* __restrict__ S, long s_ls) {
+                                                 c128* __restrict__ S, long s_ls, const c128* __restrict__ T,
+                                                 long t_ls, const c128* __restrict__ k2,
+                                                 c128* __restrict__ part) {
   __shared__ c128 sm[CT][CK + 1];   // conj(M) tile [i][j]
   __shared__ c128 sp[CK][CT + 1];   // P tile [j][n]
   const int l = blockIdx.z;
@@ -191,14 +198,41 @@ __global__ void __launch_bounds__(256) k_gemm_cn(const c128* __restrict__ M, int
     }
     __syncthreads();
   }
+  if constexpr (!GRAD) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int i = i0 + 16 * wv + (lane >> 4) + 4 * v;
-    if (i >= ni) continue;
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * wv + (lane >> 4) + 4 * v;
+      if (i >= ni) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const long nn = n0 + 16 * b + (lane & 15);
+        if (nn < n) S[l * s_ls + (long)i * n + nn] = mk(cr[b][v], ci[b][v]);
+      }
+    }
+  } else {
+    __shared__ c128 sred[4][CT];
+    const c128 kc = conj(k2[l]);
+    const c128* Tl = T + l * t_ls;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const long nn = n0 + 16 * b + (lane & 15);
-      if (nn < n) S[l * s_ls + (long)i * n + nn] = mk(cr[b][v], ci[b][v]);
+      c128 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 16 * wv + (lane >> 4) + 4 * v;
+        if (i < ni && nn < n) acc = acc + kc * conj(Tl[(long)i * n + nn] * mk(cr[b][v], ci[b][v]));
+      }
+      double ax = acc.x, ay = acc.y;
+      ax += __shfl_xor(ax, 16, 64);
+      ay += __shfl_xor(ay, 16, 64);
+      ax += __shfl_xor(ax, 32, 64);
+      ay += __shfl_xor(ay, 32, 64);
+      if (lane < 16) sred[wv][16 * b + lane] = mk(ax, ay);
+    }
+    __syncthreads();
+    if (t < CT && n0 + t < n) {
+      const c128 s = ((sred[0][t] + sred[1][t]) + sred[2][t]) + sred[3][t];
+      part[((long)l * gridDim.y + blockIdx.y) * n + n0 + t] = s;
     }
   }
 }
@@ -428,8 +462,19 @@ void launch_gemm_nt(int nf, const c128* A, long a_ls, int ni, const c128* w, con
 
 void launch_gemm_cn(int nf, const c128* M, int ni, int nj, const c128* P, long p_ls, long n, c128* S, long s_ls,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_gemm_cn, dim3((unsigned)((n + CT - 1) / CT), (ni + CT - 1) / CT, nf), dim3(256), 0, st, M, ni,
-                     nj, P, p_ls, n, S, s_ls);
+  hipLaunchKernelGGL(k_gemm_cn<false>, dim3((unsigned)((n + CT - 1) / CT), (ni + CT - 1) / CT, nf), dim3(256), 0, st,
+                     M, ni, nj, P, p_ls, n, S, s_ls, nullptr, 0L, nullptr, nullptr);
+  FWI_LAUNCH_CHECK();
+}
+int gemm_cn_grad_segments(int nf, int ni) { return nf * ((ni + CT - 1) / CT); }
+void launch_gemm_cn_grad(int nf, const c128* M, int ni, int nj, const c128* P, long p_ls, long n, const c128* T,
+                         long t_ls, const c128* k2, c128* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_gemm_cn<true>, dim3((unsigned)((n + CT - 1) / CT), (ni + CT - 1) / CT, nf), dim3(256), 0, st,
+                     M, ni, nj, P, p_ls, n, nullptr, 0L, T, t_ls, k2, part);
+  FWI_LAUNCH_CHECK();
+}
+void launch_grad_sum(long n, const c128* part, int nseg, int first, c128* acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_accum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, nseg, n, first, acc);
   FWI_LAUNCH_CHECK();
 }
 
