@@ -202,6 +202,8 @@ def main():
     roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not (planewave or three_d),
                               nf_launch=nf_launch)
 
+    roofline["practical_ceiling"] = stream_ceiling()
+
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
@@ -272,6 +274,37 @@ def main():
             out["cpu_baseline"]["sample"] += " (element sources: same operators and per-solve cost)"
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def stream_ceiling(gib=2.0, reps=5):
+    """What plain streaming kernels reach on this device, beside the 8 TB/s
+    peak: a device-to-device copy (read + write) and a sum (read only) over
+    `gib` GiB of float64, timed with CUDA events (torch's own kernels; a
+    hardware reference, not part of the library)."""
+    import torch
+    n = int(gib * 2**30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    x.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    copy = 2 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    read = n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(copy, 1), "read_gbs": round(read, 1), "bytes": int(2 * n * 8),
+            "note": "torch copy_ and sum over 2 GiB, CUDA events"}
 
 
 # strided-pass tile variants (columns, threads), as in the library: 8 x 256,
