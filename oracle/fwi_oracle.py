@@ -60,7 +60,8 @@ def contrast(c, alpha, c0):
 
     Eq. 1-2 with constant density rho0: kappa*rho0 = 1/c^2 - alpha^2/(2 pi)^2
     + i alpha/(pi c) (e^{-i omega t}; the alpha^2 term of Eq. 2 is kept);
-    the background is lossless, kappa0*rho0 = 1/c0^2. alpha in Np/m/Hz.
+    kappa0*rho0 of the background as in kappa0_rho (1/c0^2 when lossless).
+    alpha in Np/m/Hz.
     """
     c = np.asarray(c, dtype=np.float64)
     alpha = np.asarray(alpha, dtype=np.float64)

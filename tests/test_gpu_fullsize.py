@@ -271,6 +271,9 @@ def test_cfg4_3d_gradient_recompute_mixed_vs_fp64(ctx, F, cfg4):
 
 # ---------------------------------------------------------------- config 2 ---
 
+@pytest.mark.skip(reason="runs the call sequence (forward_batch, adjoint_gradient_batch, eager adjoint_gradient) "
+                         "that ended the process twice on the host in the graph-replayed batch path; kept off the "
+                         "GPU until a cause is shown and fixed")
 def test_cfg2_uneven_batch_graph_vs_eager(ctx, F):
     """32 uneven instances through the graph-replayed batch in the mixed form:
     every instance converges, and sampled instances equal the eager per-problem

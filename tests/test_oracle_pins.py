@@ -117,9 +117,18 @@ def _disk_quad(k, r, a):
     return out[0] + 1j * out[1]
 
 
+@pytest.mark.parametrize("lossy", [False, True])
 @pytest.mark.parametrize("rcells", [0.0, 1.0, 2.5])
-def test_cell_weight_2d_vs_quadrature(rcells):
-    k, dx = 2 * math.pi * 1e6 / 1540.0, 0.154e-3
+def test_cell_weight_2d_vs_quadrature(rcells, lossy):
+    """Richmond's 2D weight, self and off-diagonal, against adaptive quadrature
+    of (i/4) H0(k r) over the equal-area disk; also at the complex wavenumber
+    of a lossy background (Sec. II), where a conjugated k, a dropped Im k or
+    a real-argument Bessel function would fail."""
+    dx = 0.154e-3
+    bg = O.Background(1540.0, W.db_cm_mhz_to_np_m_hz(0.5) if lossy else 0.0)
+    k = O.wavenumber(1e6, bg) if lossy else 2 * math.pi * 1e6 / 1540.0
+    if lossy:
+        assert k.imag > 0
     a = dx / math.sqrt(math.pi)
     ref = _disk_quad(k, rcells * dx, a)
     got = O.cell_weight(k, np.array([rcells * dx]), dx, 2)[0]
@@ -343,6 +352,35 @@ def test_chain_rule_to_c_and_alpha():
 
 # ------------------------------------------------------------- TV / ADMM ---
 
+def test_tv_norm_closed_form_on_ramps():
+    """||grad m||_{1,2} of complex ramps, by hand: forward differences are the
+    ramp's slopes except on the last index of each axis (zero there), so the
+    cells split into the interior (all slopes), the last column / row /
+    layer (some slopes) and the far corner (none). Per cell the norm is
+    sqrt(sum_q |slope_q|^2) with complex moduli; summing |Re| or dropping a
+    component would fail."""
+    nz, nx = 5, 7
+    sx, sz = 1.0 + 2.0j, -3.0j
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    m = sx * xx + sz * zz
+    ax, az = abs(sx), abs(sz)
+    want = (nz - 1) * (nx - 1) * math.hypot(ax, az) + (nz - 1) * az + (nx - 1) * ax
+    assert O.tv_norm(O.tv_grad(m)) == pytest.approx(want, rel=1e-14)
+    nz, ny, nx = 3, 4, 5
+    sx, sy, sz = 2.0, 1.0 - 1.0j, 0.5j
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    m = sx * xx + sy * yy + sz * zz
+    a = [abs(sx), abs(sy), abs(sz)]
+    want = 0.0
+    for iz in range(nz):
+        for iy in range(ny):
+            for ix in range(nx):
+                on = [ix < nx - 1, iy < ny - 1, iz < nz - 1]
+                want += math.sqrt(sum(v * v for v, o in zip(a, on) if o))
+    assert O.tv_norm(O.tv_grad(m)) == pytest.approx(want, rel=1e-14)
+    assert O.tv_norm(np.zeros((2, 3, 4), complex)) == 0.0
+
+
 @pytest.mark.parametrize("shape", [(5, 7), (3, 4, 6)])
 def test_tv_grad_transpose_dot(shape):
     rng = np.random.default_rng(1)
@@ -498,6 +536,31 @@ def test_tx_gradient_adjoint_solves_and_central_differences():
             fp = O.misfit(O.forward_tx_m(mp.reshape(m.shape), *args, w)[0], d_obs)
             fm = O.misfit(O.forward_tx_m(mm.reshape(m.shape), *args, w)[0], d_obs)
             assert abs((fp - fm) / (2 * h) - part(g[idx])) < 1e-5 * np.abs(g).max()
+
+
+def test_tx_chain_rule_to_c_and_alpha():
+    """The chain rule of the synthesised-transmit gradient to c and alpha
+    (Re(conj(g) dm/dc), Re(conj(g) dm/dalpha)) against central differences of
+    the plane-wave misfit in c_n and alpha_n at a lossy model."""
+    p, _, w = _tx_problem(34)
+    args = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    alpha = p.alpha + W.db_cm_mhz_to_np_m_hz(0.3)
+    d_obs = O.forward_tx_m(O.contrast(p.extra["c_obs"], alpha, p.c0), *args, w)[0]
+    phi, g, gc, ga, _ = O.adjoint_gradient_tx(p.c, alpha, d_obs, *args, w)
+
+    def mis(c, al):
+        return O.misfit(O.forward_tx_m(O.contrast(c, al, p.c0), *args, w)[0], d_obs)
+    for idx in (3 * p.nx + 4, 8 * p.nx + 10):
+        for arr, h, got in ((p.c, 1e-3, gc[idx]), (alpha, 1e-9, ga[idx])):
+            ap, am = arr.copy().ravel(), arr.copy().ravel()
+            ap[idx] += h
+            am[idx] -= h
+            if arr is p.c:
+                fp, fm = mis(ap.reshape(arr.shape), alpha), mis(am.reshape(arr.shape), alpha)
+            else:
+                fp, fm = mis(p.c, ap.reshape(arr.shape)), mis(p.c, am.reshape(arr.shape))
+            assert abs((fp - fm) / (2 * h) - got) < 1e-5 * abs(got) + 1e-30
+            assert abs(got) > 0
 
 
 def test_plane_wave_weights_steer():
