@@ -60,7 +60,8 @@ extern "C" {
 typedef struct fwi_ctx fwi_ctx;
 
 /* Problem statement (Sec. II): grid of cells, constant-density background
- * c0 (lossless), frequencies and element positions on the top face z = 0.
+ * of speed of sound c0 (and attenuation alpha0, below), frequencies and
+ * element positions on the top face z = 0.
  * Each axis must satisfy 1 <= n <= 512 (padded FFT length 2^a 3^b <= 1024). */
 typedef struct fwi_problem {
   int dim;                 /* 2 or 3 */
@@ -103,6 +104,11 @@ typedef struct fwi_solve_opts {
                            is read after the next step is enqueued, so at most one
                            fully masked step follows convergence */
   int reciprocity_adjoint; /* 1: adjoint fields as sum_j conj(r_ij) p_j (no adjoint solves) */
+  int fields_c64;       /* fields_out of the forward entries as complex64 (1) or complex128 (0);
+                           the solves themselves are unchanged */
+  int tx_chunk;         /* > 0 and < the transmits per frequency: solve the transmits of one
+                           frequency at a time in chunks of tx_chunk (the workspace then holds
+                           tx_chunk RHS instead of a frequency group); 0: whole frequencies */
 } fwi_solve_opts;
 
 /* Per-call statistics (host struct, written when non-NULL). */
@@ -174,7 +180,8 @@ int fwi_set_workspace(fwi_ctx* ctx, void* dev_ptr, size_t bytes);
 /* F(m): forward solves for every transmit and frequency and the scattered
  * data (Eq. 3-6). c [n] speed of sound [m/s] > 0, alpha [n] attenuation
  * [Np/m/Hz] >= 0 or NULL (zero), both double. data_out [nf][ne][ne]
- * complex128. fields_out NULL or [nf][ne][n] complex128 total fields. */
+ * complex128. fields_out NULL or [nf][ne][n] total fields, complex128, or
+ * complex64 when opts->fields_c64 is set. */
 int fwi_forward(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha,
                 const fwi_solve_opts* opts, void* data_out, void* fields_out, fwi_stats* stats);
 
@@ -197,6 +204,16 @@ int fwi_adjoint_gradient(fwi_ctx* ctx, const fwi_problem* prob, const double* c,
  * m [n] complex128, grad_data [nf][ne][ne] complex128, grad_m_out [n] complex128. */
 int fwi_vjp(fwi_ctx* ctx, const fwi_problem* prob, const void* m, const void* grad_data,
             const fwi_solve_opts* opts, void* grad_m_out, fwi_stats* stats);
+
+/* fwi_vjp with the forward fields given instead of solved: fields [nf][ne][n]
+ * complex128 from an earlier fwi_forward_m at the same m (Eq. 17 needs the
+ * forward fields p_li; the adjoint fields are still solved). With the same
+ * options the solver is deterministic and a field does not depend on the
+ * batch it was solved in, so the result equals fwi_vjp's bit for bit: the
+ * stored-fields backward of automatic differentiation, for callers whose
+ * fields fit device memory. */
+int fwi_vjp_fields(fwi_ctx* ctx, const fwi_problem* prob, const void* m, const void* fields,
+                   const void* grad_data, const fwi_solve_opts* opts, void* grad_m_out, fwi_stats* stats);
 
 /* One iteration of Algorithm 1: forward solves at m_k, Gauss-Newton model
  * update by params->n_cg CG iterations on (s J^H J + rho grad^T grad + gamma I)

@@ -20,6 +20,10 @@
 #include "internal.hpp"
 #include "krylov.hpp"
 
+#ifdef FWI_WORKSPACE_GUARD
+#include <sanitizer/asan_interface.h>
+#endif
+
 using namespace fwi;
 
 namespace fwi {
@@ -88,6 +92,19 @@ const c64* Twiddles::get<float>(int L) const {
 namespace {
 
 // --------------------------------------------------------------- arena ---
+// Host sanitizer builds of this file (FWI_WORKSPACE_GUARD, tests only) leave
+// a poisoned gap after every workspace buffer, so that an access past a
+// planned extent is reported; the library build has no gap.
+#ifdef FWI_WORKSPACE_GUARD
+constexpr size_t kArenaGuard = 256;
+inline void guard_poison(char* p, size_t n) { ASAN_POISON_MEMORY_REGION(p, n); }
+inline void guard_clear(char* p, size_t n) { ASAN_UNPOISON_MEMORY_REGION(p, n); }
+#else
+constexpr size_t kArenaGuard = 0;
+inline void guard_poison(char*, size_t) {}
+inline void guard_clear(char*, size_t) {}
+#endif
+
 struct Arena {
   char* base = nullptr;
   size_t cap = 0, used = 0;
@@ -96,10 +113,16 @@ struct Arena {
   T* take(size_t count) {
     const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
     const size_t off = used;
-    used += bytes;
+    used += bytes + kArenaGuard;
     if (dry) return nullptr;
     if (used > cap) throw Error(FWI_E_NOMEM, "workspace exhausted");
+    guard_poison(base + off + count * sizeof(T), bytes - count * sizeof(T) + kArenaGuard);
     return reinterpret_cast<T*>(base + off);
+  }
+  // plan again from the start of the bound workspace
+  void rewind() {
+    used = 0;
+    if (base) guard_clear(base, cap);
   }
 };
 
@@ -297,6 +320,8 @@ int validate_opts(const fwi_solve_opts* o, std::string& msg) {
   }
   if (o->max_rhs < 0) return msg = "max_rhs must be >= 0", FWI_E_INVAL;
   if (o->check_every < 1) return msg = "check_every must be >= 1", FWI_E_INVAL;
+  if (o->tx_chunk < 0) return msg = "tx_chunk must be >= 0", FWI_E_INVAL;
+  if (o->fields_c64 != 0 && o->fields_c64 != 1) return msg = "fields_c64 must be 0 or 1", FWI_E_INVAL;
   return FWI_OK;
 }
 
@@ -443,6 +468,7 @@ void bind_workspace(fwi_ctx* c, Arena& a, size_t need) {
       throw Error(FWI_E_NOMEM, "caller workspace too small: need " + std::to_string(need) + " bytes");
     a.base = c->ws_ext;
     a.cap = c->ws_ext_bytes;
+    a.rewind();
     return;
   }
   if (need > c->ws_int_bytes) {
@@ -457,6 +483,7 @@ void bind_workspace(fwi_ctx* c, Arena& a, size_t need) {
   }
   a.base = c->ws_int;
   a.cap = c->ws_int_bytes;
+  a.rewind();
 }
 
 // ------------------------------------------------------- solve buffers ---
@@ -733,8 +760,18 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
   return res;
 }
 
-// Groups of whole frequencies solved together: at most max_rhs RHS per batch.
+// Transmits per solved batch when `per` transmits share a frequency: all of
+// them, or chunks of tx_chunk (one frequency at a time).
+int chunk_of(const fwi_solve_opts& o, int per) { return o.tx_chunk > 0 && o.tx_chunk < per ? o.tx_chunk : per; }
+int chunks_of(const fwi_solve_opts& o, int per) {
+  const int cs = chunk_of(o, per);
+  return (per + cs - 1) / cs;
+}
+
+// Groups of whole frequencies solved together: at most max_rhs RHS per batch
+// (one frequency per group when the transmits are chunked).
 int freqs_per_group(const fwi_problem* p, const fwi_solve_opts& o) {
+  if (chunk_of(o, p->ne) < p->ne) return 1;
   if (o.max_rhs <= 0) return p->nf;
   const int f = o.max_rhs / p->ne;
   return f < 1 ? 1 : (f > p->nf ? p->nf : f);
@@ -752,7 +789,7 @@ struct CallBufs {
   c128* gpart = nullptr;    // [nks][nfg][ne][ne] or [nseg][n]
   long gpart_len = 0;       // elements of gpart
   c128* gacc = nullptr;     // [n]
-  double* misfits = nullptr;  // [ngroups]
+  double* misfits = nullptr;  // [ngroups * chunks]
   int* rfreq = nullptr;     // [B]
   c128* wtx = nullptr;      // [nf][nt][ne] conjugated transmit weights (nt <= ne; gradient plans)
   // ADMM
@@ -764,9 +801,19 @@ struct CallBufs {
 
 constexpr int kGradSeg = 16;
 
-int gemm_splits(long n) {
-  long s = (n + 1023) / 1024;
-  return (int)(s < 1 ? 1 : (s > 64 ? 64 : s));
+// K-splits of the sampling / Jacobian GEMM over the n grid points: one split
+// per 1024 points, at most 64 while the output tiles and frequencies already
+// give >= 1024 workgroups, more (up to 512) when they do not (a 3D grid with
+// one frequency and 64 x 64 outputs is one tile). gemm_splits_max bounds every
+// launch's count (buffer plans).
+int gemm_splits_max(long n) {
+  const long s = (n + 1023) / 1024;
+  return (int)(s < 1 ? 1 : (s > 512 ? 512 : s));
+}
+int gemm_splits(long n, int nf, int ni, int nj) {
+  const long units = (long)nf * ((ni + 63) / 64) * ((nj + 63) / 64);
+  const long want = std::max<long>(64, (1024 + units - 1) / units);
+  return (int)std::min<long>(gemm_splits_max(n), want);
 }
 
 // Plans every buffer of an entry point; `entry` as in fwi_workspace_size.
@@ -776,7 +823,7 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
   const Geo g = make_geo(p);
   const long n = g.n();
   const int nfg = freqs_per_group(p, o);
-  const int B = B_override > 0 ? B_override : nfg * p->ne;
+  const int B = B_override > 0 ? B_override : nfg * chunk_of(o, p->ne);
   const int ngroups = (p->nf + nfg - 1) / nfg;
   const long ndata = (long)p->nf * p->ne * p->ne;
   cb.m64 = a.take<c128>(n);
@@ -784,9 +831,9 @@ void plan_call(Arena& a, const fwi_problem* p, const fwi_solve_opts& o, int entr
   cb.rfreq = a.take<int>(B);
   cb.data = a.take<c128>(ndata);
   cb.r = a.take<c128>(ndata);
-  cb.misfits = a.take<double>(ngroups + 2);
-  const long gp = std::max((long)gemm_splits(n) * nfg * p->ne * p->ne, (long)kGradSeg * n);
-  cb.gpart_len = std::max(gp, (long)gemm_splits(n) * p->nf * p->ne * p->ne);
+  cb.misfits = a.take<double>((size_t)ngroups * chunks_of(o, p->ne) + 2);
+  const long gp = std::max((long)gemm_splits_max(n) * nfg * p->ne * p->ne, (long)kGradSeg * n);
+  cb.gpart_len = std::max(gp, (long)gemm_splits_max(n) * p->nf * p->ne * p->ne);
   cb.gpart = a.take<c128>(cb.gpart_len);
   cb.gacc = a.take<c128>(n);
   if (entry == FWI_ENTRY_ADMM)
@@ -834,24 +881,27 @@ struct Runner {
     launch_zero_u64(2, c->d_itstat, c->stream);  // this call's iteration statistics
   }
 
-  // Solve the forward problem for frequencies [l0, l0+nf) into `fields`:
-  // `per` RHS per frequency (the elements, or nt synthesised transmits).
+  // Solve A_l x = rhs for frequencies [l0, l0 + nf), `per` right-hand sides
+  // per frequency (frequency-major), into `out`.
   template <typename T>
-  void solve_rhs(SolveBufs<T>& sb, int l0, int nf, const c128* rhs, c128* out, int per = 0) {
+  void solve_rhs(SolveBufs<T>& sb, int l0, int nf, int per, const c128* rhs, c128* out) {
     const ProblemCache& pc = c->pc;
-    const int B = nf * (per > 0 ? per : p->ne);
+    const int B = nf * per;
     const cplx<T>* mT = std::is_same<T, float>::value ? (const cplx<T>*)cb.m32 : (const cplx<T>*)cb.m64;
     const cplx<T>* gT = std::is_same<T, float>::value ? (const cplx<T>*)pc.ghat32 : (const cplx<T>*)pc.ghat64;
-    const int* rf = pc.rhs_freq + (long)l0 * p->ne;
-    if (per > 0) {
-      launch_fill_rfreq(B, per, l0, cb.rfreq, c->stream);
-      rf = cb.rfreq;
-    }
+    launch_fill_rfreq(B, per, l0, cb.rfreq, c->stream);
     // a short batch reuses the planned buffers with a smaller B
     SolveBufs<T> s = sb;
     s.ks.B = B;
-    SolveTotals r = run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, rf, out, o, s, nf);
+    SolveTotals r = run_solve<T>(c, g, cb.m64, mT, pc.ghat64, gT, B, rhs, cb.rfreq, out, o, s, nf);
     tot.merge(r);
+  }
+
+  // Fields of one solved batch into the caller's array: complex128 in place
+  // (solved there directly) or rounded to complex64.
+  c128* field_target(c128* fields_out, long off) { return fields_out && !o.fields_c64 ? fields_out + off : cb.fields; }
+  void field_store(c128* fields_out, long off, long count) {
+    if (fields_out && o.fields_c64) launch_cast_64_32(count, cb.fields, reinterpret_cast<c64*>(fields_out) + off, c->stream);
   }
 
   // Transmits synthesised from the elements (Sec. V: steered plane waves;
@@ -859,20 +909,28 @@ struct Runner {
   // weight w[l][t][e], so its incident field is sum_e w P0_l[e] and, the
   // problem being linear, its total field solves A_l p = that field. cb.wtx
   // holds conj(w) (the NN product conjugates its left operand). Data
-  // [nf][nt][ne] by the point-receiver rule of Eq. 4.
+  // [nf][nt][ne] by the point-receiver rule of Eq. 4. Transmits are solved
+  // in chunks of tx_chunk when set (one frequency at a time).
   template <typename T>
   void forward_tx(SolveBufs<T>& sb, int nt, c128* data_out, c128* fields_out) {
     const ProblemCache& pc = c->pc;
     hipStream_t st = c->stream;
     const long nd = (long)nt * p->ne;
+    const int cs = chunk_of(o, nt);
     for (int gi = 0; gi < ngroups; ++gi) {
       const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
       const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
-      c128* F = fields_out ? fields_out + (long)l0 * nt * n : cb.fields;
-      launch_gemm_cn(nf, cb.wtx + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
-      solve_rhs<T>(sb, l0, nf, cb.S, F, nt);
-      launch_gemm_nt(nf, F, (long)nt * n, nt, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0, cb.gpart,
-                     gemm_splits(n), data_out + l0 * nd, st);
+      for (int t0 = 0; t0 < nt; t0 += cs) {
+        const int ti = std::min(cs, nt - t0);  // nf == 1 unless ti == nt
+        const long off = ((long)l0 * nt + t0) * n;
+        c128* F = field_target(fields_out, off);
+        launch_gemm_cn(nf, cb.wtx + l0 * nd + (long)t0 * p->ne, ti, p->ne, P0g, (long)p->ne * n, n, cb.S,
+                       (long)ti * n, st);
+        solve_rhs<T>(sb, l0, nf, ti, cb.S, F);
+        launch_gemm_nt(nf, F, (long)ti * n, ti, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0, cb.gpart,
+                       gemm_splits(n, nf, ti, p->ne), data_out + l0 * nd + (long)t0 * p->ne, st);
+        field_store(fields_out, off, (long)nf * ti * n);
+      }
     }
   }
 
@@ -885,22 +943,32 @@ struct Runner {
     const ProblemCache& pc = c->pc;
     hipStream_t st = c->stream;
     const long nd = (long)nt * p->ne;
+    const int cs = chunk_of(o, nt);
+    int seg = 0;
     for (int gi = 0; gi < ngroups; ++gi) {
       const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
       const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
-      launch_gemm_cn(nf, cb.wtx + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
-      solve_rhs<T>(sb, l0, nf, cb.S, cb.fields, nt);
-      launch_gemm_nt(nf, cb.fields, (long)nt * n, nt, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0,
-                     cb.gpart, gemm_splits(n), data_out + l0 * nd, st);
-      launch_residual(nf * nd, data_out + l0 * nd, dobs + l0 * nd, cb.r + l0 * nd, cb.misfits + gi, st);
-      launch_gemm_cn(nf, cb.r + l0 * nd, nt, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)nt * n, st);
-      solve_rhs<T>(sb, l0, nf, cb.S, cb.lam, nt);
-      launch_gradient_accum(n, nf, nt, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
+      for (int t0 = 0; t0 < nt; t0 += cs, ++seg) {
+        const int ti = std::min(cs, nt - t0);
+        const long rows = l0 * nd + (long)t0 * p->ne;  // first data entry of the chunk
+        launch_gemm_cn(nf, cb.wtx + rows, ti, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)ti * n, st);
+        solve_rhs<T>(sb, l0, nf, ti, cb.S, cb.fields);
+        launch_gemm_nt(nf, cb.fields, (long)ti * n, ti, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0,
+                       cb.gpart, gemm_splits(n, nf, ti, p->ne), data_out + rows, st);
+        launch_residual((long)nf * ti * p->ne, data_out + rows, dobs + rows, cb.r + rows, cb.misfits + seg, st);
+        launch_gemm_cn(nf, cb.r + rows, ti, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)ti * n, st);
+        solve_rhs<T>(sb, l0, nf, ti, cb.S, cb.lam);
+        launch_gradient_accum(n, nf, ti, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, seg == 0, cb.gacc, st);
+      }
     }
     launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), cc, alpha, gm_out, gc, ga, st);
-    std::vector<double> mf(ngroups);
-    FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * ngroups, hipMemcpyDeviceToHost, st));
-    FWI_HIP(hipStreamSynchronize(st));
+    return sum_misfits(seg);
+  }
+
+  double sum_misfits(int count) {
+    std::vector<double> mf(count);
+    FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    FWI_HIP(hipStreamSynchronize(c->stream));
     double phi = 0.0;
     for (double v : mf) phi += v;
     return phi;
@@ -911,52 +979,67 @@ struct Runner {
     const ProblemCache& pc = c->pc;
     hipStream_t st = c->stream;
     const long ne2 = (long)p->ne * p->ne;
+    const int cs = chunk_of(o, p->ne);
     for (int gi = 0; gi < ngroups; ++gi) {
       const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
-      c128* F = fields_out ? fields_out + (long)l0 * p->ne * n : cb.fields;
-      solve_rhs<T>(sb, l0, nf, pc.P0 + (long)l0 * p->ne * n, F);
-      launch_gemm_nt(nf, F, (long)p->ne * n, p->ne, cb.m64, pc.P0 + (long)l0 * p->ne * n, (long)p->ne * n, p->ne, n,
-                     pc.coef + l0, cb.gpart, gemm_splits(n), data_out + l0 * ne2, st);
+      for (int i0 = 0; i0 < p->ne; i0 += cs) {
+        const int ni = std::min(cs, p->ne - i0);  // nf == 1 unless ni == ne
+        const long off = ((long)l0 * p->ne + i0) * n;
+        c128* F = field_target(fields_out, off);
+        solve_rhs<T>(sb, l0, nf, ni, pc.P0 + off, F);
+        launch_gemm_nt(nf, F, (long)ni * n, ni, cb.m64, pc.P0 + (long)l0 * p->ne * n, (long)p->ne * n, p->ne, n,
+                       pc.coef + l0, cb.gpart, gemm_splits(n, nf, ni, p->ne), data_out + l0 * ne2 + (long)i0 * p->ne,
+                       st);
+        field_store(fields_out, off, (long)nf * ni * n);
+      }
     }
   }
 
-  // misfit and J^H r (or J^H b with upstream b) by adjoint solves
+  // misfit and J^H r (or J^H b with upstream b) by adjoint solves; the
+  // forward fields are solved (in frequency groups and transmit chunks) or,
+  // when fields_in is given ([nf][ne][n], from an earlier forward call at the
+  // same model), taken from there.
   template <typename T>
   double gradient(SolveBufs<T>& sb, const c128* dobs, const c128* upstream, c128* data_out, const double* cc,
-                  const double* alpha, c128* gm_out, double* gc, double* ga) {
+                  const double* alpha, c128* gm_out, double* gc, double* ga, const c128* fields_in = nullptr) {
     const ProblemCache& pc = c->pc;
     hipStream_t st = c->stream;
     const long ne2 = (long)p->ne * p->ne;
+    const int cs = chunk_of(o, p->ne);
+    int seg = 0;
     for (int gi = 0; gi < ngroups; ++gi) {
       const int l0 = gi * nfg, nf = std::min(nfg, p->nf - l0);
       const c128* P0g = pc.P0 + (long)l0 * p->ne * n;
-      solve_rhs<T>(sb, l0, nf, P0g, cb.fields);
-      launch_gemm_nt(nf, cb.fields, (long)p->ne * n, p->ne, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0,
-                     cb.gpart, gemm_splits(n), data_out + l0 * ne2, st);
-      const c128* rg;
-      if (upstream) {
-        rg = upstream + l0 * ne2;
-      } else {
-        launch_residual(nf * ne2, data_out + l0 * ne2, dobs + l0 * ne2, cb.r + l0 * ne2, cb.misfits + gi, st);
-        rg = cb.r + l0 * ne2;
+      for (int i0 = 0; i0 < p->ne; i0 += cs, ++seg) {
+        const int ni = std::min(cs, p->ne - i0);
+        const long off = ((long)l0 * p->ne + i0) * n;
+        const long rows = l0 * ne2 + (long)i0 * p->ne;  // first data entry of the chunk
+        const c128* F = cb.fields;
+        if (fields_in) {
+          F = fields_in + off;
+        } else {
+          solve_rhs<T>(sb, l0, nf, ni, P0g + (long)i0 * n, cb.fields);
+        }
+        const c128* rg;
+        if (upstream) {
+          rg = upstream + rows;
+        } else {
+          launch_gemm_nt(nf, F, (long)ni * n, ni, cb.m64, P0g, (long)p->ne * n, p->ne, n, pc.coef + l0, cb.gpart,
+                         gemm_splits(n, nf, ni, p->ne), data_out + rows, st);
+          launch_residual((long)nf * ni * p->ne, data_out + rows, dobs + rows, cb.r + rows, cb.misfits + seg, st);
+          rg = cb.r + rows;
+        }
+        if (o.reciprocity_adjoint) {  // whole frequencies only (checked by the entry)
+          launch_gemm_cn(nf, rg, p->ne, p->ne, F, (long)p->ne * n, n, cb.lam, (long)p->ne * n, st);
+        } else {
+          launch_gemm_cn(nf, rg, ni, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)ni * n, st);
+          solve_rhs<T>(sb, l0, nf, ni, cb.S, cb.lam);
+        }
+        launch_gradient_accum(n, nf, ni, F, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, seg == 0, cb.gacc, st);
       }
-      if (o.reciprocity_adjoint) {
-        launch_gemm_cn(nf, rg, p->ne, p->ne, cb.fields, (long)p->ne * n, n, cb.lam, (long)p->ne * n, st);
-      } else {
-        launch_gemm_cn(nf, rg, p->ne, p->ne, P0g, (long)p->ne * n, n, cb.S, (long)p->ne * n, st);
-        solve_rhs<T>(sb, l0, nf, cb.S, cb.lam);
-      }
-      launch_gradient_accum(n, nf, p->ne, cb.fields, cb.lam, pc.k2 + l0, cb.gpart, kGradSeg, gi == 0, cb.gacc, st);
     }
     launch_grad_chain(n, cb.gacc, std::pow(g.dx, g.dim), inv_kappa0(g), cc, alpha, gm_out, gc, ga, st);
-    double phi = 0.0;
-    if (!upstream) {
-      std::vector<double> mf(ngroups);
-      FWI_HIP(hipMemcpyAsync(mf.data(), cb.misfits, sizeof(double) * ngroups, hipMemcpyDeviceToHost, st));
-      FWI_HIP(hipStreamSynchronize(st));
-      for (double v : mf) phi += v;
-    }
-    return phi;
+    return upstream ? 0.0 : sum_misfits(seg);
   }
 };
 
@@ -1096,9 +1179,11 @@ int forward_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doubl
 template <typename T>
 int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* m_in,
                   const void* dobs, const void* upstream, const fwi_solve_opts* opts, double* misfit_out,
-                  void* grad_m_out, double* gc, double* ga, fwi_stats* stats) {
+                  void* grad_m_out, double* gc, double* ga, fwi_stats* stats, const void* fields_in = nullptr) {
   const double t0 = now_ms();
   if ((!m_in && !cc) || (!dobs && !upstream)) throw Error(FWI_E_INVAL, "NULL array argument");
+  if (opts->reciprocity_adjoint && p && chunk_of(*opts, p->ne) < p->ne)
+    throw Error(FWI_E_UNSUPPORTED, "the reciprocity adjoint needs whole frequencies (tx_chunk 0 or >= ne)");
   Runner R(c, p, *opts);
   SolveBufs<T> sb;
   prepare<T>(c, R, sb, FWI_ENTRY_GRADIENT);
@@ -1113,7 +1198,7 @@ int gradient_impl(fwi_ctx* c, const fwi_problem* p, const double* cc, const doub
   }
   R.t_setup += now_ms() - ts;
   const double phi = R.gradient<T>(sb, (const c128*)dobs, (const c128*)upstream, R.cb.data, cc, alpha,
-                                   (c128*)grad_m_out, gc, ga);
+                                   (c128*)grad_m_out, gc, ga, (const c128*)fields_in);
   FWI_HIP(hipStreamSynchronize(c->stream));
   if (misfit_out) *misfit_out = phi;
   collect_iters(c, R.tot);
@@ -1202,7 +1287,8 @@ void jh_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int 
 void j_apply(fwi_ctx* c, const fwi_problem* p, const Geo& g, CallBufs& cb, int nt, const c128* tx, const c128* rx,
              const c128* a, c128* out) {
   const long n = g.n();
-  launch_gemm_nt(p->nf, tx, (long)nt * n, nt, a, rx, (long)p->ne * n, p->ne, n, c->pc.coef, cb.gpart, gemm_splits(n),
+  launch_gemm_nt(p->nf, tx, (long)nt * n, nt, a, rx, (long)p->ne * n, p->ne, n, c->pc.coef, cb.gpart,
+                 gemm_splits(n, p->nf, nt, p->ne),
                  out, c->stream);
 }
 
@@ -1236,6 +1322,7 @@ int admm_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, void
   if (tx && (!w || !rx)) throw Error(FWI_E_INVAL, "NULL transmit weights or receiver fields");
   if (tx && nt > p->ne) throw Error(FWI_E_INVAL, "need 1 <= nt <= ne synthesised transmits");
   Runner R(c, p, *opts);
+  R.o.fields_c64 = 0;  // the Jacobian keeps complex128 fields
   SolveBufs<T> sb;
   prepare<T>(c, R, sb, FWI_ENTRY_ADMM);
   hipStream_t st = c->stream;
@@ -1582,7 +1669,9 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
     maxw = 0;
     maxn = 0;
     for (auto& w : waves) {
-      size_t sum = 2 * sizeof(int) * w.size() + 256 * (w.size() + 1);
+      Arena d;  // the wave's counters, then each instance's buffers
+      d.take<int>(2 * w.size());
+      size_t sum = d.used;
       for (int i : w) sum += inst[i].bytes;
       maxw = std::max(maxw, sum);
       maxn = std::max(maxn, w.size());
@@ -1613,7 +1702,7 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
   BatchTotals tot;
   std::vector<double> misfits(ninst, 0.0);
   for (auto& w : waves) {
-    a.used = 0;
+    a.rewind();
     int* ctr = a.take<int>(2 * w.size());
     std::vector<BatchInst<T>*> wave;
     for (size_t k = 0; k < w.size(); ++k) {
@@ -1639,7 +1728,7 @@ int batch_impl(fwi_ctx* c, int ninst, const fwi_problem* probs, const double* co
       const int ne = I->p->ne, nf = I->p->nf;
       c128* data = I->data_out ? I->data_out : I->cb.data;
       launch_gemm_nt(nf, I->cb.fields, (long)ne * I->n, ne, I->cb.m64, I->pc->P0, (long)ne * I->n, ne, I->n,
-                     I->pc->coef, I->cb.gpart, gemm_splits(I->n), data, main);
+                     I->pc->coef, I->cb.gpart, gemm_splits(I->n, nf, ne, ne), data, main);
       if (gradient) {
         launch_residual((long)nf * ne * ne, data, I->dobs, I->cb.r, I->cb.misfits, main);
         launch_gemm_cn(nf, I->cb.r, ne, ne, I->pc->P0, (long)ne * I->n, I->n, I->cb.S, (long)ne * I->n, main);
@@ -1738,6 +1827,8 @@ void fwi_default_opts(fwi_solve_opts* o) {
   o->max_rhs = 0;
   o->check_every = 1;
   o->reciprocity_adjoint = 0;
+  o->fields_c64 = 0;
+  o->tx_chunk = 0;
 }
 
 int fwi_padded_length(int n) { return padded_length(n); }
@@ -1900,6 +1991,19 @@ int fwi_vjp(fwi_ctx* c, const fwi_problem* p, const void* m, const void* grad_da
                                       nullptr, stats)
                : gradient_impl<double>(c, p, nullptr, nullptr, m, nullptr, grad_data, o, nullptr, grad_m_out, nullptr,
                                        nullptr, stats);
+  });
+}
+
+int fwi_vjp_fields(fwi_ctx* c, const fwi_problem* p, const void* m, const void* fields, const void* grad_data,
+                   const fwi_solve_opts* o, void* grad_m_out, fwi_stats* stats) {
+  return guarded(c, [&] {
+    if (!m || !fields || !grad_data || !grad_m_out) throw Error(FWI_E_INVAL, "NULL array argument");
+    if (!o) throw Error(FWI_E_INVAL, "opts is NULL");
+    return o->precision == FWI_FP32_REFINE
+               ? gradient_impl<float>(c, p, nullptr, nullptr, m, nullptr, grad_data, o, nullptr, grad_m_out, nullptr,
+                                      nullptr, stats, fields)
+               : gradient_impl<double>(c, p, nullptr, nullptr, m, nullptr, grad_data, o, nullptr, grad_m_out, nullptr,
+                                       nullptr, stats, fields);
   });
 }
 
@@ -2088,11 +2192,11 @@ int fwi_jacobian_apply(fwi_ctx* c, const fwi_problem* p, const void* fields, con
     const Geo g = make_geo(p);
     const long n = g.n();
     Arena dry;
-    dry.take<c128>((size_t)gemm_splits(n) * p->nf * p->ne * p->ne);
+    dry.take<c128>((size_t)gemm_splits_max(n) * p->nf * p->ne * p->ne);
     Arena ar;
     bind_workspace(c, ar, dry.used);
     CallBufs cb;
-    cb.gpart = ar.take<c128>((size_t)gemm_splits(n) * p->nf * p->ne * p->ne);
+    cb.gpart = ar.take<c128>((size_t)gemm_splits_max(n) * p->nf * p->ne * p->ne);
     j_apply(c, p, g, cb, p->ne, (const c128*)fields, (const c128*)fields, (const c128*)a, (c128*)out);
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
@@ -2145,14 +2249,15 @@ int fwi_jacobian_apply_tx(fwi_ctx* c, const fwi_problem* p, int nt, const void* 
     check_tx_fields(p, nt, tx_fields, rx_fields, a, out);
     ensure_cache(c, p);
     const long n = make_geo(p).n();
-    const size_t part = (size_t)gemm_splits(n) * p->nf * nt * p->ne;
+    const size_t part = (size_t)gemm_splits_max(n) * p->nf * nt * p->ne;
     Arena dry;
     dry.take<c128>(part);
     Arena ar;
     bind_workspace(c, ar, dry.used);
     c128* gpart = ar.take<c128>(part);
     launch_gemm_nt(p->nf, (const c128*)tx_fields, (long)nt * n, nt, (const c128*)a, (const c128*)rx_fields,
-                   (long)p->ne * n, p->ne, n, c->pc.coef, gpart, gemm_splits(n), (c128*)out, c->stream);
+                   (long)p->ne * n, p->ne, n, c->pc.coef, gpart, gemm_splits(n, p->nf, nt, p->ne), (c128*)out,
+                   c->stream);
     FWI_HIP(hipStreamSynchronize(c->stream));
     return FWI_OK;
   });

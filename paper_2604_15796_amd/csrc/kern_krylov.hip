@@ -146,6 +146,14 @@ __global__ void __launch_bounds__(KT) k_givens(int j, int B, int rows, const dou
   const c128 a = col[j * JM];
   const double aa = sqrt(norm2(a));
   const double nu = sqrt(aa * aa + hn * hn);
+  if (nu == 0.0) {
+    // A v_j = 0 after orthogonalisation: column j is zero and adds nothing to
+    // the least-squares problem, so it is left out (ncol stays j) and the RHS
+    // stops with the solution of the first j columns
+    iters[b] += 1;
+    active[b] = 0;
+    return;
+  }
   double c;
   c128 s;
   if (aa == 0.0) {
@@ -257,8 +265,9 @@ __global__ void k_backsolve(int B, const int* __restrict__ ncol, const c128* __r
     for (int l = i + 1; l < k; ++l) acc = acc - Hb[i * JM + l] * y[(long)b * JM + l];
     const c128 d = Hb[i * JM + i];
     const double dn = norm2(d);
-    // acc / d
-    y[(long)b * JM + i] = mk((acc.x * d.x + acc.y * d.y) / dn, (acc.y * d.x - acc.x * d.y) / dn);
+    // acc / d (a zero diagonal cannot occur for a kept column; guarded anyway)
+    y[(long)b * JM + i] = dn > 0.0 ? mk((acc.x * d.x + acc.y * d.y) / dn, (acc.y * d.x - acc.x * d.y) / dn)
+                                   : mk(0.0, 0.0);
   }
   // the basis is normalised by |r| (cycle start) and stored with scales
   for (int i = 0; i < k; ++i) {

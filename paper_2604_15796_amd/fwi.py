@@ -49,7 +49,8 @@ class CProblem(C.Structure):
 class CSolveOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("rtol", C.c_double), ("max_iter", C.c_int), ("restart", C.c_int),
                 ("max_refine", C.c_int), ("inner_rtol", C.c_double), ("max_rhs", C.c_int),
-                ("check_every", C.c_int), ("reciprocity_adjoint", C.c_int)]
+                ("check_every", C.c_int), ("reciprocity_adjoint", C.c_int), ("fields_c64", C.c_int),
+                ("tx_chunk", C.c_int)]
 
 
 class CStats(C.Structure):
@@ -100,6 +101,7 @@ def lib():
         "fwi_forward_m": (ip, [vp, pp, vp, op, vp, vp, sp]),
         "fwi_adjoint_gradient": (ip, [vp, pp, vp, vp, vp, op, dp, vp, vp, vp, sp]),
         "fwi_vjp": (ip, [vp, pp, vp, vp, op, vp, sp]),
+        "fwi_vjp_fields": (ip, [vp, pp, vp, vp, vp, op, vp, sp]),
         "fwi_tv_admm_step": (ip, [vp, pp, C.POINTER(CAdmmParams), vp, vp, vp, vp, vp, op,
                                   C.POINTER(CAdmmReport), sp]),
         "fwi_apply_operator": (ip, [vp, pp, ip, vp, ip, C.POINTER(C.c_int), vp, vp]),
@@ -140,7 +142,7 @@ def lib():
 
 EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fwi_default_opts",
             "fwi_validate_problem", "fwi_padded_length", "fwi_workspace_size", "fwi_set_workspace",
-            "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_tv_admm_step",
+            "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_vjp_fields", "fwi_tv_admm_step",
             "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
@@ -209,10 +211,18 @@ class SolveOptions:
     max_rhs: int = 0
     check_every: int = 1
     reciprocity_adjoint: int = 0
+    fields_c64: int = 0
+    tx_chunk: int = 0
 
     def c(self):
         return CSolveOpts(self.precision, self.rtol, self.max_iter, self.restart, self.max_refine,
-                          self.inner_rtol, self.max_rhs, self.check_every, self.reciprocity_adjoint)
+                          self.inner_rtol, self.max_rhs, self.check_every, self.reciprocity_adjoint,
+                          self.fields_c64, self.tx_chunk)
+
+
+def _field_dtype(o):
+    """dtype of the fields_out array of the forward entries under options o."""
+    return torch.complex64 if o.fields_c64 else torch.complex128
 
 
 def _ptr(t):
@@ -300,7 +310,7 @@ class Context:
         if alpha is not None:
             _check_dtype(alpha, torch.float64, prob.shape, "alpha")
         data = torch.empty((prob.nf, prob.ne, prob.ne), dtype=torch.complex128, device=self.device)
-        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=_field_dtype(o), device=self.device) if fields else None
         st = CStats()
         self._stream()
         self._workspace(prob, o, ENTRY_FORWARD)
@@ -314,7 +324,7 @@ class Context:
         o = (opts or SolveOptions()).c()
         _check_dtype(m, torch.complex128, prob.shape, "m")
         data = torch.empty((prob.nf, prob.ne, prob.ne), dtype=torch.complex128, device=self.device)
-        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        F = torch.empty((prob.nf, prob.ne, prob.n), dtype=_field_dtype(o), device=self.device) if fields else None
         st = CStats()
         self._stream()
         self._workspace(prob, o, ENTRY_FORWARD)
@@ -357,7 +367,7 @@ class Context:
         _check_dtype(c, torch.float64, prob.shape, "c")
         nt = self._tx_weights(prob, w)
         data = torch.empty((prob.nf, nt, prob.ne), dtype=torch.complex128, device=self.device)
-        F = torch.empty((prob.nf, nt, prob.n), dtype=torch.complex128, device=self.device) if fields else None
+        F = torch.empty((prob.nf, nt, prob.n), dtype=_field_dtype(o), device=self.device) if fields else None
         st = CStats()
         self._stream()
         self._workspace(prob, o, ENTRY_GRADIENT)
@@ -421,6 +431,23 @@ class Context:
         self._stream()
         self._workspace(prob, o, ENTRY_GRADIENT)
         rc = self.L.fwi_vjp(self.h, prob.ref(), _ptr(m), _ptr(grad_data), C.byref(o), _ptr(gm), C.byref(st))
+        self._check(rc, allow_noconv)
+        return gm, st.as_dict()
+
+    def vjp_fields(self, prob, m, fields, grad_data, opts=None, allow_noconv=False):
+        """J^H grad_data with the forward fields [nf, ne, n] given (complex128,
+        from forward_m at the same m): adjoint solves only."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(m, torch.complex128, prob.shape, "m")
+        _check_dtype(fields, torch.complex128, (prob.nf, prob.ne, prob.n), "fields")
+        _check_dtype(grad_data, torch.complex128, (prob.nf, prob.ne, prob.ne), "grad_data")
+        gm = torch.empty(prob.n, dtype=torch.complex128, device=self.device)
+        st = CStats()
+        self._stream()
+        self._workspace(prob, o, ENTRY_GRADIENT)
+        rc = self.L.fwi_vjp_fields(self.h, prob.ref(), _ptr(m), _ptr(fields), _ptr(grad_data), C.byref(o), _ptr(gm),
+                                   C.byref(st))
         self._check(rc, allow_noconv)
         return gm, st.as_dict()
 
@@ -701,26 +728,44 @@ def workspace_size(p, opts=None, entry=ENTRY_FORWARD):
 
 # ------------------------------------------------------------- autograd ---
 class FWIData(torch.autograd.Function):
-    """d = F(m) with the adjoint-state backward J^H grad_d (Eq. 17), computed by
-    adjoint solves in the library; wavefields are recomputed in the backward
-    rather than stored."""
+    """d = F(m) with the adjoint-state backward J^H grad_d (Eq. 17): adjoint
+    solves in the library with the forward fields either kept from the
+    forward pass (when they fit `store_bytes`) or recomputed in the backward
+    (in the frequency groups and transmit chunks of the options, so that
+    never all fields are held). Both give the same gradient bit for bit."""
 
     @staticmethod
-    def forward(ctx, m, context, prob, opts):
-        data, _ = context.forward_m(prob, m.contiguous(), opts)
-        ctx.save_for_backward(m)
-        ctx.fwi = (context, prob, opts)
+    def forward(ctx, m, context, prob, opts, store_bytes):
+        need = prob.nf * prob.ne * prob.n * 16
+        if store_bytes is None:
+            store_bytes = torch.cuda.mem_get_info(context.device)[0] // 4
+        store = need <= store_bytes
+        o = opts if not opts.fields_c64 else SolveOptions(**{**opts.__dict__, "fields_c64": 0})
+        if store:
+            data, fields, _ = context.forward_m(prob, m.contiguous(), o, fields=True)
+            ctx.save_for_backward(m, fields)
+        else:
+            data, _ = context.forward_m(prob, m.contiguous(), o)
+            ctx.save_for_backward(m)
+        ctx.fwi = (context, prob, o, store)
         return data
 
     @staticmethod
     def backward(ctx, grad_data):
-        (m,) = ctx.saved_tensors
-        context, prob, opts = ctx.fwi
-        gm, _ = context.vjp(prob, m.contiguous(), grad_data.contiguous().to(torch.complex128), opts)
-        return gm.reshape(m.shape), None, None, None
+        context, prob, opts, store = ctx.fwi
+        b = grad_data.contiguous().to(torch.complex128)
+        if store:
+            m, fields = ctx.saved_tensors
+            gm, _ = context.vjp_fields(prob, m.contiguous(), fields, b, opts)
+        else:
+            (m,) = ctx.saved_tensors
+            gm, _ = context.vjp(prob, m.contiguous(), b, opts)
+        return gm.reshape(m.shape), None, None, None, None
 
 
-def fwi_data(m, context, prob, opts=None):
-    """Differentiable forward model d = F(m) (complex128)."""
+def fwi_data(m, context, prob, opts=None, store_bytes=None):
+    """Differentiable forward model d = F(m) (complex128). store_bytes: device
+    bytes the forward fields may occupy between the forward and the backward
+    pass (None: a quarter of the free device memory; 0: always recompute)."""
     prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
-    return FWIData.apply(m, context, prob, opts or SolveOptions())
+    return FWIData.apply(m, context, prob, opts or SolveOptions(), store_bytes)

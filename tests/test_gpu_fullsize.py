@@ -12,6 +12,7 @@ import torch
 
 from oracle import fwi_oracle as O
 from paper_2604_15796_amd import workloads as W
+from parity_util import strict_err
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -36,11 +37,10 @@ def t(x, dtype=None):
 
 
 def rel(a, b, floor=0.0):
-    """Relative error; `floor` bounds the denominator from below (for a
-    reference that can be exactly zero, e.g. a fully shrunk TV variable)."""
-    a = a.detach().cpu().numpy() if torch.is_tensor(a) else np.asarray(a)
-    b = b.detach().cpu().numpy() if torch.is_tensor(b) else np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), floor, 1e-300))
+    """Strict error (parity_util.strict_err: per row and element-wise);
+    `floor` bounds the denominators from below (for a reference that can be
+    exactly zero, e.g. a fully shrunk TV variable)."""
+    return strict_err(a, b, abs_floor=floor)
 
 
 def mixed(F, **kw):
