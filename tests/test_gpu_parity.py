@@ -422,7 +422,7 @@ def test_invert_algorithm1_vs_oracle(ctx, F, tx):
     assert relerr(host(g), rg) < 1e-8 and relerr(host(u), ru) < 1e-8
     assert hist[-1] < hist[0]
     c_est, a_est = ctx.sos_from_contrast(p, mt)
-    rc_est, ra_est = O.sos_from_contrast(rm, p.c0)
+    rc_est, ra_est = O.sos_from_contrast(host(mt), p.c0)  # the inverse of Eq. 1-3 on the same iterate
     assert relerr(host(c_est), rc_est) < 1e-12 and relerr(host(a_est), ra_est) < 1e-9
     rmse = lambda c: float(np.sqrt(np.mean((c - p.c) ** 2)))
     assert rmse(host(c_est)) < rmse(np.full_like(p.c, p.c0))
