@@ -315,6 +315,22 @@ int fwi_forward_batch(fwi_ctx* ctx, int ninst, const fwi_problem* probs, const d
 int fwi_apply_operator(fwi_ctx* ctx, const fwi_problem* prob, int precision, const void* m, int B,
                        const int* freq_index, const void* x, void* y);
 
+/* fwi_apply_operator that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): its scratch (the frequency
+ * indices, the contrast in the working precision and the pass
+ * intermediates, about (2 B + 1) n complex values in 2D and (6 B + 1) n in
+ * 3D) lives in a static 64 MiB device array of the library, one per GPU,
+ * held until the process ends. Same
+ * arguments and result as fwi_apply_operator (bit for bit). Requires that
+ * the context already holds this problem's Green spectra (any earlier entry
+ * point on the problem, e.g. fwi_green_spectrum, builds them; otherwise
+ * FWI_E_INVAL); a call needing more scratch than 64 MiB returns FWI_E_NOMEM
+ * and writes nothing. Every call on a GPU shares that GPU's scratch: calls
+ * that overlap on one GPU (from several contexts or streams) race. */
+int fwi_apply_operator_noalloc(fwi_ctx* ctx, const fwi_problem* prob, int precision, const void* m, int B,
+                               const int* freq_index, const void* x, void* y);
+
 /* Solve A_l x_b = rhs_b for B right-hand sides with the batched solver.
  * m [n], rhs [B][n], x_out [B][n]: complex128; freq_index host [B]. */
 int fwi_solve(fwi_ctx* ctx, const fwi_problem* prob, const void* m, int B, const int* freq_index, const void* rhs,

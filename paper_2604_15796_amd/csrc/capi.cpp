@@ -229,6 +229,14 @@ double now_ms() {
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// Scratch of fwi_apply_operator_noalloc (for callers that cannot allocate):
+// a file-scope device array, one copy per GPU the library runs on, held until
+// the process ends. Host code never uses its name as an address: each context
+// looks up its device's copy once (hipGetSymbolAddress at fwi_create, with
+// that device current) and passes that pointer on.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
 }  // namespace
 
 struct fwi_ctx {
@@ -255,6 +263,7 @@ struct fwi_ctx {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t count_ev = nullptr;               // active-count copy of the solver loop
   unsigned long long* d_itstat = nullptr;      // iteration max / sum of the current call's solves
+  char* scratch_dev = nullptr;                 // this device's copy of `scratch`
   ~fwi_ctx() {
     if (count_ev) (void)hipEventDestroy(count_ev);
     for (auto& kv : bcache) kv.second.release();
@@ -1811,6 +1820,58 @@ int invert_impl(fwi_ctx* c, const fwi_problem* p, const fwi_admm_params* prm, in
   return ret;
 }
 
+// y = A_l x for B vectors (the spectra must be cached), with the scratch
+// (frequency indices, cast contrast, pass intermediates) carved from `bound`
+// (the static scratch) or, when null, from the context's workspace.
+void apply_operator_in(fwi_ctx* c, const fwi_problem* p, int precision, const void* m, int B, const int* freq_index,
+                       const void* x, void* y, Arena* bound) {
+  const Geo g = make_geo(p);
+  const long n = g.n();
+  Arena dry;
+  auto plan = [&](Arena& a, int*& rf, void*& mT, void*& U1, void*& U2) {
+    rf = a.take<int>(B);
+    const size_t es = precision == FWI_FP32_REFINE ? sizeof(c64) : sizeof(c128);
+    mT = a.take<char>(es * n);
+    U1 = a.take<char>(es * B * g.u1());
+    U2 = a.take<char>(es * B * std::max(1L, g.u2()));
+  };
+  int* rf;
+  void *mT, *U1, *U2;
+  plan(dry, rf, mT, U1, U2);
+  Arena a;
+  if (bound) {
+    if (dry.used > bound->cap)
+      throw Error(FWI_E_NOMEM, "the operator needs " + std::to_string(dry.used) + " bytes of scratch; the static "
+                               "scratch holds " + std::to_string(bound->cap) + " (use fwi_apply_operator)");
+    a = *bound;
+    a.rewind();
+  } else {
+    bind_workspace(c, a, dry.used);
+  }
+  plan(a, rf, mT, U1, U2);
+  hipStream_t st = c->stream;
+  FWI_HIP(hipMemcpyAsync(rf, freq_index, sizeof(int) * B, hipMemcpyHostToDevice, st));
+  if (precision == FWI_FP32_REFINE) {
+    launch_cast_64_32(n, (const c128*)m, (c64*)mT, st);
+    launch_vie<float>(g, c->tw, B, (const c64*)x, nullptr, nullptr, (const c64*)mT, c->pc.ghat32, rf, (c64*)U1,
+                      (c64*)U2, (c64*)y, nullptr, EPI_VIE, st);
+  } else {
+    launch_vie<double>(g, c->tw, B, (const c128*)x, nullptr, nullptr, (const c128*)m, c->pc.ghat64, rf, (c128*)U1,
+                       (c128*)U2, (c128*)y, nullptr, EPI_VIE, st);
+  }
+  FWI_HIP(hipStreamSynchronize(st));
+}
+
+void check_operator_args(const fwi_problem* p, const void* m, int B, const int* freq_index, const void* x,
+                         const void* y) {
+  std::string msg;
+  int rc = validate_problem(p, msg);
+  if (rc) throw Error(rc, msg);
+  if (!m || !x || !y || !freq_index || B < 1) throw Error(FWI_E_INVAL, "bad operator arguments");
+  for (int b = 0; b < B; ++b)
+    if (freq_index[b] < 0 || freq_index[b] >= p->nf) throw Error(FWI_E_INVAL, "frequency index out of range");
+}
+
 }  // namespace
 
 // ===================================================================== ABI ===
@@ -1883,6 +1944,7 @@ int fwi_create(fwi_ctx** out, int device, void* stream) {
     FWI_HIP(hipEventCreateWithFlags(&c->count_ev, hipEventDisableTiming));
     FWI_HIP(hipMalloc((void**)&c->d_itstat, 2 * sizeof(unsigned long long)));
     launch_zero_u64(2, c->d_itstat, c->stream);
+    FWI_HIP(hipGetSymbolAddress((void**)&c->scratch_dev, HIP_SYMBOL(scratch)));
   } catch (const Error& e) {
     fwi_destroy(c);
     return e.code;
@@ -2061,40 +2123,26 @@ int fwi_sos_from_contrast(fwi_ctx* c, const fwi_problem* p, const void* m, doubl
 int fwi_apply_operator(fwi_ctx* c, const fwi_problem* p, int precision, const void* m, int B, const int* freq_index,
                        const void* x, void* y) {
   return guarded(c, [&] {
-    std::string msg;
-    int rc = validate_problem(p, msg);
-    if (rc) throw Error(rc, msg);
-    if (!m || !x || !y || !freq_index || B < 1) throw Error(FWI_E_INVAL, "bad operator arguments");
-    for (int b = 0; b < B; ++b)
-      if (freq_index[b] < 0 || freq_index[b] >= p->nf) throw Error(FWI_E_INVAL, "frequency index out of range");
+    check_operator_args(p, m, B, freq_index, x, y);
     ensure_cache(c, p);
-    const Geo g = make_geo(p);
-    const long n = g.n();
-    Arena dry;
-    auto plan = [&](Arena& a, int*& rf, void*& mT, void*& U1, void*& U2) {
-      rf = a.take<int>(B);
-      const size_t es = precision == FWI_FP32_REFINE ? sizeof(c64) : sizeof(c128);
-      mT = a.take<char>(es * n);
-      U1 = a.take<char>(es * B * g.u1());
-      U2 = a.take<char>(es * B * std::max(1L, g.u2()));
-    };
-    int* rf;
-    void *mT, *U1, *U2;
-    plan(dry, rf, mT, U1, U2);
-    Arena a;
-    bind_workspace(c, a, dry.used);
-    plan(a, rf, mT, U1, U2);
-    hipStream_t st = c->stream;
-    FWI_HIP(hipMemcpyAsync(rf, freq_index, sizeof(int) * B, hipMemcpyHostToDevice, st));
-    if (precision == FWI_FP32_REFINE) {
-      launch_cast_64_32(n, (const c128*)m, (c64*)mT, st);
-      launch_vie<float>(g, c->tw, B, (const c64*)x, nullptr, nullptr, (const c64*)mT, c->pc.ghat32, rf, (c64*)U1,
-                        (c64*)U2, (c64*)y, nullptr, EPI_VIE, st);
-    } else {
-      launch_vie<double>(g, c->tw, B, (const c128*)x, nullptr, nullptr, (const c128*)m, c->pc.ghat64, rf, (c128*)U1,
-                         (c128*)U2, (c128*)y, nullptr, EPI_VIE, st);
-    }
-    FWI_HIP(hipStreamSynchronize(st));
+    apply_operator_in(c, p, precision, m, B, freq_index, x, y, nullptr);
+    return FWI_OK;
+  });
+}
+
+int fwi_apply_operator_noalloc(fwi_ctx* c, const fwi_problem* p, int precision, const void* m, int B,
+                               const int* freq_index, const void* x, void* y) {
+  return guarded(c, [&] {
+    check_operator_args(p, m, B, freq_index, x, y);
+    if (problem_key(p) != c->pc.key)
+      throw Error(FWI_E_INVAL, "no cached spectra for this problem on this context (building them allocates): "
+                               "call an entry point such as fwi_green_spectrum on it first");
+    if (!c->scratch_dev) throw Error(FWI_E_DEVICE, "static scratch address unknown");
+    Arena s;
+    s.base = c->scratch_dev;
+    s.cap = kStaticScratchBytes;
+    s.dry = false;
+    apply_operator_in(c, p, precision, m, B, freq_index, x, y, &s);
     return FWI_OK;
   });
 }

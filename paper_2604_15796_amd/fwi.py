@@ -105,6 +105,7 @@ def lib():
         "fwi_tv_admm_step": (ip, [vp, pp, C.POINTER(CAdmmParams), vp, vp, vp, vp, vp, op,
                                   C.POINTER(CAdmmReport), sp]),
         "fwi_apply_operator": (ip, [vp, pp, ip, vp, ip, C.POINTER(C.c_int), vp, vp]),
+        "fwi_apply_operator_noalloc": (ip, [vp, pp, ip, vp, ip, C.POINTER(C.c_int), vp, vp]),
         "fwi_solve": (ip, [vp, pp, vp, ip, C.POINTER(C.c_int), vp, op, vp, sp]),
         "fwi_incident": (ip, [vp, pp, ip, vp]),
         "fwi_green_spectrum": (ip, [vp, pp, ip, vp]),
@@ -143,7 +144,7 @@ def lib():
 EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fwi_default_opts",
             "fwi_validate_problem", "fwi_padded_length", "fwi_workspace_size", "fwi_set_workspace",
             "fwi_forward", "fwi_forward_m", "fwi_adjoint_gradient", "fwi_vjp", "fwi_vjp_fields", "fwi_tv_admm_step",
-            "fwi_apply_operator", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
+            "fwi_apply_operator", "fwi_apply_operator_noalloc", "fwi_solve", "fwi_incident", "fwi_green_spectrum", "fwi_fft_padded",
             "fwi_jacobian_apply", "fwi_jacobian_adjoint_apply", "fwi_host_bessel01", "fwi_profile",
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
@@ -633,6 +634,20 @@ class Context:
         self._internal_workspace()
         rc = self.L.fwi_apply_operator(self.h, prob.ref(), precision, _ptr(m), len(fi),
                                        fi.ctypes.data_as(C.POINTER(C.c_int)), _ptr(x), _ptr(y))
+        self._check(rc)
+        return y
+
+    def apply_operator_noalloc(self, prob, m, freq_index, x, precision=FWI_FP64):
+        """apply_operator with the library's static scratch (allocates nothing on
+        the device; the problem's spectra must already be cached)."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        fi = np.ascontiguousarray(np.asarray(freq_index, dtype=np.int32))
+        dt = torch.complex64 if precision == FWI_FP32_REFINE else torch.complex128
+        _check_dtype(x, dt, (len(fi), prob.n), "x")
+        y = torch.empty_like(x)
+        self._stream()
+        rc = self.L.fwi_apply_operator_noalloc(self.h, prob.ref(), precision, _ptr(m), len(fi),
+                                               fi.ctypes.data_as(C.POINTER(C.c_int)), _ptr(x), _ptr(y))
         self._check(rc)
         return y
 

@@ -237,6 +237,8 @@ void every_entry(fwi_ctx* ctx, int dim) {
     void* x = std::calloc(3 * n, es);
     void* y = std::calloc(3 * n, es);
     check(fwi_apply_operator(ctx, &q.p, prec, gm, 3, fi.data(), x, y), "apply_operator", ctx);
+    check(fwi_apply_operator_noalloc(ctx, &q.p, prec, gm, 3, fi.data(), x, y), "apply_operator_noalloc", ctx);
+    check(fwi_apply_operator_noalloc(ctx, &q.p, prec, gm, 1, fi.data(), x, y), "apply_operator_noalloc", ctx);
     auto* rhs = dev<std::complex<double>>(3 * n, 1.0);
     auto* xs = dev<std::complex<double>>(3 * n);
     check(fwi_solve(ctx, &q.p, gm, 3, fi.data(), rhs, &o, xs, &st), "solve", ctx);

@@ -19,6 +19,7 @@
 #define __forceinline__ inline
 #define __restrict__
 #define __launch_bounds__(x)
+#define __align__(x) alignas(x)
 
 struct EmuDim {
   unsigned x = 0, y = 0, z = 0;
