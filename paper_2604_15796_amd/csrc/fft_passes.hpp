@@ -437,7 +437,22 @@ struct StridedArgs {
   int lin, lout;          // nonzero input points, output points kept
   long nplanes;           // planes in the launch
   long gpstride;          // Ghat stride between points of a line (conv)
+  int tile_major;         // conv: one-dimensional grid ordered tile by tile (see conv_item)
 };
+
+// Work item of a convolution workgroup in the tile-major order: item j is
+// column tile j / nplanes of plane j % nplanes, so the planes (right-hand
+// sides) that share a tile of the kernel spectrum run back to back, and the
+// items are dealt so that each XCD takes a contiguous range of them
+// (workgroups go to the 8 XCDs in turn): a spectrum tile is then fetched into
+// one L2 and reused by every plane, instead of the whole spectrum being
+// streamed from HBM once per plane when it does not fit the caches (3D).
+__device__ __forceinline__ void conv_item(long nplanes, int& tile, long& plane) {
+  const unsigned x = blockIdx.x, n = gridDim.x;
+  const unsigned j = n % 8 == 0 ? (x % 8) * (n / 8) + x / 8 : x;
+  tile = (int)(j / (unsigned long)nplanes);
+  plane = (long)(j % (unsigned long)nplanes);
+}
 
 constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolution pass
 
@@ -451,7 +466,11 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
   using C = LineCfg<T, L, NLV, NTV, true>;
   __shared__ cplx<T> sh[C::LDS_ELEMS];
   constexpr unsigned ES = sizeof(cplx<T>);
-  const int line0 = col_tile<C::NL, (int)ES>() * C::NL;
+  int tile = 0;
+  long plane_tm = 0;  // tile-major convolution: the workgroup's plane
+  if (MODE == 2 && a.tile_major) conv_item(a.nplanes, tile, plane_tm);
+  else tile = col_tile<C::NL, (int)ES>();
+  const int line0 = tile * C::NL;
   const int nl = a.nlines - line0;
   // line-fastest mapping: the thread's line is fixed; a line past the plane
   // gets an offset past every view (its loads read zero, its stores drop)
@@ -466,7 +485,7 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
     cplx<T> gpre[Map::TT][Map::R];
     int fcur = -1;
     for (int q = 0; q < CONV_RPW; ++q) {
-      const long plane = (long)blockIdx.y * CONV_RPW + q;
+      const long plane = a.tile_major ? plane_tm + q : (long)blockIdx.y * CONV_RPW + q;
       if (plane >= a.nplanes) break;
       const int b = (int)(plane / a.planes_per_rhs);
       if (a.active && !a.active[b]) continue;  // uniform per workgroup
@@ -622,9 +641,18 @@ void launch_strided_v(const StridedArgs<T>& a, long planes, int mode, hipStream_
   const bool hin = 2 * a.lin <= L, hout = 2 * a.lout <= L;
   if (mode == 2) {
     if (!hin || !hout) throw Error(-6, "convolution lines must be zero-padded to twice their length");
-    // 64-bit path: one tile variant only
-    if (wide) launch_strided_k<T, L, 0, 2, true, true>(args, dim3((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y), st);
-    else launch_strided_k<T, L, V, 2, true, false>(args, grid, st);
+    // 64-bit path: one tile variant, planes along y
+    if (wide) {
+      args.tile_major = 0;
+      launch_strided_k<T, L, 0, 2, true, true>(args, dim3((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y), st);
+    } else if (args.tile_major) {
+      if (CONV_RPW != 1) throw Error(-6, "tile-major convolution takes one plane per workgroup");
+      const long items = (long)grid.x * planes;
+      if (items > 0x7fffffffL) throw Error(-6, "too many convolution work items for one launch");
+      launch_strided_k<T, L, V, 2, true, false>(args, dim3((unsigned)items), st);
+    } else {
+      launch_strided_k<T, L, V, 2, true, false>(args, grid, st);
+    }
   } else if (mode == 0) {
     if (wide) {
       const dim3 g0((a.nlines + col_nl<T, L, 0>() - 1) / col_nl<T, L, 0>(), grid.y);
@@ -700,6 +728,11 @@ int row_inv_nl(int L) {
   FWI_LENGTHS(row_inv_nl_v, L, v, nl);
   return nl;
 }
+
+// The convolution pass runs tile-major (conv_item) when one frequency's
+// spectrum exceeds an XCD's 4 MiB L2: swept plane by plane, it would be
+// streamed from HBM once per right-hand side.
+inline int conv_tile_major(const Geo& g, size_t es) { return g.npad() * (long)es > (4L << 20) ? 1 : 0; }
 
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
@@ -788,6 +821,7 @@ void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
     s.nlines = g.Lx;
     s.planes_per_rhs = 1;
     s.lin = s.lout = g.nz;
+    s.tile_major = conv_tile_major(g, sizeof(cplx<T>));
     prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, s, B, 2, st);
     prof_end(KC_CONV + po, st, 2.0 * g.u1() * es, gbytes, masked, B);
@@ -823,6 +857,7 @@ void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
     c.nlines = g.Ly * g.Lx;
     c.planes_per_rhs = 1;
     c.lin = c.lout = g.nz;
+    c.tile_major = conv_tile_major(g, sizeof(cplx<T>));
     prof_begin(KC_CONV + po, st);
     strided_call<T>(g.Lz, c, B, 2, st);
     prof_end(KC_CONV + po, st, 2.0 * g.u2() * es, gbytes, masked, B);

@@ -117,9 +117,10 @@ __global__ void __launch_bounds__(KT) k_hsum(int j, int B, const int* __restrict
   }
 }
 
-// One wave per RHS: finish column j (norm of the orthogonalised vector from
-// its per-row sums, previous rotations, new rotation), update the residual
-// estimate and the convergence mask, count the RHS still active.
+// One workgroup per RHS: finish column j (norm of the orthogonalised vector
+// from its per-row sums, summed by the whole workgroup in a fixed order;
+// previous rotations, new rotation), update the residual estimate and the
+// convergence mask, count the RHS still active.
 template <typename T, int JM>
 __global__ void __launch_bounds__(KT) k_givens(int j, int B, int rows, const double* __restrict__ rowpart,
                                                int* __restrict__ active, c128* __restrict__ H,
@@ -127,13 +128,13 @@ __global__ void __launch_bounds__(KT) k_givens(int j, int B, int rows, const dou
                                                c128* __restrict__ gv, const double* __restrict__ target,
                                                int* __restrict__ ncol, int* __restrict__ iters,
                                                cplx<T>* __restrict__ vscale_next, int* __restrict__ counters) {
-  const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * (KT / 64) + (threadIdx.x >> 6);
-  if (b >= B || !active[b]) return;  // uniform per wave
+  __shared__ double red[KT / 64];
+  const int b = blockIdx.x;
+  if (b >= B || !active[b]) return;  // uniform per workgroup
   double s2 = 0.0;
-  for (int k = lane; k < rows; k += 64) s2 += rowpart[(long)b * rows + k];
-  s2 = wave_sum(s2);
-  if (lane != 0) return;
+  for (int k = threadIdx.x; k < rows; k += KT) s2 += rowpart[(long)b * rows + k];
+  s2 = block_sum<KT>(s2, red);
+  if (threadIdx.x != 0) return;
   const double hn = sqrt(s2);
   c128* col = H + (long)b * (JM + 1) * JM + j;  // col[i*JM] = H[i][j]
   for (int i = 0; i < j; ++i) {
@@ -424,7 +425,7 @@ void krylov_hsum(const KrylovState<T>& s, int j, int ndot, hipStream_t st) {
 
 template <typename T>
 void krylov_givens(const KrylovState<T>& s, int j, const double* rowpart, int rows, hipStream_t st) {
-  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3((s.B + KT / 64 - 1) / (KT / 64)), dim3(KT), 0, st,
+  FWI_JM_SWITCH(s.JM, hipLaunchKernelGGL((k_givens<T, JMC>), dim3(s.B), dim3(KT), 0, st,
                                           j, s.B, rows, rowpart, s.active, s.H, s.cs, s.sn, s.gv, s.target, s.ncol,
                                           s.iters, s.vscale + (long)(j + 1) * s.B, s.counters));
   FWI_LAUNCH_CHECK();
