@@ -45,8 +45,7 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # profiles/gradient3d_hbm_traffic.md, profiles/gradient3d_valu.md).
 MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.9e6},
             "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.7e6},
-            "k_strided<float, 512, 8, 256, 2, true, false>": {"traffic": 898.5e6, "valu_busy": 0.776},
-            "k_strided<float, 192, 16, 256, 2, true, false>": {"valu_busy": 0.75}}
+            "k_strided<float, 192, 16, 256, 2, true, false>": {"traffic": 5473.9e6, "valu_busy": 0.779}}
 
 
 def parse():
