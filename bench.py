@@ -72,7 +72,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=2,
                     help="gradient-3d: transmits of the first frequency whose fields the oracle solves")
     ap.add_argument("--workload", default="gradient-3d",
-                    choices=["gradient-256", "planewave-256", "uneven-batch", "invert-384", "gradient-3d"],
+                    choices=["gradient-3d", "gradient-256", "planewave-256", "gradient-384", "gradient-64",
+                             "uneven-batch", "invert-384"],
                     help="gradient-3d (default, the largest single-GPU configuration): 128x128x96, 4 "
                          "frequencies, 64 elements, one frequency per batched solve (fields recomputed per "
                          "frequency); gradient-256: 2D 256^2, 8 frequencies, 64 elements; planewave-256: the "
@@ -110,18 +111,22 @@ def main():
         return bench_invert(args)
     out = bench_gradient(args, args.workload)
     if args.workload == "gradient-3d" and not args.no_extra and not args.counter_sample:
+        # the other single-GPU configurations, timed the same way (their own
+        # lines, summarised under their names)
         import copy
         import torch
-        torch.cuda.empty_cache()
-        a2 = copy.copy(args)
-        a2.max_rhs, a2.no_cpu = 0, True
-        o2 = bench_gradient(a2, "gradient-256")
-        out["gradient_256"] = {
-            "workload": o2["config"]["workload"], "value": o2["value"], "unit": o2["unit"],
-            "ms_per_step": o2["ms_per_step"], "steps": o2["steps"], "roofline": o2["roofline"],
-            "accuracy": o2.get("accuracy"), "fp64_plain": o2.get("fp64_plain"),
-            "speedup_vs_fp64_plain": o2.get("speedup_vs_fp64_plain"), "autotune_ms": {
-                k: o2["autotune"][k] for k in ("fixed_tiles_ms_per_step", "autotuned_ms_per_step")}}
+        for key, wl in (("gradient_256", "gradient-256"), ("gradient_384", "gradient-384"),
+                        ("gradient_64", "gradient-64")):
+            torch.cuda.empty_cache()
+            a2 = copy.copy(args)
+            a2.max_rhs, a2.no_cpu = 0, True
+            o2 = bench_gradient(a2, wl)
+            out[key] = {
+                "workload": o2["config"]["workload"], "value": o2["value"], "unit": o2["unit"],
+                "ms_per_step": o2["ms_per_step"], "steps": o2["steps"], "precision": o2["config"]["precision"],
+                "roofline": o2["roofline"], "accuracy": o2.get("accuracy"), "fp64_plain": o2.get("fp64_plain"),
+                "speedup_vs_fp64_plain": o2.get("speedup_vs_fp64_plain"), "oracle": o2.get("oracle"),
+                "autotune_ms": {k: o2["autotune"][k] for k in ("fixed_tiles_ms_per_step", "autotuned_ms_per_step")}}
     if out is not None:
         print(json.dumps(out), flush=True)
 
@@ -143,7 +148,11 @@ def bench_gradient(args, workload):
     dev = torch.device("cuda", 0)
     three_d = workload == "gradient-3d"
     planewave = workload == "planewave-256"
-    p = W.config4() if three_d else W.config1()
+    fp64_only = workload == "gradient-64"  # the 64^2 configuration is plain FP64 (complex128) by definition
+    p = {"gradient-3d": W.config4, "gradient-256": W.config1, "planewave-256": W.config1,
+         "gradient-384": W.config3, "gradient-64": W.config0}[workload]()
+    if "c_obs" not in p.extra:  # the 384^2 phantom: observed model with +1% seeded SoS noise
+        p.extra["c_obs"] = W.perturb_sos(p.c, seed=303)
     max_rhs = args.max_rhs
     if three_d and max_rhs == 0:
         max_rhs = p.ne  # one frequency per batched solve: fields recomputed, never all stored
@@ -179,6 +188,8 @@ def bench_gradient(args, workload):
                              inner_rtol=args.inner_rtol, check_every=args.check_every, max_rhs=max_rhs)
     plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=args.restart,
                              check_every=args.check_every, max_rhs=max_rhs)
+    if fp64_only:
+        mixed = plain
     nt = w_tx.shape[1] if planewave else p.ne
     solves_per_step = 2 * p.nf * nt
 
@@ -235,17 +246,23 @@ def bench_gradient(args, workload):
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "c64", "data": "synthetic",
-           "config": {"workload": ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements firing 60 plane "
-                                   "waves -60..60 deg: forward+adjoint gradient (480+480 solves)") if planewave else
-                                  ("3D 128x128x96 dx=0.2mm, 4 freqs 0.4-0.8 MHz, 64 elements: forward+adjoint "
-                                   "gradient (256+256 solves), one frequency per batched solve") if three_d else
-                                  ("2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
-                                   "forward+adjoint gradient (512+512 solves)"),
+           "vs_baseline": None, "dtype": "c128" if fp64_only else "c64", "data": "synthetic",
+           "config": {"workload": {
+                          "planewave-256": "2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements firing 60 plane "
+                                           "waves -60..60 deg: forward+adjoint gradient (480+480 solves)",
+                          "gradient-3d": "3D 128x128x96 dx=0.2mm, 4 freqs 0.4-0.8 MHz, 64 elements: forward+adjoint "
+                                         "gradient (256+256 solves), one frequency per batched solve",
+                          "gradient-256": "2D 256x256 dx=0.154mm, 8 freqs 0.3-1.0 MHz, 64 elements: "
+                                          "forward+adjoint gradient (512+512 solves)",
+                          "gradient-384": "2D 384x384 dx=0.1283mm, 12 freqs 0.3-1.2 MHz, 128 elements, thyroid-like "
+                                          "phantom: forward+adjoint gradient (1536+1536 solves)",
+                          "gradient-64": "2D 64x64 dx=0.154mm, 1 MHz, 16 elements, 2 mm disk: forward+adjoint "
+                                         "gradient (16+16 solves), plain FP64"}[workload],
                       "max_rhs": max_rhs,
                       "transmits_per_freq": int(nt),
                       "grid": list(p.shape), "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
-                      "precision": "complex64 GMRES in FP64-residual refinement",
+                      "precision": "complex128 GMRES" if fp64_only else
+                                   "complex64 GMRES in FP64-residual refinement",
                       "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
            "setup_ms": round(setup_ms, 2),
            "roofline": roofline,
@@ -275,7 +292,7 @@ def bench_gradient(args, workload):
         out["fp64_plain"] = {"ms_per_step": round(ms_plain, 3),
                              "solves_per_s": round(solves_per_step / (ms_plain * 1e-3), 2),
                              "rtol": args.rtol}
-        out["speedup_vs_fp64_plain"] = round(ms_plain / ms_step, 3)
+        out["speedup_vs_fp64_plain"] = None if fp64_only else round(ms_plain / ms_step, 3)
         log(f"accuracy: field {field_err:.2e}, grad {grad_err:.2e}; fp64 plain {ms_plain:.1f} ms")
         if not planewave:
             # reported apart from the metric: with transmit set = receive set the
@@ -295,6 +312,18 @@ def bench_gradient(args, workload):
         del g32, g64
         torch.cuda.empty_cache()
 
+    if fp64_only:
+        # the whole gradient of the 64^2 configuration against the oracle at the timed options
+        from oracle import fwi_oracle as O
+        phi, g_gpu, _, _, _ = step(mixed)
+        args2 = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+        od_obs = O.forward(p.extra["c_obs"], p.alpha, *args2)[0]
+        ophi, og, _, _, _ = O.adjoint_gradient(p.c, p.alpha, od_obs, *args2)
+        g_gpu = g_gpu.cpu().numpy()
+        out["oracle"] = {"grad_rel_err": float(np.linalg.norm(g_gpu - og) / np.linalg.norm(og)),
+                         "grad_max_abs_err_over_max": float(np.abs(g_gpu - og).max() / np.abs(og).max()),
+                         "misfit_rel_err": abs(phi - ophi) / ophi,
+                         "note": "full gradient and misfit; each side computes its own observed data"}
     if not args.no_cpu:
         if three_d:
             out["cpu_baseline"] = oracle_leg_3d(p, ctx, prob, c, a, d_obs, mixed, args.cpu_sample)
