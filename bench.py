@@ -43,9 +43,19 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # GRBM_GUI_ACTIVE. Reported only while the timed dominant class runs that
 # kernel (profiles/gradient256_hbm_traffic.md, profiles/gradient256_valu.md,
 # profiles/gradient3d_hbm_traffic.md, profiles/gradient3d_valu.md).
-MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.9e6},
-            "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.7e6},
-            "k_strided<float, 192, 16, 256, 2, true, false>": {"traffic": 5473.9e6, "valu_busy": 0.779}}
+# Each figure holds for the launches of the counted run: `batch` RHS per
+# launch and `steps` Arnoldi steps per complex64 cycle (a restart length at or
+# above that gives the same launches). It is reported only when the timed run
+# launches the same.
+MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.9e6, "batch": 512, "steps": 8},
+            "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.7e6, "batch": 512, "steps": 8},
+            "k_strided<float, 192, 16, 256, 2, true, false>": {"traffic": 5473.9e6, "valu_busy": 0.779,
+                                                               "batch": 64, "steps": 7}}
+
+
+def measured_at(name, batch, steps):
+    m = MEASURED.get(name, {})
+    return m if m.get("batch") == batch and m.get("steps") == steps else {}
 
 
 def parse():
@@ -58,10 +68,13 @@ def parse():
                     help="floor of each complex64 cycle's relative target; default 1e-6 for gradient-256 (one "
                          "cycle reaches the outer tolerance, the FP64 residual certifies it) and 1e-3 for "
                          "uneven-batch (graph-replayed cycles always run every step, masked)")
-    ap.add_argument("--restart", type=int, default=16)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="GMRES basis length (8, 16 or 32); default: chosen by the solver autotuner on the "
+                         "gradient workloads, 16 elsewhere")
     ap.add_argument("--check-every", type=int, default=1)
-    ap.add_argument("--max-rhs", type=int, default=0,
-                    help="cap on RHS per batched solve (0: all frequencies of the step at once)")
+    ap.add_argument("--max-rhs", type=int, default=None,
+                    help="cap on RHS per batched solve (0: all frequencies of the step at once); default: chosen "
+                         "by the solver autotuner on the gradient workloads, 0 elsewhere")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in FFT tile variants")
@@ -108,6 +121,8 @@ def main():
               "host twice with no cause found, and stays off the GPU until one is shown.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "invert-384":
+        if args.restart is None:
+            args.restart = 16
         return bench_invert(args)
     out = bench_gradient(args, args.workload)
     if args.workload == "gradient-3d" and not args.no_extra and not args.counter_sample:
@@ -119,7 +134,7 @@ def main():
                         ("gradient_64", "gradient-64")):
             torch.cuda.empty_cache()
             a2 = copy.copy(args)
-            a2.max_rhs, a2.no_cpu = 0, True
+            a2.max_rhs, a2.restart, a2.no_cpu = None, None, True
             o2 = bench_gradient(a2, wl)
             out[key] = {
                 "workload": o2["config"]["workload"], "value": o2["value"], "unit": o2["unit"],
@@ -153,15 +168,15 @@ def bench_gradient(args, workload):
          "gradient-384": W.config3, "gradient-64": W.config0}[workload]()
     if "c_obs" not in p.extra:  # the 384^2 phantom: observed model with +1% seeded SoS noise
         p.extra["c_obs"] = W.perturb_sos(p.c, seed=303)
-    max_rhs = args.max_rhs
-    if three_d and max_rhs == 0:
-        max_rhs = p.ne  # one frequency per batched solve: fields recomputed, never all stored
+    # one frequency per batched solve in 3D: fields recomputed, never all stored
+    shape_default = p.ne if three_d else 0
     prob = fwi.ProblemArgs(p)
     ctx = fwi.Context(0)
     c = torch.as_tensor(p.c).to(dev)
     a = torch.as_tensor(p.alpha).to(dev)
     c_obs = torch.as_tensor(p.extra["c_obs"]).to(dev)
-    ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32, max_rhs=max_rhs)
+    ref_opts = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=32,
+                                max_rhs=shape_default if args.max_rhs is None else args.max_rhs)
     # plane-wave transmits: unit-amplitude steering weights [nf, nt, ne]
     w_tx = torch.as_tensor(W.plane_wave_weights(p.freqs, p.elems, np.linspace(-60.0, 60.0, 60), p.c0)).to(dev) \
         if planewave else None
@@ -173,7 +188,28 @@ def bench_gradient(args, workload):
     setup_ms = st0["t_setup_ms"]
     log(f"setup done: spectra and incident fields {setup_ms:.1f} ms, {st0['iterations']} its")
 
-    # autotune the FFT-pass tiles for this grid (untimed set-up)
+    # batch shape (RHS per batched solve) and restart length, chosen by the
+    # library's solver autotuner on the timed step itself (untimed set-up,
+    # built-in FFT tiles); caps that keep more than two frequencies' fields and
+    # Krylov bases resident are not offered in 3D
+    max_rhs, restart, solver_tune = args.max_rhs, args.restart, None
+    tunable = not (planewave or fp64_only or args.counter_sample or args.no_tune or args.tuning)
+    if tunable and (max_rhs is None or restart is None):
+        nrhs = p.nf * p.ne
+        caps = [max_rhs] if max_rhs is not None else \
+            ([p.ne, 2 * p.ne] if three_d else [0, nrhs // 2, nrhs // 4])
+        restarts = [restart] if restart is not None else [8, 16, 32]
+        base = fwi.SolveOptions(precision=fwi.FWI_FP64 if fp64_only else fwi.FWI_FP32_REFINE, rtol=args.rtol,
+                                inner_rtol=args.inner_rtol, check_every=args.check_every)
+        r = ctx.autotune_solver(prob, c, a, d_obs, base, max_rhs=caps, restart=restarts, reps=1)
+        max_rhs, restart = r["max_rhs"], r["restart"]
+        solver_tune = {"chosen": {"max_rhs": max_rhs, "restart": restart},
+                       "ms_per_step": {f"max_rhs={m},restart={k}": round(t, 2) for (m, k), t in r["ms"].items()}}
+        log(f"solver autotune: {solver_tune}")
+    max_rhs = shape_default if max_rhs is None else max_rhs
+    restart = 16 if restart is None else restart
+
+    # autotune the FFT-pass tiles for this grid and batch (untimed set-up)
     tune = {}
     if args.tuning:
         ctx.set_tuning(bytes.fromhex(args.tuning))
@@ -184,9 +220,9 @@ def bench_gradient(args, workload):
         log(f"autotune: {tune}")
     tuned_table = ctx.get_tuning()
 
-    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
+    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=restart,
                              inner_rtol=args.inner_rtol, check_every=args.check_every, max_rhs=max_rhs)
-    plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=args.restart,
+    plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=restart,
                              check_every=args.check_every, max_rhs=max_rhs)
     if fp64_only:
         mixed = plain
@@ -241,7 +277,9 @@ def bench_gradient(args, workload):
     value = solves_per_step / (ms_step * 1e-3)
     log(f"timed: {ms_step:.1f} ms/step, {value:.1f} solves/s; stats {stats}")
     nf_launch = max(1, min(p.nf, max_rhs // p.ne)) if max_rhs else p.nf
-    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not planewave, nf_launch=nf_launch)
+    batch = min(max_rhs, p.nf * p.ne) if max_rhs else p.nf * p.ne
+    roofline = roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=not planewave, nf_launch=nf_launch,
+                              batch=batch, steps=min(stats["iterations"], restart))
     roofline["practical_ceiling"] = stream_ceiling()
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -263,9 +301,10 @@ def bench_gradient(args, workload):
                       "grid": list(p.shape), "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
                       "precision": "complex128 GMRES" if fp64_only else
                                    "complex64 GMRES in FP64-residual refinement",
-                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": args.restart},
+                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": restart},
            "setup_ms": round(setup_ms, 2),
            "roofline": roofline,
+           "solver_autotune": solver_tune,
            "autotune": {"fixed_tiles_ms_per_step": None if fixed_ms is None else round(fixed_ms, 3),
                         "autotuned_ms_per_step": round(ms_step, 3), "steps_each": args.steps, "passes": tune,
                         "tuning_hex": ctx.get_tuning().hex()},
@@ -298,7 +337,7 @@ def bench_gradient(args, workload):
             # reported apart from the metric: with transmit set = receive set the
             # adjoint fields are combinations of the forward fields (no adjoint
             # solves; not counted as solves)
-            recip = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
+            recip = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=restart,
                                      inner_rtol=args.inner_rtol, check_every=args.check_every,
                                      max_rhs=max_rhs, reciprocity_adjoint=1)
             _, g_r, _, _, _ = step(recip)
@@ -463,7 +502,7 @@ def strided_tile(L, es, v):
     return nl, (512 if v == 2 else 256)
 
 
-def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True, nf_launch=None):
+def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True, nf_launch=None, batch=None, steps=None):
     """Roofline of the dominant kernel class over the timed launches.
 
     The 2D convolution pass (forward FFT, spectrum product, inverse FFT along
@@ -496,7 +535,7 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True, nf_launch=N
         rhs = (prof["bytes"] - launches * gbytes) / per_rhs_bytes
         flops = rhs * per_rhs_flops
         tf = flops / sec / 1e12
-        m = MEASURED.get(name, {}) if measured else {}
+        m = measured_at(name, batch, steps) if measured else {}
         entry.update({"bound": "alu", "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
                       "peak_unpacked_fp32": FP32_UNPACKED_PEAK_TFLOPS,
@@ -505,7 +544,7 @@ def roofline_entry(fwi, ctx, prob, p, dominant, prof, measured=True, nf_launch=N
                       "traffic": m.get("traffic"), "valu_busy": m.get("valu_busy"), "hbm": hbm})
     else:
         name = hbm_kernel_name(ctx, prob, dominant) if p.dim == 2 else None
-        m = MEASURED.get(name, {}) if name and measured else {}
+        m = measured_at(name, batch, steps) if name and measured else {}
         entry.update({"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": hbm["frac"], "bytes_per_launch": hbm["bytes_per_launch"], "kernel_name": name,
                       "traffic": m.get("traffic")})
@@ -550,7 +589,7 @@ def bench_uneven(args):
     al = [torch.as_tensor(p.alpha).to(dev) for p in insts]
     obs = [torch.as_tensor(W.perturb_sos(p.c, seed=200 + k)).to(dev) for k, p in enumerate(insts)]
     d_obs, _ = ctx.forward_batch(insts, obs, al, fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=1e-12, restart=16))
-    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart,
+    mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=args.restart or 16,
                              inner_rtol=args.inner_rtol)
     solves = sum(2 * p.nf * p.ne for p in insts)
 
@@ -585,7 +624,7 @@ def bench_uneven(args):
            "config": {"workload": "uneven batch: 32 2D instances, N in {128..512}, 32-128 elements, "
                                   "1-4 frequencies in 0.3-1.5 MHz, forward+adjoint gradients",
                       "instances": len(insts), "solves_per_step": solves, "rtol": args.rtol,
-                      "restart": args.restart, "path": "graph-replayed refinement cycles"},
+                      "restart": args.restart or 16, "path": "graph-replayed refinement cycles"},
            "batch": st,
            "autotune": {"fixed_tiles_ms_per_step": round(fixed_ms, 3), "autotuned_ms_per_step": round(ms, 3),
                         "passes": {str(k): v for k, v in tune.items()}}}

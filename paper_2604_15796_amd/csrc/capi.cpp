@@ -506,6 +506,16 @@ struct SolveBufs {
   c128* U2_64 = nullptr;
 };
 
+// Inner-product partials per RHS: the k_dots blocks, or one per workgroup of
+// the inverse row pass when the products are fused into it (its smallest
+// tile holds 2048 points, max(2048 / Lx, 1) rows; at most kMaxDotParts).
+int dot_parts(const Geo& g, int nblk) {
+  const long rows = (long)g.nz * g.ny;
+  const long nl0 = std::max(2048 / g.Lx, 1);
+  const long fused = std::min<long>(kMaxDotParts, (rows + nl0 - 1) / nl0);
+  return (int)std::max<long>(nblk, fused);
+}
+
 template <typename T>
 void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   KrylovState<T>& k = s.ks;
@@ -521,7 +531,7 @@ void plan_solve(Arena& a, const Geo& g, int B, int JM, SolveBufs<T>& s) {
   k.sn = a.take<c128>((size_t)B * JM);
   k.gv = a.take<c128>((size_t)B * (JM + 1));
   k.y = a.take<c128>((size_t)B * JM);
-  k.dotp = a.take<c128>((size_t)B * std::max(k.nblk, kMaxDotParts) * (JM + 1));
+  k.dotp = a.take<c128>((size_t)B * dot_parts(g, k.nblk) * (JM + 1));
   k.hcoef = a.take<c128>((size_t)B * (JM + 1));
   k.nrmp = a.take<double>((size_t)B * k.nblk);
   k.rnorm = a.take<double>(B);
@@ -2440,6 +2450,73 @@ int fwi_autotune(fwi_ctx* c, const fwi_problem* p, int precision, int B, int rep
       if (strided_sum[0] > 0.0) rep->variant[KC_Y_FWD] = rep->variant[KC_Y_INV] =
           pick_variant(strided_sum, default_variant(PK_STRIDED, dbl, g.Ly));
     }
+    return FWI_OK;
+  });
+}
+
+int fwi_autotune_solver(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* dobs,
+                        const fwi_solve_opts* base, const int* max_rhs, int n_mr, const int* restart, int n_rs,
+                        int reps, fwi_solver_tune_report* rep) {
+  return guarded(c, [&] {
+    if (!p || !cc || !dobs || !base || !max_rhs || !restart || !rep || reps < 1)
+      throw Error(FWI_E_INVAL, "bad solver autotune arguments");
+    if (n_mr < 1 || n_mr > 8 || n_rs < 1 || n_rs > 3)
+      throw Error(FWI_E_INVAL, "1..8 batch caps and 1..3 restart lengths");
+    std::string msg;
+    int rc = validate_opts(base, msg);
+    if (rc) throw Error(rc, msg);
+    for (int i = 0; i < n_mr; ++i)
+      if (max_rhs[i] < 0) throw Error(FWI_E_INVAL, "max_rhs candidates must be >= 0");
+    // the library's own workspace grows to the largest candidate's plan;
+    // a grown one is released at the end so that the tuning leaves no
+    // allocation larger than the caller's own calls make
+    const size_t ws_before = c->ws_int_bytes;
+    struct Release {
+      fwi_ctx* c;
+      size_t before;
+      ~Release() {
+        if (c->ws_int_bytes > before) {
+          (void)hipStreamSynchronize(c->stream);
+          (void)hipFree(c->ws_int);
+          c->ws_int = nullptr;
+          c->ws_int_bytes = 0;
+        }
+      }
+    } release{c, ws_before};
+    fwi_solver_tune_report r{};
+    double best = std::numeric_limits<double>::infinity();
+    for (int i = 0; i < n_mr; ++i) {
+      for (int j = 0; j < n_rs; ++j) {
+        fwi_solve_opts o = *base;
+        o.max_rhs = max_rhs[i];
+        o.restart = restart[j];
+        rc = validate_opts(&o, msg);
+        if (rc) throw Error(rc, msg);
+        double t = std::numeric_limits<double>::infinity();
+        bool converged = true;
+        for (int k = 0; k <= reps; ++k) {  // the first call is untimed
+          const double t0 = now_ms();
+          rc = o.precision == FWI_FP32_REFINE
+                   ? gradient_impl<float>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
+                                          nullptr, nullptr)
+                   : gradient_impl<double>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
+                                           nullptr, nullptr);
+          const double dt = now_ms() - t0;  // the call returns after synchronising its stream
+          if (rc != FWI_OK && rc != FWI_E_NOCONV) return rc;
+          converged = converged && rc == FWI_OK;
+          if (k > 0) t = std::min(t, dt);
+        }
+        r.ms[i][j] = t;
+        if (converged && t < best) {
+          best = t;
+          r.max_rhs = o.max_rhs;
+          r.restart = o.restart;
+        }
+      }
+    }
+    if (!(best < std::numeric_limits<double>::infinity()))
+      throw Error(FWI_E_NOCONV, "no candidate pair converged");
+    *rep = r;
     return FWI_OK;
   });
 }

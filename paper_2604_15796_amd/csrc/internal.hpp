@@ -126,7 +126,7 @@ enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3, EPI_V
 // i < nvec, one part per workgroup of the inverse row pass. Done only when
 // every workgroup's rows belong to one RHS and there are at most kMaxDotParts
 // parts per RHS; launch_vie reports whether it did them (and `nparts`).
-constexpr int kMaxDotParts = 256;
+constexpr int kMaxDotParts = 2048;
 struct VieDots {
   const void* basis = nullptr;   // V_0 [B][n] (cplx<T>), vector i at basis + i*vs
   long vs = 0;

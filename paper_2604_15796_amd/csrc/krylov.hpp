@@ -20,7 +20,7 @@ struct KrylovState {
   c128* sn = nullptr;          // [B][JM]
   c128* gv = nullptr;          // [B][JM+1]
   c128* y = nullptr;           // [B][JM] correction x += sum_i y_i V_i (stored V_i; |r| and scales folded in)
-  c128* dotp = nullptr;        // [B][parts][JM+1], parts <= max(nblk, kMaxDotParts)
+  c128* dotp = nullptr;        // [B][parts][JM+1]: nblk parts (k_dots) or one per inverse-row-pass workgroup
   c128* hcoef = nullptr;       // [B][JM+1] Gram-Schmidt coefficients of the current step
   double* nrmp = nullptr;      // [B][nblk]
   double* rnorm = nullptr;     // [B] residual norm at cycle start

@@ -130,6 +130,8 @@ def lib():
                                             C.POINTER(vp), C.POINTER(CBatchStats)]),
         "fwi_forward_batch": (ip, [vp, ip, pp, C.POINTER(vp), C.POINTER(vp), op, C.POINTER(vp),
                                    C.POINTER(CBatchStats)]),
+        "fwi_autotune_solver": (ip, [vp, pp, vp, vp, vp, op, C.POINTER(C.c_int), ip, C.POINTER(C.c_int), ip, ip,
+                                     C.POINTER(CSolverTuneReport)]),
         "fwi_get_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
         "fwi_set_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
     }
@@ -149,7 +151,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
             "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx", "fwi_invert",
-            "fwi_sos_from_contrast", "fwi_host_gauss_legendre"]
+            "fwi_sos_from_contrast", "fwi_host_gauss_legendre", "fwi_autotune_solver"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -169,6 +171,10 @@ class CBatchStats(C.Structure):
 
 class CTuneReport(C.Structure):
     _fields_ = [("variant_ms", (C.c_double * 3) * 5), ("variant", C.c_int * 5), ("default_variant", C.c_int * 5)]
+
+
+class CSolverTuneReport(C.Structure):
+    _fields_ = [("max_rhs", C.c_int), ("restart", C.c_int), ("ms", (C.c_double * 3) * 8)]
 
 
 # ---------------------------------------------------------------- structs ---
@@ -564,6 +570,24 @@ class Context:
             if any(ms):
                 out[name] = {"ms": ms, "chosen": rep.variant[k], "default": rep.default_variant[k]}
         return out
+
+    def autotune_solver(self, prob, c, alpha, d_obs, opts=None, max_rhs=(0,), restart=(8,), reps=1):
+        """Time the gradient step for every (max_rhs, restart) pair and return
+        {"max_rhs", "restart" (the fastest pair), "ms": {(max_rhs, restart): ms}}.
+        Uses the library's own workspace; the context's tuning is unchanged."""
+        prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
+        o = (opts or SolveOptions()).c()
+        _check_dtype(c, torch.float64, prob.shape, "c")
+        _check_dtype(d_obs, torch.complex128, (prob.nf, prob.ne, prob.ne), "d_obs")
+        mr = (C.c_int * len(max_rhs))(*[int(v) for v in max_rhs])
+        rs = (C.c_int * len(restart))(*[int(v) for v in restart])
+        rep = CSolverTuneReport()
+        self._stream()
+        self._internal_workspace()
+        self._check(self.L.fwi_autotune_solver(self.h, prob.ref(), _ptr(c), _ptr(alpha), _ptr(d_obs), C.byref(o),
+                                               mr, len(max_rhs), rs, len(restart), reps, C.byref(rep)))
+        ms = {(int(a), int(b)): rep.ms[i][j] for i, a in enumerate(max_rhs) for j, b in enumerate(restart)}
+        return {"max_rhs": rep.max_rhs, "restart": rep.restart, "ms": ms}
 
     def set_addressing(self, wide):
         """wide=True forces the 64-bit addressing path of the strided FFT passes

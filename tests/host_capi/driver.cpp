@@ -252,6 +252,23 @@ void every_entry(fwi_ctx* ctx, int dim) {
     check(fwi_fft_padded(ctx, &q.p, prec, x, spec), "fft_padded", ctx);
     fwi_tune_report rep{};
     check(fwi_autotune(ctx, &q.p, prec, 5, 1, &rep), "autotune", ctx);
+    {
+      // batch caps of whole frequencies, one frequency and the whole problem; two restart lengths
+      const int mr[3] = {0, ne, 2 * ne};
+      const int rs[2] = {8, 16};
+      fwi_solver_tune_report srep{};
+      fwi_solve_opts ot = opts(prec, 8);
+      check(fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, mr, 3, rs, 2, 1, &srep), "autotune_solver", ctx);
+      if (srep.restart != 8 && srep.restart != 16) {
+        std::fprintf(stderr, "[driver] autotune_solver chose restart %d\n", srep.restart);
+        g_fail = 1;
+      }
+      const int bad[1] = {-1};
+      if (fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, bad, 1, rs, 2, 1, &srep) != FWI_E_INVAL) {
+        std::fprintf(stderr, "[driver] negative batch cap not refused\n");
+        g_fail = 1;
+      }
+    }
     double* co = dev<double>(n);
     check(fwi_sos_from_contrast(ctx, &q.p, gm, co, co), "sos_from_contrast", ctx);
     std::free(co);

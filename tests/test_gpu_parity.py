@@ -283,6 +283,33 @@ def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
     assert st["solves"] == (1 if recip else 2) * p.nf * p.ne
 
 
+def test_solver_autotune_picks_a_candidate_and_keeps_parity(ctx, F):
+    """Batch-shape / restart tuning of the gradient step: the chosen pair is one
+    of the candidates with the smallest time, the context's own results are not
+    changed by tuning, and the gradient with the chosen options still matches
+    the oracle."""
+    p = W.small2d(seed=29, nx=30, nz=26, ne=6, nf=3)
+    d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    c, a, d = dev(p.c, torch.float64), dev(p.alpha, torch.float64), dev(d_obs)
+    base = F.SolveOptions(precision=0, rtol=1e-12)
+    before = ctx.adjoint_gradient(p, c, a, d, base)[1].clone()
+    caps, restarts = (0, p.ne, 2 * p.ne), (8, 16)
+    r = ctx.autotune_solver(p, c, a, d, base, max_rhs=caps, restart=restarts, reps=1)
+    assert set(r["ms"]) == {(m, k) for m in caps for k in restarts}
+    assert all(math.isfinite(t) and t > 0 for t in r["ms"].values())
+    assert r["ms"][(r["max_rhs"], r["restart"])] == min(r["ms"].values())
+    after = ctx.adjoint_gradient(p, c, a, d, base)[1]
+    assert torch.equal(before, after)
+    tuned = F.SolveOptions(precision=0, rtol=1e-12, max_rhs=r["max_rhs"], restart=r["restart"])
+    phi, gm, gc, ga, st = ctx.adjoint_gradient(p, c, a, d, tuned)
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    assert abs(phi - rphi) < 1e-10 * rphi
+    assert relerr(host(gm), rg) < 1e-9
+    assert relerr(host(gc), rgc) < 1e-9
+    with pytest.raises(RuntimeError):
+        ctx.autotune_solver(p, c, a, d, base, max_rhs=caps, restart=(12,))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("case", ["homogeneous", "single_rhs"])
 def test_degenerate_problems_vs_oracle(ctx, F, prec, case):
