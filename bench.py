@@ -47,9 +47,11 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # launch and `steps` Arnoldi steps per complex64 cycle (a restart length at or
 # above that gives the same launches). It is reported only when the timed run
 # launches the same.
-MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.9e6, "batch": 512, "steps": 8},
-            "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1691.7e6, "batch": 512, "steps": 8},
-            "k_strided<float, 192, 16, 256, 2, true, false>": {"traffic": 5473.9e6, "valu_busy": 0.779,
+MEASURED = {"k_row_inv<float, 512, 4, 4>": {"traffic": 1761.8e6, "batch": 512, "steps": 8},
+            "k_row_fwd<float, 512, 4, true, 3>": {"traffic": 1793.2e6, "batch": 512, "steps": 8},
+            "k_strided<float, 512, 16, 512, 2, true, false>": {"traffic": 897.9e6, "valu_busy": 0.761,
+                                                               "batch": 512, "steps": 8},
+            "k_strided<float, 192, 16, 256, 2, true, false>": {"traffic": 5473.9e6, "valu_busy": 0.788,
                                                                "batch": 64, "steps": 7}}
 
 
@@ -82,8 +84,10 @@ def parse():
                     help="oracle forward (and adjoint) solves per frequency in the CPU sample")
     ap.add_argument("--no-extra", action="store_true",
                     help="gradient-3d: skip the 256^2 workload reported beside it")
-    ap.add_argument("--cpu-sample", type=int, default=2,
-                    help="gradient-3d: transmits of the first frequency whose fields the oracle solves")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="transmits (spread over the array) whose fields the oracle solves at the sampled "
+                         "frequencies; default 2 at the first frequency (3D), 8 at all 8 frequencies (256^2), 8 at "
+                         "the lowest and the highest (384^2)")
     ap.add_argument("--workload", default="gradient-3d",
                     choices=["gradient-3d", "gradient-256", "planewave-256", "gradient-384", "gradient-64",
                              "uneven-batch", "invert-384"],
@@ -134,13 +138,13 @@ def main():
                         ("gradient_64", "gradient-64")):
             torch.cuda.empty_cache()
             a2 = copy.copy(args)
-            a2.max_rhs, a2.restart, a2.no_cpu = None, None, True
+            a2.max_rhs, a2.restart, a2.cpu_sample = None, None, None
             o2 = bench_gradient(a2, wl)
             out[key] = {
                 "workload": o2["config"]["workload"], "value": o2["value"], "unit": o2["unit"],
                 "ms_per_step": o2["ms_per_step"], "steps": o2["steps"], "precision": o2["config"]["precision"],
                 "roofline": o2["roofline"], "accuracy": o2.get("accuracy"), "fp64_plain": o2.get("fp64_plain"),
-                "speedup_vs_fp64_plain": o2.get("speedup_vs_fp64_plain"), "oracle": o2.get("oracle"),
+                "speedup_vs_fp64_plain": o2.get("speedup_vs_fp64_plain"), "cpu_baseline": o2.get("cpu_baseline"),
                 "autotune_ms": {k: o2["autotune"][k] for k in ("fixed_tiles_ms_per_step", "autotuned_ms_per_step")}}
     if out is not None:
         print(json.dumps(out), flush=True)
@@ -351,114 +355,159 @@ def bench_gradient(args, workload):
         del g32, g64
         torch.cuda.empty_cache()
 
-    if fp64_only:
-        # the whole gradient of the 64^2 configuration against the oracle at the timed options
-        from oracle import fwi_oracle as O
-        phi, g_gpu, _, _, _ = step(mixed)
-        args2 = (2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
-        od_obs = O.forward(p.extra["c_obs"], p.alpha, *args2)[0]
-        ophi, og, _, _, _ = O.adjoint_gradient(p.c, p.alpha, od_obs, *args2)
-        g_gpu = g_gpu.cpu().numpy()
-        out["oracle"] = {"grad_rel_err": float(np.linalg.norm(g_gpu - og) / np.linalg.norm(og)),
-                         "grad_max_abs_err_over_max": float(np.abs(g_gpu - og).max() / np.abs(og).max()),
-                         "misfit_rel_err": abs(phi - ophi) / ophi,
-                         "note": "full gradient and misfit; each side computes its own observed data"}
     if not args.no_cpu:
-        if three_d:
-            out["cpu_baseline"] = oracle_leg_3d(p, ctx, prob, c, a, d_obs, mixed, args.cpu_sample)
-        else:
+        if fp64_only:
+            out["cpu_baseline"] = oracle_full_step(p, step, mixed)
+        elif planewave:
             out["cpu_baseline"] = cpu_baseline(p, ctx, prob, c, a, args.cpu_solves)
-            if planewave:
-                out["cpu_baseline"]["sample"] += " (element sources: same operators and per-solve cost)"
+            out["cpu_baseline"]["sample"] += " (element sources: same operators and per-solve cost)"
+        else:
+            S, L = sample_of(p, workload, args.cpu_sample)
+            out["cpu_baseline"] = oracle_leg(p, ctx, prob, c, a, d_obs, mixed, S, L)
     ctx.close()
     return out
 
 
-def oracle_leg_3d(p, ctx, prob, c, a, d_obs, opts, nsample):
-    """The FP64 oracle on a bounded sample of the 3D workload, timed on the
-    host, and the timed options checked against it.
+def spread(count, n):
+    """`count` indices spread over 0 .. n-1, first and last included."""
+    count = max(1, min(count, n))
+    return sorted({int(round(q * (n - 1) / max(count - 1, 1))) for q in range(count)})
 
-    Sample (first frequency): the forward fields of transmits S (the first
-    and the last element when nsample = 2), the observed field of the first
-    transmit and its adjoint field for the residual restricted to the
-    receivers R = S. Timed on all host threads (scipy.fft workers = all); one
-    forward solve again on one worker. Checks, with exactly the timed options:
-    the GPU fields of S against the oracle's (max relative error per field),
-    and the gradient of the partial misfit 1/2 sum over (first transmit, R) of
-    |r|^2, which the GPU computes through fwi_adjoint_gradient with observed
-    data equal to its own data outside those entries (so the residual is
-    exactly zero there), against the oracle's."""
+
+# the oracle's bounded sample per workload: (transmits, frequencies), each
+# spread over the array / the band
+ORACLE_SAMPLE = {"gradient-3d": (2, 1), "gradient-256": (8, 8), "gradient-384": (8, 2)}
+
+
+def sample_of(p, workload, ntx=None):
+    """Transmits S and frequencies L of the oracle's sample of the workload."""
+    dtx, dnf = ORACLE_SAMPLE[workload]
+    return spread(ntx or dtx, p.ne), spread(dnf, p.nf)
+
+
+def oracle_leg(p, ctx, prob, c, a, d_obs, opts, S, L):
+    """The FP64 oracle on a bounded sample of the workload, timed on the host,
+    and the timed options checked against it.
+
+    Sample: the forward fields of transmits S at frequencies L, then at the
+    first frequency l0 of L the observed field of the first transmit i0 and
+    its adjoint field for the residual restricted to the receivers R = S.
+    Timed on all host threads (scipy.fft workers = all); one forward solve
+    again on one worker. Checks, with exactly the timed options: the GPU
+    fields of S at L against the oracle's (max relative error per field), and
+    the gradient of the partial misfit 1/2 sum over (l0, i0, R) of |r|^2,
+    which the GPU computes through fwi_adjoint_gradient with observed data
+    equal to its own data outside those entries (so the residual is exactly
+    zero there), against the oracle's."""
     import torch
 
     from oracle import fwi_oracle as O
-    l = 0
-    S = [0, p.ne - 1] if nsample >= 2 else [0]
-    S = S[:max(1, nsample)]
+    dim = p.dim
+    ny = p.ny if dim == 3 else 1
+    args_o = (dim, p.nx, ny, p.nz, p.dx)
     R = list(S)
-    i0 = S[0]
+    i0, l0 = S[0], L[0]
     m = O.contrast(p.c, p.alpha, p.c0)
     m_obs = O.contrast(p.extra["c_obs"], p.alpha, p.c0)
-    cen = O.cell_centres(3, p.nx, p.ny, p.nz, p.dx)
-    k = O.wavenumber(p.freqs[l], p.c0)
-    dV = O.cell_volume(3, p.dx)
-    P0 = O.incident_fields(k, cen, p.elems[S], 3)       # rows in the order of S (= R)
-    args3 = (3, p.nx, p.ny, p.nz, p.dx)
+    cen = O.cell_centres(*args_o)
+    dV = O.cell_volume(dim, p.dx)
+    ks = {l: O.wavenumber(p.freqs[l], p.c0) for l in L}
+    P0 = {l: O.incident_fields(ks[l], cen, p.elems[S], dim) for l in L}   # rows in the order of S (= R)
     workers = O.FFT_WORKERS
     c0 = os.times()
     t0 = time.perf_counter()
-    fld = O.solve(k, m, P0, *args3)                      # forward fields of S
-    fobs = O.solve(k, m_obs, P0[:1], *args3)[0]          # observed field of transmit i0
-    mf = m.reshape(-1)
-    data_r = k**2 * dV * (P0 @ (mf * fld[0]))            # P^s[i0, R]
-    dobs_r = k**2 * dV * (P0 @ (m_obs.reshape(-1) * fobs))
+    fld = {l: O.solve(ks[l], m, P0[l], *args_o) for l in L}              # forward fields of S at L
+    k = ks[l0]
+    fobs = O.solve(k, m_obs, P0[l0][:1], *args_o)[0]                   # observed field of transmit i0
+    data_r = k**2 * dV * (P0[l0] @ (m.reshape(-1) * fld[l0][0]))       # P^s[l0, i0, R]
+    dobs_r = k**2 * dV * (P0[l0] @ (m_obs.reshape(-1) * fobs))
     r = data_r - dobs_r
-    lam = O.solve(k, m, (np.conj(r) @ P0)[None], *args3)[0]
-    g_or = dV * np.conj(k**2) * np.conj(fld[0] * lam)
+    lam = O.solve(k, m, (np.conj(r) @ P0[l0])[None], *args_o)[0]
+    g_or = dV * np.conj(k**2) * np.conj(fld[l0][0] * lam)
     dt = time.perf_counter() - t0
     c1 = os.times()
     cpu = (c1.user - c0.user) + (c1.system - c0.system)
-    nsolve = len(S) + 2
+    nsolve = len(S) * len(L) + 2
     O.FFT_WORKERS = 1
     c2 = os.times()
     t1 = time.perf_counter()
-    O.solve(k, m, P0[:1], *args3)
+    O.solve(k, m, P0[l0][:1], *args_o)
     dt1 = time.perf_counter() - t1
     c3 = os.times()
     O.FFT_WORKERS = workers
     cpu1 = (c3.user - c2.user) + (c3.system - c2.system)
     # the GPU at the timed options
     data, fields, _ = ctx.forward(prob, c, a, opts, fields=True)
-    ferr = max(float(np.linalg.norm(fields[l, i].cpu().numpy() - fld[q]) / np.linalg.norm(fld[q]))
-               for q, i in enumerate(S))
+    ferr = max(float(np.linalg.norm(fields[l, i].cpu().numpy() - fld[l][q]) / np.linalg.norm(fld[l][q]))
+               for l in L for q, i in enumerate(S))
     del fields
     torch.cuda.empty_cache()
     d_part = data.clone()
     for j in R:
-        d_part[l, i0, j] = d_obs[l, i0, j]
+        d_part[l0, i0, j] = d_obs[l0, i0, j]
     phi, g_gpu, _, _, _ = ctx.adjoint_gradient(prob, c, a, d_part, opts)
     g_gpu = g_gpu.cpu().numpy()
     phi_or = 0.5 * float(np.sum(np.abs(r) ** 2))
     gerr = float(np.linalg.norm(g_gpu - g_or) / np.linalg.norm(g_or))
     gerr_el = float(np.abs(g_gpu - g_or).max() / np.abs(g_or).max())
     rate = nsolve / dt
-    log(f"cpu oracle: {nsolve} 3D solves in {dt:.1f} s ({cpu / dt:.1f} cores busy of {len(os.sched_getaffinity(0))}), "
-        f"one solve on one worker {dt1:.1f} s; GPU vs oracle: field {ferr:.2e}, partial gradient {gerr:.2e}, "
-        f"misfit {phi:.6e} vs {phi_or:.6e}")
+    grid = f"{p.nx}x{p.ny}x{p.nz}" if dim == 3 else f"{p.nx}x{p.nz}"
+    log(f"cpu oracle ({grid}): {nsolve} solves in {dt:.1f} s ({cpu / dt:.1f} cores busy of "
+        f"{len(os.sched_getaffinity(0))}), one solve on one worker {dt1:.1f} s; GPU vs oracle: field {ferr:.2e}, "
+        f"partial gradient {gerr:.2e}, misfit {phi:.6e} vs {phi_or:.6e}")
     return {"value": round(rate, 4), "unit": "solves/s", "cores": max(1, round(cpu / dt)), "kind": "oracle",
-            "sample": f"first frequency: forward solves of transmits {S}, the observed field of transmit {i0} and "
-                      f"its adjoint solve ({nsolve} of the {2 * p.nf * p.ne} solves of a step; scipy GMRES rtol "
-                      f"1e-12 on the 2N-padded FFT convolution), {dt:.1f} s on all host threads; the step rate "
-                      f"is extrapolated per solve",
+            "sample": f"{grid}: forward solves of transmits {S} at frequencies {L}, the observed field of "
+                      f"transmit {i0} and its adjoint solve at frequency {l0} ({nsolve} of the "
+                      f"{2 * p.nf * p.ne} solves of a step; scipy GMRES rtol 1e-12 on the 2N-padded FFT "
+                      f"convolution), {dt:.1f} s on all host threads; the step rate is extrapolated per solve",
             "extrapolated": True, "cpu_time_s": round(cpu, 2), "threads_available": len(os.sched_getaffinity(0)),
             "workers1": {"value": round(1.0 / dt1, 4), "cores": max(1, round(cpu1 / dt1)), "sample":
                          f"one forward solve with scipy.fft on one worker, {dt1:.1f} s"},
-            "gpu_vs_oracle": {"field_rel_err_max": ferr, "fields": [[l, i] for i in S],
+            "gpu_vs_oracle": {"field_rel_err_max": ferr, "fields": [[l, i] for l in L for i in S],
                               "partial_grad_rel_err": gerr, "partial_grad_max_abs_err_over_max": gerr_el,
                               "partial_misfit": phi, "partial_misfit_oracle": phi_or,
-                              "partial": f"1/2 sum |r|^2 over transmit {i0}, receivers {R}, frequency {l}",
-                              "options": "the timed options (complex64 GMRES in FP64-residual refinement, "
+                              "partial": f"1/2 sum |r|^2 over transmit {i0}, receivers {R}, frequency {l0}",
+                              "options": f"the timed options ({'complex128 GMRES' if opts.precision == 0 else 'complex64 GMRES in FP64-residual refinement'}, "
                                          f"rtol {opts.rtol}, inner_rtol {opts.inner_rtol}, restart "
                                          f"{opts.restart}, max_rhs {opts.max_rhs})"}}
+
+
+def oracle_full_step(p, step, opts):
+    """The whole gradient step of a small workload on the oracle, timed on the
+    host (all threads, then one FFT worker), and the GPU's gradient and misfit
+    at the timed options against it. Each side computes its own observed
+    data (the oracle's forward of the observed model is not timed)."""
+    from oracle import fwi_oracle as O
+    args2 = (p.dim, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    od_obs = O.forward(p.extra["c_obs"], p.alpha, *args2)[0]
+    workers = O.FFT_WORKERS
+    times = {}
+    for w in (workers, 1):
+        O.FFT_WORKERS = w
+        c0 = os.times()
+        t0 = time.perf_counter()
+        ophi, og, _, _, _ = O.adjoint_gradient(p.c, p.alpha, od_obs, *args2)
+        dt = time.perf_counter() - t0
+        c1 = os.times()
+        times[w] = (dt, (c1.user - c0.user) + (c1.system - c0.system))
+    O.FFT_WORKERS = workers
+    phi, g_gpu, _, _, _ = step(opts)
+    g_gpu = g_gpu.cpu().numpy()
+    nsolve = 2 * p.nf * p.ne
+    dt, cpu = times[workers]
+    dt1, cpu1 = times[1]
+    log(f"cpu oracle ({p.nx}x{p.nz}): whole step ({nsolve} solves) in {dt:.2f} s, {dt1:.2f} s on one worker")
+    return {"value": round(nsolve / dt, 4), "unit": "solves/s", "cores": max(1, round(cpu / dt)), "kind": "oracle",
+            "sample": f"the whole gradient step ({p.nx}x{p.nz}, {nsolve} solves: forward, adjoint, sampling and "
+                      f"gradient; scipy GMRES rtol 1e-12), {dt:.2f} s on all host threads",
+            "extrapolated": False, "cpu_time_s": round(cpu, 2), "threads_available": len(os.sched_getaffinity(0)),
+            "workers1": {"value": round(nsolve / dt1, 4), "cores": max(1, round(cpu1 / dt1)),
+                         "sample": f"the same step with scipy.fft on one worker, {dt1:.2f} s"},
+            "gpu_vs_oracle": {"grad_rel_err": float(np.linalg.norm(g_gpu - og) / np.linalg.norm(og)),
+                              "grad_max_abs_err_over_max": float(np.abs(g_gpu - og).max() / np.abs(og).max()),
+                              "misfit_rel_err": abs(phi - ophi) / ophi,
+                              "note": "full gradient and misfit at the timed options; each side computes its "
+                                      "own observed data"}}
 
 
 def stream_ceiling(gib=2.0, reps=5):

@@ -110,15 +110,27 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const c128* __restrict__ A, lon
     }
 }
 
-__global__ void k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, int ni, int nj,
-                                const c128* __restrict__ coef, c128* __restrict__ C) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the split-K partials part[nks][tot] in a fixed order: a workgroup
+// takes 64 consecutive outputs, wave w sums the splits w, w + 16, ... (one
+// coalesced row of 64 per split), then the 16 wave sums are added in wave
+// order.
+__global__ void __launch_bounds__(1024) k_gemm_nt_final(const c128* __restrict__ part, int nks, int nf, int ni,
+                                                        int nj, const c128* __restrict__ coef, c128* __restrict__ C) {
+  __shared__ c128 red[16][64];
   const long tot = (long)nf * ni * nj;
-  if (idx >= tot) return;
-  const int l = (int)(idx / ((long)ni * nj));
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const long idx = (long)blockIdx.x * 64 + lane;
   c128 s = mk(0.0, 0.0);
-  for (int k = 0; k < nks; ++k) s = s + part[(long)k * tot + idx];
-  C[idx] = coef[l] * s;
+  if (idx < tot)
+    for (int k = w; k < nks; k += 16) s = s + part[(long)k * tot + idx];
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && idx < tot) {
+    c128 t = red[0][lane];
+#pragma unroll
+    for (int q = 1; q < 16; ++q) t = t + red[q][lane];
+    C[idx] = coef[(int)(idx / ((long)ni * nj))] * t;
+  }
 }
 
 // ------------------------------------------------------------- gemm (NN) ---
@@ -455,7 +467,7 @@ void launch_gemm_nt(int nf, const c128* A, long a_ls, int ni, const c128* w, con
                      nf);
   FWI_LAUNCH_CHECK();
   const long tot = (long)nf * ni * nj;
-  hipLaunchKernelGGL(k_gemm_nt_final, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, part, nks, nf, ni, nj,
+  hipLaunchKernelGGL(k_gemm_nt_final, dim3((unsigned)((tot + 63) / 64)), dim3(1024), 0, st, part, nks, nf, ni, nj,
                      coef, C);
   FWI_LAUNCH_CHECK();
 }

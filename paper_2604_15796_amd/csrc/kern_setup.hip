@@ -1,6 +1,7 @@
 // Set-up kernels: contrast (Eq. 1-3), the circulant Green table of the
 // discrete volume integral operator (Eq. 5, Sec. IV-A) and the incident fields
 // of point elements (Sec. II). All evaluated in FP64.
+#include <algorithm>
 #include <complex>
 
 #include "bessel.hpp"
@@ -313,12 +314,21 @@ extern "C" int fwi_host_gauss_legendre(int q, double* x, double* w) {
 
 namespace fwi {
 
-// Input checks (single block): out[0] = #(c <= 0 or non-finite), out[1] = #(alpha < 0 or non-finite)
-__global__ void __launch_bounds__(1024) k_check_sos(long n, const double* __restrict__ c,
-                                                    const double* __restrict__ alpha, int* __restrict__ out) {
-  __shared__ double red[16];
+// Input checks: out[0] = #(c <= 0 or non-finite), out[1] = #(alpha < 0 or
+// non-finite) (k_check_sos), out[0] = #non-finite complex entries
+// (k_check_complex). Counts are summed per workgroup and added to out[] with
+// integer atomics (exact in any order); k_check_clear zeroes out[] in the same
+// stream first. Grid-stride loops over up to 2048 workgroups.
+__global__ void k_check_clear(int* __restrict__ out) {
+  if (threadIdx.x < 2) out[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_check_sos(long n, const double* __restrict__ c,
+                                                   const double* __restrict__ alpha, int* __restrict__ out) {
+  __shared__ double red[4];
   double bc = 0.0, ba = 0.0;
-  for (long i = threadIdx.x; i < n; i += 1024) {
+  const long stride = (long)gridDim.x * 256;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const double v = c[i];
     if (!(v > 0.0) || !isfinite(v)) bc += 1.0;
     if (alpha) {
@@ -326,32 +336,38 @@ __global__ void __launch_bounds__(1024) k_check_sos(long n, const double* __rest
       if (!(a >= 0.0) || !isfinite(a)) ba += 1.0;
     }
   }
-  const double sc = block_sum<1024>(bc, red);
-  const double sa = block_sum<1024>(ba, red);
+  const double sc = block_sum<256>(bc, red);
+  const double sa = block_sum<256>(ba, red);
   if (threadIdx.x == 0) {
-    out[0] = (int)sc;
-    out[1] = (int)sa;
+    if (sc > 0.0) atomicAdd(out, (int)sc);
+    if (sa > 0.0) atomicAdd(out + 1, (int)sa);
   }
 }
 
-// out[0] = #non-finite complex entries
-__global__ void __launch_bounds__(1024) k_check_complex(long n, const c128* __restrict__ x, int* __restrict__ out) {
-  __shared__ double red[16];
+__global__ void __launch_bounds__(256) k_check_complex(long n, const c128* __restrict__ x, int* __restrict__ out) {
+  __shared__ double red[4];
   double b = 0.0;
-  for (long i = threadIdx.x; i < n; i += 1024) {
+  const long stride = (long)gridDim.x * 256;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const c128 v = x[i];
     if (!isfinite(v.x) || !isfinite(v.y)) b += 1.0;
   }
-  const double s = block_sum<1024>(b, red);
-  if (threadIdx.x == 0) out[0] = (int)s;
+  const double s = block_sum<256>(b, red);
+  if (threadIdx.x == 0 && s > 0.0) atomicAdd(out, (int)s);
 }
 
+static unsigned check_blocks(long n) { return (unsigned)std::max<long>(1, std::min<long>((n + 255) / 256, 2048)); }
+
 void launch_check_sos(long n, const double* c, const double* alpha, int* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_sos, dim3(1), dim3(1024), 0, st, n, c, alpha, out);
+  hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, st, out);
+  FWI_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_check_sos, dim3(check_blocks(n)), dim3(256), 0, st, n, c, alpha, out);
   FWI_LAUNCH_CHECK();
 }
 void launch_check_complex(long n, const c128* x, int* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_complex, dim3(1), dim3(1024), 0, st, n, x, out);
+  hipLaunchKernelGGL(k_check_clear, dim3(1), dim3(64), 0, st, out);
+  FWI_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_check_complex, dim3(check_blocks(n)), dim3(256), 0, st, n, x, out);
   FWI_LAUNCH_CHECK();
 }
 
