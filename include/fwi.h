@@ -158,6 +158,19 @@ int fwi_set_stream(fwi_ctx* ctx, void* hip_stream);
  * 64-bit path for every later call (a testing aid for that path; results are
  * the same), 0 restores the automatic choice. FWI_E_INVAL for other values. */
 int fwi_set_addressing(fwi_ctx* ctx, int wide);
+/* 3D complex64 operator (Sec. IV-A, the convolution of Eq. 5 by FFT): with
+ * on = 1, on grids whose padded lateral and elevation lengths allow it
+ * (Lx/4, Ly/2 in {(64, 128), (32, 64)}), one kernel per z-plane does the
+ * lateral and elevation transforms together, in four lateral by two elevation
+ * frequency classes, so the intermediate between them never goes to memory;
+ * the padded spectrum and the cached complex64 kernel spectrum are then
+ * stored class-major (same values, permuted). on = 0 (the default) keeps the
+ * separate lateral and elevation passes, which are faster on MI355X (the
+ * fused kernel holds a plane per workgroup and runs one workgroup per compute
+ * unit). Results agree to complex64 rounding. The problem cache is keyed on
+ * the setting, so a change rebuilds the spectra at the next call.
+ * FWI_E_INVAL for other values. */
+int fwi_set_plane_fusion(fwi_ctx* ctx, int on);
 void fwi_default_opts(fwi_solve_opts* opts);
 
 /* Host-only argument check; returns FWI_OK or FWI_E_INVAL / FWI_E_UNSUPPORTED.

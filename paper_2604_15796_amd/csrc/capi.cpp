@@ -36,6 +36,7 @@ thread_local int tl_nfreq = 0;
 thread_local const FftTuning* tl_tune = nullptr;
 thread_local int tl_force_variant = -1;
 thread_local int tl_force_wide = 0;
+thread_local int tl_xy_off = 0;
 
 int default_variant(int pass, bool dbl, int L) {
   (void)L;
@@ -242,6 +243,7 @@ static __device__ __align__(256) char scratch[kStaticScratchBytes];
 struct fwi_ctx {
   int device = 0;
   int force_wide = 0;          // fwi_set_addressing
+  int xy_off = 1;              // fused lateral-elevation passes off unless fwi_set_plane_fusion(ctx, 1)
   hipStream_t stream = nullptr;
   std::string err;
   Twiddles tw;
@@ -346,6 +348,7 @@ Geo make_geo(const fwi_problem* p) {
   g.dx = p->dx;
   g.c0 = p->c0;
   g.alpha0 = p->alpha0;
+  g.xy = xy_applies(g);
   return g;
 }
 
@@ -376,6 +379,9 @@ std::string problem_key(const fwi_problem* p) {
   put(&ah, sizeof(double));
   put(&q, sizeof(int));
   put(&p->alpha0, sizeof(double));
+  // the layout of the cached complex64 kernel spectrum
+  const int xy = tl_xy_off;
+  put(&xy, sizeof(int));
   return k;
 }
 
@@ -448,7 +454,8 @@ double build_cache(fwi_ctx* c, const fwi_problem* p, ProblemCache& pc, const std
     for (int e = 0; e < pc.ne; ++e) hrf[(size_t)l * pc.ne + e] = l;
     launch_green_table(g, k, table, st);
     launch_fft_full(g, c->tw, table, work, pc.ghat64 + (long)l * np, st);
-    launch_cast_64_32(np, pc.ghat64 + (long)l * np, pc.ghat32 + (long)l * np, st);
+    if (g.xy) launch_cast_xy_64_32(g, pc.ghat64 + (long)l * np, pc.ghat32 + (long)l * np, st);
+    else launch_cast_64_32(np, pc.ghat64 + (long)l * np, pc.ghat32 + (long)l * np, st);
     launch_incident(g, k, pc.ne, pc.elems, ap, pc.P0 + (long)l * pc.ne * n, st);
   }
   FWI_HIP(hipMemcpyAsync(pc.k2, hk2.data(), sizeof(c128) * pc.nf, hipMemcpyHostToDevice, st));
@@ -625,7 +632,7 @@ struct ArnoldiDriver {
   int B;
   // first pass of step 0 on V_0 (scaled by vscale_0 in the last pass)
   void first_rows() {
-    launch_vie_rows<T>(g, tw, B, ks.V, ks.active, mT, s.U1, st);
+    launch_vie_rows<T>(g, tw, B, ks.V, ks.active, mT, s.U1, st, nullptr, nullptr, nullptr, s.U2);
   }
   // rest of step j: w into V_{j+1}, inner products, column j of H
   void tail(int j) {
@@ -644,7 +651,8 @@ struct ArnoldiDriver {
   // then the rotations of column j
   void orth_givens(int j, bool transform) {
     const OrthIn o = arnoldi_orth(ks, j, s.rowpart, transform);
-    launch_vie_rows<T>(g, tw, B, ks.V + (long)(j + 1) * ks.vstride(), ks.active, mT, s.U1, st, nullptr, &o);
+    launch_vie_rows<T>(g, tw, B, ks.V + (long)(j + 1) * ks.vstride(), ks.active, mT, s.U1, st, nullptr, &o,
+                       nullptr, s.U2);
     krylov_givens(ks, j, s.rowpart, g.nz * g.ny, st);
   }
 };
@@ -701,7 +709,7 @@ SolveTotals run_solve(fwi_ctx* c, const Geo& g, const c128* m64, const cplx<T>* 
       // x_0 = 0, r = b: the first pass casts b into V_0, sums |b|^2 per row
       // and transforms V_0 (every RHS; masks come with the cycle start)
       const StartIn si{b64, s.rowpart};
-      launch_vie_rows<T>(g, c->tw, B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
+      launch_vie_rows<T>(g, c->tw, B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si, s.U2);
       krylov_rows_norm(ks, s.rowpart, g.nz * g.ny, st);
     } else {
       // FP64 residual of x plus the last cycle's correction (added to x by
@@ -1110,6 +1118,7 @@ int guarded(fwi_ctx* c, F&& body) {
       tl_tune = &c->tune;
       tl_force_variant = -1;
       tl_force_wide = c->force_wide;
+      tl_xy_off = c->xy_off;
       tl_active = 0;
       tl_nfreq = 0;
     }
@@ -1120,6 +1129,7 @@ int guarded(fwi_ctx* c, F&& body) {
       tl_tune = nullptr;
       tl_force_variant = -1;
       tl_force_wide = 0;
+      tl_xy_off = 0;
     }
   } scope(c);
   try {
@@ -1491,7 +1501,7 @@ void enqueue_cycle(fwi_ctx* c, BatchInst<T>& I, const c128* rhs, c128* x, int cy
   if (part == CP_HEAD) {
     if (cyc == 0) {
       const StartIn si{rhs, s.rowpart};  // first pass of the first step included
-      launch_vie_rows<T>(I.g, c->tw, ks.B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si);
+      launch_vie_rows<T>(I.g, c->tw, ks.B, ks.V, nullptr, mT, s.U1, st, nullptr, nullptr, &si, s.U2);
       krylov_rows_norm(ks, s.rowpart, I.g.nz * I.g.ny, st);
     } else {
       launch_residual_basis(I.g, c->tw, ks.B, x, I.cb.m64, pc.ghat64, pc.rhs_freq, s, rhs, st);
@@ -1987,6 +1997,12 @@ int fwi_set_stream(fwi_ctx* c, void* stream) {
 int fwi_set_addressing(fwi_ctx* c, int wide) {
   if (!c || (wide != 0 && wide != 1)) return FWI_E_INVAL;
   c->force_wide = wide;
+  return FWI_OK;
+}
+
+int fwi_set_plane_fusion(fwi_ctx* c, int on) {
+  if (!c || (on != 0 && on != 1)) return FWI_E_INVAL;
+  c->xy_off = on ? 0 : 1;  // the problem cache is keyed on it, so a change rebuilds the spectra
   return FWI_OK;
 }
 

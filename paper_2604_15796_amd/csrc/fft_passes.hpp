@@ -734,9 +734,33 @@ int row_inv_nl(int L) {
 // streamed from HBM once per right-hand side.
 inline int conv_tile_major(const Geo& g, size_t es) { return g.npad() * (long)es > (4L << 20) ? 1 : 0; }
 
+}  // namespace fwi
+#include "xy_passes.hpp"
+namespace fwi {
+
+// Arguments of the fused lateral-elevation passes of geometry g.
+template <typename T>
+XyArgs<T> xy_args(const Geo& g, const Twiddles& tw, int B, const int* active, cplx<T>* U2) {
+  XyArgs<T> a{};
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.Lx = g.Lx;
+  a.Ly = g.Ly;
+  a.B = B;
+  a.active = active;
+  a.twx = tw.get<T>(g.Lx);
+  a.twy = tw.get<T>(g.Ly);
+  a.twm = tw.get<T>(g.Lx / 4);
+  a.twh = tw.get<T>(g.Ly / 2);
+  a.U2 = U2;
+  return a;
+}
+
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
-                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth, const StartIn* start) {
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth, const StartIn* start,
+                     cplx<T>* U2) {
   const long rows_per_rhs = (long)g.nz * g.ny;
   const double es = sizeof(cplx<T>);
   const bool masked = active != nullptr;  // converged RHS skipped (profiled bytes)
@@ -789,6 +813,28 @@ void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
   }
   // the orthogonalising first pass and the orthogonalisation alone are classes of their own
   const int cls = orth ? (orth->transform ? KC_ORTH_FWD : KC_ORTH) : KC_ROW_FWD;
+  if constexpr (sizeof(T) == 4) {
+    if (g.xy && f.kind != RI_ORTH_ONLY) {
+      // fused lateral-elevation pass: the operand straight to the padded
+      // spectrum U2 (class-major), no x-pass intermediate
+      if (!U2) throw Error(-6, "the fused lateral-elevation pass needs the y-pass buffer");
+      XyArgs<T> xa = xy_args<T>(g, tw, B, active, U2);
+      xa.x = x;
+      xa.m = m;
+      xa.basis = static_cast<const cplx<T>*>(f.lc_basis);
+      xa.vs = f.lc_vs;
+      xa.nvec = f.lc_nvec;
+      xa.coef = f.lc_coef;
+      xa.cstride = f.lc_cstride;
+      xa.xout = f.lc_out;
+      xa.rowpart = f.lc_rowpart;
+      xa.src = f.lc_src;
+      prof_begin(cls + po, st);
+      FWI_XY_SHAPES(launch_xy_fwd_s, T, g.Lx / 4, g.Ly / 2, xa, f.kind, st);
+      prof_end(cls + po, st, per_rhs + (double)(g.u2() - g.u1()) * es, n * es, masked, B);
+      return;
+    }
+  }
   prof_begin(cls + po, st);
   row_fwd_call<T>(g.Lx, f, st);
   prof_end(cls + po, st, per_rhs, n * es, masked, B);
@@ -805,6 +851,55 @@ void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
   const double gbytes = (double)(tl_nfreq > 0 ? tl_nfreq : 1) * g.npad() * es;
   const double n = (double)g.n();
   const int po = sizeof(T) == 8 ? KC_COUNT : 0;  // FP64 launches are separate classes
+  if constexpr (sizeof(T) == 4) {
+    if (g.xy) {
+      // U2 holds the class-major padded spectrum (launch_vie_rows): the
+      // convolution along z, then the fused inverse lateral-elevation pass
+      StridedArgs<T> c{};
+      c.in = U2;
+      c.out = U2;
+      c.tw = tw.get<T>(g.Lz);
+      c.ghat = ghat;
+      c.rhs_freq = rhs_freq;
+      c.active = active;
+      c.in_ps = c.out_ps = (long)g.nz * g.Ly * g.Lx;
+      c.pstride = (long)g.Ly * g.Lx;
+      c.gstride = g.npad();
+      c.gpstride = (long)g.Ly * g.Lx;
+      c.nlines = g.Ly * g.Lx;
+      c.planes_per_rhs = 1;
+      c.lin = c.lout = g.nz;
+      c.tile_major = conv_tile_major(g, sizeof(cplx<T>));
+      prof_begin(KC_CONV + po, st);
+      strided_call<T>(g.Lz, c, B, 2, st);
+      prof_end(KC_CONV + po, st, 2.0 * g.u2() * es, gbytes, masked, B);
+      if (epi != EPI_VIE && epi != EPI_COPY) throw Error(-6, "the fused lateral-elevation pass has no residual epilogue");
+      XyArgs<T> xa = xy_args<T>(g, tw, B, active, U2);
+      xa.x = x;
+      xa.scale = scale;
+      xa.y = y;
+      if (dots) {
+        dots->nparts = 0;
+        if (epi == EPI_VIE && g.nz <= kMaxDotParts && dots->nvec <= kMaxDotVec) {
+          epi = EPI_VIE_DOT;
+          xa.dbasis = static_cast<const cplx<T>*>(dots->basis);
+          xa.dvs = dots->vs;
+          xa.dnvec = dots->nvec;
+          xa.vscale = static_cast<const cplx<T>*>(dots->vscale);
+          xa.dotp = dots->dotp;
+          xa.dstride = dots->dstride;
+          dots->nparts = g.nz;
+        }
+      }
+      const double epi_bytes = epi == EPI_VIE_DOT ? (2.0 + (dots ? dots->nvec : 0)) * n * es
+                               : epi == EPI_VIE   ? 2.0 * n * es
+                                                  : n * es;
+      prof_begin(KC_ROW_INV + po, st);
+      FWI_XY_SHAPES(launch_xy_inv_s, T, g.Lx / 4, g.Ly / 2, xa, epi, st);
+      prof_end(KC_ROW_INV + po, st, (double)g.u2() * es + epi_bytes, 0.0, masked, B);
+      return;
+    }
+  }
   if (g.dim == 2) {
     // pass 2: columns along z, convolution, in place
     StridedArgs<T> s{};
@@ -925,7 +1020,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
                 const XUpdate* xu) {
-  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr, nullptr);
+  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr, nullptr, U2);
   launch_vie_tail<T>(g, tw, B, x, scale, active, ghat, rhs_freq, U1, U2, y, rhs, epi, st, y32, rowpart, dots);
 }
 

@@ -89,6 +89,9 @@ struct FftTuning {
 extern thread_local const FftTuning* tl_tune;
 extern thread_local int tl_force_variant;  // >= 0: every pass uses this variant
 extern thread_local int tl_force_wide;     // 1: strided passes use 64-bit addressing
+extern thread_local int tl_xy_off;         // 1: no fused lateral-elevation passes (separate x and y passes)
+// (Lx / 4, Ly / 2) of the grids built with fused lateral-elevation passes
+__host__ __device__ constexpr bool xy_shape(int MX, int HY) { return (MX == 64 && HY == 128) || (MX == 32 && HY == 64); }
 int default_variant(int pass, bool dbl, int L);
 int tune_variant(int pass, bool dbl, int L);
 int padded_length(int n);         // smallest supported L >= 2n, 0 if none
@@ -112,12 +115,19 @@ struct Geo {
   int Lx = 0, Ly = 1, Lz = 0;
   double dx = 0, c0 = 0;
   double alpha0 = 0;  // background attenuation [Np/m/Hz] (3D only)
+  // 3D complex64 operator with fused lateral-elevation passes (xy_passes.hpp):
+  // its padded spectra, and the complex64 kernel spectrum, are class-major
+  int xy = 0;
   long n() const { return (long)nx * ny * nz; }
   long npad() const { return (long)Lx * Ly * Lz; }
   // per-RHS intermediate sizes (elements): after the x pass / after the y pass
   long u1() const { return (long)nz * ny * Lx; }
   long u2() const { return dim == 3 ? (long)nz * Ly * Lx : 0; }
 };
+inline int xy_applies(const Geo& g) {
+  return g.dim == 3 && !tl_xy_off && g.Lx % 4 == 0 && g.Ly % 2 == 0 && 2 * g.nx <= g.Lx && 2 * g.ny <= g.Ly &&
+         xy_shape(g.Lx / 4, g.Ly / 2);
+}
 
 enum Epilogue { EPI_VIE = 0, EPI_RESID = 1, EPI_COPY = 2, EPI_RESID32 = 3, EPI_VIE_DOT = 4 };
 
@@ -192,11 +202,13 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 VieDots* dots = nullptr,  // returns through dots->nparts (0: not fused)
                 const XUpdate* xu = nullptr);
 // The same operator in two launches groups: the first pass (rows of x, or of
-// the combined input of xu / orth, transformed into U1) and the rest.
+// the combined input of xu / orth, transformed into U1, or into U2 when the
+// lateral and elevation passes are fused) and the rest.
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
                      cplx<T>* U1, hipStream_t st, const XUpdate* xu = nullptr, const OrthIn* orth = nullptr,
-                     const StartIn* start = nullptr);
+                     const StartIn* start = nullptr,
+                     cplx<T>* U2 = nullptr);  // written instead of U1 by a fused lateral-elevation pass (g.xy)
 template <typename T>
 void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const cplx<T>* scale,
                      const int* active, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2,
@@ -238,6 +250,7 @@ struct Aperture {
 void launch_incident(const Geo& g, c128 k, int ne, const double* elem_xyz_dev, const Aperture& ap, c128* P0,
                      hipStream_t st);
 void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st);
+void launch_cast_xy_64_32(const Geo& g, const c128* in, c64* out, hipStream_t st);  // class-major (g.xy)
 void launch_scale_c128(long count, double s, c128* x, hipStream_t st);
 
 }  // namespace fwi

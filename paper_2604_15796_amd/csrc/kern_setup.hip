@@ -266,6 +266,27 @@ void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st) {
   FWI_LAUNCH_CHECK();
 }
 
+// The complex64 kernel spectrum of a geometry with fused lateral-elevation
+// passes: cast, with the (ky, kx) frequencies of every z-plane stored
+// class-major (kx = 4k + c at column c Lx/4 + k, ky = 2m + d at row
+// d Ly/2 + m), the order of the padded spectra those passes write.
+__global__ void k_cast_xy_64_32(long count, int Lx, int Ly, const c128* __restrict__ in, c64* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const long plane = (long)Lx * Ly;
+  const long z = i / plane;
+  const int r = (int)(i - z * plane), ky = r / Lx, kx = r - ky * Lx;
+  const int row = (ky & 1) * (Ly / 2) + (ky >> 1), col = (kx & 3) * (Lx / 4) + (kx >> 2);
+  out[z * plane + (long)row * Lx + col] = cvt<float>(in[i]);
+}
+void launch_cast_xy_64_32(const Geo& g, const c128* in, c64* out, hipStream_t st) {
+  if (g.Lx % 4 || g.Ly % 2) throw Error(-6, "class-major spectrum needs Lx % 4 == 0 and Ly % 2 == 0");
+  const long count = g.npad();
+  hipLaunchKernelGGL(k_cast_xy_64_32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, g.Lx, g.Ly, in,
+                     out);
+  FWI_LAUNCH_CHECK();
+}
+
 __global__ void k_scale_c128(long count, double s, c128* x) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) x[i] = s * x[i];

@@ -92,6 +92,7 @@ def lib():
         "fwi_last_error": (C.c_char_p, [vp]),
         "fwi_set_stream": (ip, [vp, vp]),
         "fwi_set_addressing": (ip, [vp, ip]),
+        "fwi_set_plane_fusion": (ip, [vp, ip]),
         "fwi_default_opts": (None, [op]),
         "fwi_validate_problem": (ip, [pp]),
         "fwi_padded_length": (ip, [ip]),
@@ -151,7 +152,7 @@ EXPORTED = ["fwi_create", "fwi_destroy", "fwi_last_error", "fwi_set_stream", "fw
             "fwi_profile_read", "fwi_autotune", "fwi_get_tuning", "fwi_set_tuning", "fwi_adjoint_gradient_batch",
             "fwi_forward_batch", "fwi_set_addressing", "fwi_forward_tx", "fwi_adjoint_gradient_tx",
             "fwi_jacobian_apply_tx", "fwi_jacobian_adjoint_apply_tx", "fwi_tv_admm_step_tx", "fwi_invert",
-            "fwi_sos_from_contrast", "fwi_host_gauss_legendre", "fwi_autotune_solver"]
+            "fwi_sos_from_contrast", "fwi_host_gauss_legendre", "fwi_autotune_solver", "fwi_set_plane_fusion"]
 TUNING_BYTES = 4 * 2 * 11
 PASS_NAMES = ["row_fwd", "conv", "row_inv", "y_fwd", "y_inv"]
 
@@ -593,6 +594,11 @@ class Context:
         """wide=True forces the 64-bit addressing path of the strided FFT passes
         (otherwise used only for planes of 2 GiB or more)."""
         self._check(self.L.fwi_set_addressing(self.h, 1 if wide else 0))
+
+    def set_plane_fusion(self, on):
+        """on=True: the 3D complex64 operator uses the fused per-plane
+        lateral-elevation pass where the grid allows it (off by default)."""
+        self._check(self.L.fwi_set_plane_fusion(self.h, 1 if on else 0))
 
     def get_tuning(self):
         buf = (C.c_byte * TUNING_BYTES)()

@@ -142,8 +142,10 @@ void run_eager_gradient(fwi_ctx* ctx, Inst& I, int prec, int restart) {
   std::free(dga);
 }
 
-void every_entry(fwi_ctx* ctx, int dim) {
-  Prob q = dim == 2 ? make(2, 24, 1, 20, 4, 2) : make(3, 10, 8, 9, 3, 2);
+void every_entry(fwi_ctx* ctx, int dim, bool planes = false) {
+  // planes: a 3D grid whose padded lateral and elevation lengths (128) take
+  // the fused lateral-elevation passes of the complex64 operator
+  Prob q = dim == 2 ? make(2, 24, 1, 20, 4, 2) : planes ? make(3, 60, 58, 6, 3, 2) : make(3, 10, 8, 9, 3, 2);
   const long n = q.n;
   const int ne = q.p.ne, nf = q.p.nf;
   double* c = dev<double>(n, 1540.0);
@@ -339,6 +341,14 @@ int main(int argc, char** argv) {
   if (what == "all" || what == "entries") {
     every_entry(ctx, 2);
     every_entry(ctx, 3);
+    every_entry(ctx, 3, true);
+    check(fwi_set_plane_fusion(ctx, 1), "plane fusion on", ctx);
+    every_entry(ctx, 3, true);
+    check(fwi_set_plane_fusion(ctx, 0), "plane fusion off", ctx);
+    if (fwi_set_plane_fusion(ctx, 2) != FWI_E_INVAL) {
+      std::fprintf(stderr, "[driver] plane fusion value 2 not refused\n");
+      g_fail = 1;
+    }
   }
   fwi_destroy(ctx);
   hipStreamDestroy(user);

@@ -205,7 +205,8 @@ static int row_inv_rows(int L) {
 
 template <typename T>
 void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const int* active, const cplx<T>* m,
-                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth, const StartIn* start) {
+                     cplx<T>* U1, hipStream_t st, const XUpdate* xu, const OrthIn* orth, const StartIn* start,
+                     cplx<T>* U2) {
   (void)tw.get<T>(g.Lx);
   if ((xu != nullptr) + (orth != nullptr) + (start != nullptr) > 1) throw Error(-6, "one combined input per pass");
   const long n = g.n(), rows = (long)g.nz * g.ny, u1 = g.u1();
@@ -214,6 +215,15 @@ void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
   const OrthIn ov = orth ? *orth : OrthIn{};
   const StartIn sv = start ? *start : StartIn{};
   const bool has_xu = xu, has_orth = orth, has_start = start;
+  // the fused lateral-elevation pass writes the padded spectrum U2 instead of U1
+  const bool xy = sizeof(T) == 4 && g.xy && !(orth && !orth->transform);
+  if (xy) {
+    (void)tw.get<T>(g.Ly);
+    (void)tw.get<T>(g.Lx / 4);
+    (void)tw.get<T>(g.Ly / 2);
+    if (!U2) throw Error(-6, "the fused lateral-elevation pass needs the y-pass buffer");
+  }
+  const long u2 = g.u2();
   if (has_xu && (sizeof(T) != 8 || active)) throw Error(-6, "the fused solution update is for complex128 residuals");
   if (has_start && (!m || active)) throw Error(-6, "the start pass needs the contrast and every RHS");
   emu::submit(st, "row_fwd", [=] {
@@ -244,7 +254,8 @@ void launch_vie_rows(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
     }
     if (transform) {
       rd(m, e * n);
-      wr(U1, e * B * u1);
+      if (xy) wr(U2, e * B * u2);
+      else wr(U1, e * B * u1);
     }
   });
 }
@@ -260,10 +271,21 @@ void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
   const long n = g.n(), rows = (long)g.nz * g.ny, u1 = g.u1(), u2 = g.u2(), np = g.npad();
   const size_t e = es<T>();
   VieDots dv{};
+  const bool xy = sizeof(T) == 4 && g.xy;
+  if (xy) {
+    (void)tw.get<T>(g.Lx / 4);
+    (void)tw.get<T>(g.Ly / 2);
+    if (epi != EPI_VIE && epi != EPI_COPY) throw Error(-6, "the fused lateral-elevation pass has no residual epilogue");
+  }
   if (dots) {
     dots->nparts = 0;
     const int nl = row_inv_rows<T>(g.Lx);
-    if (epi == EPI_VIE && rows % nl == 0 && rows / nl <= kMaxDotParts && dots->nvec <= 33) {
+    if (xy) {
+      if (epi == EPI_VIE && g.nz <= kMaxDotParts && dots->nvec <= 33) {
+        dots->nparts = g.nz;
+        dv = *dots;
+      }
+    } else if (epi == EPI_VIE && rows % nl == 0 && rows / nl <= kMaxDotParts && dots->nvec <= 33) {
       dots->nparts = (int)(rows / nl);
       dv = *dots;
     }
@@ -273,12 +295,18 @@ void launch_vie_tail(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, 
     if (active) rd(active, sizeof(int) * B);
     rd(rhs_freq, sizeof(int) * B);
     for (int b = 0; b < B; ++b) rd(ghat + (long)rhs_freq[b] * np, e * np);
-    rd(U1, e * B * u1);
-    if (g.dim == 3) {
+    if (xy) {
+      rd(U2, e * B * u2);
       wr(U2, e * B * u2);
       rd(U2, e * B * u2);
+    } else {
+      rd(U1, e * B * u1);
+      if (g.dim == 3) {
+        wr(U2, e * B * u2);
+        rd(U2, e * B * u2);
+      }
+      wr(U1, e * B * u1);
     }
-    wr(U1, e * B * u1);
     if (scale) rd(scale, e * B);
     rd(x, e * B * n);
     if (epi == EPI_VIE) {
@@ -305,7 +333,7 @@ void launch_vie(const Geo& g, const Twiddles& tw, int B, const cplx<T>* x, const
                 const cplx<T>* m, const cplx<T>* ghat, const int* rhs_freq, cplx<T>* U1, cplx<T>* U2, cplx<T>* y,
                 const cplx<T>* rhs, int epi, hipStream_t st, c64* y32, double* rowpart, VieDots* dots,
                 const XUpdate* xu) {
-  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr, nullptr);
+  launch_vie_rows<T>(g, tw, B, x, active, m, U1, st, xu, nullptr, nullptr, U2);
   launch_vie_tail<T>(g, tw, B, x, scale, active, ghat, rhs_freq, U1, U2, y, rhs, epi, st, y32, rowpart, dots);
 }
 
@@ -336,7 +364,7 @@ void launch_fft_padded(const Geo& g, const Twiddles& tw, const cplx<T>* in, cplx
                               const cplx<T>*, const cplx<T>*, const int*, cplx<T>*, cplx<T>*, cplx<T>*,              \
                               const cplx<T>*, int, hipStream_t, c64*, double*, VieDots*, const XUpdate*);            \
   template void launch_vie_rows<T>(const Geo&, const Twiddles&, int, const cplx<T>*, const int*, const cplx<T>*,     \
-                                   cplx<T>*, hipStream_t, const XUpdate*, const OrthIn*, const StartIn*);            \
+                                   cplx<T>*, hipStream_t, const XUpdate*, const OrthIn*, const StartIn*, cplx<T>*);  \
   template void launch_vie_tail<T>(const Geo&, const Twiddles&, int, const cplx<T>*, const cplx<T>*, const int*,     \
                                    const cplx<T>*, const int*, cplx<T>*, cplx<T>*, cplx<T>*, const cplx<T>*, int,    \
                                    hipStream_t, c64*, double*, VieDots*);                                            \
@@ -385,6 +413,14 @@ void launch_incident(const Geo& g, c128, int ne, const double* exyz, const Apert
 void launch_cast_64_32(long count, const c128* in, c64* out, hipStream_t st) {
   if (count == 0) return;
   emu::submit(st, "cast", [=] {
+    rd(in, 16 * count);
+    wr(out, 8 * count);
+  });
+}
+void launch_cast_xy_64_32(const Geo& g, const c128* in, c64* out, hipStream_t st) {
+  if (g.Lx % 4 || g.Ly % 2) throw Error(-6, "class-major spectrum needs Lx % 4 == 0 and Ly % 2 == 0");
+  const long count = g.npad();
+  emu::submit(st, "cast_xy", [=] {
     rd(in, 16 * count);
     wr(out, 8 * count);
   });

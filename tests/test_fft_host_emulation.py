@@ -31,3 +31,21 @@ def test_line_fft_plans_on_host(tmp_path):
     bad = [l for l in lines if not l.endswith(" ok")]
     assert not bad, "\n".join(bad)
     assert sum(" BIG=1 " in l for l in lines) >= 8  # the radix-16/32 plans are exercised
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_fused_lateral_elevation_passes_on_host(tmp_path):
+    """The fused 3D lateral-elevation passes (csrc/xy_passes.hpp) on one
+    z-plane, one workgroup as host threads, built with the address sanitizer:
+    class-major forward spectrum against a direct 2D DFT of the padded
+    operand, the inverse against a direct inverse DFT, the Gram-Schmidt and
+    start operands with their per-row norms, and the operator epilogue."""
+    exe = tmp_path / "xy_plans"
+    subprocess.run(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-I{EMU}", f"-I{CSRC}",
+                    str(EMU / "xy_plans.cpp"), "-o", str(exe), "-lpthread"], check=True, timeout=600)
+    p = subprocess.run([str(exe)], capture_output=True, text=True, timeout=900)
+    lines = [l for l in p.stdout.splitlines() if l.strip()]
+    assert p.returncode == 0, p.stdout + p.stderr
+    assert len(lines) == 22, p.stdout
+    bad = [l for l in lines if not l.endswith(" ok")]
+    assert not bad, "\n".join(bad)

@@ -144,6 +144,56 @@ def test_operator_3d_vs_oracle(ctx, shape):
             assert relerr(y[b], ref) < (2e-6 if prec else 1e-13)
 
 
+@pytest.mark.parametrize("shape", [(6, 60, 58), (5, 64, 64)])
+def test_operator_3d_fused_planes_vs_oracle(ctx, shape):
+    """Grids whose padded lateral and elevation lengths (128) take the fused
+    lateral-elevation passes of the complex64 operator: against the oracle,
+    and against the separate passes (fusion switched off)."""
+    nz, ny, nx = shape
+    p = W.small3d(seed=sum(shape), nx=nx, ny=ny, nz=nz)
+    m = O.contrast(p.c, p.alpha, p.c0)
+    x = W.random_complex(9, (3,) + p.shape)
+    Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), 3, p.nx, p.ny, p.nz, p.dx)
+    refs = [O.vie_apply(Gh, m, x[b]).ravel() for b in range(3)]
+    outs = {}
+    try:
+        for on in (True, False):
+            ctx.set_plane_fusion(on)
+            y = host(ctx.apply_operator(p, dev(m), [0, 0, 0], dev(x.reshape(3, -1), torch.complex64), precision=1))
+            for b in range(3):
+                assert relerr(y[b], refs[b]) < 2e-6
+            outs[on] = y
+    finally:
+        ctx.set_plane_fusion(False)
+    assert relerr(outs[True], outs[False]) < 2e-6
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_forward_and_gradient_3d_fused_planes_vs_oracle(ctx, F, fused):
+    """Mixed-precision forward fields, data and adjoint gradient on a grid that
+    takes the fused lateral-elevation passes (start, Gram-Schmidt and
+    inner-product forms of the passes), with and without the fusion."""
+    p = W.small3d(seed=71, nx=58, ny=60, nz=5, ne=3, nf=1)
+    args = (3, p.nx, p.ny, p.nz, p.dx, p.c0, p.freqs, p.elems)
+    d_obs = O.forward(p.extra["c_obs"], p.alpha, *args)[0]
+    rd, rf, _ = O.forward(p.c, p.alpha, *args)
+    rphi, rg, _, _, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, *args)
+    opts = F.SolveOptions(precision=1, rtol=1e-7, restart=8, inner_rtol=1e-6, max_iter=400)
+    c, a = dev(p.c, torch.float64), dev(p.alpha, torch.float64)
+    try:
+        ctx.set_plane_fusion(fused)
+        data, fields, st = ctx.forward(p, c, a, opts, fields=True)
+        phi, gm, _, _, st2 = ctx.adjoint_gradient(p, c, a, dev(d_obs), opts)
+    finally:
+        ctx.set_plane_fusion(False)
+    assert st["unconverged"] == 0 and st["max_rel_residual"] <= 1e-7
+    assert st2["unconverged"] == 0
+    assert relerr(host(fields), rf) < 1e-6
+    assert relerr(host(data), rd) < 1e-6
+    assert abs(phi - rphi) < 1e-6 * rphi
+    assert relerr(host(gm), rg) < 1e-6
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_operator_every_tile_variant_and_autotune(ctx, F, dim):
     """Each tile variant of each pass gives the same operator; the autotuner's
