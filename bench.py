@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--iters", type=int, default=20, help="ADMM iterations of the invert-384 workload")
     ap.add_argument("--tuning", default=None,
                     help="hex tuning table (as printed in tuning_hex) to use instead of autotuning")
+    ap.add_argument("--plane-fusion", action="store_true",
+                    help="3D: fused lateral-elevation passes of the complex64 operator (off by default; slower "
+                         "on MI355X, see fwi_set_plane_fusion)")
     ap.add_argument("--counter-sample", action="store_true",
                     help="short run for hardware-counter passes: warmup, one step, then a plain copy of "
                          "known size (the incident-field cache) for calibrating FETCH_SIZE / WRITE_SIZE")
@@ -176,6 +179,8 @@ def bench_gradient(args, workload):
     shape_default = p.ne if three_d else 0
     prob = fwi.ProblemArgs(p)
     ctx = fwi.Context(0)
+    if args.plane_fusion:
+        ctx.set_plane_fusion(True)
     c = torch.as_tensor(p.c).to(dev)
     a = torch.as_tensor(p.alpha).to(dev)
     c_obs = torch.as_tensor(p.extra["c_obs"]).to(dev)
@@ -305,7 +310,8 @@ def bench_gradient(args, workload):
                       "grid": list(p.shape), "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
                       "precision": "complex128 GMRES" if fp64_only else
                                    "complex64 GMRES in FP64-residual refinement",
-                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": restart},
+                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": restart,
+                      "plane_fusion": bool(args.plane_fusion)},
            "setup_ms": round(setup_ms, 2),
            "roofline": roofline,
            "solver_autotune": solver_tune,
