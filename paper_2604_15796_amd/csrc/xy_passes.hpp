@@ -215,13 +215,24 @@ __device__ __forceinline__ void xy_fwd_body(const XyArgs<T>& a, int z, int b, cp
         if (okk(k)) nrm[k >> 1] += (double)pv[k].x * (double)pv[k].x + (double)pv[k].y * (double)pv[k].y;
     }
   }
+  if constexpr (NORM) {
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    if constexpr (NORM) {
+    for (int k = 0; k < NP; ++k)
       if (okk(k)) a.xout[pb + ek(k)] = pv[k];
+  }
+  // times m, branch-free so that every load is in flight at once: without a
+  // contrast the operand stands in for m and the blend makes the factor 1
+  {
+    const T km = a.m ? (T)1 : (T)0;
+    const cplx<T>* mp = a.m ? a.m + mb : a.x + pb;
+    cplx<T> mv[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) mv[k] = mp[ek(k)];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const cplx<T> u = pv[k] * mk(km * mv[k].x + ((T)1 - km), km * mv[k].y);
+      pv[k] = okk(k) ? u : mk((T)0, (T)0);
     }
-    if (a.m) pv[k] = pv[k] * a.m[mb + ek(k)];
-    if (!okk(k)) pv[k] = mk((T)0, (T)0);
   }
   if constexpr (NORM) {
     // per grid row, in a fixed order: the row's MX partials through LDS
@@ -317,23 +328,28 @@ __device__ __forceinline__ void xy_inv_body(const XyArgs<T>& a, int z, int b, cp
   auto xk = [&](int k) { return xl + (k & 1) * MX; };
   auto okk = [&](int k) { return yk(k) < a.ny && xk(k) < a.nx; };
   auto ek = [&](int k) { return okk(k) ? yk(k) * a.nx + xk(k) : 0; };
+  if constexpr (EPI == EPI_VIE || EPI == EPI_VIE_DOT) {
+    cplx<T> xv[NP];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    if constexpr (EPI == EPI_VIE || EPI == EPI_VIE_DOT) {
-      const cplx<T> xv = a.x[pb + ek(k)];
-      acc[k] = (xv - acc[k]) * s;  // the operator is linear: s (x - conv(m x))
-    }
-    if (okk(k)) a.y[pb + ek(k)] = acc[k];
+    for (int k = 0; k < NP; ++k) xv[k] = a.x[pb + ek(k)];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = (xv[k] - acc[k]) * s;  // the operator is linear: s (x - conv(m x))
   }
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+    if (okk(k)) a.y[pb + ek(k)] = acc[k];
   if constexpr (EPI == EPI_VIE_DOT) {
     // one part per plane: fixed-order sums (thread, wave, then the waves)
     const int lane = t & 63, wv = t >> 6;
     for (int j = 0; j < a.dnvec; ++j) {
       const cplx<T>* Vj = a.dbasis + (long)j * a.dvs + pb;
       double r = 0.0, mm = 0.0;
+      cplx<T> vv[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) vv[k] = Vj[ek(k)];
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
-        const cplx<T> v = Vj[ek(k)];
+        const cplx<T> v = vv[k];
         const double vx = okk(k) ? (double)v.x : 0.0, vy = okk(k) ? (double)v.y : 0.0;
         const double yx = acc[k].x, yy = acc[k].y;
         r = fma(vx, yx, r);
