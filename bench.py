@@ -67,9 +67,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--inner-rtol", type=float, default=None,
-                    help="floor of each complex64 cycle's relative target; default 1e-6 for gradient-256 (one "
-                         "cycle reaches the outer tolerance, the FP64 residual certifies it) and 1e-3 for "
-                         "uneven-batch (graph-replayed cycles always run every step, masked)")
+                    help="floor of each complex64 cycle's relative target; default: chosen by the solver "
+                         "autotuner between rtol and rtol/2 on the gradient workloads (rtol/2 trades complex64 "
+                         "iterations for a second refinement cycle), rtol elsewhere, 1e-3 for uneven-batch")
     ap.add_argument("--restart", type=int, default=None,
                     help="GMRES basis length (8, 16 or 32); default: chosen by the solver autotuner on the "
                          "gradient workloads, 16 elsewhere")
@@ -117,8 +117,9 @@ def log(*a):
 
 def main():
     args = parse()
+    args.tune_inner = args.inner_rtol is None
     if args.inner_rtol is None:
-        args.inner_rtol = 1e-3 if args.workload == "uneven-batch" else 1e-6
+        args.inner_rtol = 1e-3 if args.workload == "uneven-batch" else args.rtol
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU frequency-sharded layout is design-only.", file=sys.stderr)
@@ -197,23 +198,24 @@ def bench_gradient(args, workload):
     setup_ms = st0["t_setup_ms"]
     log(f"setup done: spectra and incident fields {setup_ms:.1f} ms, {st0['iterations']} its")
 
-    # batch shape (RHS per batched solve) and restart length, chosen by the
-    # library's solver autotuner on the timed step itself (untimed set-up,
-    # built-in FFT tiles); caps that keep more than two frequencies' fields and
-    # Krylov bases resident are not offered in 3D
-    max_rhs, restart, solver_tune = args.max_rhs, args.restart, None
+    # batch shape (RHS per batched solve), restart length and inner tolerance,
+    # chosen by the library's solver autotuner on the timed step itself
+    # (untimed set-up, built-in FFT tiles); caps that keep more than two
+    # frequencies' fields and Krylov bases resident are not offered in 3D
+    max_rhs, restart, inner, solver_tune = args.max_rhs, args.restart, args.inner_rtol, None
     tunable = not (planewave or fp64_only or args.counter_sample or args.no_tune or args.tuning)
-    if tunable and (max_rhs is None or restart is None):
+    if tunable and (max_rhs is None or restart is None or args.tune_inner):
         nrhs = p.nf * p.ne
         caps = [max_rhs] if max_rhs is not None else \
             ([p.ne, 2 * p.ne] if three_d else [0, nrhs // 2, nrhs // 4])
         restarts = [restart] if restart is not None else [8, 16, 32]
-        base = fwi.SolveOptions(precision=fwi.FWI_FP64 if fp64_only else fwi.FWI_FP32_REFINE, rtol=args.rtol,
-                                inner_rtol=args.inner_rtol, check_every=args.check_every)
-        r = ctx.autotune_solver(prob, c, a, d_obs, base, max_rhs=caps, restart=restarts, reps=1)
-        max_rhs, restart = r["max_rhs"], r["restart"]
-        solver_tune = {"chosen": {"max_rhs": max_rhs, "restart": restart},
-                       "ms_per_step": {f"max_rhs={m},restart={k}": round(t, 2) for (m, k), t in r["ms"].items()}}
+        inners = [args.rtol, args.rtol / 2] if args.tune_inner else [inner]
+        base = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, check_every=args.check_every)
+        r = ctx.autotune_solver(prob, c, a, d_obs, base, max_rhs=caps, restart=restarts, inner_rtol=inners, reps=1)
+        max_rhs, restart, inner = r["max_rhs"], r["restart"], r["inner_rtol"]
+        solver_tune = {"chosen": {"max_rhs": max_rhs, "restart": restart, "inner_rtol": inner},
+                       "ms_per_step": {f"max_rhs={m},restart={k},inner_rtol={t:g}": round(v, 2)
+                                       for (m, k, t), v in r["ms"].items()}}
         log(f"solver autotune: {solver_tune}")
     max_rhs = shape_default if max_rhs is None else max_rhs
     restart = 16 if restart is None else restart
@@ -230,7 +232,7 @@ def bench_gradient(args, workload):
     tuned_table = ctx.get_tuning()
 
     mixed = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=restart,
-                             inner_rtol=args.inner_rtol, check_every=args.check_every, max_rhs=max_rhs)
+                             inner_rtol=inner, check_every=args.check_every, max_rhs=max_rhs)
     plain = fwi.SolveOptions(precision=fwi.FWI_FP64, rtol=args.rtol, restart=restart,
                              check_every=args.check_every, max_rhs=max_rhs)
     if fp64_only:
@@ -310,7 +312,7 @@ def bench_gradient(args, workload):
                       "grid": list(p.shape), "nf": p.nf, "ne": p.ne, "solves_per_step": solves_per_step,
                       "precision": "complex128 GMRES" if fp64_only else
                                    "complex64 GMRES in FP64-residual refinement",
-                      "rtol": args.rtol, "inner_rtol": args.inner_rtol, "restart": restart,
+                      "rtol": args.rtol, "inner_rtol": inner, "restart": restart,
                       "plane_fusion": bool(args.plane_fusion)},
            "setup_ms": round(setup_ms, 2),
            "roofline": roofline,
@@ -348,7 +350,7 @@ def bench_gradient(args, workload):
             # adjoint fields are combinations of the forward fields (no adjoint
             # solves; not counted as solves)
             recip = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, restart=restart,
-                                     inner_rtol=args.inner_rtol, check_every=args.check_every,
+                                     inner_rtol=inner, check_every=args.check_every,
                                      max_rhs=max_rhs, reciprocity_adjoint=1)
             _, g_r, _, _, _ = step(recip)
             ms_r, _ = timed_steps(step, recip, args.steps, torch)

@@ -424,32 +424,41 @@ typedef struct fwi_tune_report {
 } fwi_tune_report;
 int fwi_autotune(fwi_ctx* ctx, const fwi_problem* prob, int precision, int B, int reps, fwi_tune_report* report);
 
-/* Batch shape and restart length of the gradient step (the two solver
- * options that set how much work each launch of the Arnoldi kernels carries
- * and how many launches a solve takes): for every pair of candidate batch caps
- * max_rhs[i] (as fwi_solve_opts.max_rhs; 0 = all frequencies in one batch)
- * and restart lengths restart[j] (8, 16 or 32), with every other option taken
- * from `base`, runs fwi_adjoint_gradient once untimed and then `reps` times,
- * and reports the host wall time of the fastest call (each call synchronises
- * its stream) and the fastest pair. c, alpha, d_obs as in
- * fwi_adjoint_gradient; the gradient itself is discarded. The caller lists
- * only the caps whose memory it accepts (a larger batch keeps more fields and
- * Krylov vectors resident). Runs on the context's current workspace (a
- * caller workspace must fit the largest candidate; the library's own one is
- * released at the end if the search grew it); the FFT tile table and every
- * other context setting are left as they were. A candidate whose solves
- * end unconverged is timed but never chosen (FWI_E_NOCONV when none converges).
- * Errors: FWI_E_INVAL for NULL arguments, reps < 1, counts outside 1..8 caps
- * and 1..3 restarts, a negative cap or a restart other than 8/16/32; any
- * error of fwi_adjoint_gradient (the first one ends the search). */
+/* Batch shape, restart length and inner tolerance of the gradient step (the
+ * solver options that set how much work each launch of the Arnoldi kernels
+ * carries and how many launches and refinement cycles a solve takes): for
+ * every combination of candidate batch caps max_rhs[i] (as
+ * fwi_solve_opts.max_rhs; 0 = all frequencies in one batch), restart lengths
+ * restart[j] (8, 16 or 32) and inner tolerances inner_rtol[h] (as
+ * fwi_solve_opts.inner_rtol, in (0, 1); NULL: base's own, n_inner ignored),
+ * with every other option taken from `base`, runs fwi_adjoint_gradient once
+ * untimed and then `reps` times, and reports the host wall time of the
+ * fastest call (each call synchronises its stream) and the fastest
+ * combination. The inner tolerance only acts under FWI_FP32_REFINE: a tighter
+ * one costs complex64 iterations and can save a refinement cycle (an FP64
+ * operator application); the converged result meets rtol either way. c,
+ * alpha, d_obs as in fwi_adjoint_gradient; the gradient itself is discarded.
+ * The caller lists only the caps whose memory it accepts (a larger batch
+ * keeps more fields and Krylov vectors resident). Runs on the context's
+ * current workspace (a caller workspace must fit the largest candidate; the
+ * library's own one is released at the end if the search grew it); the FFT
+ * tile table and every other context setting are left as they were. A
+ * candidate whose solves end unconverged is timed but never chosen
+ * (FWI_E_NOCONV when none converges).
+ * Errors: FWI_E_INVAL for NULL arguments, reps < 1, counts outside 1..8 caps,
+ * 1..3 restarts and 1..3 inner tolerances, a negative cap, a restart other
+ * than 8/16/32 or an inner tolerance outside (0, 1); any error of
+ * fwi_adjoint_gradient (the first one ends the search). */
 typedef struct fwi_solver_tune_report {
-  int max_rhs;        /* chosen */
-  int restart;        /* chosen */
-  double ms[8][3];    /* [i][j] best time of candidate pair (max_rhs[i], restart[j]) */
+  int max_rhs;          /* chosen */
+  int restart;          /* chosen */
+  double inner_rtol;    /* chosen */
+  double ms[3][8][3];   /* [h][i][j] best time of (inner_rtol[h], max_rhs[i], restart[j]) */
 } fwi_solver_tune_report;
 int fwi_autotune_solver(fwi_ctx* ctx, const fwi_problem* prob, const double* c, const double* alpha,
                         const void* d_obs, const fwi_solve_opts* base, const int* max_rhs, int n_max_rhs,
-                        const int* restart, int n_restart, int reps, fwi_solver_tune_report* report);
+                        const int* restart, int n_restart, const double* inner_rtol, int n_inner, int reps,
+                        fwi_solver_tune_report* report);
 /* Copy the tuning table out / in (count = 4*2*11 bytes, -1 = built-in default);
  * in = NULL restores the defaults. For caching tuning results across runs. */
 int fwi_get_tuning(const fwi_ctx* ctx, signed char* out, int count);

@@ -2472,17 +2472,24 @@ int fwi_autotune(fwi_ctx* c, const fwi_problem* p, int precision, int B, int rep
 
 int fwi_autotune_solver(fwi_ctx* c, const fwi_problem* p, const double* cc, const double* alpha, const void* dobs,
                         const fwi_solve_opts* base, const int* max_rhs, int n_mr, const int* restart, int n_rs,
-                        int reps, fwi_solver_tune_report* rep) {
+                        const double* inner_rtol, int n_in, int reps, fwi_solver_tune_report* rep) {
   return guarded(c, [&] {
     if (!p || !cc || !dobs || !base || !max_rhs || !restart || !rep || reps < 1)
       throw Error(FWI_E_INVAL, "bad solver autotune arguments");
-    if (n_mr < 1 || n_mr > 8 || n_rs < 1 || n_rs > 3)
-      throw Error(FWI_E_INVAL, "1..8 batch caps and 1..3 restart lengths");
+    if (!inner_rtol) n_in = 1;  // the base options' own inner tolerance
+    if (n_mr < 1 || n_mr > 8 || n_rs < 1 || n_rs > 3 || n_in < 1 || n_in > 3)
+      throw Error(FWI_E_INVAL, "1..8 batch caps, 1..3 restart lengths and 1..3 inner tolerances");
     std::string msg;
     int rc = validate_opts(base, msg);
     if (rc) throw Error(rc, msg);
     for (int i = 0; i < n_mr; ++i)
       if (max_rhs[i] < 0) throw Error(FWI_E_INVAL, "max_rhs candidates must be >= 0");
+    for (int j = 0; j < n_rs; ++j)
+      if (restart[j] != 8 && restart[j] != 16 && restart[j] != 32)
+        throw Error(FWI_E_INVAL, "restart candidates must be 8, 16 or 32");
+    for (int h = 0; inner_rtol && h < n_in; ++h)
+      if (!(inner_rtol[h] > 0.0 && inner_rtol[h] < 1.0))
+        throw Error(FWI_E_INVAL, "inner_rtol candidates must be in (0, 1)");
     // the library's own workspace grows to the largest candidate's plan;
     // a grown one is released at the end so that the tuning leaves no
     // allocation larger than the caller's own calls make
@@ -2501,37 +2508,41 @@ int fwi_autotune_solver(fwi_ctx* c, const fwi_problem* p, const double* cc, cons
     } release{c, ws_before};
     fwi_solver_tune_report r{};
     double best = std::numeric_limits<double>::infinity();
-    for (int i = 0; i < n_mr; ++i) {
-      for (int j = 0; j < n_rs; ++j) {
-        fwi_solve_opts o = *base;
-        o.max_rhs = max_rhs[i];
-        o.restart = restart[j];
-        rc = validate_opts(&o, msg);
-        if (rc) throw Error(rc, msg);
-        double t = std::numeric_limits<double>::infinity();
-        bool converged = true;
-        for (int k = 0; k <= reps; ++k) {  // the first call is untimed
-          const double t0 = now_ms();
-          rc = o.precision == FWI_FP32_REFINE
-                   ? gradient_impl<float>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
-                                          nullptr, nullptr)
-                   : gradient_impl<double>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
-                                           nullptr, nullptr);
-          const double dt = now_ms() - t0;  // the call returns after synchronising its stream
-          if (rc != FWI_OK && rc != FWI_E_NOCONV) return rc;
-          converged = converged && rc == FWI_OK;
-          if (k > 0) t = std::min(t, dt);
-        }
-        r.ms[i][j] = t;
-        if (converged && t < best) {
-          best = t;
-          r.max_rhs = o.max_rhs;
-          r.restart = o.restart;
+    for (int h = 0; h < n_in; ++h) {
+      for (int i = 0; i < n_mr; ++i) {
+        for (int j = 0; j < n_rs; ++j) {
+          fwi_solve_opts o = *base;
+          o.max_rhs = max_rhs[i];
+          o.restart = restart[j];
+          if (inner_rtol) o.inner_rtol = inner_rtol[h];
+          rc = validate_opts(&o, msg);
+          if (rc) throw Error(rc, msg);
+          double t = std::numeric_limits<double>::infinity();
+          bool converged = true;
+          for (int k = 0; k <= reps; ++k) {  // the first call is untimed
+            const double t0 = now_ms();
+            rc = o.precision == FWI_FP32_REFINE
+                     ? gradient_impl<float>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
+                                            nullptr, nullptr)
+                     : gradient_impl<double>(c, p, cc, alpha, nullptr, dobs, nullptr, &o, nullptr, nullptr, nullptr,
+                                             nullptr, nullptr);
+            const double dt = now_ms() - t0;  // the call returns after synchronising its stream
+            if (rc != FWI_OK && rc != FWI_E_NOCONV) return rc;
+            converged = converged && rc == FWI_OK;
+            if (k > 0) t = std::min(t, dt);
+          }
+          r.ms[h][i][j] = t;
+          if (converged && t < best) {
+            best = t;
+            r.max_rhs = o.max_rhs;
+            r.restart = o.restart;
+            r.inner_rtol = o.inner_rtol;
+          }
         }
       }
     }
     if (!(best < std::numeric_limits<double>::infinity()))
-      throw Error(FWI_E_NOCONV, "no candidate pair converged");
+      throw Error(FWI_E_NOCONV, "no candidate converged");
     *rep = r;
     return FWI_OK;
   });

@@ -131,8 +131,8 @@ def lib():
                                             C.POINTER(vp), C.POINTER(CBatchStats)]),
         "fwi_forward_batch": (ip, [vp, ip, pp, C.POINTER(vp), C.POINTER(vp), op, C.POINTER(vp),
                                    C.POINTER(CBatchStats)]),
-        "fwi_autotune_solver": (ip, [vp, pp, vp, vp, vp, op, C.POINTER(C.c_int), ip, C.POINTER(C.c_int), ip, ip,
-                                     C.POINTER(CSolverTuneReport)]),
+        "fwi_autotune_solver": (ip, [vp, pp, vp, vp, vp, op, C.POINTER(C.c_int), ip, C.POINTER(C.c_int), ip,
+                                     C.POINTER(C.c_double), ip, ip, C.POINTER(CSolverTuneReport)]),
         "fwi_get_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
         "fwi_set_tuning": (ip, [vp, C.POINTER(C.c_byte), ip]),
     }
@@ -175,7 +175,8 @@ class CTuneReport(C.Structure):
 
 
 class CSolverTuneReport(C.Structure):
-    _fields_ = [("max_rhs", C.c_int), ("restart", C.c_int), ("ms", (C.c_double * 3) * 8)]
+    _fields_ = [("max_rhs", C.c_int), ("restart", C.c_int), ("inner_rtol", C.c_double),
+                ("ms", ((C.c_double * 3) * 8) * 3)]
 
 
 # ---------------------------------------------------------------- structs ---
@@ -572,9 +573,12 @@ class Context:
                 out[name] = {"ms": ms, "chosen": rep.variant[k], "default": rep.default_variant[k]}
         return out
 
-    def autotune_solver(self, prob, c, alpha, d_obs, opts=None, max_rhs=(0,), restart=(8,), reps=1):
-        """Time the gradient step for every (max_rhs, restart) pair and return
-        {"max_rhs", "restart" (the fastest pair), "ms": {(max_rhs, restart): ms}}.
+    def autotune_solver(self, prob, c, alpha, d_obs, opts=None, max_rhs=(0,), restart=(8,), inner_rtol=None,
+                        reps=1):
+        """Time the gradient step for every (max_rhs, restart, inner_rtol)
+        combination (inner_rtol=None: the options' own) and return
+        {"max_rhs", "restart", "inner_rtol" (the fastest),
+        "ms": {(max_rhs, restart, inner_rtol): ms}}.
         Uses the library's own workspace; the context's tuning is unchanged."""
         prob = prob if isinstance(prob, ProblemArgs) else ProblemArgs(prob)
         o = (opts or SolveOptions()).c()
@@ -582,13 +586,17 @@ class Context:
         _check_dtype(d_obs, torch.complex128, (prob.nf, prob.ne, prob.ne), "d_obs")
         mr = (C.c_int * len(max_rhs))(*[int(v) for v in max_rhs])
         rs = (C.c_int * len(restart))(*[int(v) for v in restart])
+        inner = [float(o.inner_rtol)] if inner_rtol is None else [float(v) for v in inner_rtol]
+        ir = None if inner_rtol is None else (C.c_double * len(inner))(*inner)
         rep = CSolverTuneReport()
         self._stream()
         self._internal_workspace()
         self._check(self.L.fwi_autotune_solver(self.h, prob.ref(), _ptr(c), _ptr(alpha), _ptr(d_obs), C.byref(o),
-                                               mr, len(max_rhs), rs, len(restart), reps, C.byref(rep)))
-        ms = {(int(a), int(b)): rep.ms[i][j] for i, a in enumerate(max_rhs) for j, b in enumerate(restart)}
-        return {"max_rhs": rep.max_rhs, "restart": rep.restart, "ms": ms}
+                                               mr, len(max_rhs), rs, len(restart), ir, len(inner), reps,
+                                               C.byref(rep)))
+        ms = {(int(a), int(b), t): rep.ms[h][i][j] for h, t in enumerate(inner)
+              for i, a in enumerate(max_rhs) for j, b in enumerate(restart)}
+        return {"max_rhs": rep.max_rhs, "restart": rep.restart, "inner_rtol": rep.inner_rtol, "ms": ms}
 
     def set_addressing(self, wide):
         """wide=True forces the 64-bit addressing path of the strided FFT passes

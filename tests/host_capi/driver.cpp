@@ -260,14 +260,26 @@ void every_entry(fwi_ctx* ctx, int dim, bool planes = false) {
       const int rs[2] = {8, 16};
       fwi_solver_tune_report srep{};
       fwi_solve_opts ot = opts(prec, 8);
-      check(fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, mr, 3, rs, 2, 1, &srep), "autotune_solver", ctx);
-      if (srep.restart != 8 && srep.restart != 16) {
-        std::fprintf(stderr, "[driver] autotune_solver chose restart %d\n", srep.restart);
+      const double ir[2] = {1e-3, 1e-4};
+      check(fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, mr, 3, rs, 2, ir, 2, 1, &srep), "autotune_solver", ctx);
+      if ((srep.restart != 8 && srep.restart != 16) || (srep.inner_rtol != ir[0] && srep.inner_rtol != ir[1])) {
+        std::fprintf(stderr, "[driver] autotune_solver chose restart %d, inner %g\n", srep.restart, srep.inner_rtol);
+        g_fail = 1;
+      }
+      check(fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, mr, 1, rs, 1, nullptr, 0, 1, &srep), "autotune_solver",
+            ctx);
+      if (srep.inner_rtol != ot.inner_rtol) {
+        std::fprintf(stderr, "[driver] autotune_solver without inner candidates chose %g\n", srep.inner_rtol);
         g_fail = 1;
       }
       const int bad[1] = {-1};
-      if (fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, bad, 1, rs, 2, 1, &srep) != FWI_E_INVAL) {
+      if (fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, bad, 1, rs, 2, nullptr, 0, 1, &srep) != FWI_E_INVAL) {
         std::fprintf(stderr, "[driver] negative batch cap not refused\n");
+        g_fail = 1;
+      }
+      const double bad_ir[1] = {2.0};
+      if (fwi_autotune_solver(ctx, &q.p, c, a, dobs, &ot, mr, 1, rs, 1, bad_ir, 1, 1, &srep) != FWI_E_INVAL) {
+        std::fprintf(stderr, "[driver] inner tolerance above 1 not refused\n");
         g_fail = 1;
       }
     }

@@ -334,30 +334,47 @@ def test_adjoint_gradient_vs_oracle(ctx, F, prec, recip):
 
 
 def test_solver_autotune_picks_a_candidate_and_keeps_parity(ctx, F):
-    """Batch-shape / restart tuning of the gradient step: the chosen pair is one
-    of the candidates with the smallest time, the context's own results are not
-    changed by tuning, and the gradient with the chosen options still matches
-    the oracle."""
+    """Batch-shape / restart / inner-tolerance tuning of the gradient step: the
+    chosen combination is one of the candidates with the smallest time, the
+    context's own results are not changed by tuning, and the gradient with the
+    chosen options still matches the oracle, in FP64 and in complex64 with
+    FP64-residual refinement (where the inner tolerance is a candidate too)."""
     p = W.small2d(seed=29, nx=30, nz=26, ne=6, nf=3)
     d_obs, _, _ = O.forward(p.extra["c_obs"], p.alpha, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
     c, a, d = dev(p.c, torch.float64), dev(p.alpha, torch.float64), dev(d_obs)
+    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
     base = F.SolveOptions(precision=0, rtol=1e-12)
     before = ctx.adjoint_gradient(p, c, a, d, base)[1].clone()
     caps, restarts = (0, p.ne, 2 * p.ne), (8, 16)
     r = ctx.autotune_solver(p, c, a, d, base, max_rhs=caps, restart=restarts, reps=1)
-    assert set(r["ms"]) == {(m, k) for m in caps for k in restarts}
+    assert set(r["ms"]) == {(m, k, base.inner_rtol) for m in caps for k in restarts}
     assert all(math.isfinite(t) and t > 0 for t in r["ms"].values())
-    assert r["ms"][(r["max_rhs"], r["restart"])] == min(r["ms"].values())
+    assert r["ms"][(r["max_rhs"], r["restart"], r["inner_rtol"])] == min(r["ms"].values())
     after = ctx.adjoint_gradient(p, c, a, d, base)[1]
     assert torch.equal(before, after)
     tuned = F.SolveOptions(precision=0, rtol=1e-12, max_rhs=r["max_rhs"], restart=r["restart"])
     phi, gm, gc, ga, st = ctx.adjoint_gradient(p, c, a, d, tuned)
-    rphi, rg, rgc, rga, _ = O.adjoint_gradient(p.c, p.alpha, d_obs, 2, p.nx, 1, p.nz, p.dx, p.c0, p.freqs, p.elems)
     assert abs(phi - rphi) < 1e-10 * rphi
     assert relerr(host(gm), rg) < 1e-9
     assert relerr(host(gc), rgc) < 1e-9
+    # complex64 inner solves: inner tolerance candidates as well
+    base32 = F.SolveOptions(precision=1, rtol=1e-8)
+    inners = (1e-3, 1e-5, 1e-8)
+    r = ctx.autotune_solver(p, c, a, d, base32, max_rhs=(0, p.ne), restart=(8,), inner_rtol=inners, reps=1)
+    assert set(r["ms"]) == {(m, 8, t) for m in (0, p.ne) for t in inners}
+    assert r["inner_rtol"] in inners and r["restart"] == 8 and r["max_rhs"] in (0, p.ne)
+    assert r["ms"][(r["max_rhs"], r["restart"], r["inner_rtol"])] == min(r["ms"].values())
+    tuned = F.SolveOptions(precision=1, rtol=1e-8, max_rhs=r["max_rhs"], restart=8, inner_rtol=r["inner_rtol"])
+    phi, gm, gc, ga, st = ctx.adjoint_gradient(p, c, a, d, tuned)
+    assert st["unconverged"] == 0 and st["max_rel_residual"] <= 1e-8
+    assert abs(phi - rphi) < 1e-6 * rphi
+    assert relerr(host(gm), rg) < 1e-6
     with pytest.raises(RuntimeError):
         ctx.autotune_solver(p, c, a, d, base, max_rhs=caps, restart=(12,))
+    with pytest.raises(RuntimeError):
+        ctx.autotune_solver(p, c, a, d, base32, max_rhs=caps, restart=(8,), inner_rtol=(1.5,))
+    with pytest.raises(RuntimeError):
+        ctx.autotune_solver(p, c, a, d, base32, max_rhs=caps, restart=(8,), inner_rtol=(1e-3, 1e-4, 1e-5, 1e-6))
 
 
 @pytest.mark.parametrize("prec", [0, 1])
