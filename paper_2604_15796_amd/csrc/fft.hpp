@@ -65,6 +65,13 @@ __host__ __device__ constexpr int plan_radix(int L, int s, bool big = false) {
        : L == 768 ? (s == 1 ? 8 : s == 2 ? 4 : 3)
        : L == 1024 ? (s == 1 ? 8 : 4) : 0;
 }
+// Twiddle power tables (convolution passes): a twiddled stage with radix R
+// stores the powers w^1 .. w^(R-1) of each butterfly class k < Ns in a row of
+// pow_stride(R) slots (R - 1 rounded up to a power of two, so rows stay
+// aligned for 16-byte LDS loads).
+__host__ __device__ constexpr int pow_stride(int R) {
+  return R <= 2 ? 1 : R <= 3 ? 2 : R <= 5 ? 4 : R <= 9 ? 8 : R <= 17 ? 16 : 32;
+}
 // radix of stage s of the plan in direction dir (0: forward order, 1: reversed)
 __host__ __device__ constexpr int stage_radix(int L, int dir, int s, bool big = false) {
   return dir == 0 ? plan_radix(L, s, big) : plan_radix(L, plan_stages(L, big) - 1 - s, big);
@@ -322,12 +329,16 @@ struct LineCfg {
 // HIN: legs R/2 .. R-1 are zero and not loaded (first stage over zero-padded
 // data). HOUT: only legs 0 .. R/2-1 are stored (last stage of a cropped
 // transform), so the rest of the butterfly is never computed.
-template <class C, int R, int Ns, bool SYNC, bool HIN, bool HOUT, class Src, class Snk>
-__device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __restrict__ tw, Src&& src, Snk&& snk) {
+// PT: the stage's twiddle powers come from a power table in LDS (pt, see
+// pow_stride), not from one table value and a product tree.
+template <class C, int R, int Ns, bool SYNC, bool HIN, bool HOUT, bool PT = false, class Src, class Snk>
+__device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __restrict__ tw, Src&& src, Snk&& snk,
+                                          const cplx<typename C::T>* pt = nullptr) {
   using T = typename C::T;
   constexpr int L = C::L, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
   static_assert(!HIN || Ns == 1, "zero legs only in a first stage");
   static_assert(!HOUT || Ns * R == L, "cropping only in a last stage");
+  static_assert(!PT || R <= 8, "power tables for radices up to 8");
   constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
   constexpr bool RD_SPLIT = (L / R) % 8 == 0;
   constexpr bool WR_SPLIT = Ns % 8 == 0 || (Ns == 1 && R % 8 == 0);
@@ -341,7 +352,7 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
 #pragma unroll
       for (int r = 0; r < RIN; ++r)
         v[t][r] = RD_SPLIT ? stage_load(src, line, j, r * (L / R), t, r) : stage_load(src, line, j + r * (L / R), 0, t, r);
-      if constexpr (Ns > 1) {
+      if constexpr (Ns > 1 && !PT) {
         const int k = j % Ns;
         tw1[t] = tw[k * (L / (Ns * R))];
         if constexpr (R > 8) tw8[t] = tw[8 * k * (L / (Ns * R))];
@@ -355,7 +366,11 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
       int line, j;
       C::template split<R>(t, line, j);
       const int k = j % Ns;
-      if constexpr (Ns > 1) {
+      if constexpr (Ns > 1 && PT) {
+        const cplx<T>* pw = pt + k * pow_stride(R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[t][r] = v[t][r] * pw[r - 1];
+      } else if constexpr (Ns > 1) {
         cplx<T> w1 = tw1[t];
         if (sgn > 0) w1.y = -w1.y;
         if constexpr (R > 8) {
@@ -382,8 +397,9 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
 // multiply by the kernel spectrum gh(t, r, line, p), first inverse stage
 // (radix R, Ns = 1). The last forward stage leaves butterfly j holding points
 // j + r L/R, which are exactly the inputs of inverse butterfly j.
-template <class C, int R, class Src, class Gh, class Snk>
-__device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restrict__ tw, Src&& src, Gh&& gh, Snk&& snk) {
+template <class C, int R, bool PT = false, class Src, class Gh, class Snk>
+__device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restrict__ tw, Src&& src, Gh&& gh, Snk&& snk,
+                                             const cplx<typename C::T>* pt = nullptr) {
   using T = typename C::T;
   constexpr int L = C::L, Ns = L / R, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
   constexpr bool RD_SPLIT = (L / R) % 8 == 0;
@@ -397,8 +413,10 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
 #pragma unroll
       for (int r = 0; r < R; ++r)
         v[t][r] = RD_SPLIT ? stage_load(src, line, j, r * (L / R), t, r) : stage_load(src, line, j + r * (L / R), 0, t, r);
-      tw1[t] = tw[j];  // k = j < Ns, step 1
-      if constexpr (R > 8) tw8[t] = tw[8 * j];
+      if constexpr (!PT) {
+        tw1[t] = tw[j];  // k = j < Ns, step 1
+        if constexpr (R > 8) tw8[t] = tw[8 * j];
+      }
     }
   }
   __syncthreads();
@@ -407,8 +425,16 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
     if (NB % C::NT == 0 || (int)threadIdx.x + t * C::NT < NB) {
       int line, j;
       C::template split<R>(t, line, j);
-      if constexpr (R > 8) apply_twiddles_big<R>(v[t], tw1[t], tw8[t]);
-      else apply_twiddles<R>(v[t], tw1[t]);
+      if constexpr (PT) {
+        static_assert(R <= 8, "power tables for radices up to 8");
+        const cplx<T>* pw = pt + j * pow_stride(R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[t][r] = v[t][r] * pw[r - 1];
+      } else if constexpr (R > 8) {
+        apply_twiddles_big<R>(v[t], tw1[t], tw8[t]);
+      } else {
+        apply_twiddles<R>(v[t], tw1[t]);
+      }
       dft<R>(v[t], -1);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[t][r] = v[t][r] * gh(t, r, line, j + r * Ns);
@@ -423,25 +449,68 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
 }
 
 // LDS -> LDS stages s .. S-2 of direction dir (the last stage is done by the caller).
-template <class C, int dir, int s, int Ns>
-__device__ __forceinline__ void fft_mid_stages(int sgn, const cplx<typename C::T>* __restrict__ tw,
-                                               cplx<typename C::T>* sh) {
-  constexpr int S = plan_stages(C::L, C::BIG);
-  if constexpr (s < S - 1) {
-    constexpr int R = stage_radix(C::L, dir, s, C::BIG);
-    fft_stage<C, R, Ns, true, false, false>(
-        sgn, tw, [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; },
-        [&](int line, int pb, int ro, cplx<typename C::T> v) { sh[C::lds(line, pb, ro)] = v; });
-    __syncthreads();
-    fft_mid_stages<C, dir, s + 1, Ns * R>(sgn, tw, sh);
-  }
-}
-
 // Ns before stage s of direction dir
 template <int L, bool BIG, int dir, int s>
 __host__ __device__ constexpr int ns_before() {
   if constexpr (s == 0) return 1;
   else return ns_before<L, BIG, dir, s - 1>() * stage_radix(L, dir, s - 1, BIG);
+}
+
+// Power table of a convolution (forward plan, then the reversed inverse
+// plan): the rows of stage (dir, s), s >= 1, start at pow_off<L, BIG, dir,
+// s>() (multiples of 8 slots), one row per butterfly class k < Ns; row k holds
+// w^(k r L / (Ns R)) for r = 1 .. R-1 with the stage's sign (conjugated in
+// the inverse plan). pow_off<L, BIG, 1, S>() is the table size.
+template <int L, bool BIG, int dir, int s>
+__host__ __device__ constexpr int pow_off() {
+  if constexpr (dir == 0 && s <= 1) {
+    return 0;
+  } else if constexpr (dir == 1 && s <= 1) {
+    return pow_off<L, BIG, 0, plan_stages(L, BIG)>();
+  } else {
+    constexpr int size = ns_before<L, BIG, dir, s - 1>() * pow_stride(stage_radix(L, dir, s - 1, BIG));
+    return (pow_off<L, BIG, dir, s - 1>() + size + 7) / 8 * 8;
+  }
+}
+template <class C>
+__host__ __device__ constexpr int pow_table_size() {
+  return pow_off<C::L, C::BIG, 1, plan_stages(C::L, C::BIG)>();
+}
+template <class C, int dir, int s>
+__device__ __forceinline__ void pow_fill(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* tab) {
+  constexpr int S = plan_stages(C::L, C::BIG);
+  if constexpr (s < S) {
+    constexpr int R = stage_radix(C::L, dir, s, C::BIG), Ns = ns_before<C::L, C::BIG, dir, s>();
+    constexpr int SR = pow_stride(R), OFF = pow_off<C::L, C::BIG, dir, s>(), STEP = C::L / (Ns * R);
+    // one slot per thread, so that no wave holds the others at the first
+    // barrier (a thread per row, filling R - 1 slots, measured slower)
+    for (int i = (int)threadIdx.x; i < Ns * SR; i += C::NT) {
+      const int k = i / SR, r = i % SR + 1;
+      if (r < R) {
+        cplx<typename C::T> w = tw[k * r * STEP];  // k r STEP < L
+        if (dir == 1) w.y = -w.y;
+        tab[OFF + i] = w;
+      }
+    }
+    pow_fill<C, dir, s + 1>(tw, tab);
+  }
+}
+
+// LDS -> LDS stages s .. S-2 of direction dir (the last stage is done by the
+// caller); PT: twiddle powers from the power table tab.
+template <class C, int dir, int s, int Ns, bool PT = false>
+__device__ __forceinline__ void fft_mid_stages(int sgn, const cplx<typename C::T>* __restrict__ tw,
+                                               cplx<typename C::T>* sh, const cplx<typename C::T>* tab = nullptr) {
+  constexpr int S = plan_stages(C::L, C::BIG);
+  if constexpr (s < S - 1) {
+    constexpr int R = stage_radix(C::L, dir, s, C::BIG);
+    fft_stage<C, R, Ns, true, false, false, PT>(
+        sgn, tw, [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; },
+        [&](int line, int pb, int ro, cplx<typename C::T> v) { sh[C::lds(line, pb, ro)] = v; },
+        PT ? tab + pow_off<C::L, C::BIG, dir, s>() : nullptr);
+    __syncthreads();
+    fft_mid_stages<C, dir, s + 1, Ns * R, PT>(sgn, tw, sh, tab);
+  }
 }
 
 // Full forward/inverse transform: first stage from src (global), middle stages
@@ -484,25 +553,34 @@ struct ConvMidMap {
 // Convolution along a line: forward (from src), multiply by gh, inverse (to
 // snk). The input occupies at most the first half of the line and only the
 // first half of the output is kept (linear convolution by zero padding).
-template <class C, class Src, class Gh, class Snk>
+// PT: the twiddle powers of every twiddled stage come from a power table that
+// the workgroup builds in LDS at tab (pow_table_size<C>() values) while the
+// first stage loads its data; the first barrier publishes it.
+template <class C, bool PT = false, class Src, class Gh, class Snk>
 __device__ __forceinline__ void fft_line_convolve(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* sh,
-                                                  Src&& src, Gh&& gh, Snk&& snk) {
+                                                  Src&& src, Gh&& gh, Snk&& snk, cplx<typename C::T>* tab = nullptr) {
   using T = typename C::T;
   constexpr int S = plan_stages(C::L, C::BIG);
   constexpr int R0 = stage_radix(C::L, 0, 0, C::BIG);
+  static_assert(!PT || !C::BIG, "power tables for the radix-8/6/4/3 plans");
   auto to_lds = [&](int line, int pb, int ro, cplx<T> v) { sh[C::lds(line, pb, ro)] = v; };
   auto from_lds = [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; };
+  if constexpr (PT) {
+    pow_fill<C, 0, 1>(tw, tab);
+    pow_fill<C, 1, 1>(tw, tab);
+  }
   fft_stage<C, R0, 1, false, true, false>(-1, tw, src, to_lds);
   __syncthreads();
-  fft_mid_stages<C, 0, 1, R0>(-1, tw, sh);
+  fft_mid_stages<C, 0, 1, R0, PT>(-1, tw, sh, tab);
   constexpr int RL = stage_radix(C::L, 0, S - 1, C::BIG);
-  fft_conv_mid<C, RL>(tw, from_lds, gh, to_lds);
+  fft_conv_mid<C, RL, PT>(tw, from_lds, gh, to_lds, PT ? tab + pow_off<C::L, C::BIG, 0, S - 1>() : nullptr);
   __syncthreads();
   // inverse plan is the reverse of the forward plan; its first stage (radix RL) is done
-  fft_mid_stages<C, 1, 1, RL>(+1, tw, sh);
+  fft_mid_stages<C, 1, 1, RL, PT>(+1, tw, sh, tab);
   constexpr int RI = stage_radix(C::L, 1, S - 1, C::BIG);
   constexpr int NsI = ns_before<C::L, C::BIG, 1, S - 1>();
-  fft_stage<C, RI, NsI, false, false, true>(+1, tw, from_lds, snk);
+  fft_stage<C, RI, NsI, false, false, true, PT>(+1, tw, from_lds, snk,
+                                                PT ? tab + pow_off<C::L, C::BIG, 1, S - 1>() : nullptr);
 }
 
 }  // namespace fwi

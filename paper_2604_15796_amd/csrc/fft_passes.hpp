@@ -456,6 +456,25 @@ __device__ __forceinline__ void conv_item(long nplanes, int& tile, long& plane) 
 
 constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolution pass
 
+// The complex64 convolution keeps its twiddle powers in an LDS table (the pass
+// is bound by vector issue; the table replaces the product trees, about a
+// sixth of its instructions) when the plan is a radix-8/6/4/3 one and the
+// table does not cost a workgroup per compute unit (160 KB of LDS, 32 wave
+// slots per compute unit).
+template <class C>
+constexpr bool conv_pow_table() {
+  if constexpr (sizeof(typename C::T) != 4 || C::BIG) {
+    return false;
+  } else {
+    constexpr long kLds = 160 * 1024, es = sizeof(cplx<typename C::T>);
+    constexpr long slots = 32 / (C::NT / 64);
+    constexpr long base = C::LDS_ELEMS * es, with = base + pow_table_size<C>() * es;
+    constexpr long wg0 = kLds / base < slots ? kLds / base : slots;
+    constexpr long wg1 = kLds / with < slots ? kLds / with : slots;
+    return wg1 == wg0;
+  }
+}
+
 // MODE 0 forward, 1 inverse, 2 convolution. HALF: the input occupies at most
 // the first half of a line (mode 0), only the first half of the output is kept
 // (mode 1); the convolution always has both. WIDE: 64-bit addressing for
@@ -464,7 +483,8 @@ constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolutio
 template <typename T, int L, int NLV, int NTV, int MODE, bool HALF, bool WIDE>
 __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
   using C = LineCfg<T, L, NLV, NTV, true>;
-  __shared__ cplx<T> sh[C::LDS_ELEMS];
+  constexpr bool PT = MODE == 2 && conv_pow_table<C>();
+  __shared__ cplx<T> sh[C::LDS_ELEMS + (PT ? pow_table_size<C>() : 0)];  // lines, then the power table
   constexpr unsigned ES = sizeof(cplx<T>);
   int tile = 0;
   long plane_tm = 0;  // tile-major convolution: the workgroup's plane
@@ -526,13 +546,13 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
           const int p = pb + ro;
           if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
         };
-        fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr);
       } else {
         const BufView iv(a.in + plane * a.in_ps, (unsigned)a.lin * ps8);
         const BufView ov(a.out + plane * a.out_ps, (unsigned)a.lout * ps8);
         auto src = [&](int, int pb, int ro) { return iv.ld<T>(loff + (unsigned)(pb + ro) * ps8); };
         auto snk = [&](int, int pb, int ro, cplx<T> v) { ov.st<T>(loff + (unsigned)(pb + ro) * ps8, v); };
-        fft_line_convolve<C>(a.tw, sh, src, gh, snk);
+        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr);
       }
       __syncthreads();  // LDS is reused by the next plane
     }

@@ -46,7 +46,8 @@ void run_workgroup(Body body) {
   for (auto& t : th) t.join();
 }
 
-// MODE 0: forward over a zero-padded line, 1: inverse cropped to half, 2: convolution
+// MODE 0: forward over a zero-padded line, 1: inverse cropped to half, 2: convolution,
+// 3: convolution with the twiddle powers from a power table (radix-8/6/4/3 plans)
 template <typename T, int L, int NL, int NT, bool LF, int MODE>
 double check(unsigned seed) {
   using C = LineCfg<T, L, NL, NT, LF>;
@@ -56,6 +57,7 @@ double check(unsigned seed) {
   const int lout = MODE == 0 ? L : L / 2 - (int)(seed % 2);  // ragged crop
   const cplx<T> fill = mk((T)-7, (T)-7);
   std::vector<cplx<T>> in(NL * L), out(NL * L, fill), gh(NL * L), sh(C::LDS_ELEMS);
+  std::vector<cplx<T>> tab(MODE == 3 ? pow_table_size<C>() : 1, fill);  // the workgroup's LDS table
   for (auto& v : in) v = mk((T)nd(g), (T)nd(g));
   for (auto& v : gh) v = mk((T)nd(g), (T)nd(g));
   const auto tw = twiddle_table<T>(L);
@@ -81,7 +83,8 @@ double check(unsigned seed) {
           if (Map::at(t, r, line, p)) gpre[t][r] = gh[line * L + p];
         }
       auto ghf = [&](int t, int r, int, int) { return gpre[t][r]; };
-      fft_line_convolve<C>(tw.data(), sh.data(), src, ghf, snk);
+      if constexpr (MODE == 3) fft_line_convolve<C, true>(tw.data(), sh.data(), src, ghf, snk, tab.data());
+      else fft_line_convolve<C>(tw.data(), sh.data(), src, ghf, snk);
     }
   });
   double err = 0, nrm = 0;
@@ -93,7 +96,7 @@ double check(unsigned seed) {
       y = direct_dft(x, -1);
     } else if (MODE == 1) {
       y = direct_dft(x, +1);
-    } else {
+    } else {  // MODE 2, 3
       auto X = direct_dft(x, -1);
       for (int p = 0; p < L; ++p) X[p] *= cld(gh[l * L + p].x, gh[l * L + p].y);
       y = direct_dft(X, +1);
@@ -113,10 +116,12 @@ void all_modes(const char* name) {
   using C = LineCfg<T, L, NL, NT, LF>;
   const double e0 = check<T, L, NL, NT, LF, 0>(L + NL), e1 = check<T, L, NL, NT, LF, 1>(L + 2 * NL),
                e2 = check<T, L, NL, NT, LF, 2>(L + 3 * NL);
+  double e3 = 0;
+  if constexpr (!C::BIG) e3 = check<T, L, NL, NT, LF, 3>(L + 5 * NL);
   const double tol = sizeof(T) == 4 ? 2e-6 : 1e-14;
-  const bool ok = e0 < tol && e1 < tol && e2 < tol;
-  std::printf("%-6s L=%4d NL=%2d NT=%3d LF=%d BIG=%d fwd %.2e inv %.2e conv %.2e %s\n", name, L, NL, NT, (int)LF,
-              (int)C::BIG, e0, e1, e2, ok ? "ok" : "FAIL");
+  const bool ok = e0 < tol && e1 < tol && e2 < tol && e3 < tol;
+  std::printf("%-6s L=%4d NL=%2d NT=%3d LF=%d BIG=%d fwd %.2e inv %.2e conv %.2e table %.2e %s\n", name, L, NL, NT,
+              (int)LF, (int)C::BIG, e0, e1, e2, e3, ok ? "ok" : "FAIL");
 }
 
 #define FWI_EMU_LENGTHS(T, NL, NT, LF)                                                                      \

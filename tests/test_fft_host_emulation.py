@@ -5,8 +5,11 @@ stand-in for the HIP runtime header, one workgroup running as host threads
 with a shared barrier, and every FFT length, plan family (radix 8/6/4/3 and
 radix 16/32), line layout and precision is compared with a direct DFT:
 forward transforms of zero-padded lines, inverse transforms cropped to half a
-line, and the fused convolution (forward, multiply, inverse). This checks the
-index arithmetic of the Stockham stages without a GPU.
+line, and the fused convolution (forward, multiply, inverse), with the
+twiddle powers built per butterfly and read from a per-stage power table.
+This checks the index arithmetic of the Stockham stages without a GPU; the
+build uses the address sanitizer, and every array (the LDS image and the
+power table included) is sized exactly, so an access out of bounds fails.
 """
 import os
 import pathlib
@@ -23,9 +26,9 @@ CSRC = ROOT / "paper_2604_15796_amd" / "csrc"
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 def test_line_fft_plans_on_host(tmp_path):
     exe = tmp_path / "fft_plans"
-    subprocess.run(["g++", "-std=c++20", "-O1", f"-I{EMU}", f"-I{CSRC}", str(EMU / "fft_plans.cpp"),
-                    "-o", str(exe), "-lpthread"], check=True, timeout=600)
-    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=600).stdout
+    subprocess.run(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-I{EMU}", f"-I{CSRC}",
+                    str(EMU / "fft_plans.cpp"), "-o", str(exe), "-lpthread"], check=True, timeout=600)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=900).stdout
     lines = [l for l in out.splitlines() if l.strip()]
     assert len(lines) == 40, out
     bad = [l for l in lines if not l.endswith(" ok")]
