@@ -34,10 +34,13 @@ __device__ __forceinline__ auto stage_load(Src& src, int line, int pb, int ro, i
 
 // ---------------------------------------------------------------- plans ---
 // Two plan families: radices 8/6/4/3 (any tile), and for tiles holding at
-// least big_ppt(L) points per thread, radices 16/32 with fewer stages (fewer
-// LDS exchanges and barriers).
-__host__ __device__ constexpr int big_ppt(int L) {
-  return L == 512 || L == 1024 ? 32 : (L == 128 || L == 256 || L == 768) ? 16 : 1 << 30;
+// least big_ppt(L) points per thread, radices 32/16/12 with fewer stages
+// (fewer LDS exchanges and barriers, fewer twiddled points). Length 192 has
+// a 16 x 12 plan for the strided (line-fastest) tiles only.
+__host__ __device__ constexpr int big_ppt(int L, bool lf = true) {
+  return L == 512 || L == 1024 ? 32
+       : (L == 128 || L == 256 || L == 768) ? 16
+       : (L == 192 && lf) ? 12 : 1 << 30;
 }
 __host__ __device__ constexpr int plan_stages(int L, bool big = false) {
   return big ? (L == 768 ? 3 : 2)
@@ -48,6 +51,7 @@ __host__ __device__ constexpr int plan_stages(int L, bool big = false) {
 __host__ __device__ constexpr int plan_radix(int L, int s, bool big = false) {
   // forward plan, stage s
   return big ? (L == 128 ? (s == 0 ? 16 : 8)
+              : L == 192 ? (s == 0 ? 16 : 12)
               : L == 256 ? 16
               : L == 512 ? (s == 0 ? 16 : 32)
               : L == 768 ? (s == 2 ? 3 : 16)
@@ -139,6 +143,25 @@ __device__ __forceinline__ void dft(cplx<T>* v, int sgn) {
     v[4] = e[1] - t1;
     v[2] = e[2] + t2;
     v[5] = e[2] - t2;
+  } else if constexpr (R == 12) {
+    // prime-factor split 12 = 3 x 4 (Good-Thomas): input n = 4 n1 + 3 n2,
+    // output k = 4 k1 + 9 k2 (mod 12), i.e. k = k1 mod 3 and k = k2 mod 4, so
+    // the kernel exp(sgn 2 pi i n k / 12) factors into a 3-point and a
+    // 4-point one with no twiddles in between
+    cplx<T> a[4][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = v[(4 * n1 + 3 * n2) % 12];
+      dft<3>(a[n2], sgn);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cplx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      dft<4>(b, sgn);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = b[k2];
+    }
   } else if constexpr (R == 16) {
     dft_ct<4, 4>(v, sgn);
   } else if constexpr (R == 32) {
@@ -248,7 +271,7 @@ __device__ __forceinline__ void apply_twiddles(cplx<T>* v, cplx<T> w1) {
   }
 }
 
-// Radix 16 / 32: w^r = (w^8)^(r div 8) w^(r mod 8) from two table values.
+// Radix 12 / 16 / 32: w^r = (w^8)^(r div 8) w^(r mod 8) from two table values.
 template <int R, typename T>
 __device__ __forceinline__ void apply_twiddles_big(cplx<T>* v, cplx<T> w1, cplx<T> w8) {
   cplx<T> p[8];
@@ -259,8 +282,8 @@ __device__ __forceinline__ void apply_twiddles_big(cplx<T>* v, cplx<T> w1, cplx<
   p[5] = p[4] * w1;
   p[6] = p[4] * p[2];
   p[7] = p[4] * p[3];
-  cplx<T> q[R / 8];
-  if constexpr (R / 8 > 1) q[1] = w8;
+  cplx<T> q[(R + 7) / 8];
+  if constexpr (R > 8) q[1] = w8;
   if constexpr (R / 8 > 2) {
     q[2] = w8 * w8;
     q[3] = q[2] * w8;
@@ -291,7 +314,7 @@ struct LineCfg {
   static constexpr int L = L_, NL = NL_, NT = NT_;
   static constexpr bool LF = LF_;
   static constexpr int LP = L + L / 8;  // padded line length (points)
-  static constexpr bool BIG = NL * L / NT >= big_ppt(L);  // radix-16/32 plan
+  static constexpr bool BIG = NL * L / NT >= big_ppt(L, LF);  // radix-32/16/12 plan
   static constexpr int LDS_ELEMS = NL * LP;
   __device__ static __forceinline__ int lds(int line, int p) {
     return LF ? (p + (p >> 3)) * NL + line : line * LP + p + (p >> 3);
@@ -338,7 +361,7 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
   constexpr int L = C::L, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
   static_assert(!HIN || Ns == 1, "zero legs only in a first stage");
   static_assert(!HOUT || Ns * R == L, "cropping only in a last stage");
-  static_assert(!PT || R <= 8, "power tables for radices up to 8");
+  static_assert(!PT || R <= 16, "power tables for radices up to 16");
   constexpr int RIN = HIN ? R / 2 : R, ROUT = HOUT ? R / 2 : R;
   constexpr bool RD_SPLIT = (L / R) % 8 == 0;
   constexpr bool WR_SPLIT = Ns % 8 == 0 || (Ns == 1 && R % 8 == 0);
@@ -426,7 +449,7 @@ __device__ __forceinline__ void fft_conv_mid(const cplx<typename C::T>* __restri
       int line, j;
       C::template split<R>(t, line, j);
       if constexpr (PT) {
-        static_assert(R <= 8, "power tables for radices up to 8");
+        static_assert(R <= 16, "power tables for radices up to 16");
         const cplx<T>* pw = pt + j * pow_stride(R);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[t][r] = v[t][r] * pw[r - 1];
@@ -470,6 +493,15 @@ __host__ __device__ constexpr int pow_off() {
   } else {
     constexpr int size = ns_before<L, BIG, dir, s - 1>() * pow_stride(stage_radix(L, dir, s - 1, BIG));
     return (pow_off<L, BIG, dir, s - 1>() + size + 7) / 8 * 8;
+  }
+}
+template <int L, bool BIG, int s = 0>
+__host__ __device__ constexpr int plan_max_radix() {
+  if constexpr (s >= plan_stages(L, BIG)) {
+    return 0;
+  } else {
+    constexpr int r = plan_radix(L, s, BIG), rest = plan_max_radix<L, BIG, s + 1>();
+    return r > rest ? r : rest;
   }
 }
 template <class C>
@@ -562,7 +594,7 @@ __device__ __forceinline__ void fft_line_convolve(const cplx<typename C::T>* __r
   using T = typename C::T;
   constexpr int S = plan_stages(C::L, C::BIG);
   constexpr int R0 = stage_radix(C::L, 0, 0, C::BIG);
-  static_assert(!PT || !C::BIG, "power tables for the radix-8/6/4/3 plans");
+  static_assert(!PT || plan_max_radix<C::L, C::BIG>() <= 16, "power tables for radices up to 16");
   auto to_lds = [&](int line, int pb, int ro, cplx<T> v) { sh[C::lds(line, pb, ro)] = v; };
   auto from_lds = [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; };
   if constexpr (PT) {

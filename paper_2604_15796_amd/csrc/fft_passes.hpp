@@ -458,12 +458,12 @@ constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolutio
 
 // The complex64 convolution keeps its twiddle powers in an LDS table (the pass
 // is bound by vector issue; the table replaces the product trees, about a
-// sixth of its instructions) when the plan is a radix-8/6/4/3 one and the
+// sixth of its instructions) when the plan's radices are at most 16 and the
 // table does not cost a workgroup per compute unit (160 KB of LDS, 32 wave
 // slots per compute unit).
 template <class C>
 constexpr bool conv_pow_table() {
-  if constexpr (sizeof(typename C::T) != 4 || C::BIG) {
+  if constexpr (sizeof(typename C::T) != 4 || plan_max_radix<C::L, C::BIG>() > 16) {
     return false;
   } else {
     constexpr long kLds = 160 * 1024, es = sizeof(cplx<typename C::T>);
