@@ -39,8 +39,8 @@ thread_local int tl_force_wide = 0;
 thread_local int tl_xy_off = 0;
 
 int default_variant(int pass, bool dbl, int L) {
-  (void)L;
   if (pass == PK_ROW_FWD || pass == PK_ROW_INV) return 0;  // 2048 points per workgroup
+  if (pass == PK_CONV && L == 192) return 1;                 // (16, 256): the radix 16 x 12 plan
   if (pass == PK_CONV && !dbl) return 2;                     // (16, 512) columns, threads
   return dbl ? 0 : 1;                                        // (8, 256) / (16, 256)
 }
