@@ -36,10 +36,12 @@ __device__ __forceinline__ auto stage_load(Src& src, int line, int pb, int ro, i
 // Two plan families: radices 8/6/4/3 (any tile), and for tiles holding at
 // least big_ppt(L) points per thread, radices 32/16/12 with fewer stages
 // (fewer LDS exchanges and barriers, fewer twiddled points). Length 192 has
-// a 16 x 12 plan for the strided (line-fastest) tiles only.
+// a 16 x 12 plan for the strided (line-fastest) tiles only; length 768 an
+// 8 x 8 x 12 plan (three stages instead of 8 x 8 x 4 x 3).
 __host__ __device__ constexpr int big_ppt(int L, bool lf = true) {
   return L == 512 || L == 1024 ? 32
-       : (L == 128 || L == 256 || L == 768) ? 16
+       : (L == 128 || L == 256) ? 16
+       : L == 768 ? 12
        : (L == 192 && lf) ? 12 : 1 << 30;
 }
 __host__ __device__ constexpr int plan_stages(int L, bool big = false) {
@@ -54,7 +56,7 @@ __host__ __device__ constexpr int plan_radix(int L, int s, bool big = false) {
               : L == 192 ? (s == 0 ? 16 : 12)
               : L == 256 ? 16
               : L == 512 ? (s == 0 ? 16 : 32)
-              : L == 768 ? (s == 2 ? 3 : 16)
+              : L == 768 ? (s == 2 ? 12 : 8)
               : L == 1024 ? 32 : 0)
        : s == 0 ? 8
        : L == 32 ? 4

@@ -136,7 +136,7 @@ int main() {
   FWI_EMU_LENGTHS(float, 4, 256, false);   // row passes
   all_modes<float, 512, 16, 256, false>("float");   // row pass, radix-16/32 plan
   all_modes<float, 128, 32, 256, false>("float");   // radix 16 x 8
-  all_modes<float, 768, 8, 256, false>("float");    // radix 16/16/3, butterflies not a divisor of NT
+  all_modes<float, 768, 8, 256, false>("float");    // radix 8/8/12, butterflies not a divisor of NT
   all_modes<double, 512, 4, 256, true>("double");   // narrow strided tiles
   all_modes<double, 1024, 4, 256, true>("double");
   all_modes<float, 512, 4, 256, true>("float");
