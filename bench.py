@@ -215,7 +215,7 @@ def bench_gradient(args, workload):
         restarts = [restart] if restart is not None else [8, 16, 32]
         inners = [args.rtol, args.rtol / 2] if args.tune_inner else [inner]
         base = fwi.SolveOptions(precision=fwi.FWI_FP32_REFINE, rtol=args.rtol, check_every=args.check_every)
-        r = ctx.autotune_solver(prob, c, a, d_obs, base, max_rhs=caps, restart=restarts, inner_rtol=inners, reps=1)
+        r = ctx.autotune_solver(prob, c, a, d_obs, base, max_rhs=caps, restart=restarts, inner_rtol=inners, reps=2)
         max_rhs, restart, inner = r["max_rhs"], r["restart"], r["inner_rtol"]
         solver_tune = {"chosen": {"max_rhs": max_rhs, "restart": restart, "inner_rtol": inner},
                        "ms_per_step": {f"max_rhs={m},restart={k},inner_rtol={t:g}": round(v, 2)
