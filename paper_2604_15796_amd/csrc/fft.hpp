@@ -355,10 +355,17 @@ struct LineCfg {
 // data). HOUT: only legs 0 .. R/2-1 are stored (last stage of a cropped
 // transform), so the rest of the butterfly is never computed.
 // PT: the stage's twiddle powers come from a power table in LDS (pt, see
-// pow_stride), not from one table value and a product tree.
-template <class C, int R, int Ns, bool SYNC, bool HIN, bool HOUT, bool PT = false, class Src, class Snk>
+// pow_stride), not from one table value and a product tree. hook() runs after
+// the stage has issued its loads and before it waits for them: further loads
+// issued there (a prefetch) are in flight with the stage's own and are not
+// waited for by its butterflies.
+struct NoHook {
+  __device__ void operator()() const {}
+};
+template <class C, int R, int Ns, bool SYNC, bool HIN, bool HOUT, bool PT = false, class Src, class Snk,
+          class Hook = NoHook>
 __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __restrict__ tw, Src&& src, Snk&& snk,
-                                          const cplx<typename C::T>* pt = nullptr) {
+                                          const cplx<typename C::T>* pt = nullptr, Hook&& hook = Hook()) {
   using T = typename C::T;
   constexpr int L = C::L, NB = C::NL * (L / R), TT = (NB + C::NT - 1) / C::NT;
   static_assert(!HIN || Ns == 1, "zero legs only in a first stage");
@@ -384,6 +391,7 @@ __device__ __forceinline__ void fft_stage(int sgn, const cplx<typename C::T>* __
       }
     }
   }
+  hook();
   if constexpr (SYNC) __syncthreads();
 #pragma unroll
   for (int t = 0; t < TT; ++t) {
@@ -510,23 +518,49 @@ template <class C>
 __host__ __device__ constexpr int pow_table_size() {
   return pow_off<C::L, C::BIG, 1, plan_stages(C::L, C::BIG)>();
 }
-template <class C, int dir, int s>
-__device__ __forceinline__ void pow_fill(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* tab) {
+// The table is built in two halves: pow_load issues the table loads into
+// registers (one slot per thread and iteration, so that no wave carries the
+// whole table; a thread per row, filling R - 1 slots, measured slower), and
+// pow_store writes them to LDS later, so that their latency overlaps other
+// work. pow_regs<C>() registers per thread hold the values in between.
+template <class C, int dir = 0, int s = 1>
+__host__ __device__ constexpr int pow_regs() {
+  constexpr int S = plan_stages(C::L, C::BIG);
+  if constexpr (s < S) {
+    constexpr int slots = ns_before<C::L, C::BIG, dir, s>() * pow_stride(stage_radix(C::L, dir, s, C::BIG));
+    return (slots + C::NT - 1) / C::NT + pow_regs<C, dir, s + 1>();
+  } else if constexpr (dir == 0) {
+    return pow_regs<C, 1, 1>();
+  } else {
+    return 0;
+  }
+}
+template <class C, bool STORE, int dir = 0, int s = 1, int K = 0>
+__device__ __forceinline__ void pow_fill(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* tab,
+                                         cplx<typename C::T>* rv) {
   constexpr int S = plan_stages(C::L, C::BIG);
   if constexpr (s < S) {
     constexpr int R = stage_radix(C::L, dir, s, C::BIG), Ns = ns_before<C::L, C::BIG, dir, s>();
     constexpr int SR = pow_stride(R), OFF = pow_off<C::L, C::BIG, dir, s>(), STEP = C::L / (Ns * R);
-    // one slot per thread, so that no wave holds the others at the first
-    // barrier (a thread per row, filling R - 1 slots, measured slower)
-    for (int i = (int)threadIdx.x; i < Ns * SR; i += C::NT) {
+    constexpr int IT = (Ns * SR + C::NT - 1) / C::NT;
+#pragma unroll
+    for (int q = 0; q < IT; ++q) {
+      const int i = (int)threadIdx.x + q * C::NT;
       const int k = i / SR, r = i % SR + 1;
-      if (r < R) {
-        cplx<typename C::T> w = tw[k * r * STEP];  // k r STEP < L
-        if (dir == 1) w.y = -w.y;
-        tab[OFF + i] = w;
+      const bool used = i < Ns * SR && r < R;
+      if constexpr (STORE) {
+        cplx<typename C::T> w = rv[K + q];
+        if (dir == 1) w.y = -w.y;  // here, not at the load: nothing waits for the load before the store
+        if (used) tab[OFF + i] = w;
+      } else {
+        // unconditional (a spare slot loads entry 0), so that no branch
+        // around a load makes the compiler wait for it early
+        rv[K + q] = tw[used ? k * r * STEP : 0];  // k r STEP < L
       }
     }
-    pow_fill<C, dir, s + 1>(tw, tab);
+    pow_fill<C, STORE, dir, s + 1, K + IT>(tw, tab, rv);
+  } else if constexpr (dir == 0) {
+    pow_fill<C, STORE, 1, 1, K>(tw, tab, rv);
   }
 }
 
@@ -588,22 +622,30 @@ struct ConvMidMap {
 // snk). The input occupies at most the first half of the line and only the
 // first half of the output is kept (linear convolution by zero padding).
 // PT: the twiddle powers of every twiddled stage come from a power table that
-// the workgroup builds in LDS at tab (pow_table_size<C>() values) while the
-// first stage loads its data; the first barrier publishes it.
-template <class C, bool PT = false, class Src, class Gh, class Snk>
+// the workgroup builds in LDS at tab (pow_table_size<C>() values): its loads
+// are issued after the first stage's data loads and stored after that stage's
+// butterflies; the first barrier publishes it. pre() runs at the same point
+// (the caller's prefetch of the kernel spectrum), so neither delays the first
+// stage.
+template <class C, bool PT = false, class Src, class Gh, class Snk, class Pre = NoHook>
 __device__ __forceinline__ void fft_line_convolve(const cplx<typename C::T>* __restrict__ tw, cplx<typename C::T>* sh,
-                                                  Src&& src, Gh&& gh, Snk&& snk, cplx<typename C::T>* tab = nullptr) {
+                                                  Src&& src, Gh&& gh, Snk&& snk, cplx<typename C::T>* tab = nullptr,
+                                                  Pre&& pre = Pre()) {
   using T = typename C::T;
   constexpr int S = plan_stages(C::L, C::BIG);
   constexpr int R0 = stage_radix(C::L, 0, 0, C::BIG);
   static_assert(!PT || plan_max_radix<C::L, C::BIG>() <= 16, "power tables for radices up to 16");
   auto to_lds = [&](int line, int pb, int ro, cplx<T> v) { sh[C::lds(line, pb, ro)] = v; };
   auto from_lds = [&](int line, int pb, int ro) { return sh[C::lds(line, pb, ro)]; };
-  if constexpr (PT) {
-    pow_fill<C, 0, 1>(tw, tab);
-    pow_fill<C, 1, 1>(tw, tab);
-  }
-  fft_stage<C, R0, 1, false, true, false>(-1, tw, src, to_lds);
+  constexpr int NREG = PT ? pow_regs<C>() : 1;
+  cplx<T> rv[NREG];
+  // (the table loads go first: loads complete in issue order, and the table is
+  // stored before the first barrier, the spectrum only used after it)
+  fft_stage<C, R0, 1, false, true, false>(-1, tw, src, to_lds, nullptr, [&] {
+    if constexpr (PT) pow_fill<C, false>(tw, tab, rv);
+    pre();
+  });
+  if constexpr (PT) pow_fill<C, true>(tw, tab, rv);
   __syncthreads();
   fft_mid_stages<C, 0, 1, R0, PT>(-1, tw, sh, tab);
   constexpr int RL = stage_radix(C::L, 0, S - 1, C::BIG);

@@ -510,7 +510,10 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
       const int b = (int)(plane / a.planes_per_rhs);
       if (a.active && !a.active[b]) continue;  // uniform per workgroup
       const int f = a.rhs_freq[b];
-      if (f != fcur) {
+      // the spectrum tile is loaded after the first stage's data (hook of
+      // fft_line_convolve), only when the frequency changes
+      auto prefetch = [&] {
+        if (q > 0 && f == fcur) return;  // the first plane always loads (no branch around its loads)
         if constexpr (WIDE) {
           const cplx<T>* gp = a.ghat + (long)f * a.gstride + line0;
 #pragma unroll
@@ -531,8 +534,7 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
               if (Map::at(t, r, line, p)) gpre[t][r] = gv.ld<T>(loff + (unsigned)p * gps8);
             }
         }
-        fcur = f;
-      }
+      };
       auto gh = [&](int t, int r, int, int) -> cplx<T> { return gpre[t][r]; };
       if constexpr (WIDE) {
         const cplx<T>* ip = a.in + plane * a.in_ps + line0;
@@ -546,14 +548,15 @@ __global__ void __launch_bounds__(NTV) k_strided(StridedArgs<T> a) {
           const int p = pb + ro;
           if (p < a.lout && line < nl) op[p * a.pstride + line] = v;
         };
-        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr);
+        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr, prefetch);
       } else {
         const BufView iv(a.in + plane * a.in_ps, (unsigned)a.lin * ps8);
         const BufView ov(a.out + plane * a.out_ps, (unsigned)a.lout * ps8);
         auto src = [&](int, int pb, int ro) { return iv.ld<T>(loff + (unsigned)(pb + ro) * ps8); };
         auto snk = [&](int, int pb, int ro, cplx<T> v) { ov.st<T>(loff + (unsigned)(pb + ro) * ps8, v); };
-        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr);
+        fft_line_convolve<C, PT>(a.tw, sh, src, gh, snk, PT ? sh + C::LDS_ELEMS : nullptr, prefetch);
       }
+      fcur = f;
       __syncthreads();  // LDS is reused by the next plane
     }
   } else {
