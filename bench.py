@@ -49,11 +49,11 @@ FP32_UNPACKED_PEAK_TFLOPS = 78.6
 # launches the same.
 MEASURED = {"k_row_inv<float, 512, 4, 4>": [{"traffic": 1761.8e6, "batch": 512, "steps": 8}],
             "k_row_fwd<float, 512, 4, true, 3>": [{"traffic": 1793.2e6, "batch": 512, "steps": 8}],
-            "k_strided<float, 512, 16, 512, 2, true, false>": [{"traffic": 897.9e6, "valu_busy": 0.761,
+            "k_strided<float, 512, 16, 512, 2, true, false>": [{"traffic": 897.9e6, "valu_busy": 0.744,
                                                                 "batch": 512, "steps": 8}],
-            "k_strided<float, 192, 16, 256, 2, true, false>": [{"traffic": 5701.3e6, "valu_busy": 0.859,
+            "k_strided<float, 192, 16, 256, 2, true, false>": [{"traffic": 5701.2e6, "valu_busy": 0.781,
                                                                 "batch": 64, "steps": 7},
-                                                               {"traffic": 11426.7e6, "valu_busy": 0.930,
+                                                               {"traffic": 11430.3e6, "valu_busy": 0.853,
                                                                 "batch": 128, "steps": 7}]}
 
 

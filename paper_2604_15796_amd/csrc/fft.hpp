@@ -308,24 +308,28 @@ __device__ __forceinline__ void apply_twiddles_big(cplx<T>* v, cplx<T> w1, cplx<
 //
 // LDS padding: one extra element (row passes) or one extra row of NL elements
 // (strided passes) after every 8 points. The first stage of every plan has
-// radix 8 and writes points 8j + r, so without padding the 64 lanes of a wave
-// would land on a few banks; with it they spread over all of them.
+// radix 8 or more and writes points R j + r, so without padding the 64 lanes
+// of a wave would land on a few banks; with it they spread over all of them.
+// Strided tiles whose row of NL points spans 128 bytes or more need no
+// padding: the 16 lanes served together are the NL lines of one point (or
+// part of them), contiguous in LDS, and every index is then a per-thread base
+// plus a compile-time offset (no per-point padding arithmetic).
 template <typename T_, int L_, int NL_, int NT_, bool LF_>
 struct LineCfg {
   using T = T_;
   static constexpr int L = L_, NL = NL_, NT = NT_;
   static constexpr bool LF = LF_;
-  static constexpr int LP = L + L / 8;  // padded line length (points)
+  static constexpr bool PAD = !LF || NL * (int)sizeof(cplx<T>) < 128;
+  static constexpr int LP = PAD ? L + L / 8 : L;  // padded line length (points)
   static constexpr bool BIG = NL * L / NT >= big_ppt(L, LF);  // radix-32/16/12 plan
   static constexpr int LDS_ELEMS = NL * LP;
-  __device__ static __forceinline__ int lds(int line, int p) {
-    return LF ? (p + (p >> 3)) * NL + line : line * LP + p + (p >> 3);
-  }
-  // LDS index of point pb + ro, where ro is a compile-time offset and ro or pb
-  // is a multiple of 8: the padding term splits and ro becomes an immediate
-  // offset of the LDS instruction.
+  __device__ static __forceinline__ int pad(int p) { return PAD ? p + (p >> 3) : p; }
+  __device__ static __forceinline__ int lds(int line, int p) { return LF ? pad(p) * NL + line : line * LP + pad(p); }
+  // LDS index of point pb + ro, where ro is a compile-time offset and (for a
+  // padded layout) ro or pb is a multiple of 8: the padding term splits and ro
+  // becomes an immediate offset of the LDS instruction.
   __device__ static __forceinline__ int lds(int line, int pb, int ro) {
-    return lds(line, pb) + (ro + (ro >> 3)) * (LF ? NL : 1);
+    return lds(line, pb) + pad(ro) * (LF ? NL : 1);
   }
   // (line, j) of butterfly t of this thread in a radix-R stage; the butterfly
   // index is threadIdx.x + t NT.

@@ -459,8 +459,9 @@ constexpr int CONV_RPW = 1;  // right-hand sides per workgroup in the convolutio
 // The complex64 convolution keeps its twiddle powers in an LDS table (the pass
 // is bound by vector issue; the table replaces the product trees, about a
 // sixth of its instructions) when the plan's radices are at most 16 and the
-// table does not cost a workgroup per compute unit (160 KB of LDS, 32 wave
-// slots per compute unit).
+// table costs no workgroup per compute unit, or one where five or more remain
+// (160 KB of LDS, 32 wave slots per compute unit; measured on the length-192
+// tile: five workgroups with the table beat six without it).
 template <class C>
 constexpr bool conv_pow_table() {
   if constexpr (sizeof(typename C::T) != 4 || plan_max_radix<C::L, C::BIG>() > 16) {
@@ -471,7 +472,7 @@ constexpr bool conv_pow_table() {
     constexpr long base = C::LDS_ELEMS * es, with = base + pow_table_size<C>() * es;
     constexpr long wg0 = kLds / base < slots ? kLds / base : slots;
     constexpr long wg1 = kLds / with < slots ? kLds / with : slots;
-    return wg1 == wg0;
+    return wg1 == wg0 || (wg1 >= 5 && wg1 == wg0 - 1);
   }
 }
 
