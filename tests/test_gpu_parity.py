@@ -224,7 +224,8 @@ def test_operator_depth_192_every_tile_vs_oracle(ctx, F, dim):
     """A depth axis padded to 192 points (the 3D workload's): the 16-line
     tile runs the radix 16 x 12 plan, the others the 8 x 8 x 3 plan, and the
     complex64 convolutions take their twiddle powers from the LDS table.
-    Every tile variant, both precisions, ragged RHS count, against the oracle."""
+    Every tile variant, both precisions, ragged RHS count, and the 16-line
+    tile in its 64-bit addressing form, against the oracle."""
     if dim == 2:
         p = W.small2d(seed=33, nx=36, nz=96, nf=1)
     else:
@@ -235,15 +236,17 @@ def test_operator_depth_192_every_tile_vs_oracle(ctx, F, dim):
     Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), p.dim, p.nx, p.ny, p.nz, p.dx)
     ref = np.stack([O.vie_apply(Gh, m, x[b]).ravel() for b in range(5)])
     try:
-        for v in range(3):
+        for v, wide in ((0, False), (1, False), (2, False), (1, True)):
             ctx.set_tuning(bytes([v] * F.TUNING_BYTES))
+            ctx.set_addressing(wide)  # 64-bit addressing form of the same kernels
             for prec in (0, 1):
                 dt = torch.complex64 if prec else torch.complex128
                 y = host(ctx.apply_operator(p, dev(m), [0] * 5, dev(x.reshape(5, -1), dt), precision=prec))
                 for b in range(5):
-                    assert relerr(y[b], ref[b]) < (2e-6 if prec else 1e-13), (v, prec, b)
+                    assert relerr(y[b], ref[b]) < (2e-6 if prec else 1e-13), (v, wide, prec, b)
     finally:
         ctx.set_tuning(None)
+        ctx.set_addressing(False)
 
 
 def test_operator_and_solve_with_64bit_addressing(ctx, F):
