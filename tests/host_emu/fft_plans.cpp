@@ -142,5 +142,7 @@ int main() {
   all_modes<float, 512, 4, 256, true>("float");
   all_modes<float, 96, 4, 256, true>("float");
   all_modes<double, 192, 16, 256, true>("double");  // radix 16 x 12 in complex128
+  all_modes<float, 256, 32, 256, true>("float");    // 32-column strided tiles of length 256
+  all_modes<float, 256, 32, 512, true>("float");
   return 0;
 }

@@ -30,7 +30,7 @@ def test_line_fft_plans_on_host(tmp_path):
                     str(EMU / "fft_plans.cpp"), "-o", str(exe), "-lpthread"], check=True, timeout=600)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=900).stdout
     lines = [l for l in out.splitlines() if l.strip()]
-    assert len(lines) == 41, out
+    assert len(lines) == 43, out
     bad = [l for l in lines if not l.endswith(" ok")]
     assert not bad, "\n".join(bad)
     assert sum(" BIG=1 " in l for l in lines) >= 10  # the radix-32/16/12 plans are exercised

@@ -249,6 +249,28 @@ def test_operator_depth_192_every_tile_vs_oracle(ctx, F, dim):
         ctx.set_addressing(False)
 
 
+def test_operator_elevation_256_every_tile_vs_oracle(ctx, F):
+    """A 3D elevation axis padded to 256 points (the 3D workload's): its
+    complex64 strided tiles hold 32 columns (16 in complex128). Every tile
+    variant, both precisions, against the oracle."""
+    p = W.small3d(seed=35, nx=10, ny=128, nz=6)
+    assert F.lib().fwi_padded_length(p.ny) == 256
+    m = O.contrast(p.c, p.alpha, p.c0)
+    x = W.random_complex(13, (3,) + p.shape)
+    Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), 3, p.nx, p.ny, p.nz, p.dx)
+    ref = np.stack([O.vie_apply(Gh, m, x[b]).ravel() for b in range(3)])
+    try:
+        for v in range(3):
+            ctx.set_tuning(bytes([v] * F.TUNING_BYTES))
+            for prec in (0, 1):
+                dt = torch.complex64 if prec else torch.complex128
+                y = host(ctx.apply_operator(p, dev(m), [0] * 3, dev(x.reshape(3, -1), dt), precision=prec))
+                for b in range(3):
+                    assert relerr(y[b], ref[b]) < (2e-6 if prec else 1e-13), (v, prec, b)
+    finally:
+        ctx.set_tuning(None)
+
+
 def test_operator_and_solve_with_64bit_addressing(ctx, F):
     """The 64-bit addressing path of the strided passes (automatic only for
     planes of 2 GiB or more) forced on small grids: the 2D and 3D operators in
