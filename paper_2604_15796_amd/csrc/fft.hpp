@@ -11,8 +11,8 @@
 // global memory directly (cropping is a store predicate), so a pass costs one
 // read and one write of its data in HBM and S-1 LDS exchanges in between.
 //
-// Lengths are 2^a 3^b (32 ... 1024) with radices 8, 6, 4, 3, or 16 and 32 for
-// tiles with many points per thread; every plan starts with a radix of at
+// Lengths are 2^a 3^b (32 ... 1024) with radices 8, 6, 4, 3, or 32, 16 and 12
+// for tiles with many points per thread; every plan starts with a radix of at
 // least 8, which makes the zero half of a padded input a whole set of
 // predicated-off loads, and the inverse plan is the reverse of the forward one.
 #pragma once
