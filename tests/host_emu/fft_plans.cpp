@@ -130,10 +130,24 @@ void all_modes(const char* name) {
       all_modes<T, 256, NL, NT, LF>(#T), all_modes<T, 384, NL, NT, LF>(#T), all_modes<T, 512, NL, NT, LF>(#T), \
       all_modes<T, 768, NL, NT, LF>(#T), all_modes<T, 1024, NL, NT, LF>(#T)
 
+// FWI_EMU_PART 0 .. 3 selects a quarter of the configurations (the test
+// builds and runs the quarters in parallel); undefined: all of them.
+#if defined(FWI_EMU_PART)
+#define FWI_EMU_IN(k) (FWI_EMU_PART == (k))
+#else
+#define FWI_EMU_IN(k) 1
+#endif
 int main() {
+#if FWI_EMU_IN(0)
   FWI_EMU_LENGTHS(float, 16, 256, true);   // strided passes, radix-16/32 plans from 256 up
+#endif
+#if FWI_EMU_IN(1)
   FWI_EMU_LENGTHS(double, 8, 256, true);   // complex128 strided passes
+#endif
+#if FWI_EMU_IN(2)
   FWI_EMU_LENGTHS(float, 4, 256, false);   // row passes
+#endif
+#if FWI_EMU_IN(3)
   all_modes<float, 512, 16, 256, false>("float");   // row pass, radix-16/32 plan
   all_modes<float, 128, 32, 256, false>("float");   // radix 16 x 8
   all_modes<float, 768, 8, 256, false>("float");    // radix 8/8/12, butterflies not a divisor of NT
@@ -144,5 +158,6 @@ int main() {
   all_modes<double, 192, 16, 256, true>("double");  // radix 16 x 12 in complex128
   all_modes<float, 256, 32, 256, true>("float");    // 32-column strided tiles of length 256
   all_modes<float, 256, 32, 512, true>("float");
+#endif
   return 0;
 }

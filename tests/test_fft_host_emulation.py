@@ -25,10 +25,17 @@ CSRC = ROOT / "paper_2604_15796_amd" / "csrc"
 
 @pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 def test_line_fft_plans_on_host(tmp_path):
-    exe = tmp_path / "fft_plans"
-    subprocess.run(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-I{EMU}", f"-I{CSRC}",
-                    str(EMU / "fft_plans.cpp"), "-o", str(exe), "-lpthread"], check=True, timeout=600)
-    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, timeout=900).stdout
+    # four quarters of the configurations, built and run in parallel
+    parts = range(4)
+    exes = [tmp_path / f"fft_plans_{k}" for k in parts]
+    builds = [subprocess.Popen(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-DFWI_EMU_PART={k}",
+                                f"-I{EMU}", f"-I{CSRC}", str(EMU / "fft_plans.cpp"), "-o", str(exes[k]), "-lpthread"])
+              for k in parts]
+    assert all(b.wait(timeout=900) == 0 for b in builds)
+    runs = [subprocess.Popen([str(e)], stdout=subprocess.PIPE, text=True) for e in exes]
+    outs = [r.communicate(timeout=900)[0] for r in runs]
+    assert all(r.returncode == 0 for r in runs)
+    out = "".join(outs)
     lines = [l for l in out.splitlines() if l.strip()]
     assert len(lines) == 43, out
     bad = [l for l in lines if not l.endswith(" ok")]
@@ -44,12 +51,16 @@ def test_fused_lateral_elevation_passes_on_host(tmp_path):
     class-major forward spectrum against a direct 2D DFT of the padded
     operand, the inverse against a direct inverse DFT, the Gram-Schmidt and
     start operands with their per-row norms, and the operator epilogue."""
-    exe = tmp_path / "xy_plans"
-    subprocess.run(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-I{EMU}", f"-I{CSRC}",
-                    str(EMU / "xy_plans.cpp"), "-o", str(exe), "-lpthread"], check=True, timeout=600)
-    p = subprocess.run([str(exe)], capture_output=True, text=True, timeout=900)
-    lines = [l for l in p.stdout.splitlines() if l.strip()]
-    assert p.returncode == 0, p.stdout + p.stderr
-    assert len(lines) == 22, p.stdout
+    exes = [tmp_path / f"xy_plans_{k}" for k in (0, 1)]  # the two shapes, in parallel
+    builds = [subprocess.Popen(["g++", "-std=c++20", "-O1", "-fsanitize=address", f"-DFWI_XY_PART={k}",
+                                f"-I{EMU}", f"-I{CSRC}", str(EMU / "xy_plans.cpp"), "-o", str(e), "-lpthread"])
+              for k, e in enumerate(exes)]
+    assert all(b.wait(timeout=900) == 0 for b in builds)
+    runs = [subprocess.Popen([str(e)], stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True) for e in exes]
+    res = [r.communicate(timeout=900) for r in runs]
+    out = "".join(o for o, _ in res)
+    lines = [l for l in out.splitlines() if l.strip()]
+    assert all(r.returncode == 0 for r in runs), out + "".join(e for _, e in res)
+    assert len(lines) == 22, out
     bad = [l for l in lines if not l.endswith(" ok")]
     assert not bad, "\n".join(bad)
