@@ -219,18 +219,20 @@ def test_operator_every_tile_variant_and_autotune(ctx, F, dim):
     ctx.set_tuning(None)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_operator_depth_192_every_tile_vs_oracle(ctx, F, dim):
+@pytest.mark.parametrize("dim,nz", [(2, 96), (3, 96), (2, 384)])
+def test_operator_depth_192_every_tile_vs_oracle(ctx, F, dim, nz):
     """A depth axis padded to 192 points (the 3D workload's): the 16-line
     tile runs the radix 16 x 12 plan, the others the 8 x 8 x 3 plan, and the
-    complex64 convolutions take their twiddle powers from the LDS table.
-    Every tile variant, both precisions, ragged RHS count, and the 16-line
-    tile in its 64-bit addressing form, against the oracle."""
+    complex64 convolutions take their twiddle powers from the LDS table; and
+    one padded to 768 (the 384^2 workload's), whose tiles run the 8 x 8 x 12
+    and 8 x 8 x 4 x 3 plans. Every tile variant, both precisions, ragged RHS
+    count, and the 16-line tile in its 64-bit addressing form, against the
+    oracle."""
     if dim == 2:
-        p = W.small2d(seed=33, nx=36, nz=96, nf=1)
+        p = W.small2d(seed=33 + nz, nx=36 if nz < 200 else 20, nz=nz, nf=1)
     else:
-        p = W.small3d(seed=34, nx=12, ny=10, nz=96)
-    assert F.lib().fwi_padded_length(p.nz) == 192
+        p = W.small3d(seed=34, nx=12, ny=10, nz=nz)
+    assert F.lib().fwi_padded_length(p.nz) == 2 * nz
     m = O.contrast(p.c, p.alpha, p.c0)
     x = W.random_complex(12, (5,) + p.shape)
     Gh = O.green_spectrum(O.wavenumber(p.freqs[0], p.c0), p.dim, p.nx, p.ny, p.nz, p.dx)
